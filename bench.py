@@ -1,0 +1,198 @@
+"""Throughput benchmark of the RK4 stage operator (one MI355X).
+
+Workload (the headline configuration): cube [-1,1]^3 of 32^3 Kuhn cubes x 6 =
+196,608 tetrahedra, interior vertices jittered by U(-0.1h, 0.1h) (seed 2),
+p = 3 (20 modes per component, 23.6M E+H DOF), eps ~ U[1,4] per element,
+mu = 1, upwind flux, PEC walls, divergence-free Gaussian pulse e0 = curl(z g),
+width 0.2, RK4 at CFL 0.3, FP32 state. The same workload is also timed with
+the FP64 state and reported in the "fp64" field.
+
+Metric: GDOF-updates/s per RK stage = K * 6N * 4 * steps / t / 1e9 (E+H DOF).
+A "step" is one full RK4 step (four fused stage launches) over the whole mesh,
+with all data resident in HBM. Timed with HIP events on the stream the
+kernels run on; W warm-up steps are excluded.
+
+roofline: algorithmic HBM bytes per stage launch (17/4 state passes of 6N
+values plus the per-element geometry and connectivity records, see
+mdg_query) / the average stage-kernel duration, against 8 TB/s.
+traffic: measured HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE,
+read from the committed counter summary when it was taken on the current
+kernel source, else null.
+cpu_baseline: the FP64 oracle (numpy) evaluating the operator on a bounded
+sample of elements of the same mesh on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2002_08733_amd", "csrc", "stage_kernel.hip")
+
+
+def kernel_source_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup_solver(w, precision, dt, q=4):
+    import torch
+    from paper_2002_08733_amd import Solver
+    s = Solver(w.p, precision, w.flux, dt=dt)
+    s.set_mesh(w.verts, w.tets)
+    s.set_material(w.eps, w.mu)
+    s.bind_torch_workspace()
+    x = s.projection_points(q)
+    s.project(q, W.gaussian_curl_e(x, 0.2), None)
+    del x
+    torch.cuda.synchronize()
+    return s
+
+
+def time_steps(s, steps, warmup):
+    import torch
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    s.step(warmup, sp)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(steps, sp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1000.0  # seconds
+
+
+def cpu_baseline(w, dt, sample):
+    """The FP64 oracle on a bounded sample of the same mesh (one operator
+    application = one RK stage's arithmetic on those elements)."""
+    from threadpoolctl import threadpool_info
+    from oracle import OracleDG
+    t0 = time.time()
+    O = OracleDG(w.verts, w.tets, w.p, eps=w.eps, mu=w.mu, flux=w.flux)
+    setup = time.time() - t0
+    rng = np.random.default_rng(0)
+    shp = (w.nt, 3, O.N)
+    cE, cH = rng.standard_normal(shp), rng.standard_normal(shp)
+    idx = np.sort(rng.choice(w.nt, size=sample, replace=False))
+    O.rhs(cE, cH, elems=idx[:256])  # warm caches
+    t0 = time.time()
+    O.rhs(cE, cH, elems=idx)
+    el = time.time() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    gdof = sample * 6 * O.N / el / 1e9
+    return {"value": gdof, "unit": "GDOF/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one operator application on {sample} random elements of the same "
+                      f"{w.nt}-element mesh ({el:.1f} s; oracle setup {setup:.1f} s excluded)",
+            "host_cpus": os.cpu_count()}
+
+
+def traffic_for(kernel_hash, precision):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    ent = d.get(precision)
+    if not ent or ent.get("kernel_src_sha") != kernel_hash:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=32, help="cubes per axis (32 = headline workload)")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    w = W.jittered(args.n, 3, seed=2, flux="upwind")
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+    khash = kernel_source_hash()
+    results = {}
+    precs = [args.precision] + ([] if args.skip_fp64 else [p for p in ("fp32", "fp64") if p != args.precision])
+    for prec in precs:
+        log(f"[bench] setup {prec} n={args.n} K={w.nt}")
+        s = setup_solver(w, prec, dt)
+        info = s.query()
+        W0 = s.energy()
+        log(f"[bench] {prec}: warmup {args.warmup}, timing {args.steps} steps")
+        sec = time_steps(s, args.steps, args.warmup)
+        W1 = s.energy()
+        stages = 4 * args.steps
+        N = info["nmodes"]
+        gdof = w.nt * 6 * N * stages / sec / 1e9
+        t_stage = sec / stages
+        achieved = info["bytes_per_stage"] / t_stage / 1e9
+        tr = traffic_for(khash, prec)
+        results[prec] = {
+            "value": gdof, "ms_per_step": 1000.0 * sec / args.steps, "us_per_stage": 1e6 * t_stage,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
+                         "algorithmic_bytes_per_launch": info["bytes_per_stage"],
+                         "kernel": "mdg::stage_kernel", "kernel_src_sha": khash},
+            "flops_per_stage": info["flops_per_stage"],
+            "energy_ratio": W1 / W0, "tile": info["tile_size"], "halo_per_elem": info["n_halo"] / w.nt,
+        }
+        log(f"[bench] {prec}: {gdof:.1f} GDOF/s, {1e6 * t_stage:.1f} us/stage, "
+            f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM), W1/W0={W1 / W0:.6f}")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+
+    main_r = results[args.precision]
+    out = {
+        "metric": "GDOF-updates/s per RK stage at p=3 (FP32 vs FP64) and % of HBM roofline",
+        "value": main_r["value"], "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"jittered cube [-1,1]^3, {args.n}^3 cubes x 6 = {w.nt} tets, p=3, "
+                               "eps~U[1,4], mu=1, upwind, PEC, Gaussian pulse, RK4 CFL 0.3",
+                   "elements": w.nt, "order": 3, "dof": w.nt * 6 * 20, "dt": dt, "flux": "upwind"},
+        "roofline": main_r["roofline"],
+        "us_per_stage": main_r["us_per_stage"],
+    }
+    other = [p for p in results if p != args.precision]
+    for p in other:
+        out[p] = {"value": results[p]["value"], "unit": "GDOF/s", "us_per_stage": results[p]["us_per_stage"],
+                  "roofline": results[p]["roofline"]}
+    if not args.skip_cpu:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} elements")
+        out["cpu_baseline"] = cpu_baseline(w, dt, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * mdg.h -- C ABI of libmdg: matrix-free discontinuous Galerkin time-domain
+ * Maxwell solver on tetrahedral meshes for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kapidani & Schoeberl, "A matrix-free Discontinuous Galerkin method
+ * for the time dependent Maxwell equations in unbounded domains"
+ * (arXiv:2002.08733). Cited below as [KS] with section / equation labels.
+ *
+ * What the library computes (the "hot path", one RK stage per kernel launch):
+ *   eps d_t e = curl h - j,  mu d_t h = -curl e            [KS Sec. I, eqs. ampere_cont, faraday_cont]
+ * discretised with element-wise P_p vector fields expanded in the covariantly
+ * mapped orthonormal Dubiner basis A_T^-T e_j phi_l         [KS Sec. II, eq. mapped_eh]
+ * so that the mass matrix is 3x3 block diagonal and the volume curl is one
+ * geometry-independent reference matrix                    [KS Sec. III, eq. matrix_free_curl]
+ * with central [KS Sec. III, eqs. uwc/cwc] or upwind numerical fluxes, PEC
+ * boundaries [KS Sec. IV], complex-stretching PML auxiliary fields
+ * [KS Sec. IV, eqs. p_variable, q_variable] and classic RK4 time stepping.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Element frame: the vertices of each tetrahedron are sorted by ascending
+ *    global vertex id; v0 is the origin of the affine map r = A r^ + v0 with
+ *    A = [v1-v0, v2-v0, v3-v0] (columns) [KS Sec. II, eq. mapping_template].
+ *  - Field coefficients are *covariant* reference coefficients u[t][j][l]
+ *    (element t in the caller's order, component j = 0..2, mode l = 0..N-1),
+ *    so that e(r) = A_t^-T sum_l u[t][:][l] phi_l(A_t^-1 (r - v0)).
+ *    N = (p+1)(p+2)(p+3)/6. Mode order: total degree d ascending, then the
+ *    Dubiner index i, then j (phi_ijk as in [KS Sec. II, eq. dubiner_functions],
+ *    corrected to an orthonormal polynomial basis: the middle factor carries
+ *    (1-x)^j and the last Jacobi weight is (2i+2j+2, 0)).
+ *  - PML auxiliaries p, q use the same covariant expansion as e, h.
+ *  - All host arrays are row-major, caller-owned and only read (or written)
+ *    during the call. Device memory is owned by the caller (see
+ *    mdg_bind_workspace) or, if the caller passes NULL there, by the library.
+ *  - Every function returns an mdg_status; on error, mdg_last_error() gives a
+ *    message valid until the next call on the same handle. No C++ exception
+ *    crosses this boundary. A handle is not thread-safe; use one per stream.
+ */
+#ifndef MDG_H
+#define MDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdg_solver mdg_solver;
+typedef int32_t mdg_status;
+
+enum {
+  MDG_OK = 0,
+  MDG_E_ARG = -1,         /* invalid argument (NULL, size, range) */
+  MDG_E_MESH = -2,        /* degenerate/non-manifold/non-finite mesh */
+  MDG_E_HIP = -3,         /* HIP runtime error (message has the HIP error) */
+  MDG_E_OOM = -4,         /* workspace too small / allocation failed */
+  MDG_E_STATE = -5,       /* call order violated (e.g. step before set_mesh) */
+  MDG_E_UNSTABLE = -6,    /* energy became non-finite */
+  MDG_E_UNSUPPORTED = -7  /* option not compiled in (e.g. order > 4) */
+};
+
+enum { MDG_FP64 = 0, MDG_FP32 = 1 };
+enum { MDG_CENTRAL = 0, MDG_UPWIND = 1 };
+enum { MDG_RK4 = 0 };
+
+typedef struct mdg_options {
+  int32_t order;      /* polynomial order p, 1..4, same for e and h */
+  int32_t precision;  /* MDG_FP64 or MDG_FP32: storage and arithmetic of the state */
+  int32_t flux;       /* MDG_CENTRAL [KS eqs. uwc/cwc] or MDG_UPWIND (Riemann flux) */
+  int32_t integrator; /* MDG_RK4 */
+  double dt;          /* > 0: fixed time step; 0: computed from cfl */
+  double cfl;         /* dt = cfl * min_T(2 r_in,T sqrt(eps_T mu_T)) / (p+1)^2 when dt == 0 */
+} mdg_options;
+
+typedef struct mdg_info {
+  int32_t order, nmodes, nfacemodes, precision, flux, tile_size;
+  int64_t n_elements, n_faces_interior, n_faces_boundary, n_pml;
+  int64_t n_tiles, n_halo;        /* work decomposition of the stage kernel */
+  double dt, time;
+  double bytes_per_stage;         /* algorithmic HBM bytes of one RK stage (all elements) */
+  double flops_per_stage;         /* algorithmic flops of one RK stage (sparse reference ops) */
+  int64_t workspace_bytes;        /* device bytes mdg_bind_workspace needs */
+} mdg_info;
+
+/* Create a solver. opts is copied. *out receives the handle (NULL on error). */
+mdg_status mdg_create(const mdg_options* opts, mdg_solver** out);
+
+/* Destroy a handle; frees library-owned device memory. NULL is ignored. */
+void mdg_destroy(mdg_solver* s);
+
+/* Message of the last failed call on s (or of the last failed mdg_create when
+ * s is NULL). Never NULL. */
+const char* mdg_last_error(const mdg_solver* s);
+
+/* Mesh [KS Sec. II]: nv vertices xyz[nv][3], nt tetrahedra tet[nt][4] (vertex
+ * ids, any order inside a row). Copies its inputs. Faces with one element are
+ * PEC boundary faces [KS Sec. IV]. Errors: MDG_E_MESH for non-finite
+ * coordinates, zero-volume tets, repeated vertices or a face shared by more
+ * than two tets; MDG_E_ARG for ids out of range. Resets material, PML,
+ * sources and state. Host-only (no device call). */
+mdg_status mdg_set_mesh(mdg_solver* s, int64_t nv, const double* xyz, int64_t nt,
+                        const int64_t* tet);
+
+/* Piecewise-constant material per element [KS Sec. I, constitutive law]:
+ * eps[nt], mu[nt] > 0 and finite; NULL means 1. Host-only. */
+mdg_status mdg_set_material(mdg_solver* s, const double* eps, const double* mu);
+
+/* PML damping [KS Sec. IV]: omega[nt][3] >= 0, the per-axis damping w_x, w_y,
+ * w_z of each element (constant per element, as in [KS Sec. V]). Elements with
+ * any w_a > 0 carry the auxiliary fields p, q with eta_a = w_b + w_c - w_a,
+ * xi_a = (w_a - w_b)(w_a - w_c) and pole w_a for component a
+ * [KS Sec. IV, eqs. p_variable, q_variable]. NULL removes the PML. Host-only. */
+mdg_status mdg_set_pml(mdg_solver* s, const double* omega);
+
+/* Point current dipoles j = d delta(r - r0) g(t) [KS Sec. I, current j]:
+ * pos[n][3], dir[n][3], wave[n][3] = (f0, bw, t0) with
+ * g(t) = sin(2 pi f0 (t - t0)) exp(-(t - t0)^2 / (2 s^2)), s = 1/(2 pi bw).
+ * Each dipole acts on the lowest-index element whose closure contains r0.
+ * n <= 4. n = 0 removes all dipoles. MDG_E_ARG if a point is outside the mesh.
+ * Host-only. */
+mdg_status mdg_set_dipoles(mdg_solver* s, int32_t n, const double* pos, const double* dir,
+                           const double* wave);
+
+/* Device bytes needed by the current setup (finalises the setup: element
+ * reordering, tiles, face connectivity). */
+mdg_status mdg_workspace_size(mdg_solver* s, size_t* bytes);
+
+/* Bind device memory: dev_ptr must point to >= mdg_workspace_size bytes of
+ * device memory on the current HIP device, 256-byte aligned, and outlive the
+ * handle (or the next bind). dev_ptr == NULL makes the library allocate it.
+ * Uploads the static data on `stream` (a hipStream_t, NULL = default stream)
+ * and synchronises that stream. Zeroes the state. */
+mdg_status mdg_bind_workspace(mdg_solver* s, void* dev_ptr, size_t bytes, void* stream);
+
+/* Set the state from host FP64 arrays E[nt][3][N], H[nt][3][N] (covariant
+ * coefficients, caller's element order) and PML auxiliaries P, Q (same layout;
+ * NULL = zero; ignored on non-PML elements); t is the time of the state.
+ * Synchronous. */
+mdg_status mdg_set_state(mdg_solver* s, const double* E, const double* H, const double* P,
+                         const double* Q, double t);
+
+/* Copy the state back to host FP64 arrays (same layout; P, Q may be NULL;
+ * zero on non-PML elements). Synchronises the device. *t may be NULL. */
+mdg_status mdg_get_state(mdg_solver* s, double* E, double* H, double* P, double* Q, double* t);
+
+/* Physical points where a field must be sampled for mdg_project: q^3 points
+ * per element (collapsed Gauss-Legendre rule of order q, 1 <= q <= 16).
+ * xyz == NULL: only *npts_per_elem is written. Else xyz[nt][q^3][3]. Host-only. */
+mdg_status mdg_projection_points(mdg_solver* s, int32_t q, int64_t* npts_per_elem, double* xyz);
+
+/* L2-project fields sampled at the mdg_projection_points(q) into the state
+ * (E = Evals[nt][q^3][3], H = Hvals likewise, Cartesian components; NULL =
+ * zero field), auxiliaries zero, time t. Synchronous. */
+mdg_status mdg_project(mdg_solver* s, int32_t q, const double* Evals, const double* Hvals,
+                       double t);
+
+/* Advance nsteps classic RK4 steps. Asynchronous on `stream` (hipStream_t,
+ * NULL = default stream): four stage-kernel launches per step (eight with
+ * PML elements). Kernel faults surface at the next synchronising call. */
+mdg_status mdg_step(mdg_solver* s, int64_t nsteps, void* stream);
+
+/* One operator application [KS Sec. III-IV]: time derivatives (dE, dH, dP, dQ)
+ * of the given state at time t (source evaluated at t), same layouts as
+ * mdg_set_state. The solver state is not modified (stage scratch is).
+ * Synchronous. dP/dQ/P/Q may be NULL. */
+mdg_status mdg_rhs(mdg_solver* s, const double* E, const double* H, const double* P,
+                   const double* Q, double t, double* dE, double* dH, double* dP, double* dQ);
+
+/* Electromagnetic energy W = 1/2 sum_T [(eps e, e)_T + (mu h, h)_T] of the
+ * current state, accumulated in FP64 on the device [KS Sec. III]. Synchronous. */
+mdg_status mdg_energy(mdg_solver* s, double* W);
+
+/* Sizes, decomposition and algorithmic cost of the current setup. */
+mdg_status mdg_query(mdg_solver* s, mdg_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDG_H */

@@ -1,0 +1,372 @@
+// api.hip -- extern "C" entry points of libmdg (declared in include/mdg.h).
+//
+// Host-only calls (mesh, material, PML, dipoles, projection points, query)
+// never touch the device. Device memory is either bound by the caller or
+// allocated here on demand; all device work is enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "refbasis.hpp"
+#include "solver.hpp"
+
+using namespace mdg;
+
+struct mdg_solver {
+  Solver s;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+mdg_status guarded(mdg_solver* h, F&& fn) {
+  if (!h) return MDG_E_ARG;
+  try {
+    h->s.err.clear();
+    fn(h->s);
+    return MDG_OK;
+  } catch (const Error& e) {
+    h->s.err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    h->s.err = "host allocation failed";
+    return MDG_E_OOM;
+  } catch (const std::exception& e) {
+    h->s.err = e.what();
+    return MDG_E_ARG;
+  }
+}
+
+void need_mesh(const Solver& s) {
+  if (s.nt == 0) throw Error(MDG_E_STATE, "no mesh: call mdg_set_mesh first");
+}
+
+void need_bound(const Solver& s) {
+  need_mesh(s);
+  if (!s.bound) throw Error(MDG_E_STATE, "no workspace: call mdg_bind_workspace after the setup calls");
+}
+
+char* dev(const Solver& s, size_t off) { return static_cast<char*>(s.ws) + off; }
+
+// host FP64 SoA rows -> device array of the solver's precision
+void upload(const Solver& s, const std::vector<double>& h, size_t off, hipStream_t st) {
+  if (h.empty()) return;
+  if (s.opt.precision == MDG_FP32) {
+    std::vector<float> f(h.begin(), h.end());
+    hip_check(hipMemcpyAsync(dev(s, off), f.data(), f.size() * 4, hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipStreamSynchronize(st), "upload sync");
+  } else {
+    hip_check(hipMemcpyAsync(dev(s, off), h.data(), h.size() * 8, hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipStreamSynchronize(st), "upload sync");
+  }
+}
+
+void download(const Solver& s, size_t off, size_t n, std::vector<double>& h) {
+  h.resize(n);
+  if (s.opt.precision == MDG_FP32) {
+    std::vector<float> f(n);
+    hip_check(hipMemcpy(f.data(), dev(s, off), n * 4, hipMemcpyDeviceToHost), "download");
+    for (size_t i = 0; i < n; ++i) h[i] = f[i];
+  } else {
+    hip_check(hipMemcpy(h.data(), dev(s, off), n * 8, hipMemcpyDeviceToHost), "download");
+  }
+}
+
+void ensure_final(Solver& s) {
+  need_mesh(s);
+  if (!s.finalized) finalize(s);
+}
+
+void write_state(Solver& s, const double* E, const double* H, const double* P, const double* Q, size_t off,
+                 size_t aoff) {
+  std::vector<double> buf;
+  pack_state(s, E, H, buf);
+  upload(s, buf, off, nullptr);
+  if (s.Kp > 0) {
+    pack_aux(s, P, Q, buf);
+    upload(s, buf, aoff, nullptr);
+  }
+}
+
+void read_state(Solver& s, double* E, double* H, double* P, double* Q, size_t off, size_t aoff) {
+  hip_check(hipDeviceSynchronize(), "synchronize");
+  std::vector<double> buf;
+  if (E || H) {
+    download(s, off, size_t(6) * s.N * s.Kpad, buf);
+    unpack_state(s, buf, E, H);
+  }
+  const size_t n = size_t(s.nt) * 3 * s.N;
+  if (P || Q) {
+    if (s.Kp > 0) {
+      download(s, aoff, size_t(6) * s.N * s.Kppad, buf);
+      unpack_aux(s, buf, P, Q);
+    } else {
+      if (P) std::memset(P, 0, n * sizeof(double));
+      if (Q) std::memset(Q, 0, n * sizeof(double));
+    }
+  }
+}
+
+void fill_sources(const Solver& s, double t, StageParams& sp) {
+  sp.nsrc = (int)s.dips.size();
+  for (int i = 0; i < MAX_DIPOLES; ++i) {
+    sp.src_elem[i] = -1;
+    sp.src_amp[i] = 0.0;
+  }
+  for (int i = 0; i < sp.nsrc; ++i) {
+    sp.src_elem[i] = s.iperm[s.dips[i].elem];
+    sp.src_amp[i] = dipole_amplitude(s.dips[i], t);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
+  if (!out) return MDG_E_ARG;
+  *out = nullptr;
+  g_create_error.clear();
+  if (!o) { g_create_error = "NULL options"; return MDG_E_ARG; }
+  if (o->order < 1 || o->order > 4) { g_create_error = "order must be 1..4"; return MDG_E_UNSUPPORTED; }
+  if (o->precision != MDG_FP64 && o->precision != MDG_FP32) { g_create_error = "bad precision"; return MDG_E_ARG; }
+  if (o->flux != MDG_CENTRAL && o->flux != MDG_UPWIND) { g_create_error = "bad flux"; return MDG_E_ARG; }
+  if (o->integrator != MDG_RK4) { g_create_error = "only MDG_RK4 is available"; return MDG_E_UNSUPPORTED; }
+  if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
+  mdg_solver* h = new (std::nothrow) mdg_solver();
+  if (!h) return MDG_E_OOM;
+  h->s.opt = *o;
+  h->s.P = o->order;
+  h->s.N = nmodes3(o->order);
+  h->s.NF = nmodes2(o->order);
+  *out = h;
+  return MDG_OK;
+}
+
+void mdg_destroy(mdg_solver* h) {
+  if (!h) return;
+  if (h->s.ws_owned && h->s.ws) (void)hipFree(h->s.ws);
+  delete h;
+}
+
+const char* mdg_last_error(const mdg_solver* h) {
+  if (!h) return g_create_error.c_str();
+  return h->s.err.c_str();
+}
+
+mdg_status mdg_set_mesh(mdg_solver* h, int64_t nv, const double* xyz, int64_t nt, const int64_t* tet) {
+  return guarded(h, [&](Solver& s) { setup_mesh(s, nv, xyz, nt, tet); });
+}
+
+mdg_status mdg_set_material(mdg_solver* h, const double* eps, const double* mu) {
+  return guarded(h, [&](Solver& s) { need_mesh(s); setup_material(s, eps, mu); });
+}
+
+mdg_status mdg_set_pml(mdg_solver* h, const double* omega) {
+  return guarded(h, [&](Solver& s) { need_mesh(s); setup_pml(s, omega); });
+}
+
+mdg_status mdg_set_dipoles(mdg_solver* h, int32_t n, const double* pos, const double* dir, const double* wave) {
+  return guarded(h, [&](Solver& s) { need_mesh(s); setup_dipoles(s, n, pos, dir, wave); });
+}
+
+mdg_status mdg_workspace_size(mdg_solver* h, size_t* bytes) {
+  return guarded(h, [&](Solver& s) {
+    if (!bytes) throw Error(MDG_E_ARG, "NULL bytes");
+    ensure_final(s);
+    *bytes = s.L.total;
+  });
+}
+
+mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stream) {
+  return guarded(h, [&](Solver& s) {
+    ensure_final(s);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s.ws_owned && s.ws) {
+      hip_check(hipFree(s.ws), "hipFree");
+      s.ws = nullptr;
+      s.ws_owned = false;
+    }
+    s.bound = false;
+    if (!ptr) {
+      void* p = nullptr;
+      hipError_t e = hipMalloc(&p, s.L.total);
+      if (e != hipSuccess) throw Error(MDG_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      s.ws = p;
+      s.ws_owned = true;
+    } else {
+      if (bytes < s.L.total) throw Error(MDG_E_OOM, "workspace smaller than mdg_workspace_size");
+      if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0) throw Error(MDG_E_ARG, "workspace must be 256-byte aligned");
+      s.ws = ptr;
+    }
+    s.ws_bytes = s.L.total;
+    hip_check(hipMemsetAsync(s.ws, 0, s.L.total, st), "hipMemsetAsync");
+    hip_check(hipStreamSynchronize(st), "sync");
+    upload(s, s.geo, s.L.geo, st);
+    hip_check(hipMemcpyAsync(dev(s, s.L.nbr), s.nbr_code.data(), s.nbr_code.size() * 4, hipMemcpyHostToDevice, st), "nbr");
+    hip_check(hipMemcpyAsync(dev(s, s.L.tile_start), s.tile_start.data(), s.tile_start.size() * 4, hipMemcpyHostToDevice, st), "tiles");
+    hip_check(hipMemcpyAsync(dev(s, s.L.tile_count), s.tile_count.data(), s.tile_count.size() * 4, hipMemcpyHostToDevice, st), "tiles");
+    hip_check(hipMemcpyAsync(dev(s, s.L.halo_off), s.halo_off.data(), s.halo_off.size() * 4, hipMemcpyHostToDevice, st), "halo");
+    if (!s.halo_ent.empty())
+      hip_check(hipMemcpyAsync(dev(s, s.L.halo_ent), s.halo_ent.data(), s.halo_ent.size() * 4, hipMemcpyHostToDevice, st), "halo");
+    hip_check(hipStreamSynchronize(st), "sync");
+    if (s.Kp > 0) upload(s, s.pmlrec, s.L.pml, st);
+    if (!s.dips.empty()) {
+      std::vector<double> src(size_t(MAX_DIPOLES) * 3 * s.N, 0.0);
+      for (size_t i = 0; i < s.dips.size(); ++i)
+        std::copy(s.dips[i].coef.begin(), s.dips[i].coef.end(), src.begin() + i * 3 * s.N);
+      upload(s, src, s.L.src, st);
+    }
+    s.dt = s.opt.dt > 0 ? s.opt.dt : cfl_dt(s);
+    s.t = 0.0;
+    s.bound = true;
+  });
+}
+
+mdg_status mdg_set_state(mdg_solver* h, const double* E, const double* H, const double* P, const double* Q,
+                         double t) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (!E || !H) throw Error(MDG_E_ARG, "E and H are required");
+    write_state(s, E, H, P, Q, s.L.Y, s.L.aY);
+    s.t = t;
+  });
+}
+
+mdg_status mdg_get_state(mdg_solver* h, double* E, double* H, double* P, double* Q, double* t) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    read_state(s, E, H, P, Q, s.L.Y, s.L.aY);
+    if (t) *t = s.t;
+  });
+}
+
+mdg_status mdg_projection_points(mdg_solver* h, int32_t q, int64_t* npts, double* xyz) {
+  return guarded(h, [&](Solver& s) {
+    need_mesh(s);
+    if (q < 1 || q > 16) throw Error(MDG_E_ARG, "q must be 1..16");
+    if (npts) *npts = int64_t(q) * q * q;
+    if (xyz) projection_points(s, q, xyz);
+  });
+}
+
+mdg_status mdg_project(mdg_solver* h, int32_t q, const double* Ev, const double* Hv, double t) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (q < 1 || q > 16) throw Error(MDG_E_ARG, "q must be 1..16");
+    std::vector<double> ce, ch;
+    const size_t n = size_t(s.nt) * 3 * s.N;
+    if (Ev) project_fields(s, q, Ev, ce); else ce.assign(n, 0.0);
+    if (Hv) project_fields(s, q, Hv, ch); else ch.assign(n, 0.0);
+    write_state(s, ce.data(), ch.data(), nullptr, nullptr, s.L.Y, s.L.aY);
+    s.t = t;
+  });
+}
+
+mdg_status mdg_step(mdg_solver* h, int64_t nsteps, void* stream) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (nsteps < 0) throw Error(MDG_E_ARG, "nsteps < 0");
+    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
+    const DevLayout& L = s.L;
+    for (int64_t n = 0; n < nsteps; ++n) {
+      for (int i = 0; i < 4; ++i) {
+        StageParams sp{};
+        sp.stage = i;
+        sp.bcoef = bw[i];
+        sp.cdt = i < 3 ? cn[i + 1] * s.dt : 0.0;
+        sp.dt = s.dt;
+        fill_sources(s, s.t + cn[i] * s.dt, sp);
+        // stage inputs: Y -> Ua -> Ub -> Ua, final update in place into Y
+        const size_t in = i == 0 ? L.Y : (i == 2 ? L.Ub : L.Ua);
+        const size_t outb = i == 1 ? L.Ub : L.Ua;
+        const size_t ain = i == 0 ? L.aY : (i == 2 ? L.aUb : L.aUa);
+        const size_t aout = i == 1 ? L.aUb : L.aUa;
+        sp.Y = dev(s, L.Y);
+        sp.Uin = dev(s, in);
+        sp.Uout = dev(s, outb);
+        sp.ACC = dev(s, L.ACC);
+        sp.aY = dev(s, L.aY);
+        sp.aUin = dev(s, ain);
+        sp.aUout = dev(s, aout);
+        sp.aACC = dev(s, L.aACC);
+        launch_stage(s, sp, stream);
+      }
+      s.t += s.dt;
+    }
+  });
+}
+
+mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double* P, const double* Q, double t,
+                   double* dE, double* dH, double* dP, double* dQ) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (!E || !H || !dE || !dH) throw Error(MDG_E_ARG, "E, H, dE, dH are required");
+    const DevLayout& L = s.L;
+    write_state(s, E, H, P, Q, L.Ua, L.aUa);
+    StageParams sp{};
+    sp.stage = -1;
+    sp.dt = s.dt;
+    fill_sources(s, t, sp);
+    sp.Y = dev(s, L.Y);
+    sp.Uin = dev(s, L.Ua);
+    sp.Uout = dev(s, L.Ub);
+    sp.ACC = dev(s, L.ACC);
+    sp.aY = dev(s, L.aY);
+    sp.aUin = dev(s, L.aUa);
+    sp.aUout = dev(s, L.aUb);
+    sp.aACC = dev(s, L.aACC);
+    launch_stage(s, sp, nullptr);
+    read_state(s, dE, dH, dP, dQ, L.Ub, L.aUb);
+  });
+}
+
+mdg_status mdg_energy(mdg_solver* h, double* W) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (!W) throw Error(MDG_E_ARG, "NULL W");
+    hip_check(hipDeviceSynchronize(), "synchronize");
+    launch_energy(s, dev(s, s.L.Y), nullptr);
+    hip_check(hipMemcpy(W, dev(s, s.L.eout), sizeof(double), hipMemcpyDeviceToHost), "energy copy");
+    if (!std::isfinite(*W)) throw Error(MDG_E_UNSTABLE, "energy is not finite");
+  });
+}
+
+mdg_status mdg_query(mdg_solver* h, mdg_info* info) {
+  return guarded(h, [&](Solver& s) {
+    if (!info) throw Error(MDG_E_ARG, "NULL info");
+    std::memset(info, 0, sizeof(*info));
+    info->order = s.P;
+    info->nmodes = s.N;
+    info->nfacemodes = s.NF;
+    info->precision = s.opt.precision;
+    info->flux = s.opt.flux;
+    if (s.nt == 0) return;
+    ensure_final(s);
+    info->tile_size = s.tile;
+    info->n_elements = s.nt;
+    info->n_faces_interior = s.n_int;
+    info->n_faces_boundary = s.n_bnd;
+    info->n_pml = s.Kp;
+    info->n_tiles = s.ntiles;
+    info->n_halo = s.nhalo;
+    info->dt = s.bound ? s.dt : (s.opt.dt > 0 ? s.opt.dt : cfl_dt(s));
+    info->time = s.t;
+    info->bytes_per_stage = bytes_per_stage(s);
+    info->flops_per_stage = flops_per_stage(s);
+    info->workspace_bytes = (int64_t)s.L.total;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,570 @@
+// setup.cpp -- host-side setup of libmdg: mesh canonicalisation, face
+// matching, element geometry, element ordering and tiling for the stage
+// kernel, PML and source records, projection and state (un)packing.
+//
+// Geometry [KS Sec. II]: every tetrahedron is stored with its vertices sorted
+// by ascending global id; A = [v1-v0, v2-v0, v3-v0] (eq. mapping_template).
+// With the covariant basis A^-T e_j phi_l (eq. mapped_eh):
+//   mass     (eps phi_jl, phi_km)_T = eps |det A| (A^-1 A^-T)_jk delta_lm      [KS Sec. III]
+//   curl     (curl phi_jl, phi_km)_T = sign(det A) (curl^ phi^_jl, phi^_km)_T^ [eq. matrix_free_curl]
+// so the only per-element data of the operator are G0^-1 = A^T A / |det A|,
+// sign(det A), 1/eps, 1/mu (and impedance weights for the upwind flux).
+//
+// Face coupling: a face is parametrised from its three vertices in ascending
+// global-id order on both of its elements, so both elements see the same
+// physical point at the same parameter s and the same tangents t1, t2; their
+// face-basis coefficients can be combined without any permutation.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "refbasis.hpp"
+#include "refops_gen.h"
+#include "solver.hpp"
+
+namespace mdg {
+
+static void inv3(const double* a, double* r, double* det_out) {
+  const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                     a[2] * (a[3] * a[7] - a[4] * a[6]);
+  *det_out = det;
+  const double id = 1.0 / det;
+  r[0] = (a[4] * a[8] - a[5] * a[7]) * id;
+  r[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+  r[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+  r[3] = (a[5] * a[6] - a[3] * a[8]) * id;
+  r[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+  r[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+  r[6] = (a[3] * a[7] - a[4] * a[6]) * id;
+  r[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+  r[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+}
+
+void setup_mesh(Solver& s, int64_t nv, const double* xyz, int64_t nt, const int64_t* tet) {
+  if (nv < 4 || nt < 1 || !xyz || !tet) throw Error(MDG_E_ARG, "set_mesh: empty mesh or NULL array");
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(xyz[i])) throw Error(MDG_E_MESH, "set_mesh: non-finite vertex coordinate");
+  s.nv = nv;
+  s.nt = nt;
+  s.xyz.assign(xyz, xyz + 3 * nv);
+  s.tet.resize(4 * nt);
+  for (int64_t k = 0; k < nt; ++k) {
+    int64_t* t = &s.tet[4 * k];
+    for (int v = 0; v < 4; ++v) {
+      t[v] = tet[4 * k + v];
+      if (t[v] < 0 || t[v] >= nv) throw Error(MDG_E_ARG, "set_mesh: vertex id out of range in tet " + std::to_string(k));
+    }
+    std::sort(t, t + 4);
+    for (int v = 0; v < 3; ++v)
+      if (t[v] == t[v + 1]) throw Error(MDG_E_MESH, "set_mesh: repeated vertex in tet " + std::to_string(k));
+  }
+  // geometry
+  s.A.resize(9 * nt);
+  s.Ainv.resize(9 * nt);
+  s.det.resize(nt);
+  for (int64_t k = 0; k < nt; ++k) {
+    const double* x0 = &s.xyz[3 * s.tet[4 * k]];
+    double* A = &s.A[9 * k];
+    double emax = 0;
+    for (int c = 0; c < 3; ++c) {
+      const double* xc = &s.xyz[3 * s.tet[4 * k + c + 1]];
+      for (int r = 0; r < 3; ++r) {
+        A[3 * r + c] = xc[r] - x0[r];
+        emax = std::max(emax, std::fabs(A[3 * r + c]));
+      }
+    }
+    double det;
+    inv3(A, &s.Ainv[9 * k], &det);
+    if (!std::isfinite(det) || std::fabs(det) <= 1e-12 * emax * emax * emax)
+      throw Error(MDG_E_MESH, "set_mesh: degenerate (zero-volume) tet " + std::to_string(k));
+    s.det[k] = det;
+  }
+  // faces: sort face-sides by their vertex triple and pair equal neighbours
+  struct FS { int64_t a, b, c, side; };
+  std::vector<FS> fs(4 * nt);
+  for (int64_t k = 0; k < nt; ++k)
+    for (int f = 0; f < 4; ++f) {
+      int fv[3];
+      face_vertices(f, fv);
+      const int64_t* t = &s.tet[4 * k];
+      fs[4 * k + f] = {t[fv[0]], t[fv[1]], t[fv[2]], 4 * k + f};
+    }
+  std::sort(fs.begin(), fs.end(), [](const FS& x, const FS& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    if (x.c != y.c) return x.c < y.c;
+    return x.side < y.side;
+  });
+  s.side.assign(4 * nt, -1);
+  s.n_int = s.n_bnd = 0;
+  for (size_t i = 0; i < fs.size();) {
+    size_t j = i + 1;
+    while (j < fs.size() && fs[j].a == fs[i].a && fs[j].b == fs[i].b && fs[j].c == fs[i].c) ++j;
+    if (j - i > 2) throw Error(MDG_E_MESH, "set_mesh: face shared by more than two tets");
+    if (j - i == 2) {
+      s.side[fs[i].side] = fs[i + 1].side;
+      s.side[fs[i + 1].side] = fs[i].side;
+      ++s.n_int;
+    } else {
+      ++s.n_bnd;
+    }
+    i = j;
+  }
+  s.eps.assign(nt, 1.0);
+  s.mu.assign(nt, 1.0);
+  s.omega.clear();
+  s.dips.clear();
+  s.finalized = false;
+  s.bound = false;
+  s.t = 0.0;
+}
+
+void setup_material(Solver& s, const double* eps, const double* mu) {
+  for (int64_t k = 0; k < s.nt; ++k) {
+    const double e = eps ? eps[k] : 1.0, m = mu ? mu[k] : 1.0;
+    if (!(e > 0) || !(m > 0) || !std::isfinite(e) || !std::isfinite(m))
+      throw Error(MDG_E_ARG, "set_material: eps and mu must be positive and finite");
+  }
+  s.eps.assign(s.nt, 1.0);
+  s.mu.assign(s.nt, 1.0);
+  if (eps) std::copy(eps, eps + s.nt, s.eps.begin());
+  if (mu) std::copy(mu, mu + s.nt, s.mu.begin());
+  s.finalized = false;
+  s.bound = false;
+}
+
+void setup_pml(Solver& s, const double* omega) {
+  if (!omega) {
+    s.omega.clear();
+  } else {
+    for (int64_t i = 0; i < 3 * s.nt; ++i)
+      if (!(omega[i] >= 0) || !std::isfinite(omega[i]))
+        throw Error(MDG_E_ARG, "set_pml: damping must be finite and >= 0");
+    s.omega.assign(omega, omega + 3 * s.nt);
+  }
+  s.finalized = false;
+  s.bound = false;
+}
+
+void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const double* wave) {
+  if (n < 0 || n > MAX_DIPOLES) throw Error(MDG_E_ARG, "set_dipoles: 0 <= n <= 4");
+  if (n > 0 && (!pos || !dir || !wave)) throw Error(MDG_E_ARG, "set_dipoles: NULL array");
+  std::vector<Dipole> out;
+  std::vector<double> val(s.N);
+  for (int d = 0; d < n; ++d) {
+    Dipole dp;
+    for (int c = 0; c < 3; ++c) {
+      dp.pos[c] = pos[3 * d + c];
+      dp.dir[c] = dir[3 * d + c];
+      dp.wave[c] = wave[3 * d + c];
+    }
+    if (!(dp.wave[1] > 0)) throw Error(MDG_E_ARG, "set_dipoles: bandwidth must be > 0");
+    dp.elem = -1;
+    double rh[3] = {0, 0, 0};
+    for (int64_t k = 0; k < s.nt && dp.elem < 0; ++k) {
+      const double* x0 = &s.xyz[3 * s.tet[4 * k]];
+      const double* Ai = &s.Ainv[9 * k];
+      double r[3];
+      for (int i = 0; i < 3; ++i)
+        r[i] = Ai[3 * i] * (dp.pos[0] - x0[0]) + Ai[3 * i + 1] * (dp.pos[1] - x0[1]) +
+               Ai[3 * i + 2] * (dp.pos[2] - x0[2]);
+      const double tol = -1e-12;
+      if (r[0] >= tol && r[1] >= tol && r[2] >= tol && 1 - r[0] - r[1] - r[2] >= tol) {
+        dp.elem = k;
+        std::memcpy(rh, r, sizeof rh);
+      }
+    }
+    if (dp.elem < 0) throw Error(MDG_E_ARG, "set_dipoles: point outside the mesh");
+    dubiner3<double>(s.P, rh[0], rh[1], rh[2], val.data(), nullptr);
+    const double* Ai = &s.Ainv[9 * dp.elem];
+    double ad[3];
+    for (int i = 0; i < 3; ++i) ad[i] = Ai[3 * i] * dp.dir[0] + Ai[3 * i + 1] * dp.dir[1] + Ai[3 * i + 2] * dp.dir[2];
+    dp.coef.resize(3 * s.N);
+    for (int j = 0; j < 3; ++j)
+      for (int l = 0; l < s.N; ++l) dp.coef[j * s.N + l] = val[l] * ad[j];
+    out.push_back(dp);
+  }
+  s.dips = out;
+  s.finalized = false;
+  s.bound = false;
+}
+
+double dipole_amplitude(const Dipole& d, double t) {
+  const double pi = 3.14159265358979323846;
+  const double sg = 1.0 / (2.0 * pi * d.wave[1]);
+  const double tau = t - d.wave[2];
+  return std::sin(2.0 * pi * d.wave[0] * tau) * std::exp(-tau * tau / (2.0 * sg * sg));
+}
+
+int tile_size_for(int P, bool fp32) {
+  // elements per workgroup (two lanes each); the trace exchange in LDS needs
+  // 4 NF (4 TILE + halo) reals, kept under 64 KiB
+  const int NF = nmodes2(P);
+  const int rs = fp32 ? 4 : 8;
+  for (int t : {128, 64, 32, 16}) {
+    const double est = (4.0 * NF + 1) * (4.0 * t + 1.6 * t) * rs;
+    if (est <= 60000.0) return t;
+  }
+  return 16;
+}
+
+static uint64_t spread21(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+void finalize(Solver& s) {
+  if (s.nt == 0) throw Error(MDG_E_STATE, "no mesh");
+  const int64_t nt = s.nt;
+  std::vector<char> ispml(nt, 0);
+  if (!s.omega.empty())
+    for (int64_t k = 0; k < nt; ++k)
+      ispml[k] = (s.omega[3 * k] > 0 || s.omega[3 * k + 1] > 0 || s.omega[3 * k + 2] > 0);
+  // Morton order of centroids inside the bounding box, PML elements last
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < s.nv; ++v)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = std::min(lo[c], s.xyz[3 * v + c]);
+      hi[c] = std::max(hi[c], s.xyz[3 * v + c]);
+    }
+  std::vector<uint64_t> key(nt);
+  for (int64_t k = 0; k < nt; ++k) {
+    uint64_t code = 0;
+    for (int c = 0; c < 3; ++c) {
+      double m = 0;
+      for (int v = 0; v < 4; ++v) m += s.xyz[3 * s.tet[4 * k + v] + c];
+      m *= 0.25;
+      const double span = std::max(hi[c] - lo[c], 1e-300);
+      uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, (m - lo[c]) / span * 2097151.0));
+      code |= spread21(q) << c;
+    }
+    key[k] = code;
+  }
+  s.perm.resize(nt);
+  std::iota(s.perm.begin(), s.perm.end(), 0);
+  std::stable_sort(s.perm.begin(), s.perm.end(), [&](int64_t a, int64_t b) {
+    if (ispml[a] != ispml[b]) return ispml[a] < ispml[b];
+    return key[a] < key[b];
+  });
+  s.iperm.resize(nt);
+  for (int64_t k = 0; k < nt; ++k) s.iperm[s.perm[k]] = k;
+  s.K = nt;
+  s.K0 = 0;
+  for (int64_t k = 0; k < nt; ++k) s.K0 += !ispml[k];
+  s.Kp = nt - s.K0;
+  s.Kppad = (std::max<int64_t>(s.Kp, 1) + 63) / 64 * 64;
+
+  const bool fp32 = s.opt.precision == MDG_FP32;
+  const size_t rs = s.real_size();
+  for (int tile = tile_size_for(s.P, fp32);; tile /= 2) {
+    s.tile = tile;
+    // padded by a full tile: lanes past the end of a partial tile load freely
+    s.Kpad = (nt + tile + 63) / 64 * 64;
+    s.tile_start.clear();
+    s.tile_count.clear();
+    for (int part = 0; part < 2; ++part) {
+      const int64_t b = part == 0 ? 0 : s.K0, e = part == 0 ? s.K0 : s.K;
+      for (int64_t x = b; x < e; x += tile) {
+        s.tile_start.push_back((int32_t)x);
+        s.tile_count.push_back((int32_t)std::min<int64_t>(tile, e - x));
+      }
+      if (part == 0) s.ntiles0 = (int64_t)s.tile_start.size();
+    }
+    s.ntiles = (int64_t)s.tile_start.size();
+    // connectivity codes and halo lists
+    s.nbr_code.assign(4 * s.Kpad, -1);
+    auto NB = [&](int f, int64_t k) -> int32_t& { return s.nbr_code[blk_index(k, f, 4)]; };
+    s.halo_off.assign(s.ntiles + 1, 0);
+    s.halo_ent.clear();
+    s.hmax = 0;
+    struct HE { int32_t fn; int64_t kn; int64_t k; int f; };
+    std::vector<HE> ents;
+    for (int64_t t = 0; t < s.ntiles; ++t) {
+      const int64_t b = s.tile_start[t], c = s.tile_count[t];
+      ents.clear();
+      for (int64_t k = b; k < b + c; ++k) {
+        const int64_t ku = s.perm[k];
+        for (int f = 0; f < 4; ++f) {
+          const int64_t sd = s.side[4 * ku + f];
+          if (sd < 0) continue;  // PEC
+          const int64_t kn = s.iperm[sd / 4];
+          const int fn = (int)(sd % 4);
+          if (kn >= b && kn < b + c)
+            NB(f, k) = (int32_t)(fn * tile + (kn - b));
+          else
+            ents.push_back({fn, kn, k, f});
+        }
+      }
+      std::stable_sort(ents.begin(), ents.end(), [](const HE& x, const HE& y) {
+        if (x.fn != y.fn) return x.fn < y.fn;
+        return x.kn < y.kn;
+      });
+      for (size_t h = 0; h < ents.size(); ++h) {
+        NB(ents[h].f, ents[h].k) = (int32_t)(4 * tile + h);
+        s.halo_ent.push_back((int32_t)(ents[h].kn * 4 + ents[h].fn));
+      }
+      s.halo_off[t + 1] = (int32_t)s.halo_ent.size();
+      s.hmax = std::max<int>(s.hmax, (int)ents.size());
+    }
+    const size_t lds = (4ull * s.NF + 1) * (4ull * tile + s.hmax) * rs;
+    if (lds <= 64 * 1024 || tile <= 16) break;
+  }
+  s.nhalo = (int64_t)s.halo_ent.size();
+  if (s.nhalo > 0 && s.K >= (int64_t(1) << 29)) throw Error(MDG_E_ARG, "mesh too large");
+
+  // geometry records
+  s.geo.assign(size_t(NGEO) * s.Kpad, 0.0);
+  auto G = [&](int row, int64_t k) -> double& { return s.geo[blk_index(k, row, NGEO)]; };
+  for (int64_t k = 0; k < s.Kpad; ++k) {
+    if (k >= s.K) {  // padding: harmless values
+      G(G_XX, k) = G(G_YY, k) = G(G_ZZ, k) = 1.0;
+      G(G_IEPS, k) = G(G_IMU, k) = G(G_SIGN, k) = G(G_Z, k) = 1.0;
+      for (int f = 0; f < 4; ++f) G(G_WZ0 + f, k) = 0.5;
+      continue;
+    }
+    const int64_t u = s.perm[k];
+    const double* A = &s.A[9 * u];
+    const double J = std::fabs(s.det[u]);
+    double AtA[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double v = 0;
+        for (int r = 0; r < 3; ++r) v += A[3 * r + i] * A[3 * r + j];
+        AtA[3 * i + j] = v / J;
+      }
+    G(G_XX, k) = AtA[0];
+    G(G_XY, k) = AtA[1];
+    G(G_XZ, k) = AtA[2];
+    G(G_YY, k) = AtA[4];
+    G(G_YZ, k) = AtA[5];
+    G(G_ZZ, k) = AtA[8];
+    G(G_IEPS, k) = 1.0 / s.eps[u];
+    G(G_IMU, k) = 1.0 / s.mu[u];
+    G(G_SIGN, k) = s.det[u] > 0 ? 1.0 : -1.0;
+    const double Zm = std::sqrt(s.mu[u] / s.eps[u]);
+    G(G_Z, k) = Zm;
+    for (int f = 0; f < 4; ++f) {
+      const int64_t sd = s.side[4 * u + f];
+      if (sd < 0) {
+        G(G_WZ0 + f, k) = 0.5;
+      } else {
+        const int64_t un = sd / 4;
+        const double Zp = std::sqrt(s.mu[un] / s.eps[un]);
+        G(G_WZ0 + f, k) = Zm / (Zm + Zp);
+      }
+    }
+  }
+  // PML records: A^T, A^-T (row-major) and the damping
+  s.pmlrec.assign(size_t(NPML) * s.Kppad, 0.0);
+  for (int64_t k = s.K0; k < s.K; ++k) {
+    const int64_t u = s.perm[k], pk = k - s.K0;
+    const double* A = &s.A[9 * u];
+    const double* Ai = &s.Ainv[9 * u];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        s.pmlrec[blk_index(pk, PM_AT + 3 * i + j, NPML)] = A[3 * j + i];
+        s.pmlrec[blk_index(pk, PM_AIT + 3 * i + j, NPML)] = Ai[3 * j + i];
+      }
+    for (int c = 0; c < 3; ++c) s.pmlrec[blk_index(pk, PM_OM + c, NPML)] = s.omega[3 * u + c];
+  }
+  // device layout
+  DevLayout& L = s.L;
+  size_t off = 0;
+  const size_t field = size_t(6) * s.N * s.Kpad * rs;
+  const size_t afield = s.Kp > 0 ? size_t(6) * s.N * s.Kppad * rs : 0;
+  L.Y = off; off = align256(off + field);
+  L.Ua = off; off = align256(off + field);
+  L.Ub = off; off = align256(off + field);
+  L.ACC = off; off = align256(off + field);
+  L.aY = off; off = align256(off + afield);
+  L.aUa = off; off = align256(off + afield);
+  L.aUb = off; off = align256(off + afield);
+  L.aACC = off; off = align256(off + afield);
+  L.geo = off; off = align256(off + size_t(NGEO) * s.Kpad * rs);
+  L.nbr = off; off = align256(off + size_t(4) * s.Kpad * 4);
+  L.tile_start = off; off = align256(off + size_t(s.ntiles) * 4);
+  L.tile_count = off; off = align256(off + size_t(s.ntiles) * 4);
+  L.halo_off = off; off = align256(off + size_t(s.ntiles + 1) * 4);
+  L.halo_ent = off; off = align256(off + std::max<size_t>(s.nhalo, 1) * 4);
+  L.pml = off; off = align256(off + (s.Kp > 0 ? size_t(NPML) * s.Kppad * rs : 0));
+  L.src = off; off = align256(off + size_t(MAX_DIPOLES) * 3 * s.N * rs);
+  const size_t nblk = (s.K + 255) / 256;
+  L.epart = off; off = align256(off + nblk * 8);
+  L.eout = off; off = align256(off + 8);
+  L.total = off;
+  if (field >= (size_t(1) << 32) || size_t(NGEO) * s.Kpad * rs >= (size_t(1) << 32))
+    throw Error(MDG_E_UNSUPPORTED, "mesh too large: a state array exceeds 4 GiB");
+  s.finalized = true;
+}
+
+double cfl_dt(const Solver& s) {
+  // dt = cfl * min_T (2 r_in sqrt(eps mu)) / (p+1)^2, r_in = 3|T| / sum |faces|
+  double best = 1e300;
+  for (int64_t k = 0; k < s.nt; ++k) {
+    const int64_t* t = &s.tet[4 * k];
+    double area = 0;
+    for (int f = 0; f < 4; ++f) {
+      int fv[3];
+      face_vertices(f, fv);
+      const double* a = &s.xyz[3 * t[fv[0]]];
+      const double* b = &s.xyz[3 * t[fv[1]]];
+      const double* c = &s.xyz[3 * t[fv[2]]];
+      double u[3], v[3];
+      for (int i = 0; i < 3; ++i) { u[i] = b[i] - a[i]; v[i] = c[i] - a[i]; }
+      const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2],
+                   cz = u[0] * v[1] - u[1] * v[0];
+      area += 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+    }
+    const double vol = std::fabs(s.det[k]) / 6.0;
+    const double rin = 3.0 * vol / area;
+    best = std::min(best, 2.0 * rin * std::sqrt(s.eps[k] * s.mu[k]));
+  }
+  return s.opt.cfl * best / double((s.P + 1) * (s.P + 1));
+}
+
+void projection_points(const Solver& s, int q, double* xyz) {
+  std::vector<double> pts, w;
+  tet_rule<double>(q, pts, w);
+  const size_t Q = w.size();
+  for (int64_t k = 0; k < s.nt; ++k) {
+    const double* x0 = &s.xyz[3 * s.tet[4 * k]];
+    const double* A = &s.A[9 * k];
+    for (size_t i = 0; i < Q; ++i)
+      for (int r = 0; r < 3; ++r)
+        xyz[(k * Q + i) * 3 + r] =
+            x0[r] + A[3 * r] * pts[3 * i] + A[3 * r + 1] * pts[3 * i + 1] + A[3 * r + 2] * pts[3 * i + 2];
+  }
+}
+
+void project_fields(const Solver& s, int q, const double* vals, std::vector<double>& coef) {
+  // Cartesian L2 projection c_l = (1/|det A|) int_T F phi_l = sum_q w_q F(x_q) phi^_l(r^_q),
+  // then covariant coefficients u_l = A^T c_l.
+  std::vector<double> pts, w;
+  tet_rule<double>(q, pts, w);
+  const size_t Q = w.size();
+  const int N = s.N;
+  std::vector<double> phi(Q * N);
+  for (size_t i = 0; i < Q; ++i) dubiner3<double>(s.P, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], &phi[i * N], nullptr);
+  coef.assign(size_t(s.nt) * 3 * N, 0.0);
+  std::vector<double> c(3 * N);
+  for (int64_t k = 0; k < s.nt; ++k) {
+    std::fill(c.begin(), c.end(), 0.0);
+    for (size_t i = 0; i < Q; ++i) {
+      const double* F = &vals[(k * Q + i) * 3];
+      for (int r = 0; r < 3; ++r)
+        for (int l = 0; l < N; ++l) c[r * N + l] += w[i] * F[r] * phi[i * N + l];
+    }
+    const double* A = &s.A[9 * k];
+    for (int j = 0; j < 3; ++j)
+      for (int l = 0; l < N; ++l)
+        coef[(k * 3 + j) * N + l] = A[j] * c[l] + A[3 + j] * c[N + l] + A[6 + j] * c[2 * N + l];
+  }
+}
+
+void pack_state(const Solver& s, const double* E, const double* H, std::vector<double>& out) {
+  const int N = s.N, R3 = 3 * N;
+  out.assign(size_t(6) * N * s.Kpad, 0.0);
+  for (int64_t k = 0; k < s.K; ++k) {
+    const int64_t u = s.perm[k];
+    for (int j = 0; j < R3; ++j) {
+      if (E) out[blk_index(k, j, 2 * R3)] = E[u * R3 + j];
+      if (H) out[blk_index(k, R3 + j, 2 * R3)] = H[u * R3 + j];
+    }
+  }
+}
+
+void unpack_state(const Solver& s, const std::vector<double>& in, double* E, double* H) {
+  const int N = s.N, R3 = 3 * N;
+  for (int64_t k = 0; k < s.K; ++k) {
+    const int64_t u = s.perm[k];
+    for (int j = 0; j < R3; ++j) {
+      if (E) E[u * R3 + j] = in[blk_index(k, j, 2 * R3)];
+      if (H) H[u * R3 + j] = in[blk_index(k, R3 + j, 2 * R3)];
+    }
+  }
+}
+
+void pack_aux(const Solver& s, const double* P, const double* Q, std::vector<double>& out) {
+  // internal auxiliary = A^-T P / eps (Cartesian, scaled): the PML terms then
+  // need no material factor inside the kernel
+  const int N = s.N, R3 = 3 * N;
+  out.assign(size_t(6) * N * s.Kppad, 0.0);
+  for (int which = 0; which < 2; ++which) {
+    const double* in = which == 0 ? P : Q;
+    if (!in) continue;
+    for (int64_t k = s.K0; k < s.K; ++k) {
+      const int64_t u = s.perm[k], pk = k - s.K0;
+      const double* Ai = &s.Ainv[9 * u];
+      const double m = which == 0 ? s.eps[u] : s.mu[u];
+      for (int l = 0; l < N; ++l)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0;
+          for (int i = 0; i < 3; ++i) v += Ai[3 * i + j] * in[(u * 3 + i) * N + l];
+          out[blk_index(pk, which * R3 + j * N + l, 2 * R3)] = v / m;
+        }
+    }
+  }
+}
+
+void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, double* Q) {
+  const int N = s.N, R3 = 3 * N;
+  for (int which = 0; which < 2; ++which) {
+    double* out = which == 0 ? P : Q;
+    if (!out) continue;
+    std::fill(out, out + size_t(s.nt) * R3, 0.0);
+    for (int64_t k = s.K0; k < s.K; ++k) {
+      const int64_t u = s.perm[k], pk = k - s.K0;
+      const double* A = &s.A[9 * u];
+      const double m = which == 0 ? s.eps[u] : s.mu[u];
+      for (int l = 0; l < N; ++l)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0;
+          for (int i = 0; i < 3; ++i) v += A[3 * i + j] * in[blk_index(pk, which * R3 + i * N + l, 2 * R3)];
+          out[(u * 3 + j) * N + l] = v * m;
+        }
+    }
+  }
+}
+
+static void nnz_of(int P, int& nd, int& nf) {
+  switch (P) {
+    case 1: nd = ref::Ops<1>::nnzD; nf = ref::Ops<1>::nnzT; break;
+    case 2: nd = ref::Ops<2>::nnzD; nf = ref::Ops<2>::nnzT; break;
+    case 3: nd = ref::Ops<3>::nnzD; nf = ref::Ops<3>::nnzT; break;
+    default: nd = ref::Ops<4>::nnzD; nf = ref::Ops<4>::nnzT; break;
+  }
+}
+
+double bytes_per_stage(const Solver& s) {
+  // classic RK4 with fused stages moves 17 state arrays per step (stage 1:
+  // 1 read + 2 writes, stages 2-3: 3 reads + 2 writes, stage 4: 3 reads +
+  // 1 write) -> 17/4 per stage; plus the geometry record and 4 neighbour codes
+  const double rs = (double)s.real_size();
+  const double state = 17.0 / 4.0 * 6.0 * s.N * rs;
+  const double geo = (s.opt.flux == MDG_UPWIND ? 14.0 : 9.0) * rs + 16.0;
+  const double pml = 17.0 / 4.0 * 6.0 * s.N * rs + NPML * rs;
+  return s.K * (state + geo) + s.Kp * pml;
+}
+
+double flops_per_stage(const Solver& s) {
+  int nd, nf;
+  nnz_of(s.P, nd, nf);
+  const double N = s.N, NF = s.NF;
+  // per lane (two per element): traces 2 nf FMA, volume 2 nd FMA, lift 2 nf
+  // FMA, flux per face, 3x3 mass per mode, RK epilogue
+  const double flux = 4.0 * NF * (s.opt.flux == MDG_UPWIND ? 14.0 : 6.0);
+  const double lane = 2.0 * (2.0 * nf + 2.0 * nd + 2.0 * nf) + flux + 18.0 * N + 4.0 * 3.0 * N;
+  const double pml = 2.0 * N * 60.0;
+  return 2.0 * lane * s.K + pml * s.Kp;
+}
+
+}  // namespace mdg

@@ -1,0 +1,139 @@
+// solver.hpp -- internal state of a libmdg handle (host side) and the
+// interfaces between host setup (setup.cpp), kernels (stage_kernel.hip) and
+// the C ABI (api.hip).
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mdg.h"
+
+namespace mdg {
+
+struct Error : std::runtime_error {
+  mdg_status code;
+  Error(mdg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// Per-element geometry record, one SoA row each (internal element order).
+enum GeoRow {
+  G_XX = 0, G_XY, G_XZ, G_YY, G_YZ, G_ZZ,  // G0^-1 = A^T A / |det A|
+  G_IEPS,                                  // 1/eps
+  G_IMU,                                   // 1/mu
+  G_SIGN,                                  // sign(det A)
+  G_Z,                                     // sqrt(mu/eps)
+  G_WZ0, G_WZ1, G_WZ2, G_WZ3,              // Z-/(Z- + Z+) per local face (1/2 on PEC faces)
+  NGEO
+};
+// Per-PML-element record rows.
+enum PmlRow { PM_AT = 0, PM_AIT = 9, PM_OM = 18, NPML = 21 };
+
+constexpr int MAX_DIPOLES = 4;
+
+struct Dipole {
+  double pos[3], dir[3], wave[3];  // wave = (f0, bw, t0)
+  int64_t elem;                    // user order
+  std::vector<double> coef;        // [3][N] covariant load vector phi_l(r0) (A^-1 d)_j
+};
+
+// Device array layout: blocks of BLK = 64 consecutive elements ("AoSoA"),
+// inside a block row-major over the per-element quantities, element fastest:
+//   state  [K/64][field E,H][3N rows][64]    (row = component*N + mode)
+//   geo    [K/64][NGEO][64],  nbr [K/64][4][64]
+//   aux    [Kp/64][field P,Q][3N][64],  pml [Kp/64][NPML][64]
+// A wave reads one row of 64 elements as one contiguous 256/512-byte segment;
+// the field and the row of an access are small constant offsets.
+constexpr int BLK = 64;
+inline size_t blk_index(int64_t e, int row, int rows_per_block) {
+  return (size_t(e / BLK) * rows_per_block + row) * BLK + size_t(e % BLK);
+}
+
+// Device buffer offsets (bytes into the workspace).
+struct DevLayout {
+  size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
+  size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
+  size_t geo, nbr, tile_start, tile_count, halo_off, halo_ent, pml, src;
+  size_t epart, eout;
+  size_t total;
+};
+
+struct Solver {
+  mdg_options opt{};
+  int P = 0, N = 0, NF = 0;
+  std::string err;
+  // ---- mesh (caller's element order, canonical vertex order)
+  int64_t nv = 0, nt = 0;
+  std::vector<double> xyz;
+  std::vector<int64_t> tet;            // [nt][4], ascending ids
+  std::vector<double> A, Ainv, det;    // [nt][9], [nt][9], [nt]
+  std::vector<int64_t> side;           // [nt][4]: neighbour elem*4+face, or -1
+  int64_t n_int = 0, n_bnd = 0;
+  std::vector<double> eps, mu, omega;  // omega [nt][3] (empty = no PML)
+  std::vector<Dipole> dips;
+  // ---- decomposition (valid when finalized)
+  bool finalized = false;
+  int tile = 0;
+  int64_t K = 0, K0 = 0, Kp = 0, Kpad = 0, Kppad = 0;
+  std::vector<int64_t> perm;   // internal -> user
+  std::vector<int64_t> iperm;  // user -> internal
+  int64_t ntiles = 0, ntiles0 = 0, nhalo = 0;
+  int hmax = 0;
+  std::vector<int32_t> tile_start, tile_count, halo_off, halo_ent, nbr_code;
+  std::vector<double> geo;     // blocked [Kpad/64][NGEO][64]
+  std::vector<double> pmlrec;  // blocked [Kppad/64][NPML][64]
+  // ---- device
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  bool bound = false;
+  DevLayout L{};
+  double t = 0.0, dt = 0.0;
+  size_t real_size() const { return opt.precision == MDG_FP32 ? 4 : 8; }
+};
+
+// ---- setup.cpp
+void setup_mesh(Solver& s, int64_t nv, const double* xyz, int64_t nt, const int64_t* tet);
+void setup_material(Solver& s, const double* eps, const double* mu);
+void setup_pml(Solver& s, const double* omega);
+void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const double* wave);
+void finalize(Solver& s);  // ordering, tiles, halo, geometry records, layout
+double cfl_dt(const Solver& s);
+int tile_size_for(int P, bool fp32);
+double dipole_amplitude(const Dipole& d, double t);
+void projection_points(const Solver& s, int q, double* xyz);
+void project_fields(const Solver& s, int q, const double* vals, std::vector<double>& coef);
+// state conversion between the caller's FP64 [nt][3][N] arrays and the
+// internal blocked layout (as double); auxiliaries are stored as A^-T P / eps
+// (P) and A^-T Q / mu (Q).
+void pack_state(const Solver& s, const double* E, const double* H, std::vector<double>& out);
+void unpack_state(const Solver& s, const std::vector<double>& in, double* E, double* H);
+void pack_aux(const Solver& s, const double* P, const double* Q, std::vector<double>& out);
+void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, double* Q);
+double bytes_per_stage(const Solver& s);
+double flops_per_stage(const Solver& s);
+
+// ---- stage_kernel.hip
+struct StageParams {
+  int stage;      // 0..3 RK4 stage, -1 = operator output only
+  double bcoef;   // b_i
+  double cdt;     // c_{i+1} dt (stages 0..2)
+  double dt;
+  int nsrc;
+  int64_t src_elem[MAX_DIPOLES];
+  double src_amp[MAX_DIPOLES];
+  // state buffers (E and H together, blocked layout)
+  void* Y;
+  const void* Uin;
+  void* Uout;
+  void* ACC;
+  void* aY;
+  const void* aUin;
+  void* aUout;
+  void* aACC;
+};
+void launch_stage(const Solver& s, const StageParams& sp, void* stream);
+void launch_energy(const Solver& s, const void* Y, void* stream);
+
+}  // namespace mdg

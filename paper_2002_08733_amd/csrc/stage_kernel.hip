@@ -1,0 +1,737 @@
+// stage_kernel.hip -- fused RK4 stage of the matrix-free DG Maxwell operator
+// for gfx950 (CDNA4), plus the FP64 energy reduction.
+//
+// One launch applies the semi-discrete operator [KS Sec. III-IV] to the stage
+// input of every element and performs that stage's RK4 update in the epilogue.
+//
+// Work decomposition
+//   * Elements are ordered along a Morton curve (PML elements last) and cut
+//     into tiles of TILE consecutive elements; one workgroup per tile, two
+//     lanes per element. Lane role 0 produces the E update and reads H as its
+//     volume input; role 1 produces the H update and reads E. Both roles run
+//     the same instruction stream on different data:
+//        r_E = +s W(h) - Lift(h~) + Pen_Z([e]),   r_H = -s W(e) + Lift(e~) + Pen_Y([h])
+//     where W(v)[c] = sum_{a,d} eps_dac D_a v_d is the weak reference curl
+//     (D_a[l][m] = (d_a phi_l, phi_m), [KS eq. matrix_free_curl]; the H equation
+//     is used in its integrated-by-parts form, algebraically identical to the
+//     strong form of [KS eq. cwc] for polynomial fields), s = sign(det A).
+//   * Reference matrices are compile-time constants (generated header): every
+//     multiply by a structural zero disappears and every nonzero becomes an FMA
+//     with an inline constant. No MFMA: the operators are sparse (p = 3: 202 of
+//     1200 curl entries, 337 of 800 trace entries), and at the resulting
+//     ~2 flop/B the stage is bound by HBM, not by arithmetic.
+//   * Face coupling: every lane computes the face traces of its input field on
+//     its 4 faces, tau_k(v)[m] = sum_l T_f[m][l] (v . t^_k)[l], and stores them
+//     in LDS; faces whose neighbour lies in another tile get the neighbour's
+//     trace recomputed from global memory (halo list sorted by neighbour face so
+//     a wave mostly takes one branch). After one barrier every lane reads own
+//     and neighbour traces, forms the flux in face coefficients and lifts it
+//     with T_f^T. Both elements of a face parametrise it from the face's
+//     vertices in ascending global id, so traces combine without permutation;
+//     the tangential cross product of [KS eqs. uwc/cwc] reduces to
+//     int_F (a x n).b dS = sigma int (a.t2)(b.t1) - (a.t1)(b.t2) ds with
+//     a.t_k = a^.t^_k for covariant fields and sigma = s sigma^_f.
+//   * Upwind penalty: int_F [e]_t . v dS = sum_kl W_kl ([e].t_k)(v.t_l) with
+//     W = sqrt(det g^) g^^-1, g^_kl = t^_k^T G0^-1 t^_l (G0^-1 = A^T A/|det A|).
+//   * Mass inverse [KS Sec. III]: d_t u_l = (1/eps) G0^-1 r_l, 3x3 per mode.
+//   * PML [KS Sec. IV, eqs. p_variable, q_variable] in Cartesian, eps-scaled
+//     auxiliaries P~ = A^-T P / eps: d_t u = (1/eps) G0^-1 r - A^T(eta.c + P~),
+//     d_t P~ = -w.P~ + xi.c, c = A^-T u.
+//   * Blocks are mapped to tiles XCD-major: consecutive tiles (spatial
+//     neighbours) run on the same XCD, so halo re-reads hit its L2.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "refops_dev_gen.h"
+#include "refops_gen.h"
+#include "solver.hpp"
+
+namespace mdg {
+
+template <int P>
+using Ops = ref::Ops<P>;
+
+struct DevArgs {
+  const void* Y;      // RK base state u^n (E,H), blocked layout
+  const void* Uin;    // stage input
+  void* Uout;         // next stage input / operator output
+  void* ACC;          // RK accumulator
+  void* Yw;           // = Y (final in-place update)
+  const void* aY;     // same for the PML auxiliaries
+  const void* aUin;
+  void* aUout;
+  void* aACC;
+  void* aYw;
+  const void* geo;
+  const int32_t* nbr;
+  const int32_t* tile_start;
+  const int32_t* tile_count;
+  const int32_t* halo_off;
+  const int32_t* halo_ent;
+  const void* pml;
+  const void* src;
+  uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes;
+  int64_t pml_base;
+  int32_t tile_begin, ntiles, hmax, stage, nsrc;
+  int64_t src_elem[MAX_DIPOLES];
+  double src_amp[MAX_DIPOLES];
+  double bcoef, cdt, dt;
+};
+
+// ---- raw buffer access (gfx9 buffer descriptor, bounds-checked by hardware)
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename R>
+__device__ __forceinline__ R bld(Rsrc r, uint32_t vo, uint32_t so) {
+  if constexpr (sizeof(R) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  else return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+template <typename R>
+__device__ __forceinline__ void bst(R v, Rsrc r, uint32_t vo, uint32_t so) {
+  if constexpr (sizeof(R) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+  else {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+  }
+}
+__device__ __forceinline__ int32_t bldi(Rsrc r, uint32_t vo, uint32_t so) {
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+}
+// byte offset of element e's block origin in a blocked array with `rows` rows
+// per element: ((e/64)*rows*64 + e%64) * size
+__device__ __forceinline__ uint32_t blk_base(uint32_t e, uint32_t rows, uint32_t size) {
+  return ((e >> 6) * rows * 64u + (e & 63u)) * size;
+}
+// byte offset of row r inside a block
+template <typename R>
+__device__ __forceinline__ constexpr uint32_t rowb(int r) { return (uint32_t)r * 64u * (uint32_t)sizeof(R); }
+
+// ---- face parametrisation constants (local face f opposite vertex f)
+// tangents t^1 = v_b - v_a, t^2 = v_c - v_a of the ascending face vertices:
+//   f=0: (-1,1,0),(-1,0,1)  f=1: (0,1,0),(0,0,1)  f=2: (1,0,0),(0,0,1)  f=3: (1,0,0),(0,1,0)
+// reference sign sigma^_f = sign((t^1 x t^2) . n^_out) = (+,-,+,-)
+template <int F, typename R>
+__device__ __forceinline__ R tan0(R x, R y, R z) {
+  if constexpr (F == 0) return y - x;
+  else if constexpr (F == 1) return y;
+  else return x;
+}
+template <int F, typename R>
+__device__ __forceinline__ R tan1(R x, R y, R z) {
+  if constexpr (F == 3) return y;
+  else if constexpr (F == 0) return z - x;
+  else return z;
+}
+template <int F>
+constexpr int ref_sign() { return (F == 0 || F == 2) ? 1 : -1; }
+
+template <int F, typename R>
+__device__ __forceinline__ void add_lift(R& ax, R& ay, R& az, R L1, R L2) {
+  if constexpr (F == 0) { ax -= L1 + L2; ay += L1; az += L2; }
+  else if constexpr (F == 1) { ay += L1; az += L2; }
+  else if constexpr (F == 2) { ax += L1; az += L2; }
+  else { ax += L1; ay += L2; }
+}
+
+// metric of face F: g^_kl = t^_k^T G t^_l for symmetric G
+template <int F, typename R>
+__device__ __forceinline__ void face_metric(R gxx, R gxy, R gxz, R gyy, R gyz, R gzz, R& g11, R& g12,
+                                            R& g22) {
+  if constexpr (F == 0) {
+    g11 = gxx - 2 * gxy + gyy;
+    g22 = gxx - 2 * gxz + gzz;
+    g12 = gxx - gxy - gxz + gyz;
+  } else if constexpr (F == 1) {
+    g11 = gyy; g22 = gzz; g12 = gyz;
+  } else if constexpr (F == 2) {
+    g11 = gxx; g22 = gzz; g12 = gxz;
+  } else {
+    g11 = gxx; g22 = gyy; g12 = gxy;
+  }
+}
+
+// ---- reference-operator constants
+// FP32: the constexpr values become instruction literals (v_fmac_f32 with an
+// inline constant). FP64: VOP3 has no literal form, so the values are read from
+// packed tables in constant memory (scalar loads, consumed in table order).
+template <typename R, int P>
+struct Cst;
+template <int P>
+struct Cst<float, P> {
+  static __device__ __forceinline__ float tr(int f, int m, int l) { return (float)Ops<P>::T[f][m][l]; }
+  static __device__ __forceinline__ float tc(int f, int m, int l) { return (float)Ops<P>::T[f][m][l]; }
+  static __device__ __forceinline__ float d(int a, int l, int m) { return (float)Ops<P>::D[a][l][m]; }
+};
+template <int P>
+__device__ __forceinline__ const double* tabTR();
+template <int P>
+__device__ __forceinline__ const double* tabTC();
+template <int P>
+__device__ __forceinline__ const double* tabD();
+#define MDG_TABS(p)                                                                  \
+  template <>                                                                        \
+  __device__ __forceinline__ const double* tabTR<p>() { return mdg_TpR_##p; }        \
+  template <>                                                                        \
+  __device__ __forceinline__ const double* tabTC<p>() { return mdg_TpC_##p; }        \
+  template <>                                                                        \
+  __device__ __forceinline__ const double* tabD<p>() { return mdg_DpV_##p; }
+MDG_TABS(1)
+MDG_TABS(2)
+MDG_TABS(3)
+MDG_TABS(4)
+#undef MDG_TABS
+template <int P>
+struct Cst<double, P> {
+  static __device__ __forceinline__ double tr(int f, int m, int l) { return tabTR<P>()[Ops<P>::TiR[f][m][l]]; }
+  static __device__ __forceinline__ double tc(int f, int m, int l) { return tabTC<P>()[Ops<P>::TiC[f][m][l]]; }
+  static __device__ __forceinline__ double d(int a, int l, int m) { return tabD<P>()[Ops<P>::DiV[a][l][m]]; }
+};
+
+// traces of a vector coefficient field on face F: t0/t1 = T_F (v . t^1/2)
+template <int P, int F, typename R>
+__device__ __forceinline__ void face_trace(const R (&v)[3][Ops<P>::N], R (&t0)[Ops<P>::NF],
+                                           R (&t1)[Ops<P>::NF]) {
+  constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
+#pragma unroll
+  for (int m = 0; m < NF; ++m) {
+    R s0 = 0, s1 = 0;
+    bool first = true;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      if (Ops<P>::T[F][m][l] != 0.0) {
+        const R c = Cst<R, P>::tr(F, m, l);
+        const R a = tan0<F, R>(v[0][l], v[1][l], v[2][l]);
+        const R b = tan1<F, R>(v[0][l], v[1][l], v[2][l]);
+        s0 = first ? c * a : fma(c, a, s0);
+        s1 = first ? c * b : fma(c, b, s1);
+        first = false;
+      }
+    }
+    t0[m] = s0;
+    t1[m] = s1;
+  }
+}
+
+// acc[j][l] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m])
+template <int P, int F, typename R>
+__device__ __forceinline__ void face_lift(const R (&A1)[Ops<P>::NF], const R (&A2)[Ops<P>::NF],
+                                          R (&acc)[3][Ops<P>::N]) {
+  constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    R L1 = 0, L2 = 0;
+    bool first = true;
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      if (Ops<P>::T[F][m][l] != 0.0) {
+        const R c = Cst<R, P>::tc(F, m, l);
+        L1 = first ? c * A1[m] : fma(c, A1[m], L1);
+        L2 = first ? c * A2[m] : fma(c, A2[m], L2);
+        first = false;
+      }
+    }
+    if (!first) add_lift<F, R>(acc[0][l], acc[1][l], acc[2][l], L1, L2);
+  }
+}
+
+// acc = gs * W(v):  W[x] = D_z v_y - D_y v_z, W[y] = D_x v_z - D_z v_x, W[z] = D_y v_x - D_x v_y
+template <int P, typename R>
+__device__ __forceinline__ void volume_curl(const R (&v)[3][Ops<P>::N], R gs, R (&acc)[3][Ops<P>::N]) {
+  constexpr int N = Ops<P>::N;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    R ax = 0, ay = 0, az = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      if (Ops<P>::D[0][l][m] != 0.0) {
+        const R cx = Cst<R, P>::d(0, l, m);
+        ay = fma(cx, v[2][m], ay);
+        az = fma(-cx, v[1][m], az);
+      }
+      if (Ops<P>::D[1][l][m] != 0.0) {
+        const R cy = Cst<R, P>::d(1, l, m);
+        ax = fma(-cy, v[2][m], ax);
+        az = fma(cy, v[0][m], az);
+      }
+      if (Ops<P>::D[2][l][m] != 0.0) {
+        const R cz = Cst<R, P>::d(2, l, m);
+        ax = fma(cz, v[1][m], ax);
+        ay = fma(-cz, v[0][m], ay);
+      }
+    }
+    acc[0][l] = gs * ax;
+    acc[1][l] = gs * ay;
+    acc[2][l] = gs * az;
+  }
+}
+
+// LDS trace storage, slot-major: slot s (one face of one element) holds
+// [role][k][m] = 4 NF reals, padded to an odd stride so that consecutive lanes
+// (consecutive slots) hit distinct banks. A lane keeps one base address per
+// slot; role, k and m become immediate offsets.
+template <int NF>
+constexpr int slot_stride() { return 4 * NF + 1; }
+template <int NF>
+__device__ __forceinline__ int lbase(int slot, int role) { return slot * slot_stride<NF>() + role * 2 * NF; }
+template <int NF>
+constexpr int loff(int k, int m) { return k * NF + m; }
+
+// neighbour trace of a halo entry: load the components face F needs, trace, store
+template <int P, int F, typename R>
+__device__ __forceinline__ void halo_trace(Rsrc st, uint32_t vo, R* lds, int role, int slot) {
+  constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
+  R w[3][N];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const bool need = (F == 0) || (F == 1 && c != 0) || (F == 2 && c != 1) || (F == 3 && c != 2);
+#pragma unroll
+    for (int l = 0; l < N; ++l) w[c][l] = need ? bld<R>(st, vo, rowb<R>(c * N + l)) : R(0);
+  }
+  R t0[NF], t1[NF];
+  face_trace<P, F, R>(w, t0, t1);
+  R* d = lds + lbase<NF>(slot, role);
+#pragma unroll
+  for (int m = 0; m < NF; ++m) {
+    d[loff<NF>(0, m)] = t0[m];
+    d[loff<NF>(1, m)] = t1[m];
+  }
+}
+
+// RK4 update of one value k = L(U)_i of the stage (vo/so: its byte offset)
+template <typename R>
+__device__ __forceinline__ void rk_store(int stage, R k, Rsrc Y, Rsrc Uout, Rsrc ACC, uint32_t vo, uint32_t so,
+                                         R b, R cdt, R dt) {
+  if (stage == 0) {
+    const R y = bld<R>(Y, vo, so);
+    bst<R>(b * k, ACC, vo, so);
+    bst<R>(fma(cdt, k, y), Uout, vo, so);
+  } else if (stage == 1 || stage == 2) {
+    const R y = bld<R>(Y, vo, so), a = bld<R>(ACC, vo, so);
+    bst<R>(fma(b, k, a), ACC, vo, so);
+    bst<R>(fma(cdt, k, y), Uout, vo, so);
+  } else if (stage == 3) {
+    const R y = bld<R>(Y, vo, so), a = bld<R>(ACC, vo, so);
+    bst<R>(fma(dt, fma(b, k, a), y), Y, vo, so);  // in place: only this lane touches it
+  } else {
+    bst<R>(k, Uout, vo, so);
+  }
+}
+
+// one face of the flux/lift phase
+template <int P, int F, bool UPW, typename R>
+__device__ __forceinline__ void face_flux(const R* lds, int role, int tile, int li, int code, R g,
+                                          R sgn, R wz, R Z, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz,
+                                          R (&acc)[3][Ops<P>::N]) {
+  constexpr int NF = Ops<P>::NF;
+  const int so = F * tile + li;
+  // PEC faces (code < 0) read the own trace with the mirror factor:
+  // input field h+ = h- (role 0) / e+_t = -e-_t (role 1), i.e. factor g;
+  // output field: factor -g
+  // compiler memory barrier: this face's LDS reads stay after the previous
+  // face's work (otherwise all four faces' reads are hoisted and live at once)
+  asm volatile("" ::: "memory");
+  const bool has = code >= 0;
+  const int sn = has ? code : so;
+  const R fin = has ? R(1) : g;
+  const R* own = lds + lbase<NF>(so, role);
+  const R* nbr = lds + lbase<NF>(sn, role);
+  const R* own_o = lds + lbase<NF>(so, 1 - role);
+  const R* nbr_o = lds + lbase<NF>(sn, 1 - role);
+  R A1[NF], A2[NF];
+  const R om = role ? R(1) - wz : wz;  // own weight of the averaged input field
+  const R c = -g * R(ref_sign<F>()) * sgn;
+#pragma unroll
+  for (int m = 0; m < NF; ++m) {
+    const R xm0 = own[loff<NF>(0, m)];
+    const R xm1 = own[loff<NF>(1, m)];
+    const R xp0 = fin * nbr[loff<NF>(0, m)];
+    const R xp1 = fin * nbr[loff<NF>(1, m)];
+    const R xw0 = fma(om, xm0 - xp0, xp0);
+    const R xw1 = fma(om, xm1 - xp1, xp1);
+    A1[m] = c * xw1;
+    A2[m] = -c * xw0;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (UPW) {
+    R g11, g12, g22;
+    face_metric<F, R>(gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
+    const R idet = R(1) / sqrt(g11 * g22 - g12 * g12);
+    const R pen = role ? Z * (R(1) - wz) : wz / Z;  // 1/(Y-+Y+) or 1/(Z-+Z+)
+    const R W11 = pen * g22 * idet, W12 = -pen * g12 * idet, W22 = pen * g11 * idet;
+    const R fout = has ? R(1) : -g;  // jump of the lane's output field
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const R ym0 = own_o[loff<NF>(0, m)];
+      const R ym1 = own_o[loff<NF>(1, m)];
+      const R j0 = fma(fout, nbr_o[loff<NF>(0, m)], -ym0);
+      const R j1 = fma(fout, nbr_o[loff<NF>(1, m)], -ym1);
+      A1[m] = fma(W11, j0, fma(W12, j1, A1[m]));
+      A2[m] = fma(W12, j0, fma(W22, j1, A2[m]));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  face_lift<P, F, R>(A1, A2, acc);
+  // materialise acc here so this face's work finishes before the next face's
+  // LDS reads are issued (bounds the live range to one face)
+#pragma unroll
+  for (int c2 = 0; c2 < 3; ++c2)
+#pragma unroll
+    for (int l = 0; l < Ops<P>::N; ++l) asm volatile("" : "+v"(acc[c2][l]));
+}
+
+// LDS (4 NF + 1 reals per element and face) already limits a CU to ~6 waves
+// of the FP32 kernel and ~3 of the FP64 one, so 2 (FP32, <= 256 VGPRs) and 1
+// (FP64, <= 512 VGPRs) waves per SIMD lose nothing and avoid spills
+template <typename R>
+constexpr int waves_per_eu() { return sizeof(R) == 4 ? 2 : 1; }
+
+template <typename R, int P, bool UPW, bool PML>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
+    DevArgs a) {
+  constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N;
+  constexpr uint32_t RS = sizeof(R);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  // XCD-major block -> tile map (dispatch places block b on XCD b % 8)
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int tl = (b & 7) * (nb >> 3) + (b >> 3);
+  if (tl >= a.ntiles) return;  // whole block leaves together
+  const int t = a.tile_begin + tl;
+  const int tile = blockDim.x >> 1;
+  const int start = a.tile_start[t], cnt = a.tile_count[t];
+  const int role = threadIdx.x >= tile;
+  const int li = threadIdx.x - role * tile;
+  // lanes past the end of a partial tile still load (arrays are padded by a
+  // full tile) so every load is unconditional; they stop at the barrier
+  const uint32_t el = (uint32_t)(start + li);
+  const Rsrc rU = make_rsrc(a.Uin, a.state_bytes);
+  const Rsrc rG = make_rsrc(a.geo, a.geo_bytes);
+  const uint32_t ebase = blk_base(el, 2 * R3, RS);       // element's state block
+  const uint32_t vin = ebase + (1 - role) * rowb<R>(R3);  // input field (other field)
+  const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
+  const uint32_t vgeo = blk_base(el, NGEO, RS);
+
+  // 1. halo: traces of out-of-tile neighbours (both fields), from global memory
+  {
+    const int h0 = a.halo_off[t], nh = a.halo_off[t + 1] - h0;
+    for (int j = threadIdx.x; j < 2 * nh; j += blockDim.x) {
+      const int hr = j >= nh;
+      const int hi = j - hr * nh;
+      const int e = a.halo_ent[h0 + hi];
+      const uint32_t kn = (uint32_t)e >> 2;
+      const int fn = e & 3;
+      // role-0 slots hold traces of H (field 1), role-1 slots traces of E
+      const uint32_t vo = blk_base(kn, 2 * R3, RS) + (1 - hr) * rowb<R>(R3);
+      const int slot = 4 * tile + hi;
+      switch (fn) {
+        case 0: halo_trace<P, 0, R>(rU, vo, lds, hr, slot); break;
+        case 1: halo_trace<P, 1, R>(rU, vo, lds, hr, slot); break;
+        case 2: halo_trace<P, 2, R>(rU, vo, lds, hr, slot); break;
+        default: halo_trace<P, 3, R>(rU, vo, lds, hr, slot); break;
+      }
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // 2. input field of this lane and its traces on the four faces -> LDS
+  R v[3][N];
+  {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int l = 0; l < N; ++l) v[c][l] = bld<R>(rU, vin, rowb<R>(c * N + l));
+    R t0[NF], t1[NF];
+#define MDG_OWN_TRACE(F)                                              \
+  {                                                                   \
+    face_trace<P, F, R>(v, t0, t1);                                   \
+    R* d = lds + lbase<NF>(F * tile + li, role);                      \
+    _Pragma("unroll") for (int m = 0; m < NF; ++m) {                  \
+      d[loff<NF>(0, m)] = t0[m];                                      \
+      d[loff<NF>(1, m)] = t1[m];                                      \
+    }                                                                 \
+  }                                                                   \
+  __builtin_amdgcn_sched_barrier(0);
+    MDG_OWN_TRACE(0)
+    MDG_OWN_TRACE(1)
+    MDG_OWN_TRACE(2)
+    MDG_OWN_TRACE(3)
+#undef MDG_OWN_TRACE
+  }
+
+  // 3. volume term (weak reference curl)
+  const R g = role ? R(-1) : R(1);
+  const R sgn = bld<R>(rG, vgeo, rowb<R>(G_SIGN));
+  R acc[3][N];
+  volume_curl<P, R>(v, g * sgn, acc);
+  // keep the volume term before the barrier (otherwise it is sunk into the
+  // face phase and the input field stays live across it)
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int l = 0; l < N; ++l) asm volatile("" : "+v"(acc[c][l]));
+
+  __syncthreads();
+  if (li >= cnt) return;
+
+  // 4. numerical flux and lift, face by face
+  const R gxx = bld<R>(rG, vgeo, rowb<R>(G_XX)), gxy = bld<R>(rG, vgeo, rowb<R>(G_XY));
+  const R gxz = bld<R>(rG, vgeo, rowb<R>(G_XZ)), gyy = bld<R>(rG, vgeo, rowb<R>(G_YY));
+  const R gyz = bld<R>(rG, vgeo, rowb<R>(G_YZ)), gzz = bld<R>(rG, vgeo, rowb<R>(G_ZZ));
+  R Z = 1, wz0 = 0.5, wz1 = 0.5, wz2 = 0.5, wz3 = 0.5;  // central: plain average
+  if constexpr (UPW) {
+    Z = bld<R>(rG, vgeo, rowb<R>(G_Z));
+    wz0 = bld<R>(rG, vgeo, rowb<R>(G_WZ0));
+    wz1 = bld<R>(rG, vgeo, rowb<R>(G_WZ1));
+    wz2 = bld<R>(rG, vgeo, rowb<R>(G_WZ2));
+    wz3 = bld<R>(rG, vgeo, rowb<R>(G_WZ3));
+  }
+  const Rsrc rN = make_rsrc(a.nbr, a.nbr_bytes);
+  const uint32_t vnb = blk_base(el, 4, 4);
+  const int c0 = bldi(rN, vnb, 0), c1 = bldi(rN, vnb, 256), c2 = bldi(rN, vnb, 512), c3 = bldi(rN, vnb, 768);
+  face_flux<P, 0, UPW, R>(lds, role, tile, li, c0, g, sgn, wz0, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  face_flux<P, 1, UPW, R>(lds, role, tile, li, c1, g, sgn, wz1, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  face_flux<P, 2, UPW, R>(lds, role, tile, li, c2, g, sgn, wz2, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  face_flux<P, 3, UPW, R>(lds, role, tile, li, c3, g, sgn, wz3, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
+  __builtin_amdgcn_sched_barrier(0);
+
+  // 5. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j
+  if (role == 0) {
+    const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
+    for (int i = 0; i < a.nsrc; ++i)
+      if ((int64_t)el == a.src_elem[i]) {
+        const R amp = R(a.src_amp[i]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int l = 0; l < N; ++l) acc[c][l] = fma(-amp, src[(i * 3 + c) * N + l], acc[c][l]);
+      }
+  }
+
+  // 6. 3x3 block-diagonal mass inverse: d_t u_l = (1/eps) G0^-1 r_l
+  const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
+  const R mf = role ? imu : ieps;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const R x = acc[0][l], y = acc[1][l], z = acc[2][l];
+    acc[0][l] = mf * fma(gxx, x, fma(gxy, y, gxz * z));
+    acc[1][l] = mf * fma(gxy, x, fma(gyy, y, gyz * z));
+    acc[2][l] = mf * fma(gxz, x, fma(gyz, y, gzz * z));
+  }
+
+  const R bc = R(a.bcoef), cdt = R(a.cdt), dt = R(a.dt);
+  const int stage = a.stage;
+  // 7. PML auxiliaries
+  if constexpr (PML) {
+    const uint32_t pk = (uint32_t)((int64_t)el - a.pml_base);
+    const Rsrc rP = make_rsrc(a.pml, a.pml_bytes);
+    const uint32_t vp = blk_base(pk, NPML, RS);
+    const Rsrc raU = make_rsrc(a.aUin, a.aux_bytes), raY = make_rsrc(a.aY, a.aux_bytes);
+    const Rsrc raO = make_rsrc(a.aUout, a.aux_bytes), raA = make_rsrc(a.aACC, a.aux_bytes);
+    const uint32_t va = blk_base(pk, 2 * R3, RS) + role * rowb<R>(R3);
+    R AT[9], AiT[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      AT[i] = bld<R>(rP, vp, rowb<R>(PM_AT + i));
+      AiT[i] = bld<R>(rP, vp, rowb<R>(PM_AIT + i));
+    }
+    const R wx = bld<R>(rP, vp, rowb<R>(PM_OM + 0));
+    const R wy = bld<R>(rP, vp, rowb<R>(PM_OM + 1));
+    const R wzz = bld<R>(rP, vp, rowb<R>(PM_OM + 2));
+    const R ex = wy + wzz - wx, ey = wzz + wx - wy, ez = wx + wy - wzz;
+    const R xx = (wx - wy) * (wx - wzz), xy = (wy - wzz) * (wy - wx), xz = (wzz - wx) * (wzz - wy);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      R u[3], q[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        u[c] = bld<R>(rU, vout, rowb<R>(c * N + l));  // own output field at the stage input
+        q[c] = bld<R>(raU, va, rowb<R>(c * N + l));
+      }
+      const R cx = AiT[0] * u[0] + AiT[1] * u[1] + AiT[2] * u[2];
+      const R cy = AiT[3] * u[0] + AiT[4] * u[1] + AiT[5] * u[2];
+      const R cz = AiT[6] * u[0] + AiT[7] * u[1] + AiT[8] * u[2];
+      const R y0 = fma(ex, cx, q[0]), y1 = fma(ey, cy, q[1]), y2 = fma(ez, cz, q[2]);
+      acc[0][l] -= AT[0] * y0 + AT[1] * y1 + AT[2] * y2;
+      acc[1][l] -= AT[3] * y0 + AT[4] * y1 + AT[5] * y2;
+      acc[2][l] -= AT[6] * y0 + AT[7] * y1 + AT[8] * y2;
+      const R k[3] = {fma(xx, cx, -wx * q[0]), fma(xy, cy, -wy * q[1]), fma(xz, cz, -wzz * q[2])};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rk_store<R>(stage, k[c], raY, raO, raA, va, rowb<R>(c * N + l), bc, cdt, dt);
+    }
+  }
+
+  // 8. RK4 epilogue of the lane's output field
+  {
+    const Rsrc rY = make_rsrc(a.Y, a.state_bytes), rO = make_rsrc(a.Uout, a.state_bytes);
+    const Rsrc rA = make_rsrc(a.ACC, a.state_bytes);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int l = 0; l < N; ++l) rk_store<R>(stage, acc[c][l], rY, rO, rA, vout, rowb<R>(c * N + l), bc, cdt, dt);
+  }
+}
+
+// ---------------------------------------------------------------- energy
+// W = 1/2 sum_T sum_l eps u_l^T M u_l + mu f_l^T M f_l, M = (G0^-1)^-1 = |det A| A^-1 A^-T
+template <typename R, int N>
+__global__ __launch_bounds__(256) void energy_kernel(const R* __restrict__ Y, const R* __restrict__ geo, int64_t K,
+                                                     double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double w = 0.0;
+  if (k < K) {
+    const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
+    const double a = gk[G_XX * 64], b = gk[G_XY * 64], c = gk[G_XZ * 64];
+    const double d = gk[G_YY * 64], e = gk[G_YZ * 64], f = gk[G_ZZ * 64];
+    const double det = a * (d * f - e * e) - b * (b * f - e * c) + c * (b * e - d * c);
+    const double id = 1.0 / det;
+    const double m00 = (d * f - e * e) * id, m01 = (c * e - b * f) * id, m02 = (b * e - c * d) * id;
+    const double m11 = (a * f - c * c) * id, m12 = (b * c - a * e) * id, m22 = (a * d - b * b) * id;
+    const double eps = 1.0 / (double)gk[G_IEPS * 64], mu = 1.0 / (double)gk[G_IMU * 64];
+    const R* yk = Y + (k >> 6) * 6 * N * 64 + (k & 63);
+    double sf[2] = {0.0, 0.0};
+    for (int fld = 0; fld < 2; ++fld)
+      for (int l = 0; l < N; ++l) {
+        const double x = yk[(fld * 3 * N + 0 * N + l) * 64];
+        const double y = yk[(fld * 3 * N + 1 * N + l) * 64];
+        const double z = yk[(fld * 3 * N + 2 * N + l) * 64];
+        sf[fld] += m00 * x * x + m11 * y * y + m22 * z * z + 2.0 * (m01 * x * y + m02 * x * z + m12 * y * z);
+      }
+    w = 0.5 * (eps * sf[0] + mu * sf[1]);
+  }
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_down(w, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void energy_final(const double* __restrict__ part, int64_t n,
+                                                    double* __restrict__ out) {
+  __shared__ double red[4];
+  double w = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) w += part[i];
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_down(w, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------- launch
+static void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename R, int P, bool UPW, bool PML>
+static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
+  const int grid = (a.ntiles + 7) / 8 * 8;
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML>), dim3(grid), dim3(2 * tile), lds, st, a);
+  hip_check(hipGetLastError(), "stage_kernel launch");
+}
+
+template <typename R, int P>
+static void launch_p(const DevArgs& a, bool upw, bool pml, int tile, size_t lds, hipStream_t st) {
+  if (upw) {
+    if (pml) launch_one<R, P, true, true>(a, tile, lds, st);
+    else launch_one<R, P, true, false>(a, tile, lds, st);
+  } else {
+    if (pml) launch_one<R, P, false, true>(a, tile, lds, st);
+    else launch_one<R, P, false, false>(a, tile, lds, st);
+  }
+}
+
+template <typename R>
+static void launch_r(int P, const DevArgs& a, bool upw, bool pml, int tile, size_t lds, hipStream_t st) {
+  switch (P) {
+    case 1: launch_p<R, 1>(a, upw, pml, tile, lds, st); break;
+    case 2: launch_p<R, 2>(a, upw, pml, tile, lds, st); break;
+    case 3: launch_p<R, 3>(a, upw, pml, tile, lds, st); break;
+    case 4: launch_p<R, 4>(a, upw, pml, tile, lds, st); break;
+    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
+  }
+}
+
+void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
+  char* base = static_cast<char*>(s.ws);
+  DevArgs a{};
+  a.Y = sp.Y;
+  a.Yw = sp.Y;
+  a.Uin = sp.Uin;
+  a.Uout = sp.Uout;
+  a.ACC = sp.ACC;
+  a.aY = sp.aY;
+  a.aYw = sp.aY;
+  a.aUin = sp.aUin;
+  a.aUout = sp.aUout;
+  a.aACC = sp.aACC;
+  a.geo = base + s.L.geo;
+  a.nbr = reinterpret_cast<const int32_t*>(base + s.L.nbr);
+  a.tile_start = reinterpret_cast<const int32_t*>(base + s.L.tile_start);
+  a.tile_count = reinterpret_cast<const int32_t*>(base + s.L.tile_count);
+  a.halo_off = reinterpret_cast<const int32_t*>(base + s.L.halo_off);
+  a.halo_ent = reinterpret_cast<const int32_t*>(base + s.L.halo_ent);
+  a.pml = base + s.L.pml;
+  a.src = base + s.L.src;
+  const size_t rs = s.real_size();
+  a.state_bytes = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
+  a.aux_bytes = (uint32_t)(size_t(6) * s.N * s.Kppad * rs);
+  a.geo_bytes = (uint32_t)(size_t(NGEO) * s.Kpad * rs);
+  a.nbr_bytes = (uint32_t)(size_t(4) * s.Kpad * 4);
+  a.pml_bytes = (uint32_t)(size_t(NPML) * s.Kppad * rs);
+  a.pml_base = s.K0;
+  a.hmax = s.hmax;
+  a.stage = sp.stage;
+  a.nsrc = sp.nsrc;
+  for (int i = 0; i < MAX_DIPOLES; ++i) {
+    a.src_elem[i] = sp.src_elem[i];
+    a.src_amp[i] = sp.src_amp[i];
+  }
+  a.bcoef = sp.bcoef;
+  a.cdt = sp.cdt;
+  a.dt = sp.dt;
+  const bool fp32 = s.opt.precision == MDG_FP32;
+  const bool upw = s.opt.flux == MDG_UPWIND;
+  const size_t lds = size_t(4 * s.NF + 1) * (4 * s.tile + s.hmax) * rs;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // non-PML tiles, then PML tiles
+  for (int part = 0; part < 2; ++part) {
+    a.tile_begin = part == 0 ? 0 : (int32_t)s.ntiles0;
+    a.ntiles = part == 0 ? (int32_t)s.ntiles0 : (int32_t)(s.ntiles - s.ntiles0);
+    if (a.ntiles == 0) continue;
+    if (fp32) launch_r<float>(s.P, a, upw, part == 1, s.tile, lds, st);
+    else launch_r<double>(s.P, a, upw, part == 1, s.tile, lds, st);
+  }
+}
+
+template <typename R>
+static void launch_energy_r(const Solver& s, const void* Y, hipStream_t st) {
+  char* base = static_cast<char*>(s.ws);
+  const int64_t nblk = (s.K + 255) / 256;
+  double* part = reinterpret_cast<double*>(base + s.L.epart);
+  double* out = reinterpret_cast<double*>(base + s.L.eout);
+  const R* geo = reinterpret_cast<const R*>(base + s.L.geo);
+  const R* y = static_cast<const R*>(Y);
+  switch (s.P) {
+    case 1: hipLaunchKernelGGL((energy_kernel<R, 4>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
+    case 2: hipLaunchKernelGGL((energy_kernel<R, 10>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
+    case 3: hipLaunchKernelGGL((energy_kernel<R, 20>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
+    case 4: hipLaunchKernelGGL((energy_kernel<R, 35>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
+    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
+  }
+  hip_check(hipGetLastError(), "energy_kernel launch");
+  hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, part, nblk, out);
+  hip_check(hipGetLastError(), "energy_final launch");
+}
+
+void launch_energy(const Solver& s, const void* Y, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s.opt.precision == MDG_FP32) launch_energy_r<float>(s, Y, st);
+  else launch_energy_r<double>(s, Y, st);
+}
+
+}  // namespace mdg

@@ -1,0 +1,64 @@
+"""Shared helpers of the GPU parity tests: build a library solver and an oracle
+on the same seeded inputs and compare them in the oracle's Cartesian frame."""
+import sys
+
+import numpy as np
+
+import workloads as W
+from oracle import OracleDG
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def unit_jittered(n, seed, lo=0.0, hi=1.0, mu_var=True):
+    verts, tets = W.kuhn_cube_mesh(n, lo, hi)
+    rng = np.random.default_rng(seed)
+    verts = W.jitter_interior(verts, lo, hi, (hi - lo) / n, 0.1, rng)
+    eps = rng.uniform(1.0, 4.0, len(tets))
+    mu = rng.uniform(1.0, 2.0, len(tets)) if mu_var else np.ones(len(tets))
+    return verts, tets, eps, mu
+
+
+def dipole_args(dipoles):
+    pos = np.array([d[0] for d in dipoles], dtype=np.float64)
+    dr = np.array([d[1] for d in dipoles], dtype=np.float64)
+    wave = np.array([[d[2][0], d[2][1], 5.0 / (2 * np.pi * d[2][1])] for d in dipoles])
+    return pos, dr, wave
+
+
+def oracle_dipoles(dipoles):
+    return [(d[0], d[1], (lambda t, f0=d[2][0], bw=d[2][1]: W.dipole_waveform(t, f0, bw))) for d in dipoles]
+
+
+def make_pair(verts, tets, p, flux, precision="fp64", eps=None, mu=None, omega=None, dipoles=(), dt=1e-3):
+    from paper_2002_08733_amd import Solver
+    s = Solver(p, precision, flux, dt=dt)
+    s.set_mesh(verts, tets)
+    s.set_material(eps, mu)
+    if omega is not None:
+        s.set_pml(omega)
+    if dipoles:
+        s.set_dipoles(*dipole_args(dipoles))
+    s.bind_torch_workspace()
+    O = OracleDG(verts, tets, p, eps=eps, mu=mu, flux=flux, omega=omega,
+                 dipoles=oracle_dipoles(dipoles))
+    return s, O
+
+
+def rel_energy_err(O, aE, aH, bE, bH, aP=None, aQ=None, bP=None, bQ=None):
+    """sqrt(sum J (eps |dE|^2 + mu |dH|^2 [+ |dP|^2/eps + |dQ|^2/mu])) / same of b
+    (Cartesian coefficients)."""
+    J, e, m = O.J[:, None, None], O.eps[:, None, None], O.mu[:, None, None]
+
+    def nrm2(E, H, P, Q):
+        v = np.sum(J * (e * E * E + m * H * H))
+        if P is not None:
+            v += np.sum(J * (P * P / e + Q * Q / m))
+        return v
+
+    dP = None if aP is None else aP - bP
+    dQ = None if aQ is None else aQ - bQ
+    return np.sqrt(nrm2(aE - bE, aH - bH, dP, dQ) / nrm2(bE, bH, bP, bQ))

@@ -1,0 +1,180 @@
+"""CPU tests of libmdg's host side: the C ABI loads and exports every symbol
+that include/mdg.h declares, mesh topology and error paths, projection points,
+and the build-time reference operators pinned against brute-force assembly
+with the oracle's basis. No device call is made here."""
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy.special import eval_jacobi
+
+import workloads as W
+from oracle.basis import Dubiner, tet_quadrature, tri_quadrature
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdg.h")
+GEN_TXT = os.path.join(ROOT, "paper_2002_08733_amd", "csrc", "refops_gen.txt")
+
+
+def _ensure_built():
+    from paper_2002_08733_amd import mdg
+    if not os.path.exists(mdg.LIB_PATH) or not os.path.exists(GEN_TXT):
+        from paper_2002_08733_amd import build
+        build.build()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    _ensure_built()
+    from paper_2002_08733_amd import mdg
+    return mdg
+
+
+def test_exports_every_declared_symbol(lib):
+    names = set(re.findall(r"\b(mdg_[a-z_]+)\s*\(", open(HEADER).read()))
+    assert len(names) >= 17
+    L = lib.load_library()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(lib.SIGNATURES) == names
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_face_counts_on_kuhn_mesh(lib, n):
+    v, t = W.kuhn_cube_mesh(n, 0.0, 1.0)
+    s = lib.Solver(2)
+    s.set_mesh(v, t)
+    q = s.query()
+    assert q["n_elements"] == 6 * n ** 3
+    assert 4 * q["n_elements"] == 2 * q["n_faces_interior"] + q["n_faces_boundary"]
+    assert q["n_faces_boundary"] == 12 * n * n
+
+
+def test_vertex_order_inside_tets_is_irrelevant(lib):
+    v, t = W.kuhn_cube_mesh(3, 0.0, 1.0)
+    rng = np.random.default_rng(0)
+    t2 = np.array([row[rng.permutation(4)] for row in t])
+    a, b = lib.Solver(2), lib.Solver(2)
+    a.set_mesh(v, t)
+    b.set_mesh(v, t2)
+    qa, qb = a.query(), b.query()
+    for k in ("n_faces_interior", "n_faces_boundary", "n_halo", "n_tiles"):
+        assert qa[k] == qb[k]
+
+
+def test_error_paths(lib):
+    v, t = W.kuhn_cube_mesh(1, 0.0, 1.0)
+    s = lib.Solver(2)
+    with pytest.raises(lib.MdgError) as e:
+        s.set_material(np.ones(6), np.ones(6))  # before a mesh
+    assert e.value.status == lib.MDG_E_STATE
+    bad = t.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(lib.MdgError) as e:
+        s.set_mesh(v, bad)
+    assert e.value.status == lib.MDG_E_MESH
+    flat = v.copy()
+    flat[:, 2] = 0.0  # every tet collapses
+    with pytest.raises(lib.MdgError) as e:
+        s.set_mesh(flat, t)
+    assert e.value.status == lib.MDG_E_MESH
+    nan = v.copy()
+    nan[3, 0] = np.nan
+    with pytest.raises(lib.MdgError) as e:
+        s.set_mesh(nan, t)
+    assert e.value.status == lib.MDG_E_MESH
+    oob = t.copy()
+    oob[2, 3] = 99
+    with pytest.raises(lib.MdgError) as e:
+        s.set_mesh(v, oob)
+    assert e.value.status == lib.MDG_E_ARG
+    # three tets on one face: non-manifold
+    vv = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1.0]])
+    tt = np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]])
+    with pytest.raises(lib.MdgError) as e:
+        s.set_mesh(vv, tt)
+    assert e.value.status == lib.MDG_E_MESH
+    s.set_mesh(v, t)
+    with pytest.raises(lib.MdgError) as e:
+        s.set_material(-np.ones(6), None)
+    assert e.value.status == lib.MDG_E_ARG
+    with pytest.raises(lib.MdgError) as e:
+        s.step(1)
+    assert e.value.status == lib.MDG_E_STATE
+    with pytest.raises(lib.MdgError) as e:
+        s.set_dipoles(np.array([[5.0, 5.0, 5.0]]), np.array([[0, 0, 1.0]]), np.array([[2.0, 1.0, 0.4]]))
+    assert e.value.status == lib.MDG_E_ARG
+    with pytest.raises(lib.MdgError) as e:
+        lib.Solver(9)
+    assert e.value.status == lib.MDG_E_UNSUPPORTED
+
+
+def test_projection_points_inside_elements(lib):
+    v, t = W.kuhn_cube_mesh(2, -1.0, 1.0)
+    rng = np.random.default_rng(1)
+    v = W.jitter_interior(v, -1.0, 1.0, 1.0, 0.1, rng)
+    s = lib.Solver(3)
+    s.set_mesh(v, t)
+    x = s.projection_points(4)
+    assert x.shape == (len(t), 64, 3)
+    X = v[np.sort(t, axis=1)]
+    A = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+    r = np.einsum("kij,kqj->kqi", np.linalg.inv(A), x - X[:, None, 0])
+    assert r.min() > 0 and (1 - r.sum(axis=2)).min() > 0
+
+
+def test_cfl_step_matches_rule(lib):
+    v, t = W.kuhn_cube_mesh(4, 0.0, 1.0)
+    s = lib.Solver(2, cfl=0.3)
+    s.set_mesh(v, t)
+    ones = np.ones(len(t))
+    assert abs(s.query()["dt"] - W.cfl_dt(v, t, ones, ones, 2, 0.3)) < 1e-15
+
+
+def _read_gen():
+    D, T = {}, {}
+    for line in open(GEN_TXT):
+        k, p, a, b, c, val = line.split()
+        p, a, b, c = int(p), int(a), int(b), int(c)
+        (D if k == "D" else T).setdefault(p, {})[(a, b, c)] = float(val)
+    return D, T
+
+
+def _psi(i, j, s1, s2):
+    # orthonormal face basis of the library, written out independently
+    b = np.where(np.abs(1 - s1) > 1e-300, 2 * s2 / np.where(np.abs(1 - s1) > 1e-300, 1 - s1, 1) - 1, -1)
+    return (np.sqrt(2 * (2 * i + 1) * (i + j + 1)) * eval_jacobi(i, 0, 0, b) * (1 - s1) ** i
+            * eval_jacobi(j, 2 * i + 1, 0, 2 * s1 - 1))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_generated_reference_operators(lib, p):
+    """D_a[l][m] = (d_a phi_l, phi_m) and T_f[m][l] = int psi_m phi_l(F_f(s)) ds
+    of the generated header equal brute-force quadrature with the oracle's
+    basis; structural zeros are exact zeros."""
+    D, T = _read_gen()
+    B = Dubiner(p)
+    N = B.N
+    q, w = tet_quadrature(p + 2)
+    Dref = np.einsum("q,qal,qm->alm", w, B.grad(q), B.eval(q))
+    Dg = np.zeros((3, N, N))
+    for (a, l, m), val in D[p].items():
+        Dg[a, l, m] = val
+    np.testing.assert_allclose(Dg, Dref, atol=1e-12 * max(1, np.abs(Dref).max()))
+    assert np.all((Dg == 0) == (np.abs(Dref) < 1e-10))
+    fm = [(i, d - i) for d in range(p + 1) for i in range(d + 1)]
+    sq, sw = tri_quadrature(p + 2)
+    verts = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    NF = len(fm)
+    Tg = np.zeros((4, NF, N))
+    for (f, m, l), val in T[p].items():
+        Tg[f, m, l] = val
+    for f in range(4):
+        a, b, c = verts[[v for v in range(4) if v != f]]
+        pts = a + sq[:, :1] * (b - a) + sq[:, 1:] * (c - a)
+        ph = B.eval(pts)
+        ps = np.array([_psi(i, j, sq[:, 0], sq[:, 1]) for (i, j) in fm])
+        Tref = np.einsum("q,mq,ql->ml", sw, ps, ph)
+        np.testing.assert_allclose(Tg[f], Tref, atol=1e-12 * max(1, np.abs(Tref).max()))
+        assert np.all((Tg[f] == 0) == (np.abs(Tref) < 1e-10))
