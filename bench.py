@@ -125,7 +125,9 @@ def main():
     ap.add_argument("--n", type=int, default=32, help="cubes per axis (32 = headline workload)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -136,6 +138,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written, x3")
+        del a, b
+        torch.cuda.empty_cache()
 
     w = W.jittered(args.n, 3, seed=2, flux="upwind")
     dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)

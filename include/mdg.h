@@ -130,7 +130,10 @@ mdg_status mdg_workspace_size(mdg_solver* s, size_t* bytes);
  * device memory on the current HIP device, 256-byte aligned, and outlive the
  * handle (or the next bind). dev_ptr == NULL makes the library allocate it.
  * Uploads the static data on `stream` (a hipStream_t, NULL = default stream)
- * and synchronises that stream. Zeroes the state. */
+ * and synchronises that stream. Zeroes the state. MDG_E_UNSUPPORTED if the
+ * stage kernel's LDS face-trace exchange (tile size x face modes) exceeds the
+ * device's LDS per workgroup (160 KiB on gfx950; only p = 4 in FP64 needs
+ * more than 64 KiB). */
 mdg_status mdg_bind_workspace(mdg_solver* s, void* dev_ptr, size_t bytes, void* stream);
 
 /* Set the state from host FP64 arrays E[nt][3][N], H[nt][3][N] (covariant

@@ -192,6 +192,15 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
   return guarded(h, [&](Solver& s) {
     ensure_final(s);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    {
+      int dev_id = 0, lds_max = 0;
+      hip_check(hipGetDevice(&dev_id), "hipGetDevice");
+      hip_check(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id),
+                "hipDeviceGetAttribute");
+      if (stage_lds_bytes(s) > size_t(lds_max))
+        throw Error(MDG_E_UNSUPPORTED, "face-trace exchange needs " + std::to_string(stage_lds_bytes(s)) +
+                                           " B of LDS, the device allows " + std::to_string(lds_max));
+    }
     if (s.ws_owned && s.ws) {
       hip_check(hipFree(s.ws), "hipFree");
       s.ws = nullptr;
@@ -217,6 +226,7 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
     hip_check(hipMemcpyAsync(dev(s, s.L.tile_start), s.tile_start.data(), s.tile_start.size() * 4, hipMemcpyHostToDevice, st), "tiles");
     hip_check(hipMemcpyAsync(dev(s, s.L.tile_count), s.tile_count.data(), s.tile_count.size() * 4, hipMemcpyHostToDevice, st), "tiles");
     hip_check(hipMemcpyAsync(dev(s, s.L.halo_off), s.halo_off.data(), s.halo_off.size() * 4, hipMemcpyHostToDevice, st), "halo");
+    hip_check(hipMemcpyAsync(dev(s, s.L.halo_grp), s.halo_grp.data(), s.halo_grp.size() * 4, hipMemcpyHostToDevice, st), "halo");
     if (!s.halo_ent.empty())
       hip_check(hipMemcpyAsync(dev(s, s.L.halo_ent), s.halo_ent.data(), s.halo_ent.size() * 4, hipMemcpyHostToDevice, st), "halo");
     hip_check(hipStreamSynchronize(st), "sync");

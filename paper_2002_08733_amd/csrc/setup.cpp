@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -198,16 +199,21 @@ double dipole_amplitude(const Dipole& d, double t) {
   return std::sin(2.0 * pi * d.wave[0] * tau) * std::exp(-tau * tau / (2.0 * sg * sg));
 }
 
+size_t stage_lds_bytes(const Solver& s) {
+  return (4ull * s.NF + 1) * (4ull * s.tile + s.hmax) * s.real_size();
+}
+
 int tile_size_for(int P, bool fp32) {
-  // elements per workgroup (two lanes each); the trace exchange in LDS needs
-  // 4 NF (4 TILE + halo) reals, kept under 64 KiB
+  // elements per workgroup (eight lanes each: 2 fields x 4 parts, so 2*tile
+  // must be a multiple of the 64-lane wave); the trace exchange in LDS needs
+  // (4 NF + 1) (4 tile + halo) reals, kept under 64 KiB
   const int NF = nmodes2(P);
   const int rs = fp32 ? 4 : 8;
-  for (int t : {128, 64, 32, 16}) {
+  for (int t : {64, 32}) {
     const double est = (4.0 * NF + 1) * (4.0 * t + 1.6 * t) * rs;
     if (est <= 60000.0) return t;
   }
-  return 16;
+  return 32;
 }
 
 static uint64_t spread21(uint64_t v) {
@@ -265,7 +271,12 @@ void finalize(Solver& s) {
 
   const bool fp32 = s.opt.precision == MDG_FP32;
   const size_t rs = s.real_size();
-  for (int tile = tile_size_for(s.P, fp32);; tile /= 2) {
+  int tile0 = tile_size_for(s.P, fp32);
+  if (const char* e = std::getenv("MDG_TILE")) {  // tuning override: 32 or 64
+    const int v = std::atoi(e);
+    if (v == 32 || v == 64) tile0 = v;
+  }
+  for (int tile = tile0;; tile /= 2) {
     s.tile = tile;
     // padded by a full tile: lanes past the end of a partial tile load freely
     s.Kpad = (nt + tile + 63) / 64 * 64;
@@ -284,6 +295,7 @@ void finalize(Solver& s) {
     s.nbr_code.assign(4 * s.Kpad, -1);
     auto NB = [&](int f, int64_t k) -> int32_t& { return s.nbr_code[blk_index(k, f, 4)]; };
     s.halo_off.assign(s.ntiles + 1, 0);
+    s.halo_grp.assign(4 * s.ntiles, 0);
     s.halo_ent.clear();
     s.hmax = 0;
     struct HE { int32_t fn; int64_t kn; int64_t k; int f; };
@@ -312,11 +324,22 @@ void finalize(Solver& s) {
         NB(ents[h].f, ents[h].k) = (int32_t)(4 * tile + h);
         s.halo_ent.push_back((int32_t)(ents[h].kn * 4 + ents[h].fn));
       }
+      // start of each neighbour-face group (entries are sorted by face)
+      for (int f = 0; f < 4; ++f) {
+        int32_t st = 0;
+        while (st < (int32_t)ents.size() && ents[st].fn < f) ++st;
+        s.halo_grp[4 * t + f] = st;
+      }
       s.halo_off[t + 1] = (int32_t)s.halo_ent.size();
       s.hmax = std::max<int>(s.hmax, (int)ents.size());
     }
-    const size_t lds = (4ull * s.NF + 1) * (4ull * tile + s.hmax) * rs;
-    if (lds <= 64 * 1024 || tile <= 16) break;
+    const size_t lds = stage_lds_bytes(s);
+    if (lds <= 64 * 1024) break;
+    if (tile <= 32) {
+      // up to 160 KiB per workgroup on gfx950 (checked against the device at bind time)
+      if (lds <= LDS_MAX_BYTES) break;
+      throw Error(MDG_E_UNSUPPORTED, "face-trace exchange does not fit in the LDS of one workgroup");
+    }
   }
   s.nhalo = (int64_t)s.halo_ent.size();
   if (s.nhalo > 0 && s.K >= (int64_t(1) << 29)) throw Error(MDG_E_ARG, "mesh too large");
@@ -395,6 +418,7 @@ void finalize(Solver& s) {
   L.tile_count = off; off = align256(off + size_t(s.ntiles) * 4);
   L.halo_off = off; off = align256(off + size_t(s.ntiles + 1) * 4);
   L.halo_ent = off; off = align256(off + std::max<size_t>(s.nhalo, 1) * 4);
+  L.halo_grp = off; off = align256(off + size_t(4) * s.ntiles * 4);
   L.pml = off; off = align256(off + (s.Kp > 0 ? size_t(NPML) * s.Kppad * rs : 0));
   L.src = off; off = align256(off + size_t(MAX_DIPOLES) * 3 * s.N * rs);
   const size_t nblk = (s.K + 255) / 256;

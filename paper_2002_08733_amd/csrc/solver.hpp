@@ -54,7 +54,7 @@ inline size_t blk_index(int64_t e, int row, int rows_per_block) {
 struct DevLayout {
   size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
   size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
-  size_t geo, nbr, tile_start, tile_count, halo_off, halo_ent, pml, src;
+  size_t geo, nbr, tile_start, tile_count, halo_off, halo_ent, halo_grp, pml, src;
   size_t epart, eout;
   size_t total;
 };
@@ -80,7 +80,7 @@ struct Solver {
   std::vector<int64_t> iperm;  // user -> internal
   int64_t ntiles = 0, ntiles0 = 0, nhalo = 0;
   int hmax = 0;
-  std::vector<int32_t> tile_start, tile_count, halo_off, halo_ent, nbr_code;
+  std::vector<int32_t> tile_start, tile_count, halo_off, halo_ent, halo_grp, nbr_code;
   std::vector<double> geo;     // blocked [Kpad/64][NGEO][64]
   std::vector<double> pmlrec;  // blocked [Kppad/64][NPML][64]
   // ---- device
@@ -101,6 +101,9 @@ void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const
 void finalize(Solver& s);  // ordering, tiles, halo, geometry records, layout
 double cfl_dt(const Solver& s);
 int tile_size_for(int P, bool fp32);
+// dynamic LDS of one stage-kernel workgroup: the face-trace exchange
+size_t stage_lds_bytes(const Solver& s);
+constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
 double dipole_amplitude(const Dipole& d, double t);
 void projection_points(const Solver& s, int q, double* xyz);
 void project_fields(const Solver& s, int q, const double* vals, std::vector<double>& coef);

@@ -69,6 +69,7 @@ struct DevArgs {
   const int32_t* tile_count;
   const int32_t* halo_off;
   const int32_t* halo_ent;
+  const int32_t* halo_grp;  // per tile: start of the face-0..3 groups of its halo entries
   const void* pml;
   const void* src;
   uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes;
@@ -215,13 +216,22 @@ __device__ __forceinline__ void face_trace(const R (&v)[3][Ops<P>::N], R (&t0)[O
   }
 }
 
-// acc[j][l] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m])
-template <int P, int F, typename R>
-__device__ __forceinline__ void face_lift(const R (&A1)[Ops<P>::NF], const R (&A2)[Ops<P>::NF],
-                                          R (&acc)[3][Ops<P>::N]) {
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
+// ---- work split: every (element, role) is served by four lanes, one per
+// "part" Q (wave-uniform). Part Q traces face Q and owns the modes
+// l = Q*NQ + i (i < NQ, l < N) of the output: volume rows, lift rows, mass
+// inverse, PML and epilogue.
+template <int P>
+constexpr int nq() { return (Ops<P>::N + 3) / 4; }
+
+// acc[j][i] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m]),  l = Q*NQ + i
+template <int P, int F, int Q, typename R>
+__device__ __forceinline__ void face_lift_q(const R (&A1)[Ops<P>::NF], const R (&A2)[Ops<P>::NF],
+                                            R (&acc)[3][nq<P>()]) {
+  constexpr int N = Ops<P>::N, NF = Ops<P>::NF, NQ = nq<P>();
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
+  for (int i = 0; i < NQ; ++i) {
+    const int l = Q * NQ + i;
+    if (l >= N) continue;
     R L1 = 0, L2 = 0;
     bool first = true;
 #pragma unroll
@@ -233,38 +243,42 @@ __device__ __forceinline__ void face_lift(const R (&A1)[Ops<P>::NF], const R (&A
         first = false;
       }
     }
-    if (!first) add_lift<F, R>(acc[0][l], acc[1][l], acc[2][l], L1, L2);
+    if (!first) add_lift<F, R>(acc[0][i], acc[1][i], acc[2][i], L1, L2);
   }
 }
 
-// acc = gs * W(v):  W[x] = D_z v_y - D_y v_z, W[y] = D_x v_z - D_z v_x, W[z] = D_y v_x - D_x v_y
-template <int P, typename R>
-__device__ __forceinline__ void volume_curl(const R (&v)[3][Ops<P>::N], R gs, R (&acc)[3][Ops<P>::N]) {
-  constexpr int N = Ops<P>::N;
+// acc = gs * W(v) on the modes of part Q:
+//   W[x] = D_z v_y - D_y v_z, W[y] = D_x v_z - D_z v_x, W[z] = D_y v_x - D_x v_y
+template <int P, int Q, typename R>
+__device__ __forceinline__ void volume_q(const R (&v)[3][Ops<P>::N], R gs, R (&acc)[3][nq<P>()]) {
+  constexpr int N = Ops<P>::N, NQ = nq<P>();
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
+  for (int i = 0; i < NQ; ++i) {
+    const int l = Q * NQ + i;
     R ax = 0, ay = 0, az = 0;
+    if (l < N) {
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      if (Ops<P>::D[0][l][m] != 0.0) {
-        const R cx = Cst<R, P>::d(0, l, m);
-        ay = fma(cx, v[2][m], ay);
-        az = fma(-cx, v[1][m], az);
-      }
-      if (Ops<P>::D[1][l][m] != 0.0) {
-        const R cy = Cst<R, P>::d(1, l, m);
-        ax = fma(-cy, v[2][m], ax);
-        az = fma(cy, v[0][m], az);
-      }
-      if (Ops<P>::D[2][l][m] != 0.0) {
-        const R cz = Cst<R, P>::d(2, l, m);
-        ax = fma(cz, v[1][m], ax);
-        ay = fma(-cz, v[0][m], ay);
+      for (int m = 0; m < N; ++m) {
+        if (Ops<P>::D[0][l][m] != 0.0) {
+          const R cx = Cst<R, P>::d(0, l, m);
+          ay = fma(cx, v[2][m], ay);
+          az = fma(-cx, v[1][m], az);
+        }
+        if (Ops<P>::D[1][l][m] != 0.0) {
+          const R cy = Cst<R, P>::d(1, l, m);
+          ax = fma(-cy, v[2][m], ax);
+          az = fma(cy, v[0][m], az);
+        }
+        if (Ops<P>::D[2][l][m] != 0.0) {
+          const R cz = Cst<R, P>::d(2, l, m);
+          ax = fma(cz, v[1][m], ax);
+          ay = fma(-cz, v[0][m], ay);
+        }
       }
     }
-    acc[0][l] = gs * ax;
-    acc[1][l] = gs * ay;
-    acc[2][l] = gs * az;
+    acc[0][i] = gs * ax;
+    acc[1][i] = gs * ay;
+    acc[2][i] = gs * az;
   }
 }
 
@@ -300,49 +314,72 @@ __device__ __forceinline__ void halo_trace(Rsrc st, uint32_t vo, R* lds, int rol
   }
 }
 
-// RK4 update of one value k = L(U)_i of the stage (vo/so: its byte offset)
+// RK4 stage epilogue, one code path for every stage. The descriptors select
+// the stage: a load through a zero-length descriptor returns 0 without memory
+// traffic, a store through one is dropped.
+//   stage 0:    ACC = b k,         Uout = y + c dt k        (a = 0)
+//   stage 1,2:  ACC = a + b k,     Uout = y + c dt k
+//   stage 3:    Y   = y + dt (a + b k)                      (ACC store dropped)
+//   operator:   Uout = k                                    (y = a = 0, c dt = 1)
+struct Epi {
+  Rsrc y_rd, a_rd, a_wr, out_wr;
+  bool final_stage;
+  double c_out;  // c_{i+1} dt, dt (final) or 1 (operator)
+};
+__device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* ACC, const void* Uout,
+                                        uint32_t bytes, double bcoef, double cdt, double dt) {
+  Epi e;
+  const bool op = stage < 0;
+  e.final_stage = stage == 3;
+  e.y_rd = make_rsrc(Y, op ? 0u : bytes);
+  e.a_rd = make_rsrc(ACC, (stage >= 1 && stage <= 3) ? bytes : 0u);
+  e.a_wr = make_rsrc(ACC, (stage >= 0 && stage <= 2) ? bytes : 0u);
+  e.out_wr = make_rsrc(e.final_stage ? Y : Uout, bytes);
+  e.c_out = op ? 1.0 : (e.final_stage ? dt : cdt);
+  (void)bcoef;
+  return e;
+}
 template <typename R>
-__device__ __forceinline__ void rk_store(int stage, R k, Rsrc Y, Rsrc Uout, Rsrc ACC, uint32_t vo, uint32_t so,
-                                         R b, R cdt, R dt) {
-  if (stage == 0) {
-    const R y = bld<R>(Y, vo, so);
-    bst<R>(b * k, ACC, vo, so);
-    bst<R>(fma(cdt, k, y), Uout, vo, so);
-  } else if (stage == 1 || stage == 2) {
-    const R y = bld<R>(Y, vo, so), a = bld<R>(ACC, vo, so);
-    bst<R>(fma(b, k, a), ACC, vo, so);
-    bst<R>(fma(cdt, k, y), Uout, vo, so);
-  } else if (stage == 3) {
-    const R y = bld<R>(Y, vo, so), a = bld<R>(ACC, vo, so);
-    bst<R>(fma(dt, fma(b, k, a), y), Y, vo, so);  // in place: only this lane touches it
-  } else {
-    bst<R>(k, Uout, vo, so);
-  }
+__device__ __forceinline__ void rk_store(const Epi& e, R k, uint32_t vo, uint32_t so, R b, R c_out) {
+  const R y = bld<R>(e.y_rd, vo, so);
+  const R a = bld<R>(e.a_rd, vo, so);
+  const R acc = fma(b, k, a);
+  bst<R>(acc, e.a_wr, vo, so);
+  bst<R>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
 }
 
-// one face of the flux/lift phase
-template <int P, int F, bool UPW, typename R>
-__device__ __forceinline__ void face_flux(const R* lds, int role, int tile, int li, int code, R g,
-                                          R sgn, R wz, R Z, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz,
-                                          R (&acc)[3][Ops<P>::N]) {
+// metric of face F (runtime face index): g^_kl = t^_k^T G t^_l
+template <typename R>
+__device__ __forceinline__ void face_metric_rt(int F, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz, R& g11,
+                                               R& g12, R& g22) {
+  const R m11[4] = {gxx - 2 * gxy + gyy, gyy, gxx, gxx};
+  const R m22[4] = {gxx - 2 * gxz + gzz, gzz, gzz, gyy};
+  const R m12[4] = {gxx - gxy - gxz + gyz, gyz, gxz, gxy};
+  g11 = m11[F];
+  g22 = m22[F];
+  g12 = m12[F];
+}
+
+// flux coefficients of face F in the face basis: the lift of the face term
+// is sum_m T_F[m][l] (t^1 A1[m] + t^2 A2[m]). No reference matrix enters, so
+// the face index is a runtime (wave-uniform) value.
+template <int P, bool UPW, typename R>
+__device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, int tile, int li, int code, R g,
+                                               R sgn, R wz, R Z, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz,
+                                               R (&A1)[Ops<P>::NF], R (&A2)[Ops<P>::NF]) {
   constexpr int NF = Ops<P>::NF;
   const int so = F * tile + li;
   // PEC faces (code < 0) read the own trace with the mirror factor:
   // input field h+ = h- (role 0) / e+_t = -e-_t (role 1), i.e. factor g;
   // output field: factor -g
-  // compiler memory barrier: this face's LDS reads stay after the previous
-  // face's work (otherwise all four faces' reads are hoisted and live at once)
-  asm volatile("" ::: "memory");
   const bool has = code >= 0;
   const int sn = has ? code : so;
   const R fin = has ? R(1) : g;
   const R* own = lds + lbase<NF>(so, role);
   const R* nbr = lds + lbase<NF>(sn, role);
-  const R* own_o = lds + lbase<NF>(so, 1 - role);
-  const R* nbr_o = lds + lbase<NF>(sn, 1 - role);
-  R A1[NF], A2[NF];
   const R om = role ? R(1) - wz : wz;  // own weight of the averaged input field
-  const R c = -g * R(ref_sign<F>()) * sgn;
+  const R rsign = (F == 0 || F == 2) ? R(1) : R(-1);  // sigma^_f = (+,-,+,-)
+  const R c = -g * rsign * sgn;
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
     const R xm0 = own[loff<NF>(0, m)];
@@ -354,10 +391,11 @@ __device__ __forceinline__ void face_flux(const R* lds, int role, int tile, int 
     A1[m] = c * xw1;
     A2[m] = -c * xw0;
   }
-  __builtin_amdgcn_sched_barrier(0);
   if constexpr (UPW) {
+    const R* own_o = lds + lbase<NF>(so, 1 - role);
+    const R* nbr_o = lds + lbase<NF>(sn, 1 - role);
     R g11, g12, g22;
-    face_metric<F, R>(gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
+    face_metric_rt<R>(F, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
     const R idet = R(1) / sqrt(g11 * g22 - g12 * g12);
     const R pen = role ? Z * (R(1) - wz) : wz / Z;  // 1/(Y-+Y+) or 1/(Z-+Z+)
     const R W11 = pen * g22 * idet, W12 = -pen * g12 * idet, W22 = pen * g11 * idet;
@@ -371,27 +409,50 @@ __device__ __forceinline__ void face_flux(const R* lds, int role, int tile, int 
       A1[m] = fma(W11, j0, fma(W12, j1, A1[m]));
       A2[m] = fma(W12, j0, fma(W22, j1, A2[m]));
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
-  face_lift<P, F, R>(A1, A2, acc);
-  // materialise acc here so this face's work finishes before the next face's
-  // LDS reads are issued (bounds the live range to one face)
-#pragma unroll
-  for (int c2 = 0; c2 < 3; ++c2)
-#pragma unroll
-    for (int l = 0; l < Ops<P>::N; ++l) asm volatile("" : "+v"(acc[c2][l]));
 }
 
-// LDS (4 NF + 1 reals per element and face) already limits a CU to ~6 waves
-// of the FP32 kernel and ~3 of the FP64 one, so 2 (FP32, <= 256 VGPRs) and 1
-// (FP64, <= 512 VGPRs) waves per SIMD lose nothing and avoid spills
+// lift of all four faces onto the modes of part Q; the flux coefficients of
+// face F of this element were published in its slot F*tile + li
+template <int P, int Q, typename R>
+__device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int li, R (&acc)[3][nq<P>()]) {
+  constexpr int NF = Ops<P>::NF;
+#define MDG_LIFT_FACE(F)                                                   \
+  {                                                                        \
+    asm volatile("" ::: "memory");                                         \
+    const R* s_ = lds + lbase<NF>((F) * tile + li, role);                  \
+    R A1[NF], A2[NF];                                                      \
+    _Pragma("unroll") for (int m = 0; m < NF; ++m) {                       \
+      A1[m] = s_[loff<NF>(0, m)];                                          \
+      A2[m] = s_[loff<NF>(1, m)];                                          \
+    }                                                                      \
+    face_lift_q<P, F, Q, R>(A1, A2, acc);                                  \
+  }
+  MDG_LIFT_FACE(0)
+  MDG_LIFT_FACE(1)
+  MDG_LIFT_FACE(2)
+  MDG_LIFT_FACE(3)
+#undef MDG_LIFT_FACE
+}
+
+// Occupancy: LDS (4 NF + 1 reals per element and face) admits 2 workgroups
+// per CU; with 8 lanes per element that is 16 waves (FP32, tile 64) or 8
+// waves (FP64, tile 32) per CU, so registers are capped at 128 / 256.
 template <typename R>
-constexpr int waves_per_eu() { return sizeof(R) == 4 ? 2 : 1; }
+constexpr int waves_per_eu() { return sizeof(R) == 4 ? 4 : 2; }
+
+#define MDG_SWITCH_Q(...)                     \
+  switch (part) {                             \
+    case 0: { constexpr int Q = 0; __VA_ARGS__; } break; \
+    case 1: { constexpr int Q = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int Q = 2; __VA_ARGS__; } break; \
+    default: { constexpr int Q = 3; __VA_ARGS__; } break; \
+  }
 
 template <typename R, int P, bool UPW, bool PML>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
     DevArgs a) {
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N;
+  constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
   constexpr uint32_t RS = sizeof(R);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
@@ -400,12 +461,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const int tl = (b & 7) * (nb >> 3) + (b >> 3);
   if (tl >= a.ntiles) return;  // whole block leaves together
   const int t = a.tile_begin + tl;
-  const int tile = blockDim.x >> 1;
+  const int tile = blockDim.x >> 3;  // 8 lanes per element: 2 roles x 4 parts
+  const int tid = threadIdx.x;
+  // 2*tile is a multiple of 64, so the part is uniform within a wave
+  const int part = __builtin_amdgcn_readfirstlane(tid / (2 * tile));
+  const int rem = tid - part * 2 * tile;
+  const int role = rem >= tile;
+  const int li = rem - role * tile;
   const int start = a.tile_start[t], cnt = a.tile_count[t];
-  const int role = threadIdx.x >= tile;
-  const int li = threadIdx.x - role * tile;
   // lanes past the end of a partial tile still load (arrays are padded by a
-  // full tile) so every load is unconditional; they stop at the barrier
+  // full tile) so every load is unconditional; they stop at the last barrier
   const uint32_t el = (uint32_t)(start + li);
   const Rsrc rU = make_rsrc(a.Uin, a.state_bytes);
   const Rsrc rG = make_rsrc(a.geo, a.geo_bytes);
@@ -414,93 +479,86 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
   const uint32_t vgeo = blk_base(el, NGEO, RS);
 
-  // 1. halo: traces of out-of-tile neighbours (both fields), from global memory
+  // 1. halo: traces of out-of-tile neighbours (both fields), from global
+  // memory. Halo entries are grouped by the neighbour's local face; part Q
+  // handles the group of face Q, so a wave runs one face variant.
   {
     const int h0 = a.halo_off[t], nh = a.halo_off[t + 1] - h0;
-    for (int j = threadIdx.x; j < 2 * nh; j += blockDim.x) {
-      const int hr = j >= nh;
-      const int hi = j - hr * nh;
-      const int e = a.halo_ent[h0 + hi];
-      const uint32_t kn = (uint32_t)e >> 2;
-      const int fn = e & 3;
+    const int gs = a.halo_grp[4 * t + part];
+    const int ge = part < 3 ? a.halo_grp[4 * t + part + 1] : nh;
+    const int ng = ge - gs;
+    for (int j = rem; j < 2 * ng; j += 2 * tile) {
+      const int hr = j >= ng;
+      const int hi = gs + j - hr * ng;
+      const uint32_t kn = (uint32_t)a.halo_ent[h0 + hi] >> 2;
       // role-0 slots hold traces of H (field 1), role-1 slots traces of E
       const uint32_t vo = blk_base(kn, 2 * R3, RS) + (1 - hr) * rowb<R>(R3);
-      const int slot = 4 * tile + hi;
-      switch (fn) {
-        case 0: halo_trace<P, 0, R>(rU, vo, lds, hr, slot); break;
-        case 1: halo_trace<P, 1, R>(rU, vo, lds, hr, slot); break;
-        case 2: halo_trace<P, 2, R>(rU, vo, lds, hr, slot); break;
-        default: halo_trace<P, 3, R>(rU, vo, lds, hr, slot); break;
-      }
+      MDG_SWITCH_Q((halo_trace<P, Q, R>(rU, vo, lds, hr, 4 * tile + hi)));
     }
   }
   __builtin_amdgcn_sched_barrier(0);
 
-  // 2. input field of this lane and its traces on the four faces -> LDS
+  // 2. input field of this lane; the trace on face `part` -> LDS
   R v[3][N];
-  {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int l = 0; l < N; ++l) v[c][l] = bld<R>(rU, vin, rowb<R>(c * N + l));
-    R t0[NF], t1[NF];
-#define MDG_OWN_TRACE(F)                                              \
-  {                                                                   \
-    face_trace<P, F, R>(v, t0, t1);                                   \
-    R* d = lds + lbase<NF>(F * tile + li, role);                      \
-    _Pragma("unroll") for (int m = 0; m < NF; ++m) {                  \
-      d[loff<NF>(0, m)] = t0[m];                                      \
-      d[loff<NF>(1, m)] = t1[m];                                      \
-    }                                                                 \
-  }                                                                   \
-  __builtin_amdgcn_sched_barrier(0);
-    MDG_OWN_TRACE(0)
-    MDG_OWN_TRACE(1)
-    MDG_OWN_TRACE(2)
-    MDG_OWN_TRACE(3)
-#undef MDG_OWN_TRACE
-  }
-
-  // 3. volume term (weak reference curl)
-  const R g = role ? R(-1) : R(1);
-  const R sgn = bld<R>(rG, vgeo, rowb<R>(G_SIGN));
-  R acc[3][N];
-  volume_curl<P, R>(v, g * sgn, acc);
-  // keep the volume term before the barrier (otherwise it is sunk into the
-  // face phase and the input field stays live across it)
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int l = 0; l < N; ++l) asm volatile("" : "+v"(acc[c][l]));
+    for (int l = 0; l < N; ++l) v[c][l] = bld<R>(rU, vin, rowb<R>(c * N + l));
+  {
+    R t0[NF], t1[NF];
+    MDG_SWITCH_Q((face_trace<P, Q, R>(v, t0, t1)));
+    R* d = lds + lbase<NF>(part * tile + li, role);
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      d[loff<NF>(0, m)] = t0[m];
+      d[loff<NF>(1, m)] = t1[m];
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
 
-  __syncthreads();
-  if (li >= cnt) return;
+  // 3. volume term (weak reference curl) on this part's modes
+  const R g = role ? R(-1) : R(1);
+  const R sgn = bld<R>(rG, vgeo, rowb<R>(G_SIGN));
+  R acc[3][NQ];
+  MDG_SWITCH_Q((volume_q<P, Q, R>(v, g * sgn, acc)));
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(acc[c][i]));
 
-  // 4. numerical flux and lift, face by face
+  __syncthreads();  // traces of the tile and its halo are in LDS
+
+  // 4. flux coefficients of face `part`
   const R gxx = bld<R>(rG, vgeo, rowb<R>(G_XX)), gxy = bld<R>(rG, vgeo, rowb<R>(G_XY));
   const R gxz = bld<R>(rG, vgeo, rowb<R>(G_XZ)), gyy = bld<R>(rG, vgeo, rowb<R>(G_YY));
   const R gyz = bld<R>(rG, vgeo, rowb<R>(G_YZ)), gzz = bld<R>(rG, vgeo, rowb<R>(G_ZZ));
-  R Z = 1, wz0 = 0.5, wz1 = 0.5, wz2 = 0.5, wz3 = 0.5;  // central: plain average
+  R Z = 1, wz = 0.5;  // central: plain average
   if constexpr (UPW) {
     Z = bld<R>(rG, vgeo, rowb<R>(G_Z));
-    wz0 = bld<R>(rG, vgeo, rowb<R>(G_WZ0));
-    wz1 = bld<R>(rG, vgeo, rowb<R>(G_WZ1));
-    wz2 = bld<R>(rG, vgeo, rowb<R>(G_WZ2));
-    wz3 = bld<R>(rG, vgeo, rowb<R>(G_WZ3));
+    wz = bld<R>(rG, vgeo, rowb<R>(G_WZ0 + part));
   }
   const Rsrc rN = make_rsrc(a.nbr, a.nbr_bytes);
-  const uint32_t vnb = blk_base(el, 4, 4);
-  const int c0 = bldi(rN, vnb, 0), c1 = bldi(rN, vnb, 256), c2 = bldi(rN, vnb, 512), c3 = bldi(rN, vnb, 768);
-  face_flux<P, 0, UPW, R>(lds, role, tile, li, c0, g, sgn, wz0, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
-  __builtin_amdgcn_sched_barrier(0);
-  face_flux<P, 1, UPW, R>(lds, role, tile, li, c1, g, sgn, wz1, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
-  __builtin_amdgcn_sched_barrier(0);
-  face_flux<P, 2, UPW, R>(lds, role, tile, li, c2, g, sgn, wz2, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
-  __builtin_amdgcn_sched_barrier(0);
-  face_flux<P, 3, UPW, R>(lds, role, tile, li, c3, g, sgn, wz3, Z, gxx, gxy, gxz, gyy, gyz, gzz, acc);
-  __builtin_amdgcn_sched_barrier(0);
+  const int code = bldi(rN, blk_base(el, 4, 4), (uint32_t)part * 256u);
+  {
+    R A1[NF], A2[NF];
+    face_flux_coef<P, UPW, R>(part, lds, role, tile, li, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz, gzz, A1,
+                              A2);
+    __syncthreads();  // every flux read of this tile is done
+    // 5. publish the flux coefficients of face `part` in its own slot
+    R* d = lds + lbase<NF>(part * tile + li, role);
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      d[loff<NF>(0, m)] = A1[m];
+      d[loff<NF>(1, m)] = A2[m];
+    }
+  }
+  __syncthreads();
+  if (li >= cnt) return;
 
-  // 5. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j
+  // 6. lift of the four faces onto this part's modes
+  MDG_SWITCH_Q((lift_all_q<P, Q, R>(lds, role, tile, li, acc)));
+
+  // 7. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j
   if (role == 0) {
     const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
     for (int i = 0; i < a.nsrc; ++i)
@@ -509,30 +567,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_e
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int l = 0; l < N; ++l) acc[c][l] = fma(-amp, src[(i * 3 + c) * N + l], acc[c][l]);
+          for (int q = 0; q < NQ; ++q) {
+            const int l = part * NQ + q;
+            if (l < N) acc[c][q] = fma(-amp, src[(i * 3 + c) * N + l], acc[c][q]);
+          }
       }
   }
 
-  // 6. 3x3 block-diagonal mass inverse: d_t u_l = (1/eps) G0^-1 r_l
+  // 8. 3x3 block-diagonal mass inverse: d_t u_l = (1/eps) G0^-1 r_l
   const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
   const R mf = role ? imu : ieps;
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
-    const R x = acc[0][l], y = acc[1][l], z = acc[2][l];
-    acc[0][l] = mf * fma(gxx, x, fma(gxy, y, gxz * z));
-    acc[1][l] = mf * fma(gxy, x, fma(gyy, y, gyz * z));
-    acc[2][l] = mf * fma(gxz, x, fma(gyz, y, gzz * z));
+  for (int q = 0; q < NQ; ++q) {
+    const R x = acc[0][q], y = acc[1][q], z = acc[2][q];
+    acc[0][q] = mf * fma(gxx, x, fma(gxy, y, gxz * z));
+    acc[1][q] = mf * fma(gxy, x, fma(gyy, y, gyz * z));
+    acc[2][q] = mf * fma(gxz, x, fma(gyz, y, gzz * z));
   }
 
-  const R bc = R(a.bcoef), cdt = R(a.cdt), dt = R(a.dt);
+  const R bc = R(a.bcoef);
   const int stage = a.stage;
-  // 7. PML auxiliaries
+  // rows of this part: row(c, q) = c*N + part*NQ + q, skipped past N
+  // 9. PML auxiliaries
   if constexpr (PML) {
     const uint32_t pk = (uint32_t)((int64_t)el - a.pml_base);
     const Rsrc rP = make_rsrc(a.pml, a.pml_bytes);
     const uint32_t vp = blk_base(pk, NPML, RS);
-    const Rsrc raU = make_rsrc(a.aUin, a.aux_bytes), raY = make_rsrc(a.aY, a.aux_bytes);
-    const Rsrc raO = make_rsrc(a.aUout, a.aux_bytes), raA = make_rsrc(a.aACC, a.aux_bytes);
+    const Rsrc raU = make_rsrc(a.aUin, a.aux_bytes);
+    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.aux_bytes, a.bcoef, a.cdt, a.dt);
+    const R ca = R(ea.c_out);
     const uint32_t va = blk_base(pk, 2 * R3, RS) + role * rowb<R>(R3);
     R AT[9], AiT[9];
 #pragma unroll
@@ -546,36 +609,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const R ex = wy + wzz - wx, ey = wzz + wx - wy, ez = wx + wy - wzz;
     const R xx = (wx - wy) * (wx - wzz), xy = (wy - wzz) * (wy - wx), xz = (wzz - wx) * (wzz - wy);
 #pragma unroll
-    for (int l = 0; l < N; ++l) {
-      R u[3], q[3];
+    for (int q = 0; q < NQ; ++q) {
+      const int l = part * NQ + q;
+      if (l >= N) continue;
+      R u[3], qa[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        u[c] = bld<R>(rU, vout, rowb<R>(c * N + l));  // own output field at the stage input
-        q[c] = bld<R>(raU, va, rowb<R>(c * N + l));
+        const uint32_t so = (uint32_t)(c * N + l) * 64u * RS;
+        u[c] = bld<R>(rU, vout, so);  // own output field at the stage input
+        qa[c] = bld<R>(raU, va, so);
       }
       const R cx = AiT[0] * u[0] + AiT[1] * u[1] + AiT[2] * u[2];
       const R cy = AiT[3] * u[0] + AiT[4] * u[1] + AiT[5] * u[2];
       const R cz = AiT[6] * u[0] + AiT[7] * u[1] + AiT[8] * u[2];
-      const R y0 = fma(ex, cx, q[0]), y1 = fma(ey, cy, q[1]), y2 = fma(ez, cz, q[2]);
-      acc[0][l] -= AT[0] * y0 + AT[1] * y1 + AT[2] * y2;
-      acc[1][l] -= AT[3] * y0 + AT[4] * y1 + AT[5] * y2;
-      acc[2][l] -= AT[6] * y0 + AT[7] * y1 + AT[8] * y2;
-      const R k[3] = {fma(xx, cx, -wx * q[0]), fma(xy, cy, -wy * q[1]), fma(xz, cz, -wzz * q[2])};
+      const R y0 = fma(ex, cx, qa[0]), y1 = fma(ey, cy, qa[1]), y2 = fma(ez, cz, qa[2]);
+      acc[0][q] -= AT[0] * y0 + AT[1] * y1 + AT[2] * y2;
+      acc[1][q] -= AT[3] * y0 + AT[4] * y1 + AT[5] * y2;
+      acc[2][q] -= AT[6] * y0 + AT[7] * y1 + AT[8] * y2;
+      const R k[3] = {fma(xx, cx, -wx * qa[0]), fma(xy, cy, -wy * qa[1]), fma(xz, cz, -wzz * qa[2])};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rk_store<R>(stage, k[c], raY, raO, raA, va, rowb<R>(c * N + l), bc, cdt, dt);
+      for (int c = 0; c < 3; ++c) rk_store<R>(ea, k[c], va, (uint32_t)(c * N + l) * 64u * RS, bc, ca);
     }
   }
 
-  // 8. RK4 epilogue of the lane's output field
+  // 10. RK4 epilogue of this part's rows of the output field
   {
-    const Rsrc rY = make_rsrc(a.Y, a.state_bytes), rO = make_rsrc(a.Uout, a.state_bytes);
-    const Rsrc rA = make_rsrc(a.ACC, a.state_bytes);
+    const Epi ef = make_epi(stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
+    const R cf = R(ef.c_out);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int l = 0; l < N; ++l) rk_store<R>(stage, acc[c][l], rY, rO, rA, vout, rowb<R>(c * N + l), bc, cdt, dt);
+      for (int q = 0; q < NQ; ++q) {
+        const int l = part * NQ + q;
+        if (l < N) rk_store<R>(ef, acc[c][q], vout, (uint32_t)(c * N + l) * 64u * RS, bc, cf);
+      }
   }
 }
+#undef MDG_SWITCH_Q
 
 // ---------------------------------------------------------------- energy
 // W = 1/2 sum_T sum_l eps u_l^T M u_l + mu f_l^T M f_l, M = (G0^-1)^-1 = |det A| A^-1 A^-T
@@ -630,7 +700,12 @@ static void hip_check(hipError_t e, const char* what) {
 template <typename R, int P, bool UPW, bool PML>
 static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
   const int grid = (a.ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML>), dim3(grid), dim3(2 * tile), lds, st, a);
+  if (lds > 64 * 1024) {
+    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+              "hipFuncSetAttribute(dynamic LDS)");
+  }
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML>), dim3(grid), dim3(8 * tile), lds, st, a);
   hip_check(hipGetLastError(), "stage_kernel launch");
 }
 
@@ -675,6 +750,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.tile_count = reinterpret_cast<const int32_t*>(base + s.L.tile_count);
   a.halo_off = reinterpret_cast<const int32_t*>(base + s.L.halo_off);
   a.halo_ent = reinterpret_cast<const int32_t*>(base + s.L.halo_ent);
+  a.halo_grp = reinterpret_cast<const int32_t*>(base + s.L.halo_grp);
   a.pml = base + s.L.pml;
   a.src = base + s.L.src;
   const size_t rs = s.real_size();
@@ -696,7 +772,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.dt = sp.dt;
   const bool fp32 = s.opt.precision == MDG_FP32;
   const bool upw = s.opt.flux == MDG_UPWIND;
-  const size_t lds = size_t(4 * s.NF + 1) * (4 * s.tile + s.hmax) * rs;
+  const size_t lds = stage_lds_bytes(s);
   hipStream_t st = static_cast<hipStream_t>(stream);
   // non-PML tiles, then PML tiles
   for (int part = 0; part < 2; ++part) {

@@ -82,6 +82,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libmdg.so not found at {path}: build it with "
                           "`python -m paper_2002_08733_amd.build` (no fallback exists)")
+    # PyTorch ships its own HIP runtime with the same soname as the system one.
+    # Load and initialise it first so that libmdg binds to the runtime that owns
+    # the device memory and streams it is handed (one runtime per process).
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
