@@ -347,6 +347,13 @@ __device__ __forceinline__ void rk_store(const Epi& e, R k, uint32_t vo, uint32_
   bst<R>(acc, e.a_wr, vo, so);
   bst<R>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
 }
+// same with y and a loaded earlier
+template <typename R>
+__device__ __forceinline__ void rk_store_pre(const Epi& e, R k, R y, R a, uint32_t vo, uint32_t so, R b, R c_out) {
+  const R acc = fma(b, k, a);
+  bst<R>(acc, e.a_wr, vo, so);
+  bst<R>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
+}
 
 // metric of face F (runtime face index): g^_kl = t^_k^T G t^_l
 template <typename R>
@@ -504,6 +511,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int l = 0; l < N; ++l) v[c][l] = bld<R>(rU, vin, rowb<R>(c * N + l));
+  // RK operands of this part's output rows, loaded now so that their latency
+  // overlaps the trace, volume and flux work (absent operands read as 0)
+  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
+  R ypre[3][NQ], apre[3][NQ];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int l = part * NQ + q;
+      const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
+      ypre[c][q] = bld<R>(ef.y_rd, vout, so);
+      apre[c][q] = bld<R>(ef.a_rd, vout, so);
+    }
   {
     R t0[NF], t1[NF];
     MDG_SWITCH_Q((face_trace<P, Q, R>(v, t0, t1)));
@@ -634,14 +654,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 
   // 10. RK4 epilogue of this part's rows of the output field
   {
-    const Epi ef = make_epi(stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
     const R cf = R(ef.c_out);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int l = part * NQ + q;
-        if (l < N) rk_store<R>(ef, acc[c][q], vout, (uint32_t)(c * N + l) * 64u * RS, bc, cf);
+        if (l < N)
+          rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], vout, (uint32_t)(c * N + l) * 64u * RS, bc, cf);
       }
   }
 }
