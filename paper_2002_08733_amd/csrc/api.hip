@@ -223,8 +223,6 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
     hip_check(hipStreamSynchronize(st), "sync");
     upload(s, s.geo, s.L.geo, st);
     hip_check(hipMemcpyAsync(dev(s, s.L.nbr), s.nbr_code.data(), s.nbr_code.size() * 4, hipMemcpyHostToDevice, st), "nbr");
-    hip_check(hipMemcpyAsync(dev(s, s.L.tile_start), s.tile_start.data(), s.tile_start.size() * 4, hipMemcpyHostToDevice, st), "tiles");
-    hip_check(hipMemcpyAsync(dev(s, s.L.tile_count), s.tile_count.data(), s.tile_count.size() * 4, hipMemcpyHostToDevice, st), "tiles");
     hip_check(hipMemcpyAsync(dev(s, s.L.halo_off), s.halo_off.data(), s.halo_off.size() * 4, hipMemcpyHostToDevice, st), "halo");
     hip_check(hipMemcpyAsync(dev(s, s.L.halo_grp), s.halo_grp.data(), s.halo_grp.size() * 4, hipMemcpyHostToDevice, st), "halo");
     if (!s.halo_ent.empty())

@@ -414,8 +414,6 @@ void finalize(Solver& s) {
   L.aACC = off; off = align256(off + afield);
   L.geo = off; off = align256(off + size_t(NGEO) * s.Kpad * rs);
   L.nbr = off; off = align256(off + size_t(4) * s.Kpad * 4);
-  L.tile_start = off; off = align256(off + size_t(s.ntiles) * 4);
-  L.tile_count = off; off = align256(off + size_t(s.ntiles) * 4);
   L.halo_off = off; off = align256(off + size_t(s.ntiles + 1) * 4);
   L.halo_ent = off; off = align256(off + std::max<size_t>(s.nhalo, 1) * 4);
   L.halo_grp = off; off = align256(off + size_t(4) * s.ntiles * 4);

@@ -54,7 +54,7 @@ inline size_t blk_index(int64_t e, int row, int rows_per_block) {
 struct DevLayout {
   size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
   size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
-  size_t geo, nbr, tile_start, tile_count, halo_off, halo_ent, halo_grp, pml, src;
+  size_t geo, nbr, halo_off, halo_ent, halo_grp, pml, src;
   size_t epart, eout;
   size_t total;
 };

@@ -65,8 +65,6 @@ struct DevArgs {
   void* aYw;
   const void* geo;
   const int32_t* nbr;
-  const int32_t* tile_start;
-  const int32_t* tile_count;
   const int32_t* halo_off;
   const int32_t* halo_ent;
   const int32_t* halo_grp;  // per tile: start of the face-0..3 groups of its halo entries
@@ -75,6 +73,7 @@ struct DevArgs {
   uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes;
   int64_t pml_base;
   int32_t tile_begin, ntiles, hmax, stage, nsrc;
+  int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
   int64_t src_elem[MAX_DIPOLES];
   double src_amp[MAX_DIPOLES];
   double bcoef, cdt, dt;
@@ -85,17 +84,21 @@ typedef __amdgpu_buffer_rsrc_t Rsrc;
 __device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-template <typename R>
+// cache policy: CP_NT marks streaming data (read or written once per launch)
+// as non-temporal, so it does not push the stage input, which neighbouring
+// tiles gather for their halo faces, out of L2
+enum { CP_DEF = 0, CP_NT = 2 };
+template <typename R, int CP = CP_DEF>
 __device__ __forceinline__ R bld(Rsrc r, uint32_t vo, uint32_t so) {
-  if constexpr (sizeof(R) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
-  else return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  if constexpr (sizeof(R) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, CP));
+  else return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, CP));
 }
-template <typename R>
+template <typename R, int CP = CP_DEF>
 __device__ __forceinline__ void bst(R v, Rsrc r, uint32_t vo, uint32_t so) {
-  if constexpr (sizeof(R) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+  if constexpr (sizeof(R) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, CP);
   else {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, CP);
   }
 }
 __device__ __forceinline__ int32_t bldi(Rsrc r, uint32_t vo, uint32_t so) {
@@ -341,18 +344,18 @@ __device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* AC
 }
 template <typename R>
 __device__ __forceinline__ void rk_store(const Epi& e, R k, uint32_t vo, uint32_t so, R b, R c_out) {
-  const R y = bld<R>(e.y_rd, vo, so);
-  const R a = bld<R>(e.a_rd, vo, so);
+  const R y = bld<R, CP_NT>(e.y_rd, vo, so);
+  const R a = bld<R, CP_NT>(e.a_rd, vo, so);
   const R acc = fma(b, k, a);
-  bst<R>(acc, e.a_wr, vo, so);
-  bst<R>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
+  bst<R, CP_NT>(acc, e.a_wr, vo, so);
+  bst<R, CP_NT>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
 }
 // same with y and a loaded earlier
 template <typename R>
 __device__ __forceinline__ void rk_store_pre(const Epi& e, R k, R y, R a, uint32_t vo, uint32_t so, R b, R c_out) {
   const R acc = fma(b, k, a);
-  bst<R>(acc, e.a_wr, vo, so);
-  bst<R>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
+  bst<R, CP_NT>(acc, e.a_wr, vo, so);
+  bst<R, CP_NT>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
 }
 
 // metric of face F (runtime face index): g^_kl = t^_k^T G t^_l
@@ -475,7 +478,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const int rem = tid - part * 2 * tile;
   const int role = rem >= tile;
   const int li = rem - role * tile;
-  const int start = a.tile_start[t], cnt = a.tile_count[t];
+  const int start = a.elem_begin + tl * tile;
+  const int cnt = min(tile, a.elem_end - start);
   // lanes past the end of a partial tile still load (arrays are padded by a
   // full tile) so every load is unconditional; they stop at the last barrier
   const uint32_t el = (uint32_t)(start + li);
@@ -485,6 +489,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const uint32_t vin = ebase + (1 - role) * rowb<R>(R3);  // input field (other field)
   const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
   const uint32_t vgeo = blk_base(el, NGEO, RS);
+
+  // RK operands of this part's output rows, issued first so that their
+  // latency overlaps the halo, trace, volume and flux work (absent operands read as 0)
+  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
+  R ypre[3][NQ], apre[3][NQ];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int l = part * NQ + q;
+      const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
+      ypre[c][q] = bld<R, CP_NT>(ef.y_rd, vout, so);
+      apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
+    }
 
   // 1. halo: traces of out-of-tile neighbours (both fields), from global
   // memory. Halo entries are grouped by the neighbour's local face; part Q
@@ -511,19 +529,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int l = 0; l < N; ++l) v[c][l] = bld<R>(rU, vin, rowb<R>(c * N + l));
-  // RK operands of this part's output rows, loaded now so that their latency
-  // overlaps the trace, volume and flux work (absent operands read as 0)
-  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
-  R ypre[3][NQ], apre[3][NQ];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int l = part * NQ + q;
-      const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
-      ypre[c][q] = bld<R>(ef.y_rd, vout, so);
-      apre[c][q] = bld<R>(ef.a_rd, vout, so);
-    }
   {
     R t0[NF], t1[NF];
     MDG_SWITCH_Q((face_trace<P, Q, R>(v, t0, t1)));
@@ -766,8 +771,6 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.aACC = sp.aACC;
   a.geo = base + s.L.geo;
   a.nbr = reinterpret_cast<const int32_t*>(base + s.L.nbr);
-  a.tile_start = reinterpret_cast<const int32_t*>(base + s.L.tile_start);
-  a.tile_count = reinterpret_cast<const int32_t*>(base + s.L.tile_count);
   a.halo_off = reinterpret_cast<const int32_t*>(base + s.L.halo_off);
   a.halo_ent = reinterpret_cast<const int32_t*>(base + s.L.halo_ent);
   a.halo_grp = reinterpret_cast<const int32_t*>(base + s.L.halo_grp);
@@ -797,6 +800,8 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   // non-PML tiles, then PML tiles
   for (int part = 0; part < 2; ++part) {
     a.tile_begin = part == 0 ? 0 : (int32_t)s.ntiles0;
+    a.elem_begin = part == 0 ? 0 : (int32_t)s.K0;
+    a.elem_end = part == 0 ? (int32_t)s.K0 : (int32_t)s.K;
     a.ntiles = part == 0 ? (int32_t)s.ntiles0 : (int32_t)(s.ntiles - s.ntiles0);
     if (a.ntiles == 0) continue;
     if (fp32) launch_r<float>(s.P, a, upw, part == 1, s.tile, lds, st);
