@@ -223,10 +223,8 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
     hip_check(hipStreamSynchronize(st), "sync");
     upload(s, s.geo, s.L.geo, st);
     hip_check(hipMemcpyAsync(dev(s, s.L.nbr), s.nbr_code.data(), s.nbr_code.size() * 4, hipMemcpyHostToDevice, st), "nbr");
-    hip_check(hipMemcpyAsync(dev(s, s.L.halo_off), s.halo_off.data(), s.halo_off.size() * 4, hipMemcpyHostToDevice, st), "halo");
-    hip_check(hipMemcpyAsync(dev(s, s.L.halo_grp), s.halo_grp.data(), s.halo_grp.size() * 4, hipMemcpyHostToDevice, st), "halo");
-    if (!s.halo_ent.empty())
-      hip_check(hipMemcpyAsync(dev(s, s.L.halo_ent), s.halo_ent.data(), s.halo_ent.size() * 4, hipMemcpyHostToDevice, st), "halo");
+    hip_check(hipMemcpyAsync(dev(s, s.L.pub), s.pub_code.data(), s.pub_code.size() * 4, hipMemcpyHostToDevice, st), "pub");
+    hip_check(hipMemcpyAsync(dev(s, s.L.halo_tile), s.halo_tile.data(), s.halo_tile.size() * 4, hipMemcpyHostToDevice, st), "halo");
     hip_check(hipStreamSynchronize(st), "sync");
     if (s.Kp > 0) upload(s, s.pmlrec, s.L.pml, st);
     if (!s.dips.empty()) {
@@ -237,6 +235,7 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
     }
     s.dt = s.opt.dt > 0 ? s.opt.dt : cfl_dt(s);
     s.t = 0.0;
+    s.halo_valid = true;  // zero state, zero traces
     s.bound = true;
   });
 }
@@ -247,6 +246,7 @@ mdg_status mdg_set_state(mdg_solver* h, const double* E, const double* H, const 
     need_bound(s);
     if (!E || !H) throw Error(MDG_E_ARG, "E and H are required");
     write_state(s, E, H, P, Q, s.L.Y, s.L.aY);
+    s.halo_valid = false;
     s.t = t;
   });
 }
@@ -277,6 +277,7 @@ mdg_status mdg_project(mdg_solver* h, int32_t q, const double* Ev, const double*
     if (Ev) project_fields(s, q, Ev, ce); else ce.assign(n, 0.0);
     if (Hv) project_fields(s, q, Hv, ch); else ch.assign(n, 0.0);
     write_state(s, ce.data(), ch.data(), nullptr, nullptr, s.L.Y, s.L.aY);
+    s.halo_valid = false;
     s.t = t;
   });
 }
@@ -288,6 +289,10 @@ mdg_status mdg_step(mdg_solver* h, int64_t nsteps, void* stream) {
     static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
     const DevLayout& L = s.L;
+    if (nsteps > 0 && !s.halo_valid) {
+      launch_publish(s, dev(s, L.Y), dev(s, L.H0), stream);
+      s.halo_valid = true;
+    }
     for (int64_t n = 0; n < nsteps; ++n) {
       for (int i = 0; i < 4; ++i) {
         StageParams sp{};
@@ -309,6 +314,11 @@ mdg_status mdg_step(mdg_solver* h, int64_t nsteps, void* stream) {
         sp.aUin = dev(s, ain);
         sp.aUout = dev(s, aout);
         sp.aACC = dev(s, L.aACC);
+        // halo traces of the stage input in, of the stage output out; after
+        // the last stage H0 again holds the traces of Y
+        sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
+        sp.hout = dev(s, (i & 1) ? L.H0 : L.H1);
+        sp.publish = true;
         launch_stage(s, sp, stream);
       }
       s.t += s.dt;
@@ -335,6 +345,11 @@ mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double
     sp.aUin = dev(s, L.aUa);
     sp.aUout = dev(s, L.aUb);
     sp.aACC = dev(s, L.aACC);
+    // the input's halo traces go to H1, so H0 keeps the traces of Y
+    launch_publish(s, dev(s, L.Ua), dev(s, L.H1), nullptr);
+    sp.hin = dev(s, L.H1);
+    sp.hout = nullptr;
+    sp.publish = false;
     launch_stage(s, sp, nullptr);
     read_state(s, dE, dH, dP, dQ, L.Ub, L.aUb);
   });

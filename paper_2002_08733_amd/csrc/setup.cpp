@@ -200,7 +200,9 @@ double dipole_amplitude(const Dipole& d, double t) {
 }
 
 size_t stage_lds_bytes(const Solver& s) {
-  return (4ull * s.NF + 1) * (4ull * s.tile + s.hmax) * s.real_size();
+  // trace slots of the tile's faces and of its halo, plus 16 bytes of slack
+  // for the 16-byte granules of the halo copy
+  return (4ull * s.NF + 1) * (4ull * s.tile + s.hmax) * s.real_size() + 16;
 }
 
 int tile_size_for(int P, bool fp32) {
@@ -291,13 +293,22 @@ void finalize(Solver& s) {
       if (part == 0) s.ntiles0 = (int64_t)s.tile_start.size();
     }
     s.ntiles = (int64_t)s.tile_start.size();
-    // connectivity codes and halo lists
+    // Connectivity codes and halo traces. A face whose neighbour lies in the
+    // same tile is coded by the neighbour's trace slot (face * tile + index);
+    // a face whose neighbour lies in another tile by a halo slot 4 tile + h.
+    // The traces for halo slot h of tile t are written, one stage earlier, by
+    // the neighbour itself into tile t's block of the halo buffer, at the
+    // offset recorded in the neighbour's publish code.
     s.nbr_code.assign(4 * s.Kpad, -1);
+    s.pub_code.assign(4 * s.Kpad, -1);
     auto NB = [&](int f, int64_t k) -> int32_t& { return s.nbr_code[blk_index(k, f, 4)]; };
-    s.halo_off.assign(s.ntiles + 1, 0);
-    s.halo_grp.assign(4 * s.ntiles, 0);
-    s.halo_ent.clear();
+    auto PUB = [&](int f, int64_t k) -> int32_t& { return s.pub_code[blk_index(k, f, 4)]; };
+    s.halo_tile.assign(2 * s.ntiles, 0);
     s.hmax = 0;
+    s.nhalo = 0;
+    const int64_t SS = 4 * s.NF + 1;         // reals per trace slot
+    const int64_t align = 64 / (int64_t)rs;  // halo blocks start on 64-byte boundaries
+    int64_t hoff = 0;
     struct HE { int32_t fn; int64_t kn; int64_t k; int f; };
     std::vector<HE> ents;
     for (int64_t t = 0; t < s.ntiles; ++t) {
@@ -317,22 +328,22 @@ void finalize(Solver& s) {
         }
       }
       std::stable_sort(ents.begin(), ents.end(), [](const HE& x, const HE& y) {
-        if (x.fn != y.fn) return x.fn < y.fn;
-        return x.kn < y.kn;
+        if (x.kn != y.kn) return x.kn < y.kn;
+        return x.fn < y.fn;
       });
       for (size_t h = 0; h < ents.size(); ++h) {
         NB(ents[h].f, ents[h].k) = (int32_t)(4 * tile + h);
-        s.halo_ent.push_back((int32_t)(ents[h].kn * 4 + ents[h].fn));
+        PUB(ents[h].fn, ents[h].kn) = (int32_t)(hoff + (int64_t)h * SS);
       }
-      // start of each neighbour-face group (entries are sorted by face)
-      for (int f = 0; f < 4; ++f) {
-        int32_t st = 0;
-        while (st < (int32_t)ents.size() && ents[st].fn < f) ++st;
-        s.halo_grp[4 * t + f] = st;
-      }
-      s.halo_off[t + 1] = (int32_t)s.halo_ent.size();
-      s.hmax = std::max<int>(s.hmax, (int)ents.size());
+      const int64_t nh = (int64_t)ents.size();
+      s.halo_tile[2 * t] = (int32_t)hoff;
+      s.halo_tile[2 * t + 1] = (int32_t)nh;
+      hoff = (hoff + nh * SS + align - 1) / align * align;
+      if (hoff >= (int64_t(1) << 31)) throw Error(MDG_E_UNSUPPORTED, "mesh too large: halo buffer exceeds 2^31 reals");
+      s.nhalo += nh;
+      s.hmax = std::max<int>(s.hmax, (int)nh);
     }
+    s.hbuf_reals = std::max<int64_t>(hoff, align);
     const size_t lds = stage_lds_bytes(s);
     if (lds <= 64 * 1024) break;
     if (tile <= 32) {
@@ -341,8 +352,10 @@ void finalize(Solver& s) {
       throw Error(MDG_E_UNSUPPORTED, "face-trace exchange does not fit in the LDS of one workgroup");
     }
   }
-  s.nhalo = (int64_t)s.halo_ent.size();
-  if (s.nhalo > 0 && s.K >= (int64_t(1) << 29)) throw Error(MDG_E_ARG, "mesh too large");
+  // the output staging of the trace publication reuses the trace area
+  if (size_t(6) * s.N * s.tile * rs > stage_lds_bytes(s)) throw Error(MDG_E_UNSUPPORTED, "LDS staging too small");
+  if (s.K >= (int64_t(1) << 29)) throw Error(MDG_E_ARG, "mesh too large");
+  if (size_t(s.hbuf_reals) * rs >= (size_t(1) << 32)) throw Error(MDG_E_UNSUPPORTED, "mesh too large: halo buffer exceeds 4 GiB");
 
   // geometry records
   s.geo.assign(size_t(NGEO) * s.Kpad, 0.0);
@@ -414,9 +427,10 @@ void finalize(Solver& s) {
   L.aACC = off; off = align256(off + afield);
   L.geo = off; off = align256(off + size_t(NGEO) * s.Kpad * rs);
   L.nbr = off; off = align256(off + size_t(4) * s.Kpad * 4);
-  L.halo_off = off; off = align256(off + size_t(s.ntiles + 1) * 4);
-  L.halo_ent = off; off = align256(off + std::max<size_t>(s.nhalo, 1) * 4);
-  L.halo_grp = off; off = align256(off + size_t(4) * s.ntiles * 4);
+  L.pub = off; off = align256(off + size_t(4) * s.Kpad * 4);
+  L.halo_tile = off; off = align256(off + size_t(2) * s.ntiles * 4);
+  L.H0 = off; off = align256(off + size_t(s.hbuf_reals) * rs);
+  L.H1 = off; off = align256(off + size_t(s.hbuf_reals) * rs);
   L.pml = off; off = align256(off + (s.Kp > 0 ? size_t(NPML) * s.Kppad * rs : 0));
   L.src = off; off = align256(off + size_t(MAX_DIPOLES) * 3 * s.N * rs);
   const size_t nblk = (s.K + 255) / 256;

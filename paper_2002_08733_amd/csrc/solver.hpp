@@ -54,7 +54,8 @@ inline size_t blk_index(int64_t e, int row, int rows_per_block) {
 struct DevLayout {
   size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
   size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
-  size_t geo, nbr, halo_off, halo_ent, halo_grp, pml, src;
+  size_t geo, nbr, pub, halo_tile, pml, src;
+  size_t H0, H1;  // halo trace buffers: stage inputs' traces on cross-tile faces (ping-pong)
   size_t epart, eout;
   size_t total;
 };
@@ -80,7 +81,12 @@ struct Solver {
   std::vector<int64_t> iperm;  // user -> internal
   int64_t ntiles = 0, ntiles0 = 0, nhalo = 0;
   int hmax = 0;
-  std::vector<int32_t> tile_start, tile_count, halo_off, halo_ent, halo_grp, nbr_code;
+  std::vector<int32_t> tile_start, tile_count;
+  std::vector<int32_t> nbr_code;   // blocked [Kpad/64][4][64]: trace slot of the face's neighbour, -1 = PEC
+  std::vector<int32_t> pub_code;   // blocked [Kpad/64][4][64]: halo-buffer offset (reals) of the face's trace, or -1
+  std::vector<int32_t> halo_tile;  // [ntiles][2]: halo block offset (reals), halo slot count
+  int64_t hbuf_reals = 0;
+  bool halo_valid = false;         // H0 holds the traces of Y
   std::vector<double> geo;     // blocked [Kpad/64][NGEO][64]
   std::vector<double> pmlrec;  // blocked [Kppad/64][NPML][64]
   // ---- device
@@ -135,8 +141,14 @@ struct StageParams {
   const void* aUin;
   void* aUout;
   void* aACC;
+  // halo traces (see Solver::pub_code): read for the input, written for the output
+  const void* hin;
+  void* hout;
+  bool publish;  // write the output's halo traces (false for the operator-only call)
 };
 void launch_stage(const Solver& s, const StageParams& sp, void* stream);
+// halo traces of state U (blocked layout) into the halo buffer H
+void launch_publish(const Solver& s, const void* U, void* H, void* stream);
 void launch_energy(const Solver& s, const void* Y, void* stream);
 
 }  // namespace mdg

@@ -65,14 +65,15 @@ struct DevArgs {
   void* aYw;
   const void* geo;
   const int32_t* nbr;
-  const int32_t* halo_off;
-  const int32_t* halo_ent;
-  const int32_t* halo_grp;  // per tile: start of the face-0..3 groups of its halo entries
+  const int32_t* pub;        // publish codes: halo-buffer offset of each face's trace, or -1
+  const int32_t* halo_tile;  // per tile: halo block offset (reals), halo slot count
+  const void* hin;           // halo traces of the stage input
+  void* hout;                // halo traces of the stage output
   const void* pml;
   const void* src;
-  uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes;
+  uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes;
   int64_t pml_base;
-  int32_t tile_begin, ntiles, hmax, stage, nsrc;
+  int32_t tile_begin, ntiles, stage, nsrc, publish;
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
   int64_t src_elem[MAX_DIPOLES];
   double src_amp[MAX_DIPOLES];
@@ -296,24 +297,30 @@ __device__ __forceinline__ int lbase(int slot, int role) { return slot * slot_st
 template <int NF>
 constexpr int loff(int k, int m) { return k * NF + m; }
 
-// neighbour trace of a halo entry: load the components face F needs, trace, store
+// components of a field that enter the tangential trace on face F
+template <int F>
+constexpr bool face_needs(int c) {
+  return (F == 0) || (F == 1 && c != 0) || (F == 2 && c != 1) || (F == 3 && c != 2);
+}
+
+// trace of a field on face F from the LDS output staging [role][3N][tile],
+// stored to its halo-buffer slot: [input role of the field][k][m]
 template <int P, int F, typename R>
-__device__ __forceinline__ void halo_trace(Rsrc st, uint32_t vo, R* lds, int role, int slot) {
+__device__ __forceinline__ void publish_face(const R* stg, int role, int tile, int li, Rsrc rH, int code) {
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
   R w[3][N];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const bool need = (F == 0) || (F == 1 && c != 0) || (F == 2 && c != 1) || (F == 3 && c != 2);
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int l = 0; l < N; ++l) w[c][l] = need ? bld<R>(st, vo, rowb<R>(c * N + l)) : R(0);
-  }
+    for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((role * 3 + c) * N + l) * tile + li] : R(0);
   R t0[NF], t1[NF];
   face_trace<P, F, R>(w, t0, t1);
-  R* d = lds + lbase<NF>(slot, role);
+  // a field's traces feed the neighbour lanes of the other role
+  const uint32_t base = (uint32_t)(code + (1 - role) * 2 * NF) * (uint32_t)sizeof(R);
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
-    d[loff<NF>(0, m)] = t0[m];
-    d[loff<NF>(1, m)] = t1[m];
+    bst<R>(t0[m], rH, base, (uint32_t)(m * sizeof(R)));
+    bst<R>(t1[m], rH, base, (uint32_t)((NF + m) * sizeof(R)));
   }
 }
 
@@ -343,19 +350,27 @@ __device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* AC
   return e;
 }
 template <typename R>
-__device__ __forceinline__ void rk_store(const Epi& e, R k, uint32_t vo, uint32_t so, R b, R c_out) {
+__device__ __forceinline__ void rk_store(const Epi& e, R k, uint32_t vo, uint32_t so, R b, R c_out, bool live) {
   const R y = bld<R, CP_NT>(e.y_rd, vo, so);
   const R a = bld<R, CP_NT>(e.a_rd, vo, so);
   const R acc = fma(b, k, a);
-  bst<R, CP_NT>(acc, e.a_wr, vo, so);
-  bst<R, CP_NT>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
+  if (live) {
+    bst<R, CP_NT>(acc, e.a_wr, vo, so);
+    bst<R, CP_NT>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
+  }
 }
-// same with y and a loaded earlier
+// same with y and a loaded earlier; returns the value written to the output
+// (the next stage input, or the new Y)
 template <typename R>
-__device__ __forceinline__ void rk_store_pre(const Epi& e, R k, R y, R a, uint32_t vo, uint32_t so, R b, R c_out) {
+__device__ __forceinline__ R rk_store_pre(const Epi& e, R k, R y, R a, uint32_t vo, uint32_t so, R b, R c_out,
+                                          bool live) {
   const R acc = fma(b, k, a);
-  bst<R, CP_NT>(acc, e.a_wr, vo, so);
-  bst<R, CP_NT>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
+  const R out = fma(c_out, e.final_stage ? acc : k, y);
+  if (live) {
+    bst<R, CP_NT>(acc, e.a_wr, vo, so);
+    bst<R, CP_NT>(out, e.out_wr, vo, so);
+  }
+  return out;
 }
 
 // metric of face F (runtime face index): g^_kl = t^_k^T G t^_l
@@ -463,6 +478,7 @@ template <typename R, int P, bool UPW, bool PML>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
     DevArgs a) {
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
+  constexpr int SS = slot_stride<NF>();
   constexpr uint32_t RS = sizeof(R);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
@@ -480,8 +496,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const int li = rem - role * tile;
   const int start = a.elem_begin + tl * tile;
   const int cnt = min(tile, a.elem_end - start);
-  // lanes past the end of a partial tile still load (arrays are padded by a
-  // full tile) so every load is unconditional; they stop at the last barrier
+  // Lanes past the end of a partial tile compute on padding (arrays are padded
+  // by a full tile) so that every load is unconditional and every lane meets
+  // every barrier; their stores are suppressed.
+  const bool live = li < cnt;
   const uint32_t el = (uint32_t)(start + li);
   const Rsrc rU = make_rsrc(a.Uin, a.state_bytes);
   const Rsrc rG = make_rsrc(a.geo, a.geo_bytes);
@@ -490,8 +508,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
   const uint32_t vgeo = blk_base(el, NGEO, RS);
 
-  // RK operands of this part's output rows, issued first so that their
-  // latency overlaps the halo, trace, volume and flux work (absent operands read as 0)
+  // 1. RK operands of this part's output rows, issued first so that their
+  // latency overlaps the trace, volume and flux work (absent operands read as 0)
   const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
   R ypre[3][NQ], apre[3][NQ];
 #pragma unroll
@@ -504,31 +522,31 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
     }
 
-  // 1. halo: traces of out-of-tile neighbours (both fields), from global
-  // memory. Halo entries are grouped by the neighbour's local face; part Q
-  // handles the group of face Q, so a wave runs one face variant.
-  {
-    const int h0 = a.halo_off[t], nh = a.halo_off[t + 1] - h0;
-    const int gs = a.halo_grp[4 * t + part];
-    const int ge = part < 3 ? a.halo_grp[4 * t + part + 1] : nh;
-    const int ng = ge - gs;
-    for (int j = rem; j < 2 * ng; j += 2 * tile) {
-      const int hr = j >= ng;
-      const int hi = gs + j - hr * ng;
-      const uint32_t kn = (uint32_t)a.halo_ent[h0 + hi] >> 2;
-      // role-0 slots hold traces of H (field 1), role-1 slots traces of E
-      const uint32_t vo = blk_base(kn, 2 * R3, RS) + (1 - hr) * rowb<R>(R3);
-      MDG_SWITCH_Q((halo_trace<P, Q, R>(rU, vo, lds, hr, 4 * tile + hi)));
-    }
-  }
-  __builtin_amdgcn_sched_barrier(0);
-
-  // 2. input field of this lane; the trace on face `part` -> LDS
+  // 2. input field of this lane
   R v[3][N];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int l = 0; l < N; ++l) v[c][l] = bld<R>(rU, vin, rowb<R>(c * N + l));
+
+  // 3. halo: the traces of out-of-tile neighbours were written by those
+  // neighbours in the previous stage, as an image of this tile's halo slots.
+  // Copy the block into LDS slots 4 tile.. with asynchronous LDS loads
+  // (16 bytes per lane, no registers involved); waited for before barrier 1.
+  {
+    typedef __attribute__((address_space(3))) unsigned char lds_byte;
+    const int hoff = a.halo_tile[2 * t], nh = a.halo_tile[2 * t + 1];
+    const uint32_t nbytes = ((uint32_t)nh * SS * RS + 15u) & ~15u;
+    const Rsrc rH = make_rsrc(a.hin, a.hbuf_bytes);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6), nwv = blockDim.x >> 6;
+    lds_byte* dst = (lds_byte*)smem_raw + 4u * (uint32_t)tile * SS * RS;
+    for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
+      const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
+      if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rH, dst + c * 1024u, 16, vo, (uint32_t)hoff * RS, 0, 0);
+    }
+  }
+
+  // 4. the trace of the input field on face `part` -> LDS
   {
     R t0[NF], t1[NF];
     MDG_SWITCH_Q((face_trace<P, Q, R>(v, t0, t1)));
@@ -541,7 +559,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   }
   __builtin_amdgcn_sched_barrier(0);
 
-  // 3. volume term (weak reference curl) on this part's modes
+  // 5. volume term (weak reference curl) on this part's modes
   const R g = role ? R(-1) : R(1);
   const R sgn = bld<R>(rG, vgeo, rowb<R>(G_SIGN));
   R acc[3][NQ];
@@ -551,9 +569,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 #pragma unroll
     for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(acc[c][i]));
 
-  __syncthreads();  // traces of the tile and its halo are in LDS
-
-  // 4. flux coefficients of face `part`
+  // this wave's halo copies have landed in LDS
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  // 6. geometry and connectivity of face `part`, loaded while waiting at the
+  // barrier (the input field is dead here)
   const R gxx = bld<R>(rG, vgeo, rowb<R>(G_XX)), gxy = bld<R>(rG, vgeo, rowb<R>(G_XY));
   const R gxz = bld<R>(rG, vgeo, rowb<R>(G_XZ)), gyy = bld<R>(rG, vgeo, rowb<R>(G_YY));
   const R gyz = bld<R>(rG, vgeo, rowb<R>(G_YZ)), gzz = bld<R>(rG, vgeo, rowb<R>(G_ZZ));
@@ -562,14 +581,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     Z = bld<R>(rG, vgeo, rowb<R>(G_Z));
     wz = bld<R>(rG, vgeo, rowb<R>(G_WZ0 + part));
   }
+  const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
   const Rsrc rN = make_rsrc(a.nbr, a.nbr_bytes);
   const int code = bldi(rN, blk_base(el, 4, 4), (uint32_t)part * 256u);
+  const Rsrc rPub = make_rsrc(a.pub, a.nbr_bytes);
+  const int pcode = bldi(rPub, blk_base(el, 4, 4), (uint32_t)part * 256u);
+
+  __syncthreads();  // B1: traces of the tile and its halo are in LDS
+
+  // 7. flux coefficients of face `part`
   {
     R A1[NF], A2[NF];
     face_flux_coef<P, UPW, R>(part, lds, role, tile, li, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz, gzz, A1,
                               A2);
-    __syncthreads();  // every flux read of this tile is done
-    // 5. publish the flux coefficients of face `part` in its own slot
+    __syncthreads();  // B2: every flux read of this tile is done
+    // publish the flux coefficients of face `part` in its own slot
     R* d = lds + lbase<NF>(part * tile + li, role);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
@@ -577,13 +603,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       d[loff<NF>(1, m)] = A2[m];
     }
   }
-  __syncthreads();
-  if (li >= cnt) return;
+  __syncthreads();  // B3
 
-  // 6. lift of the four faces onto this part's modes
+  // 8. lift of the four faces onto this part's modes
   MDG_SWITCH_Q((lift_all_q<P, Q, R>(lds, role, tile, li, acc)));
 
-  // 7. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j
+  // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j
   if (role == 0) {
     const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
     for (int i = 0; i < a.nsrc; ++i)
@@ -599,8 +624,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       }
   }
 
-  // 8. 3x3 block-diagonal mass inverse: d_t u_l = (1/eps) G0^-1 r_l
-  const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
+  // 10. 3x3 block-diagonal mass inverse: d_t u_l = (1/eps) G0^-1 r_l
   const R mf = role ? imu : ieps;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -613,7 +637,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const R bc = R(a.bcoef);
   const int stage = a.stage;
   // rows of this part: row(c, q) = c*N + part*NQ + q, skipped past N
-  // 9. PML auxiliaries
+  // 11. PML auxiliaries
   if constexpr (PML) {
     const uint32_t pk = (uint32_t)((int64_t)el - a.pml_base);
     const Rsrc rP = make_rsrc(a.pml, a.pml_bytes);
@@ -653,11 +677,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       acc[2][q] -= AT[6] * y0 + AT[7] * y1 + AT[8] * y2;
       const R k[3] = {fma(xx, cx, -wx * qa[0]), fma(xy, cy, -wy * qa[1]), fma(xz, cz, -wzz * qa[2])};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rk_store<R>(ea, k[c], va, (uint32_t)(c * N + l) * 64u * RS, bc, ca);
+      for (int c = 0; c < 3; ++c) rk_store<R>(ea, k[c], va, (uint32_t)(c * N + l) * 64u * RS, bc, ca, live);
     }
   }
 
-  // 10. RK4 epilogue of this part's rows of the output field
+  // 12. RK4 epilogue of this part's rows of the output field; acc becomes
+  // the stored output
   {
     const R cf = R(ef.c_out);
 #pragma unroll
@@ -666,8 +691,29 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       for (int q = 0; q < NQ; ++q) {
         const int l = part * NQ + q;
         if (l < N)
-          rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], vout, (uint32_t)(c * N + l) * 64u * RS, bc, cf);
+          acc[c][q] = rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], vout, (uint32_t)(c * N + l) * 64u * RS,
+                                      bc, cf, live);
       }
+  }
+
+  // 13. traces of the output on faces that a neighbouring tile reads in the
+  // next stage: stage the tile's output fields in LDS, then part Q traces
+  // face Q of its element into the neighbour tile's halo block
+  if (a.publish) {
+    __syncthreads();  // B4: the lifts are done with the trace area
+    R* stg = lds;     // [role][3N][tile]
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int l = part * NQ + q;
+        if (l < N) stg[((role * 3 + c) * N + l) * tile + li] = acc[c][q];
+      }
+    __syncthreads();  // B5
+    if (live && pcode >= 0) {
+      const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
+      MDG_SWITCH_Q((publish_face<P, Q, R>(stg, role, tile, li, rHo, pcode)));
+    }
   }
 }
 #undef MDG_SWITCH_Q
@@ -715,6 +761,48 @@ __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ p
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
   __syncthreads();
   if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------- publish
+// Halo traces of a state set from the host (the stage kernels publish those
+// of their own outputs): one lane per element and field, every face with a
+// cross-tile neighbour.
+template <int P, int F, typename R>
+__device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], int fld, Rsrc rH, int code) {
+  constexpr int NF = Ops<P>::NF;
+  R t0[NF], t1[NF];
+  face_trace<P, F, R>(w, t0, t1);
+  const uint32_t base = (uint32_t)(code + (1 - fld) * 2 * NF) * (uint32_t)sizeof(R);
+#pragma unroll
+  for (int m = 0; m < NF; ++m) {
+    bst<R>(t0[m], rH, base, (uint32_t)(m * sizeof(R)));
+    bst<R>(t1[m], rH, base, (uint32_t)((NF + m) * sizeof(R)));
+  }
+}
+
+template <typename R, int P>
+__global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t state_bytes, const int32_t* pub,
+                                                      uint32_t pub_bytes, void* H, uint32_t hbuf_bytes, int K) {
+  constexpr int N = Ops<P>::N, R3 = 3 * N;
+  constexpr uint32_t RS = sizeof(R);
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  const int el = gid >> 1, fld = gid & 1;
+  if (el >= K) return;
+  const Rsrc rU = make_rsrc(U, state_bytes), rP = make_rsrc(pub, pub_bytes), rH = make_rsrc(H, hbuf_bytes);
+  const uint32_t vo = blk_base((uint32_t)el, 2 * R3, RS) + (uint32_t)fld * rowb<R>(R3);
+  int code[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) code[f] = bldi(rP, blk_base((uint32_t)el, 4, 4), (uint32_t)f * 256u);
+  if (code[0] < 0 && code[1] < 0 && code[2] < 0 && code[3] < 0) return;
+  R w[3][N];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int l = 0; l < N; ++l) w[c][l] = bld<R>(rU, vo, rowb<R>(c * N + l));
+  if (code[0] >= 0) publish_face_global<P, 0, R>(w, fld, rH, code[0]);
+  if (code[1] >= 0) publish_face_global<P, 1, R>(w, fld, rH, code[1]);
+  if (code[2] >= 0) publish_face_global<P, 2, R>(w, fld, rH, code[2]);
+  if (code[3] >= 0) publish_face_global<P, 3, R>(w, fld, rH, code[3]);
 }
 
 // ---------------------------------------------------------------- launch
@@ -771,9 +859,11 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.aACC = sp.aACC;
   a.geo = base + s.L.geo;
   a.nbr = reinterpret_cast<const int32_t*>(base + s.L.nbr);
-  a.halo_off = reinterpret_cast<const int32_t*>(base + s.L.halo_off);
-  a.halo_ent = reinterpret_cast<const int32_t*>(base + s.L.halo_ent);
-  a.halo_grp = reinterpret_cast<const int32_t*>(base + s.L.halo_grp);
+  a.pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
+  a.halo_tile = reinterpret_cast<const int32_t*>(base + s.L.halo_tile);
+  a.hin = sp.hin;
+  a.hout = sp.hout;
+  a.publish = sp.publish && sp.hout != nullptr;
   a.pml = base + s.L.pml;
   a.src = base + s.L.src;
   const size_t rs = s.real_size();
@@ -782,8 +872,8 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.geo_bytes = (uint32_t)(size_t(NGEO) * s.Kpad * rs);
   a.nbr_bytes = (uint32_t)(size_t(4) * s.Kpad * 4);
   a.pml_bytes = (uint32_t)(size_t(NPML) * s.Kppad * rs);
+  a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
   a.pml_base = s.K0;
-  a.hmax = s.hmax;
   a.stage = sp.stage;
   a.nsrc = sp.nsrc;
   for (int i = 0; i < MAX_DIPOLES; ++i) {
@@ -833,6 +923,34 @@ void launch_energy(const Solver& s, const void* Y, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (s.opt.precision == MDG_FP32) launch_energy_r<float>(s, Y, st);
   else launch_energy_r<double>(s, Y, st);
+}
+
+
+template <typename R>
+static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_t st) {
+  char* base = static_cast<char*>(s.ws);
+  const size_t rs = s.real_size();
+  const uint32_t sb = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
+  const uint32_t pb = (uint32_t)(size_t(4) * s.Kpad * 4);
+  const uint32_t hb = (uint32_t)(size_t(s.hbuf_reals) * rs);
+  const int32_t* pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
+  const int K = (int)s.K;
+  const dim3 grid((unsigned)((2 * s.K + 255) / 256));
+  switch (s.P) {
+    case 1: hipLaunchKernelGGL((publish_kernel<R, 1>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
+    case 2: hipLaunchKernelGGL((publish_kernel<R, 2>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
+    case 3: hipLaunchKernelGGL((publish_kernel<R, 3>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
+    case 4: hipLaunchKernelGGL((publish_kernel<R, 4>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
+    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
+  }
+  hip_check(hipGetLastError(), "publish_kernel launch");
+}
+
+void launch_publish(const Solver& s, const void* U, void* H, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s.nhalo == 0) return;
+  if (s.opt.precision == MDG_FP32) launch_publish_r<float>(s, U, H, st);
+  else launch_publish_r<double>(s, U, H, st);
 }
 
 }  // namespace mdg
