@@ -508,7 +508,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
   const uint32_t vgeo = blk_base(el, NGEO, RS);
 
-  // 1. RK operands of this part's output rows, issued first so that their
+  // 1. input fields of the tile, each row loaded once: lane (role, part)
+  // loads rows [part RQ, part RQ + RQ) of its input field (the other field)
+  // and stages them in LDS as [field][3N][tile], in the area that holds the
+  // face traces later
+  constexpr int RQ = (R3 + 3) / 4;
+  R* stg = lds;
+  R vq[RQ];
+#pragma unroll
+  for (int i = 0; i < RQ; ++i) {
+    const int r = min(part * RQ + i, R3 - 1);
+    vq[i] = bld<R>(rU, vin, (uint32_t)r * 64u * RS);
+  }
+
+  // 2. RK operands of this part's output rows, issued now so that their
   // latency overlaps the trace, volume and flux work (absent operands read as 0)
   const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
   R ypre[3][NQ], apre[3][NQ];
@@ -522,12 +535,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
     }
 
-  // 2. input field of this lane
-  R v[3][N];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int l = 0; l < N; ++l) v[c][l] = bld<R>(rU, vin, rowb<R>(c * N + l));
+  for (int i = 0; i < RQ; ++i) {
+    const int r = part * RQ + i;
+    if (r < R3) stg[((1 - role) * R3 + r) * tile + li] = vq[i];
+  }
+  __syncthreads();  // B0: the tile's input fields are staged
 
   // 3. halo: the traces of out-of-tile neighbours were written by those
   // neighbours in the previous stage, as an image of this tile's halo slots.
@@ -546,10 +559,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     }
   }
 
-  // 4. the trace of the input field on face `part` -> LDS
+  // 4. the lane's input field from the staging; its trace on face `part`
+  R v[3][N];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int l = 0; l < N; ++l) v[c][l] = stg[((1 - role) * R3 + c * N + l) * tile + li];
   {
     R t0[NF], t1[NF];
     MDG_SWITCH_Q((face_trace<P, Q, R>(v, t0, t1)));
+    __syncthreads();  // B0': every lane has read the staging
     R* d = lds + lbase<NF>(part * tile + li, role);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
