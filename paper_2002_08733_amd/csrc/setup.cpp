@@ -274,9 +274,13 @@ void finalize(Solver& s) {
   const bool fp32 = s.opt.precision == MDG_FP32;
   const size_t rs = s.real_size();
   int tile0 = tile_size_for(s.P, fp32);
+  bool forced = false;
   if (const char* e = std::getenv("MDG_TILE")) {  // tuning override: 32 or 64
     const int v = std::atoi(e);
-    if (v == 32 || v == 64) tile0 = v;
+    if (v == 32 || v == 64) {
+      tile0 = v;
+      forced = true;
+    }
   }
   for (int tile = tile0;; tile /= 2) {
     s.tile = tile;
@@ -345,7 +349,9 @@ void finalize(Solver& s) {
     }
     s.hbuf_reals = std::max<int64_t>(hoff, align);
     const size_t lds = stage_lds_bytes(s);
-    if (lds <= 64 * 1024) break;
+    // the default choice keeps two workgroups per CU; a forced tile only has
+    // to fit the LDS of one workgroup
+    if (lds <= 64 * 1024 || (forced && lds <= LDS_MAX_BYTES)) break;
     if (tile <= 32) {
       // up to 160 KiB per workgroup on gfx950 (checked against the device at bind time)
       if (lds <= LDS_MAX_BYTES) break;
