@@ -14,7 +14,9 @@ kernels run on; W warm-up steps are excluded.
 
 roofline: algorithmic HBM bytes per stage launch (17/4 state passes of 6N
 values plus the per-element geometry and connectivity records, see
-mdg_query) / the average stage-kernel duration, against 8 TB/s.
+mdg_query) / the average stage-kernel duration, against 8 TB/s. The
+bandwidth of a plain 1 GiB device copy on the same GPU is reported beside it
+(hbm_copy_GBs, frac_of_copy).
 traffic: measured HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE,
 read from the committed counter summary when it was taken on the current
 kernel source, else null.
@@ -105,6 +107,29 @@ def cpu_baseline(w, dt, sample):
             "host_cpus": os.cpu_count()}
 
 
+def copy_peak_gbs(mib=1024, reps=10):
+    """Achievable HBM bandwidth on this GPU: a plain 1 GiB device-to-device copy
+    (torch's copy kernel), read + write bytes over the event-timed duration."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1000.0 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / sec / 1e9
+
+
 def traffic_for(kernel_hash, precision):
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -152,6 +177,8 @@ def main():
         del a, b
         torch.cuda.empty_cache()
 
+    copy_gbs = copy_peak_gbs()
+    log(f"[bench] device copy (1 GiB): {copy_gbs:.0f} GB/s")
     w = W.jittered(args.n, 3, seed=2, flux="upwind")
     dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
     khash = kernel_source_hash()
@@ -198,11 +225,16 @@ def main():
                    "elements": w.nt, "order": 3, "dof": w.nt * 6 * 20, "dt": dt, "flux": "upwind"},
         "roofline": main_r["roofline"],
         "us_per_stage": main_r["us_per_stage"],
+        "tile": main_r["tile"],
+        "energy_ratio": main_r["energy_ratio"],
+        "hbm_copy_GBs": copy_gbs,
+        "frac_of_copy": main_r["roofline"]["achieved"] / copy_gbs,
     }
     other = [p for p in results if p != args.precision]
     for p in other:
         out[p] = {"value": results[p]["value"], "unit": "GDOF/s", "us_per_stage": results[p]["us_per_stage"],
-                  "roofline": results[p]["roofline"]}
+                  "roofline": results[p]["roofline"], "tile": results[p]["tile"],
+                  "frac_of_copy": results[p]["roofline"]["achieved"] / copy_gbs}
     if not args.skip_cpu:
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample or w.nt} elements")
         out["cpu_baseline"] = cpu_baseline(w, dt, args.cpu_sample)
