@@ -196,9 +196,9 @@ struct Cst<double, P> {
 };
 
 // traces of a vector coefficient field on face F: t0/t1 = T_F (v . t^1/2)
-template <int P, int F, typename R>
-__device__ __forceinline__ void face_trace(const R (&v)[3][Ops<P>::N], R (&t0)[Ops<P>::NF],
-                                           R (&t1)[Ops<P>::NF]) {
+// v(c, l): coefficient l of component c (a register array or an LDS row)
+template <int P, int F, typename R, typename V>
+__device__ __forceinline__ void face_trace(const V& v, R (&t0)[Ops<P>::NF], R (&t1)[Ops<P>::NF]) {
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
@@ -208,8 +208,8 @@ __device__ __forceinline__ void face_trace(const R (&v)[3][Ops<P>::N], R (&t0)[O
     for (int l = 0; l < N; ++l) {
       if (Ops<P>::T[F][m][l] != 0.0) {
         const R c = Cst<R, P>::tr(F, m, l);
-        const R a = tan0<F, R>(v[0][l], v[1][l], v[2][l]);
-        const R b = tan1<F, R>(v[0][l], v[1][l], v[2][l]);
+        const R a = tan0<F, R>(v(0, l), v(1, l), v(2, l));
+        const R b = tan1<F, R>(v(0, l), v(1, l), v(2, l));
         s0 = first ? c * a : fma(c, a, s0);
         s1 = first ? c * b : fma(c, b, s1);
         first = false;
@@ -253,8 +253,8 @@ __device__ __forceinline__ void face_lift_q(const R (&A1)[Ops<P>::NF], const R (
 
 // acc = gs * W(v) on the modes of part Q:
 //   W[x] = D_z v_y - D_y v_z, W[y] = D_x v_z - D_z v_x, W[z] = D_y v_x - D_x v_y
-template <int P, int Q, typename R>
-__device__ __forceinline__ void volume_q(const R (&v)[3][Ops<P>::N], R gs, R (&acc)[3][nq<P>()]) {
+template <int P, int Q, typename R, typename V>
+__device__ __forceinline__ void volume_q(const V& v, R gs, R (&acc)[3][nq<P>()]) {
   constexpr int N = Ops<P>::N, NQ = nq<P>();
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
@@ -265,18 +265,18 @@ __device__ __forceinline__ void volume_q(const R (&v)[3][Ops<P>::N], R gs, R (&a
       for (int m = 0; m < N; ++m) {
         if (Ops<P>::D[0][l][m] != 0.0) {
           const R cx = Cst<R, P>::d(0, l, m);
-          ay = fma(cx, v[2][m], ay);
-          az = fma(-cx, v[1][m], az);
+          ay = fma(cx, v(2, m), ay);
+          az = fma(-cx, v(1, m), az);
         }
         if (Ops<P>::D[1][l][m] != 0.0) {
           const R cy = Cst<R, P>::d(1, l, m);
-          ax = fma(-cy, v[2][m], ax);
-          az = fma(cy, v[0][m], az);
+          ax = fma(-cy, v(2, m), ax);
+          az = fma(cy, v(0, m), az);
         }
         if (Ops<P>::D[2][l][m] != 0.0) {
           const R cz = Cst<R, P>::d(2, l, m);
-          ax = fma(cz, v[1][m], ax);
-          ay = fma(-cz, v[0][m], ay);
+          ax = fma(cz, v(1, m), ax);
+          ay = fma(-cz, v(0, m), ay);
         }
       }
     }
@@ -314,7 +314,7 @@ __device__ __forceinline__ void publish_face(const R* stg, int role, int tile, i
 #pragma unroll
     for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((role * 3 + c) * N + l) * tile + li] : R(0);
   R t0[NF], t1[NF];
-  face_trace<P, F, R>(w, t0, t1);
+  face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
   // a field's traces feed the neighbour lanes of the other role
   const uint32_t base = (uint32_t)(code + (1 - role) * 2 * NF) * (uint32_t)sizeof(R);
 #pragma unroll
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       const int l = part * NQ + q;
       const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
       ypre[c][q] = bld<R, CP_NT>(ef.y_rd, vout, so);
-      apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
+      if constexpr (sizeof(R) == 8) apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
     }
 
 #pragma unroll
@@ -559,15 +559,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     }
   }
 
-  // 4. the lane's input field from the staging; its trace on face `part`
-  R v[3][N];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int l = 0; l < N; ++l) v[c][l] = stg[((1 - role) * R3 + c * N + l) * tile + li];
+  // 4. trace of the input field on face `part` and the volume term of the
+  // part's modes, both reading the input field from the staging (not held in
+  // registers, which keeps the register budget at five waves per SIMD)
+  const R* vin_lds = stg + (1 - role) * R3 * tile + li;
+  auto vl = [&](int c, int l) { return vin_lds[(c * N + l) * tile]; };
+  const R g = role ? R(-1) : R(1);
+  const R sgn = bld<R>(rG, vgeo, rowb<R>(G_SIGN));
+  R acc[3][NQ];
   {
     R t0[NF], t1[NF];
-    MDG_SWITCH_Q((face_trace<P, Q, R>(v, t0, t1)));
+    MDG_SWITCH_Q((face_trace<P, Q, R>(vl, t0, t1)));
+    asm volatile("" ::: "memory");  // the volume term reads the staging again
+    MDG_SWITCH_Q((volume_q<P, Q, R>(vl, g * sgn, acc)));
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(acc[c][i]));
     __syncthreads();  // B0': every lane has read the staging
     R* d = lds + lbase<NF>(part * tile + li, role);
 #pragma unroll
@@ -577,16 +585,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     }
   }
   __builtin_amdgcn_sched_barrier(0);
-
-  // 5. volume term (weak reference curl) on this part's modes
-  const R g = role ? R(-1) : R(1);
-  const R sgn = bld<R>(rG, vgeo, rowb<R>(G_SIGN));
-  R acc[3][NQ];
-  MDG_SWITCH_Q((volume_q<P, Q, R>(v, g * sgn, acc)));
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(acc[c][i]));
 
   // this wave's halo copies have landed in LDS
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -607,6 +605,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const int pcode = bldi(rPub, blk_base(el, 4, 4), (uint32_t)part * 256u);
 
   __syncthreads();  // B1: traces of the tile and its halo are in LDS
+  if constexpr (sizeof(R) == 4) {
+    // FP32: the accumulator rows are loaded here, still ~5 us before the
+    // epilogue, which keeps the register budget at five waves per SIMD
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int l = part * NQ + q;
+        const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
+        apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
+      }
+  }
 
   // 7. flux coefficients of face `part`
   {
@@ -790,7 +800,7 @@ template <int P, int F, typename R>
 __device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], int fld, Rsrc rH, int code) {
   constexpr int NF = Ops<P>::NF;
   R t0[NF], t1[NF];
-  face_trace<P, F, R>(w, t0, t1);
+  face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
   const uint32_t base = (uint32_t)(code + (1 - fld) * 2 * NF) * (uint32_t)sizeof(R);
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
