@@ -71,6 +71,8 @@ typedef struct mdg_options {
   int32_t integrator; /* MDG_RK4 */
   double dt;          /* > 0: fixed time step; 0: computed from cfl */
   double cfl;         /* dt = cfl * min_T(2 r_in,T sqrt(eps_T mu_T)) / (p+1)^2 when dt == 0 */
+  int32_t tile;       /* elements per stage-kernel workgroup: 32 or 64; 0 = automatic */
+  int32_t reserved;   /* must be 0 */
 } mdg_options;
 
 typedef struct mdg_info {
@@ -81,6 +83,8 @@ typedef struct mdg_info {
   double bytes_per_stage;         /* algorithmic HBM bytes of one RK stage (all elements) */
   double flops_per_stage;         /* algorithmic flops of one RK stage (sparse reference ops) */
   int64_t workspace_bytes;        /* device bytes mdg_bind_workspace needs */
+  int64_t n_instances;            /* independent instances (mdg_set_instances), >= 1 */
+  int64_t n_dipoles;
 } mdg_info;
 
 /* Create a solver. opts is copied. *out receives the handle (NULL on error). */
@@ -116,11 +120,27 @@ mdg_status mdg_set_pml(mdg_solver* s, const double* omega);
 /* Point current dipoles j = d delta(r - r0) g(t) [KS Sec. I, current j]:
  * pos[n][3], dir[n][3], wave[n][3] = (f0, bw, t0) with
  * g(t) = sin(2 pi f0 (t - t0)) exp(-(t - t0)^2 / (2 s^2)), s = 1/(2 pi bw).
- * Each dipole acts on the lowest-index element whose closure contains r0.
- * n <= 4. n = 0 removes all dipoles. MDG_E_ARG if a point is outside the mesh.
- * Host-only. */
+ * Each dipole acts on the lowest-index element whose closure contains r0
+ * (searching the whole mesh). Any n >= 0; n = 0 removes all dipoles. MDG_E_ARG
+ * if a point is outside the mesh. Host-only. */
 mdg_status mdg_set_dipoles(mdg_solver* s, int32_t n, const double* pos, const double* dir,
                            const double* wave);
+
+/* Independent instances in one solver (many sources or material samples on
+ * meshes of uneven size advanced by the same launches): the mesh given to
+ * mdg_set_mesh is the disjoint union of n instances whose elements occupy the
+ * caller's index ranges [first[i], first[i+1]), first[0] = 0, first[n] = nt.
+ * No face may join two instances (MDG_E_MESH). The stage kernel keeps each
+ * instance's elements together; all instances share dt (the smallest CFL
+ * step when dt is computed). n = 1 with first = {0, nt} is the default.
+ * Host-only; call after mdg_set_mesh, before mdg_bind_workspace. */
+mdg_status mdg_set_instances(mdg_solver* s, int32_t n, const int64_t* first);
+
+/* Dipoles as in mdg_set_dipoles, dipole i located inside instance inst[i]
+ * only (lowest-index element of that instance whose closure contains r0);
+ * inst[i] = -1 searches the whole mesh. Host-only. */
+mdg_status mdg_set_instance_dipoles(mdg_solver* s, int32_t n, const int32_t* inst, const double* pos,
+                                    const double* dir, const double* wave);
 
 /* Device bytes needed by the current setup (finalises the setup: element
  * reordering, tiles, face connectivity). */
@@ -160,8 +180,16 @@ mdg_status mdg_project(mdg_solver* s, int32_t q, const double* Evals, const doub
 
 /* Advance nsteps classic RK4 steps. Asynchronous on `stream` (hipStream_t,
  * NULL = default stream): four stage-kernel launches per step (eight with
- * PML elements). Kernel faults surface at the next synchronising call. */
+ * PML elements) and one clock tick. Source amplitudes are evaluated on the
+ * device from a device-side clock (t0 + n dt), so every launch of a step has
+ * the same arguments. Kernel faults surface at the next synchronising call. */
 mdg_status mdg_step(mdg_solver* s, int64_t nsteps, void* stream);
+
+/* Same result as mdg_step(nsteps), launched as replays of a HIP graph of
+ * steps_per_graph steps (captured on the first call, kept until the solver
+ * is re-bound or destroyed; remainder steps run eagerly). `stream` must be a
+ * non-default hipStream_t (capture needs one); MDG_E_ARG otherwise. */
+mdg_status mdg_step_graph(mdg_solver* s, int64_t nsteps, int32_t steps_per_graph, void* stream);
 
 /* One operator application [KS Sec. III-IV]: time derivatives (dE, dH, dP, dQ)
  * of the given state at time t (source evaluated at t), same layouts as
@@ -173,6 +201,10 @@ mdg_status mdg_rhs(mdg_solver* s, const double* E, const double* H, const double
 /* Electromagnetic energy W = 1/2 sum_T [(eps e, e)_T + (mu h, h)_T] of the
  * current state, accumulated in FP64 on the device [KS Sec. III]. Synchronous. */
 mdg_status mdg_energy(mdg_solver* s, double* W);
+
+/* Energy of each instance, W[n_instances], FP64 per-element values summed in
+ * element order on the host. Synchronous. */
+mdg_status mdg_energy_instances(mdg_solver* s, double* W);
 
 /* Sizes, decomposition and algorithmic cost of the current setup. */
 mdg_status mdg_query(mdg_solver* s, mdg_info* info);

@@ -117,15 +117,62 @@ void read_state(Solver& s, double* E, double* H, double* P, double* Q, size_t of
   }
 }
 
-void fill_sources(const Solver& s, double t, StageParams& sp) {
-  sp.nsrc = (int)s.dips.size();
-  for (int i = 0; i < MAX_DIPOLES; ++i) {
-    sp.src_elem[i] = -1;
-    sp.src_amp[i] = 0.0;
+// set a device clock (t0, n = 0); synchronous
+void set_clock(Solver& s, size_t off, double t0) {
+  const double c[2] = {t0, 0.0};
+  hip_check(hipMemcpy(dev(s, off), c, sizeof c, hipMemcpyHostToDevice), "clock");
+}
+
+void drop_graph(Solver& s) {
+  if (s.graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(s.graph_exec));
+  if (s.graph) (void)hipGraphDestroy(static_cast<hipGraph_t>(s.graph));
+  s.graph_exec = nullptr;
+  s.graph = nullptr;
+  s.graph_steps = 0;
+}
+
+// enqueue n RK4 steps (4 or 8 stage launches and a clock tick each)
+void enqueue_steps(Solver& s, int64_t nsteps, void* stream) {
+  static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
+  const DevLayout& L = s.L;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    for (int i = 0; i < 4; ++i) {
+      StageParams sp{};
+      sp.stage = i;
+      sp.bcoef = bw[i];
+      sp.cdt = i < 3 ? cn[i + 1] * s.dt : 0.0;
+      sp.dt = s.dt;
+      sp.cstage = cn[i];
+      sp.clock = reinterpret_cast<const double*>(dev(s, L.clock));
+      // stage inputs: Y -> Ua -> Ub -> Ua, final update in place into Y
+      const size_t in = i == 0 ? L.Y : (i == 2 ? L.Ub : L.Ua);
+      const size_t outb = i == 1 ? L.Ub : L.Ua;
+      const size_t ain = i == 0 ? L.aY : (i == 2 ? L.aUb : L.aUa);
+      const size_t aout = i == 1 ? L.aUb : L.aUa;
+      sp.Y = dev(s, L.Y);
+      sp.Uin = dev(s, in);
+      sp.Uout = dev(s, outb);
+      sp.ACC = dev(s, L.ACC);
+      sp.aY = dev(s, L.aY);
+      sp.aUin = dev(s, ain);
+      sp.aUout = dev(s, aout);
+      sp.aACC = dev(s, L.aACC);
+      // halo traces of the stage input in, of the stage output out; after
+      // the last stage H0 again holds the traces of Y
+      sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
+      sp.hout = dev(s, (i & 1) ? L.H0 : L.H1);
+      sp.publish = true;
+      launch_stage(s, sp, stream);
+    }
+    launch_tick(s, stream);
   }
-  for (int i = 0; i < sp.nsrc; ++i) {
-    sp.src_elem[i] = s.iperm[s.dips[i].elem];
-    sp.src_amp[i] = dipole_amplitude(s.dips[i], t);
+}
+
+void publish_if_needed(Solver& s, void* stream) {
+  if (!s.halo_valid) {
+    launch_publish(s, dev(s, s.L.Y), dev(s, s.L.H0), stream);
+    s.halo_valid = true;
   }
 }
 
@@ -142,6 +189,8 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
   if (o->precision != MDG_FP64 && o->precision != MDG_FP32) { g_create_error = "bad precision"; return MDG_E_ARG; }
   if (o->flux != MDG_CENTRAL && o->flux != MDG_UPWIND) { g_create_error = "bad flux"; return MDG_E_ARG; }
   if (o->integrator != MDG_RK4) { g_create_error = "only MDG_RK4 is available"; return MDG_E_UNSUPPORTED; }
+  if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_create_error = "tile must be 0, 32 or 64"; return MDG_E_ARG; }
+  if (o->reserved != 0) { g_create_error = "reserved must be 0"; return MDG_E_ARG; }
   if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
   mdg_solver* h = new (std::nothrow) mdg_solver();
   if (!h) return MDG_E_OOM;
@@ -155,6 +204,7 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
 
 void mdg_destroy(mdg_solver* h) {
   if (!h) return;
+  drop_graph(h->s);
   if (h->s.ws_owned && h->s.ws) (void)hipFree(h->s.ws);
   delete h;
 }
@@ -177,7 +227,20 @@ mdg_status mdg_set_pml(mdg_solver* h, const double* omega) {
 }
 
 mdg_status mdg_set_dipoles(mdg_solver* h, int32_t n, const double* pos, const double* dir, const double* wave) {
-  return guarded(h, [&](Solver& s) { need_mesh(s); setup_dipoles(s, n, pos, dir, wave); });
+  return guarded(h, [&](Solver& s) { need_mesh(s); setup_dipoles(s, n, nullptr, pos, dir, wave); });
+}
+
+mdg_status mdg_set_instances(mdg_solver* h, int32_t n, const int64_t* first) {
+  return guarded(h, [&](Solver& s) { need_mesh(s); setup_instances(s, n, first); });
+}
+
+mdg_status mdg_set_instance_dipoles(mdg_solver* h, int32_t n, const int32_t* inst, const double* pos,
+                                    const double* dir, const double* wave) {
+  return guarded(h, [&](Solver& s) {
+    need_mesh(s);
+    if (n > 0 && !inst) throw Error(MDG_E_ARG, "set_instance_dipoles: NULL inst");
+    setup_dipoles(s, n, inst, pos, dir, wave);
+  });
 }
 
 mdg_status mdg_workspace_size(mdg_solver* h, size_t* bytes) {
@@ -201,6 +264,7 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
         throw Error(MDG_E_UNSUPPORTED, "face-trace exchange needs " + std::to_string(stage_lds_bytes(s)) +
                                            " B of LDS, the device allows " + std::to_string(lds_max));
     }
+    drop_graph(s);
     if (s.ws_owned && s.ws) {
       hip_check(hipFree(s.ws), "hipFree");
       s.ws = nullptr;
@@ -228,13 +292,27 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
     hip_check(hipStreamSynchronize(st), "sync");
     if (s.Kp > 0) upload(s, s.pmlrec, s.L.pml, st);
     if (!s.dips.empty()) {
-      std::vector<double> src(size_t(MAX_DIPOLES) * 3 * s.N, 0.0);
-      for (size_t i = 0; i < s.dips.size(); ++i)
+      // load vectors, waveforms, and for every element the chain of dipoles on it
+      const size_t nd = s.dips.size();
+      std::vector<double> src(nd * 3 * s.N, 0.0), wave(nd * 3);
+      std::vector<int32_t> first(s.Kpad, -1), next(nd, -1);
+      for (size_t i = nd; i-- > 0;) {
         std::copy(s.dips[i].coef.begin(), s.dips[i].coef.end(), src.begin() + i * 3 * s.N);
+        for (int c = 0; c < 3; ++c) wave[3 * i + c] = s.dips[i].wave[c];
+        const int64_t k = s.iperm[s.dips[i].elem];
+        next[i] = first[k];
+        first[k] = (int32_t)i;
+      }
       upload(s, src, s.L.src, st);
+      hip_check(hipMemcpyAsync(dev(s, s.L.srcwave), wave.data(), wave.size() * 8, hipMemcpyHostToDevice, st), "src");
+      hip_check(hipMemcpyAsync(dev(s, s.L.srcid), first.data(), first.size() * 4, hipMemcpyHostToDevice, st), "src");
+      hip_check(hipMemcpyAsync(dev(s, s.L.srcnext), next.data(), next.size() * 4, hipMemcpyHostToDevice, st), "src");
+      hip_check(hipStreamSynchronize(st), "sync");
     }
     s.dt = s.opt.dt > 0 ? s.opt.dt : cfl_dt(s);
-    s.t = 0.0;
+    s.t0 = 0.0;
+    s.nstep = 0;
+    set_clock(s, s.L.clock, 0.0);
     s.halo_valid = true;  // zero state, zero traces
     s.bound = true;
   });
@@ -247,7 +325,9 @@ mdg_status mdg_set_state(mdg_solver* h, const double* E, const double* H, const 
     if (!E || !H) throw Error(MDG_E_ARG, "E and H are required");
     write_state(s, E, H, P, Q, s.L.Y, s.L.aY);
     s.halo_valid = false;
-    s.t = t;
+    s.t0 = t;
+    s.nstep = 0;
+    set_clock(s, s.L.clock, t);
   });
 }
 
@@ -255,7 +335,7 @@ mdg_status mdg_get_state(mdg_solver* h, double* E, double* H, double* P, double*
   return guarded(h, [&](Solver& s) {
     need_bound(s);
     read_state(s, E, H, P, Q, s.L.Y, s.L.aY);
-    if (t) *t = s.t;
+    if (t) *t = s.time();
   });
 }
 
@@ -278,7 +358,9 @@ mdg_status mdg_project(mdg_solver* h, int32_t q, const double* Ev, const double*
     if (Hv) project_fields(s, q, Hv, ch); else ch.assign(n, 0.0);
     write_state(s, ce.data(), ch.data(), nullptr, nullptr, s.L.Y, s.L.aY);
     s.halo_valid = false;
-    s.t = t;
+    s.t0 = t;
+    s.nstep = 0;
+    set_clock(s, s.L.clock, t);
   });
 }
 
@@ -286,43 +368,51 @@ mdg_status mdg_step(mdg_solver* h, int64_t nsteps, void* stream) {
   return guarded(h, [&](Solver& s) {
     need_bound(s);
     if (nsteps < 0) throw Error(MDG_E_ARG, "nsteps < 0");
-    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
-    const DevLayout& L = s.L;
-    if (nsteps > 0 && !s.halo_valid) {
-      launch_publish(s, dev(s, L.Y), dev(s, L.H0), stream);
-      s.halo_valid = true;
-    }
-    for (int64_t n = 0; n < nsteps; ++n) {
-      for (int i = 0; i < 4; ++i) {
-        StageParams sp{};
-        sp.stage = i;
-        sp.bcoef = bw[i];
-        sp.cdt = i < 3 ? cn[i + 1] * s.dt : 0.0;
-        sp.dt = s.dt;
-        fill_sources(s, s.t + cn[i] * s.dt, sp);
-        // stage inputs: Y -> Ua -> Ub -> Ua, final update in place into Y
-        const size_t in = i == 0 ? L.Y : (i == 2 ? L.Ub : L.Ua);
-        const size_t outb = i == 1 ? L.Ub : L.Ua;
-        const size_t ain = i == 0 ? L.aY : (i == 2 ? L.aUb : L.aUa);
-        const size_t aout = i == 1 ? L.aUb : L.aUa;
-        sp.Y = dev(s, L.Y);
-        sp.Uin = dev(s, in);
-        sp.Uout = dev(s, outb);
-        sp.ACC = dev(s, L.ACC);
-        sp.aY = dev(s, L.aY);
-        sp.aUin = dev(s, ain);
-        sp.aUout = dev(s, aout);
-        sp.aACC = dev(s, L.aACC);
-        // halo traces of the stage input in, of the stage output out; after
-        // the last stage H0 again holds the traces of Y
-        sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
-        sp.hout = dev(s, (i & 1) ? L.H0 : L.H1);
-        sp.publish = true;
-        launch_stage(s, sp, stream);
+    if (nsteps == 0) return;
+    publish_if_needed(s, stream);
+    enqueue_steps(s, nsteps, stream);
+    s.nstep += nsteps;
+  });
+}
+
+mdg_status mdg_step_graph(mdg_solver* h, int64_t nsteps, int32_t steps_per_graph, void* stream) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (nsteps < 0 || steps_per_graph < 1) throw Error(MDG_E_ARG, "nsteps >= 0 and steps_per_graph >= 1");
+    if (!stream) throw Error(MDG_E_ARG, "step_graph: graph capture needs a non-default stream");
+    if (nsteps == 0) return;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    publish_if_needed(s, stream);
+    if (s.graph_exec && s.graph_steps != steps_per_graph) drop_graph(s);
+    if (!s.graph_exec && nsteps >= steps_per_graph) {
+      hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      try {
+        enqueue_steps(s, steps_per_graph, stream);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
       }
-      s.t += s.dt;
+      hipGraph_t g = nullptr;
+      hip_check(hipStreamEndCapture(st, &g), "hipStreamEndCapture");
+      hipGraphExec_t ge = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        hip_check(e, "hipGraphInstantiate");
+      }
+      s.graph = g;
+      s.graph_exec = ge;
+      s.graph_steps = steps_per_graph;
     }
+    int64_t left = nsteps;
+    while (s.graph_exec && left >= s.graph_steps) {
+      hip_check(hipGraphLaunch(static_cast<hipGraphExec_t>(s.graph_exec), st), "hipGraphLaunch");
+      left -= s.graph_steps;
+    }
+    if (left > 0) enqueue_steps(s, left, stream);
+    s.nstep += nsteps;
   });
 }
 
@@ -336,7 +426,9 @@ mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double
     StageParams sp{};
     sp.stage = -1;
     sp.dt = s.dt;
-    fill_sources(s, t, sp);
+    sp.cstage = 0.0;
+    set_clock(s, L.rhs_clock, t);
+    sp.clock = reinterpret_cast<const double*>(dev(s, L.rhs_clock));
     sp.Y = dev(s, L.Y);
     sp.Uin = dev(s, L.Ua);
     sp.Uout = dev(s, L.Ub);
@@ -366,6 +458,24 @@ mdg_status mdg_energy(mdg_solver* h, double* W) {
   });
 }
 
+mdg_status mdg_energy_instances(mdg_solver* h, double* W) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (!W) throw Error(MDG_E_ARG, "NULL W");
+    hip_check(hipDeviceSynchronize(), "synchronize");
+    launch_energy(s, dev(s, s.L.Y), nullptr);
+    std::vector<double> e(s.K);
+    hip_check(hipMemcpy(e.data(), dev(s, s.L.eelem), s.K * sizeof(double), hipMemcpyDeviceToHost), "energy copy");
+    const int ni = (int)s.inst_first.size() - 1;
+    for (int i = 0; i < ni; ++i) {
+      double w = 0.0;
+      for (int64_t k = s.inst_first[i]; k < s.inst_first[i + 1]; ++k) w += e[s.iperm[k]];
+      if (!std::isfinite(w)) throw Error(MDG_E_UNSTABLE, "energy is not finite");
+      W[i] = w;
+    }
+  });
+}
+
 mdg_status mdg_query(mdg_solver* h, mdg_info* info) {
   return guarded(h, [&](Solver& s) {
     if (!info) throw Error(MDG_E_ARG, "NULL info");
@@ -385,7 +495,9 @@ mdg_status mdg_query(mdg_solver* h, mdg_info* info) {
     info->n_tiles = s.ntiles;
     info->n_halo = s.nhalo;
     info->dt = s.bound ? s.dt : (s.opt.dt > 0 ? s.opt.dt : cfl_dt(s));
-    info->time = s.t;
+    info->time = s.time();
+    info->n_instances = (int64_t)s.inst_first.size() - 1;
+    info->n_dipoles = (int64_t)s.dips.size();
     info->bytes_per_stage = bytes_per_stage(s);
     info->flops_per_stage = flops_per_stage(s);
     info->workspace_bytes = (int64_t)s.L.total;

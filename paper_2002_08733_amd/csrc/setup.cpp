@@ -117,9 +117,12 @@ void setup_mesh(Solver& s, int64_t nv, const double* xyz, int64_t nt, const int6
   s.mu.assign(nt, 1.0);
   s.omega.clear();
   s.dips.clear();
+  s.inst_first = {0, nt};
+  s.inst_of.assign(nt, 0);
   s.finalized = false;
   s.bound = false;
-  s.t = 0.0;
+  s.t0 = 0.0;
+  s.nstep = 0;
 }
 
 void setup_material(Solver& s, const double* eps, const double* mu) {
@@ -149,9 +152,33 @@ void setup_pml(Solver& s, const double* omega) {
   s.bound = false;
 }
 
-void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const double* wave) {
-  if (n < 0 || n > MAX_DIPOLES) throw Error(MDG_E_ARG, "set_dipoles: 0 <= n <= 4");
+void setup_instances(Solver& s, int n, const int64_t* first) {
+  if (n < 1 || !first) throw Error(MDG_E_ARG, "set_instances: n >= 1 and first[n+1] required");
+  if (first[0] != 0 || first[n] != s.nt) throw Error(MDG_E_ARG, "set_instances: first[0] = 0 and first[n] = nt");
+  for (int i = 0; i < n; ++i)
+    if (first[i + 1] <= first[i]) throw Error(MDG_E_ARG, "set_instances: empty or decreasing range");
+  std::vector<int32_t> of(s.nt);
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = first[i]; k < first[i + 1]; ++k) of[k] = i;
+  for (int64_t k = 0; k < s.nt; ++k)
+    for (int f = 0; f < 4; ++f) {
+      const int64_t sd = s.side[4 * k + f];
+      if (sd >= 0 && of[sd / 4] != of[k])
+        throw Error(MDG_E_MESH, "set_instances: a face joins instances " + std::to_string(of[k]) + " and " +
+                                    std::to_string(of[sd / 4]));
+    }
+  s.inst_first.assign(first, first + n + 1);
+  s.inst_of.swap(of);
+  s.dips.clear();
+  s.finalized = false;
+  s.bound = false;
+}
+
+void setup_dipoles(Solver& s, int n, const int32_t* inst, const double* pos, const double* dir,
+                   const double* wave) {
+  if (n < 0) throw Error(MDG_E_ARG, "set_dipoles: n >= 0");
   if (n > 0 && (!pos || !dir || !wave)) throw Error(MDG_E_ARG, "set_dipoles: NULL array");
+  const int ninst = (int)s.inst_first.size() - 1;
   std::vector<Dipole> out;
   std::vector<double> val(s.N);
   for (int d = 0; d < n; ++d) {
@@ -162,9 +189,13 @@ void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const
       dp.wave[c] = wave[3 * d + c];
     }
     if (!(dp.wave[1] > 0)) throw Error(MDG_E_ARG, "set_dipoles: bandwidth must be > 0");
+    dp.inst = inst ? inst[d] : -1;
+    if (dp.inst < -1 || dp.inst >= ninst) throw Error(MDG_E_ARG, "set_dipoles: instance out of range");
+    const int64_t k0 = dp.inst < 0 ? 0 : s.inst_first[dp.inst];
+    const int64_t k1 = dp.inst < 0 ? s.nt : s.inst_first[dp.inst + 1];
     dp.elem = -1;
     double rh[3] = {0, 0, 0};
-    for (int64_t k = 0; k < s.nt && dp.elem < 0; ++k) {
+    for (int64_t k = k0; k < k1 && dp.elem < 0; ++k) {
       const double* x0 = &s.xyz[3 * s.tet[4 * k]];
       const double* Ai = &s.Ainv[9 * k];
       double r[3];
@@ -177,7 +208,7 @@ void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const
         std::memcpy(rh, r, sizeof rh);
       }
     }
-    if (dp.elem < 0) throw Error(MDG_E_ARG, "set_dipoles: point outside the mesh");
+    if (dp.elem < 0) throw Error(MDG_E_ARG, "set_dipoles: point outside the mesh (or its instance)");
     dubiner3<double>(s.P, rh[0], rh[1], rh[2], val.data(), nullptr);
     const double* Ai = &s.Ainv[9 * dp.elem];
     double ad[3];
@@ -190,13 +221,6 @@ void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const
   s.dips = out;
   s.finalized = false;
   s.bound = false;
-}
-
-double dipole_amplitude(const Dipole& d, double t) {
-  const double pi = 3.14159265358979323846;
-  const double sg = 1.0 / (2.0 * pi * d.wave[1]);
-  const double tau = t - d.wave[2];
-  return std::sin(2.0 * pi * d.wave[0] * tau) * std::exp(-tau * tau / (2.0 * sg * sg));
 }
 
 size_t stage_lds_bytes(const Solver& s) {
@@ -259,8 +283,11 @@ void finalize(Solver& s) {
   }
   s.perm.resize(nt);
   std::iota(s.perm.begin(), s.perm.end(), 0);
+  // non-PML elements, then PML elements; inside each, instance by instance,
+  // each along its Morton curve
   std::stable_sort(s.perm.begin(), s.perm.end(), [&](int64_t a, int64_t b) {
     if (ispml[a] != ispml[b]) return ispml[a] < ispml[b];
+    if (s.inst_of[a] != s.inst_of[b]) return s.inst_of[a] < s.inst_of[b];
     return key[a] < key[b];
   });
   s.iperm.resize(nt);
@@ -274,14 +301,8 @@ void finalize(Solver& s) {
   const bool fp32 = s.opt.precision == MDG_FP32;
   const size_t rs = s.real_size();
   int tile0 = tile_size_for(s.P, fp32);
-  bool forced = false;
-  if (const char* e = std::getenv("MDG_TILE")) {  // tuning override: 32 or 64
-    const int v = std::atoi(e);
-    if (v == 32 || v == 64) {
-      tile0 = v;
-      forced = true;
-    }
-  }
+  const bool forced = s.opt.tile != 0;  // a caller's choice (e.g. an autotuner)
+  if (forced) tile0 = s.opt.tile;
   for (int tile = tile0;; tile /= 2) {
     s.tile = tile;
     // padded by a full tile: lanes past the end of a partial tile load freely
@@ -438,7 +459,14 @@ void finalize(Solver& s) {
   L.H0 = off; off = align256(off + size_t(s.hbuf_reals) * rs);
   L.H1 = off; off = align256(off + size_t(s.hbuf_reals) * rs);
   L.pml = off; off = align256(off + (s.Kp > 0 ? size_t(NPML) * s.Kppad * rs : 0));
-  L.src = off; off = align256(off + size_t(MAX_DIPOLES) * 3 * s.N * rs);
+  const size_t ndip = std::max<size_t>(s.dips.size(), 1);
+  L.src = off; off = align256(off + ndip * 3 * s.N * rs);
+  L.srcid = off; off = align256(off + size_t(s.Kpad) * 4);
+  L.srcnext = off; off = align256(off + ndip * 4);
+  L.srcwave = off; off = align256(off + ndip * 3 * 8);
+  L.clock = off; off = align256(off + 2 * 8);
+  L.rhs_clock = off; off = align256(off + 2 * 8);
+  L.eelem = off; off = align256(off + size_t(s.K) * 8);
   const size_t nblk = (s.K + 255) / 256;
   L.epart = off; off = align256(off + nblk * 8);
   L.eout = off; off = align256(off + 8);

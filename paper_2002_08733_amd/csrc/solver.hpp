@@ -30,10 +30,9 @@ enum GeoRow {
 // Per-PML-element record rows.
 enum PmlRow { PM_AT = 0, PM_AIT = 9, PM_OM = 18, NPML = 21 };
 
-constexpr int MAX_DIPOLES = 4;
-
 struct Dipole {
   double pos[3], dir[3], wave[3];  // wave = (f0, bw, t0)
+  int32_t inst;                    // instance searched for the element (-1: whole mesh)
   int64_t elem;                    // user order
   std::vector<double> coef;        // [3][N] covariant load vector phi_l(r0) (A^-1 d)_j
 };
@@ -54,7 +53,10 @@ inline size_t blk_index(int64_t e, int row, int rows_per_block) {
 struct DevLayout {
   size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
   size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
-  size_t geo, nbr, pub, halo_tile, pml, src;
+  size_t geo, nbr, pub, halo_tile, pml;
+  size_t src, srcid, srcnext, srcwave;  // dipoles: coefficients, per-element first dipole, chain, waveforms
+  size_t clock, rhs_clock;              // device time: (t0, n) of the stepping clock and of mdg_rhs
+  size_t eelem;                         // per-element energies (FP64)
   size_t H0, H1;  // halo trace buffers: stage inputs' traces on cross-tile faces (ping-pong)
   size_t epart, eout;
   size_t total;
@@ -73,6 +75,8 @@ struct Solver {
   int64_t n_int = 0, n_bnd = 0;
   std::vector<double> eps, mu, omega;  // omega [nt][3] (empty = no PML)
   std::vector<Dipole> dips;
+  std::vector<int64_t> inst_first;     // instance element ranges (caller order), size ninst + 1
+  std::vector<int32_t> inst_of;        // [nt] instance of each element (caller order)
   // ---- decomposition (valid when finalized)
   bool finalized = false;
   int tile = 0;
@@ -95,7 +99,12 @@ struct Solver {
   bool ws_owned = false;
   bool bound = false;
   DevLayout L{};
-  double t = 0.0, dt = 0.0;
+  double t0 = 0.0, dt = 0.0;  // time of the last set state; the clock counts steps from it
+  int64_t nstep = 0;
+  double time() const { return t0 + double(nstep) * dt; }
+  void* graph_exec = nullptr;  // hipGraphExec_t of graph_steps steps (mdg_step_graph)
+  void* graph = nullptr;       // hipGraph_t
+  int graph_steps = 0;
   size_t real_size() const { return opt.precision == MDG_FP32 ? 4 : 8; }
 };
 
@@ -103,14 +112,15 @@ struct Solver {
 void setup_mesh(Solver& s, int64_t nv, const double* xyz, int64_t nt, const int64_t* tet);
 void setup_material(Solver& s, const double* eps, const double* mu);
 void setup_pml(Solver& s, const double* omega);
-void setup_dipoles(Solver& s, int n, const double* pos, const double* dir, const double* wave);
+void setup_instances(Solver& s, int n, const int64_t* first);
+void setup_dipoles(Solver& s, int n, const int32_t* inst, const double* pos, const double* dir,
+                   const double* wave);
 void finalize(Solver& s);  // ordering, tiles, halo, geometry records, layout
 double cfl_dt(const Solver& s);
 int tile_size_for(int P, bool fp32);
 // dynamic LDS of one stage-kernel workgroup: the face-trace exchange
 size_t stage_lds_bytes(const Solver& s);
 constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
-double dipole_amplitude(const Dipole& d, double t);
 void projection_points(const Solver& s, int q, double* xyz);
 void project_fields(const Solver& s, int q, const double* vals, std::vector<double>& coef);
 // state conversion between the caller's FP64 [nt][3][N] arrays and the
@@ -129,9 +139,8 @@ struct StageParams {
   double bcoef;   // b_i
   double cdt;     // c_{i+1} dt (stages 0..2)
   double dt;
-  int nsrc;
-  int64_t src_elem[MAX_DIPOLES];
-  double src_amp[MAX_DIPOLES];
+  double cstage;  // c_i: the stage's time is clock t0 + (n + c_i) dt
+  const double* clock;
   // state buffers (E and H together, blocked layout)
   void* Y;
   const void* Uin;
@@ -150,5 +159,6 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream);
 // halo traces of state U (blocked layout) into the halo buffer H
 void launch_publish(const Solver& s, const void* U, void* H, void* stream);
 void launch_energy(const Solver& s, const void* Y, void* stream);
+void launch_tick(const Solver& s, void* stream);  // clock n += 1
 
 }  // namespace mdg

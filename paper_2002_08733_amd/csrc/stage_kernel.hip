@@ -70,14 +70,16 @@ struct DevArgs {
   const void* hin;           // halo traces of the stage input
   void* hout;                // halo traces of the stage output
   const void* pml;
-  const void* src;
+  const void* src;            // dipole load vectors [ndip][3][N]
+  const int32_t* srcid;       // blocked [Kpad/64][64]: first dipole acting on the element, or -1
+  const int32_t* srcnext;     // [ndip]: next dipole on the same element, or -1
+  const double* srcwave;      // [ndip][3]: f0, bw, t0
+  const double* clock;        // (t0, n): the stage's time is t0 + (n + cstage) dt
   uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes;
   int64_t pml_base;
-  int32_t tile_begin, ntiles, stage, nsrc, publish;
+  int32_t tile_begin, ntiles, stage, has_src, publish;
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
-  int64_t src_elem[MAX_DIPOLES];
-  double src_amp[MAX_DIPOLES];
-  double bcoef, cdt, dt;
+  double bcoef, cdt, dt, cstage;
 };
 
 // ---- raw buffer access (gfx9 buffer descriptor, bounds-checked by hardware)
@@ -637,20 +639,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // 8. lift of the four faces onto this part's modes
   MDG_SWITCH_Q((lift_all_q<P, Q, R>(lds, role, tile, li, acc)));
 
-  // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j
-  if (role == 0) {
-    const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
-    for (int i = 0; i < a.nsrc; ++i)
-      if ((int64_t)el == a.src_elem[i]) {
-        const R amp = R(a.src_amp[i]);
+  // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j, with the
+  // Gaussian-modulated sinusoid g evaluated in FP64 at the stage's time on the
+  // device clock
+  if (a.has_src && role == 0) {
+    const Rsrc rS = make_rsrc(a.srcid, a.nbr_bytes / 4);
+    int d = bldi(rS, blk_base(el, 1, 4), 0);
+    if (d >= 0) {
+      const double t = a.clock[0] + (a.clock[1] + a.cstage) * a.dt;
+      const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
+      for (; d >= 0; d = a.srcnext[d]) {
+        const double f0 = a.srcwave[3 * d], bw = a.srcwave[3 * d + 1], t0 = a.srcwave[3 * d + 2];
+        const double pi = 3.14159265358979323846, tau = t - t0, sg = 1.0 / (2.0 * pi * bw);
+        const R amp = R(sin(2.0 * pi * f0 * tau) * exp(-tau * tau / (2.0 * sg * sg)));
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
             const int l = part * NQ + q;
-            if (l < N) acc[c][q] = fma(-amp, src[(i * 3 + c) * N + l], acc[c][q]);
+            if (l < N) acc[c][q] = fma(-amp, src[(d * 3 + c) * N + l], acc[c][q]);
           }
       }
+    }
   }
 
   // 10. 3x3 block-diagonal mass inverse: d_t u_l = (1/eps) G0^-1 r_l
@@ -751,7 +761,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 // W = 1/2 sum_T sum_l eps u_l^T M u_l + mu f_l^T M f_l, M = (G0^-1)^-1 = |det A| A^-1 A^-T
 template <typename R, int N>
 __global__ __launch_bounds__(256) void energy_kernel(const R* __restrict__ Y, const R* __restrict__ geo, int64_t K,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, double* __restrict__ eelem) {
   __shared__ double red[4];
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double w = 0.0;
@@ -774,11 +784,17 @@ __global__ __launch_bounds__(256) void energy_kernel(const R* __restrict__ Y, co
         sf[fld] += m00 * x * x + m11 * y * y + m22 * z * z + 2.0 * (m01 * x * y + m02 * x * z + m12 * y * z);
       }
     w = 0.5 * (eps * sf[0] + mu * sf[1]);
+    eelem[k] = w;
   }
   for (int o = 32; o > 0; o >>= 1) w += __shfl_down(w, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// the device clock of a step sequence: n += 1 after the last stage of a step
+__global__ void tick_kernel(double* clock) {
+  if (threadIdx.x == 0) clock[1] = clock[1] + 1.0;
 }
 
 __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ part, int64_t n,
@@ -895,6 +911,11 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.publish = sp.publish && sp.hout != nullptr;
   a.pml = base + s.L.pml;
   a.src = base + s.L.src;
+  a.srcid = reinterpret_cast<const int32_t*>(base + s.L.srcid);
+  a.srcnext = reinterpret_cast<const int32_t*>(base + s.L.srcnext);
+  a.srcwave = reinterpret_cast<const double*>(base + s.L.srcwave);
+  a.clock = sp.clock;
+  a.has_src = s.dips.empty() ? 0 : 1;
   const size_t rs = s.real_size();
   a.state_bytes = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
   a.aux_bytes = (uint32_t)(size_t(6) * s.N * s.Kppad * rs);
@@ -904,11 +925,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
   a.pml_base = s.K0;
   a.stage = sp.stage;
-  a.nsrc = sp.nsrc;
-  for (int i = 0; i < MAX_DIPOLES; ++i) {
-    a.src_elem[i] = sp.src_elem[i];
-    a.src_amp[i] = sp.src_amp[i];
-  }
+  a.cstage = sp.cstage;
   a.bcoef = sp.bcoef;
   a.cdt = sp.cdt;
   a.dt = sp.dt;
@@ -936,16 +953,23 @@ static void launch_energy_r(const Solver& s, const void* Y, hipStream_t st) {
   double* out = reinterpret_cast<double*>(base + s.L.eout);
   const R* geo = reinterpret_cast<const R*>(base + s.L.geo);
   const R* y = static_cast<const R*>(Y);
+  double* ee = reinterpret_cast<double*>(base + s.L.eelem);
   switch (s.P) {
-    case 1: hipLaunchKernelGGL((energy_kernel<R, 4>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
-    case 2: hipLaunchKernelGGL((energy_kernel<R, 10>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
-    case 3: hipLaunchKernelGGL((energy_kernel<R, 20>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
-    case 4: hipLaunchKernelGGL((energy_kernel<R, 35>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part); break;
+    case 1: hipLaunchKernelGGL((energy_kernel<R, 4>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
+    case 2: hipLaunchKernelGGL((energy_kernel<R, 10>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
+    case 3: hipLaunchKernelGGL((energy_kernel<R, 20>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
+    case 4: hipLaunchKernelGGL((energy_kernel<R, 35>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
   hip_check(hipGetLastError(), "energy_kernel launch");
   hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, part, nblk, out);
   hip_check(hipGetLastError(), "energy_final launch");
+}
+
+void launch_tick(const Solver& s, void* stream) {
+  double* clock = reinterpret_cast<double*>(static_cast<char*>(s.ws) + s.L.clock);
+  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), clock);
+  hip_check(hipGetLastError(), "tick_kernel launch");
 }
 
 void launch_energy(const Solver& s, const void* Y, void* stream) {

@@ -33,7 +33,8 @@ class MdgError(RuntimeError):
 
 class mdg_options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("flux", ctypes.c_int32),
-                ("integrator", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double)]
+                ("integrator", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mdg_info(ctypes.Structure):
@@ -44,7 +45,8 @@ class mdg_info(ctypes.Structure):
                 ("n_tiles", ctypes.c_int64), ("n_halo", ctypes.c_int64),
                 ("dt", ctypes.c_double), ("time", ctypes.c_double),
                 ("bytes_per_stage", ctypes.c_double), ("flops_per_stage", ctypes.c_double),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("n_instances", ctypes.c_int64),
+                ("n_dipoles", ctypes.c_int64)]
 
 
 _lib = None
@@ -61,6 +63,8 @@ SIGNATURES = {
     "mdg_set_material": (_S, [_VP, _D, _D]),
     "mdg_set_pml": (_S, [_VP, _D]),
     "mdg_set_dipoles": (_S, [_VP, ctypes.c_int32, _D, _D, _D]),
+    "mdg_set_instances": (_S, [_VP, ctypes.c_int32, _I64]),
+    "mdg_set_instance_dipoles": (_S, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _D, _D, _D]),
     "mdg_workspace_size": (_S, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
     "mdg_bind_workspace": (_S, [_VP, _VP, ctypes.c_size_t, _VP]),
     "mdg_set_state": (_S, [_VP, _D, _D, _D, _D, ctypes.c_double]),
@@ -68,8 +72,10 @@ SIGNATURES = {
     "mdg_projection_points": (_S, [_VP, ctypes.c_int32, _I64, _D]),
     "mdg_project": (_S, [_VP, ctypes.c_int32, _D, _D, ctypes.c_double]),
     "mdg_step": (_S, [_VP, ctypes.c_int64, _VP]),
+    "mdg_step_graph": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, _VP]),
     "mdg_rhs": (_S, [_VP, _D, _D, _D, _D, ctypes.c_double, _D, _D, _D, _D]),
     "mdg_energy": (_S, [_VP, _D]),
+    "mdg_energy_instances": (_S, [_VP, _D]),
     "mdg_query": (_S, [_VP, ctypes.POINTER(mdg_info)]),
 }
 
@@ -115,11 +121,11 @@ def _f64(a, shape=None):
 class Solver:
     """One libmdg handle. Methods mirror the C entry points one to one."""
 
-    def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3):
+    def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3, tile=0):
         self.lib = load_library()
         o = mdg_options(order=order, precision=MDG_FP32 if precision == "fp32" else MDG_FP64,
                         flux=MDG_UPWIND if flux == "upwind" else MDG_CENTRAL,
-                        integrator=MDG_RK4, dt=float(dt), cfl=float(cfl))
+                        integrator=MDG_RK4, dt=float(dt), cfl=float(cfl), tile=int(tile), reserved=0)
         h = _VP()
         st = self.lib.mdg_create(ctypes.byref(o), ctypes.byref(h))
         if st != MDG_OK:
@@ -165,10 +171,20 @@ class Solver:
         w = _f64(omega)
         self._chk(self.lib.mdg_set_pml(self.h, _dptr(w)))
 
-    def set_dipoles(self, pos, direction, wave):
+    def set_dipoles(self, pos, direction, wave, instance=None):
         p, d, w = _f64(pos), _f64(direction), _f64(wave)
         n = 0 if p is None else p.reshape(-1, 3).shape[0]
-        self._chk(self.lib.mdg_set_dipoles(self.h, n, _dptr(p), _dptr(d), _dptr(w)))
+        if instance is None:
+            self._chk(self.lib.mdg_set_dipoles(self.h, n, _dptr(p), _dptr(d), _dptr(w)))
+        else:
+            ins = np.ascontiguousarray(instance, dtype=np.int32)
+            self._chk(self.lib.mdg_set_instance_dipoles(
+                self.h, n, ins.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(p), _dptr(d), _dptr(w)))
+
+    def set_instances(self, first):
+        """Element ranges [first[i], first[i+1]) of independent instances."""
+        f = np.ascontiguousarray(first, dtype=np.int64)
+        self._chk(self.lib.mdg_set_instances(self.h, len(f) - 1, f.ctypes.data_as(_I64)))
 
     def workspace_size(self):
         n = ctypes.c_size_t()
@@ -222,6 +238,9 @@ class Solver:
     def step(self, nsteps=1, stream=None):
         self._chk(self.lib.mdg_step(self.h, int(nsteps), stream))
 
+    def step_graph(self, nsteps, steps_per_graph, stream):
+        self._chk(self.lib.mdg_step_graph(self.h, int(nsteps), int(steps_per_graph), stream))
+
     def rhs(self, E, H, P=None, Q=None, t=0.0, aux=False):
         s = self._shape()
         E, H, P, Q = (_f64(x, s) for x in (E, H, P, Q))
@@ -236,6 +255,12 @@ class Solver:
         w = ctypes.c_double()
         self._chk(self.lib.mdg_energy(self.h, ctypes.byref(w)))
         return w.value
+
+    def energy_instances(self):
+        n = self.query()["n_instances"]
+        w = np.empty(n)
+        self._chk(self.lib.mdg_energy_instances(self.h, _dptr(w)))
+        return w
 
     def query(self):
         i = mdg_info()

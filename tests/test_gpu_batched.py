@@ -1,0 +1,167 @@
+"""GPU tests of the batched path: independent instances advanced by the same
+launches, HIP-graph replay of the step sequence, and the tile autotuner.
+
+* A batch of instances reproduces each instance run on its own (same dt,
+  same dipole), state and per-instance energy, to rounding.
+* One instance of a batch against the FP64 oracle (dipole-driven from zero).
+* Graph replay against eager stepping, replayed several times with eager
+  work and synchronisations in between; every replay is checked.
+* The autotuner returns one of its candidates, with a timing for each.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import oracle_dipoles, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_08733_amd import load_library
+    load_library()
+
+
+def _wave(d):
+    f0, bw = d[2]
+    return [f0, bw, 5.0 / (2.0 * np.pi * bw)]
+
+
+def _batch_solver(w, precision, dt, tile=0):
+    from paper_2002_08733_amd import Solver
+    s = Solver(w.p, precision, w.flux, dt=dt, tile=tile)
+    s.set_mesh(w.verts, w.tets)
+    s.set_instances(w.info["first"])
+    s.set_material(w.eps, w.mu)
+    s.set_dipoles(np.array([d[0] for d in w.dipoles]), np.array([d[1] for d in w.dipoles]),
+                  np.array([_wave(d) for d in w.dipoles]), instance=[d[3] for d in w.dipoles])
+    s.bind_torch_workspace()
+    return s
+
+
+def _instance(w, i):
+    """Mesh, material and dipole of instance i as a stand-alone problem."""
+    first = w.info["first"]
+    tets = w.tets[first[i]:first[i + 1]]
+    used = np.unique(tets)
+    remap = np.full(w.verts.shape[0], -1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return w.verts[used], remap[tets], w.eps[first[i]:first[i + 1]], w.mu[first[i]:first[i + 1]], w.dipoles[i]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_matches_individual_runs(precision):
+    from paper_2002_08733_amd import Solver
+    w = W.batched(4, 3, seed=22, nmin=2, nmax=5)  # sizes 5, 3, 4, 2
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+    say(f"[batched] {precision}: 4 instances, sizes {list(w.info['sizes'])}, K={w.nt}, dt={dt:.3e}, 30 steps")
+    s = _batch_solver(w, precision, dt)
+    s.step(30)
+    E, H, t = s.get_state()
+    Wb = s.energy_instances()
+    s.close()
+    first = w.info["first"]
+    worst = 0.0
+    for i in range(4):
+        v, tt, eps, mu, d = _instance(w, i)
+        r = Solver(3, precision, "upwind", dt=dt)
+        r.set_mesh(v, tt)
+        r.set_material(eps, mu)
+        r.set_dipoles(np.array([d[0]]), np.array([d[1]]), np.array([_wave(d)]))
+        r.bind_torch_workspace()
+        r.step(30)
+        Ei, Hi, ti = r.get_state()
+        Wi = r.energy()
+        r.close()
+        sl = slice(first[i], first[i + 1])
+        scale = max(np.abs(Ei).max(), np.abs(Hi).max())
+        d_state = max(np.abs(E[sl] - Ei).max(), np.abs(H[sl] - Hi).max()) / scale
+        d_energy = abs(Wb[i] - Wi) / Wi
+        worst = max(worst, d_state)
+        say(f"  instance {i}: state diff {d_state:.2e}, energy {Wb[i]:.6e} vs {Wi:.6e}")
+        assert abs(t - ti) < 1e-15
+        assert d_energy < (1e-12 if precision == "fp64" else 1e-5)
+    assert worst < (1e-13 if precision == "fp64" else 1e-5)
+
+
+def test_batch_instance_against_oracle():
+    from oracle import OracleDG
+    from tests.gpu_helpers import rel_energy_err
+    w = W.batched(3, 3, seed=17, nmin=2, nmax=4)
+    dt = 2e-3
+    steps = 12
+    say(f"[batched vs oracle] sizes {list(w.info['sizes'])}, fp64, dipole-driven, {steps} steps")
+    s = _batch_solver(w, "fp64", dt)
+    s.step(steps)
+    E, H, _ = s.get_state()
+    s.close()
+    first = w.info["first"]
+    for i in (0, 2):
+        v, tt, eps, mu, d = _instance(w, i)
+        O = OracleDG(v, tt, 3, eps=eps, mu=mu, flux="upwind", dipoles=oracle_dipoles([d[:3]]))
+        z = np.zeros((tt.shape[0], 3, O.N))
+        (cE, cH, _, _), _ = O.run(z, z.copy(), t0=0.0, dt=dt, nsteps=steps)
+        sl = slice(first[i], first[i + 1])
+        err = rel_energy_err(O, O.to_cartesian(E[sl]), O.to_cartesian(H[sl]), cE, cH)
+        say(f"  instance {i}: rel err {err:.3e}")
+        assert err < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_graph_replay_matches_eager(precision):
+    import torch
+    w = W.batched(3, 3, seed=19, nmin=3, nmax=6)
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+    rng = np.random.default_rng(3)
+    shp = (w.nt, 3, 20)
+    E0, H0 = rng.standard_normal(shp), rng.standard_normal(shp)
+    stream = torch.cuda.Stream()  # default priority
+    sp = stream.cuda_stream
+    g = _batch_solver(w, precision, dt)
+    e = _batch_solver(w, precision, dt)
+    for s in (g, e):
+        s.set_state(E0, H0, t=0.25)
+    say(f"[graph] {precision}: K={w.nt}, graph of 4 steps replayed with eager work in between")
+    # 10 steps: two replays and two eager steps; then more replays with
+    # eager steps, state reads and energy reductions in between
+    plan = [10, 4, 3, 8, 1, 4]
+    for k, n in enumerate(plan):
+        with torch.cuda.stream(stream):
+            g.step_graph(n, 4, sp)
+            e.step(n, sp)
+        stream.synchronize()
+        Eg, Hg, tg = g.get_state()
+        Ee, He, te = e.get_state()
+        assert tg == te
+        same = np.array_equal(Eg, Ee) and np.array_equal(Hg, He)
+        say(f"  after {sum(plan[:k + 1])} steps: identical={same}, W={g.energy():.6e}")
+        assert same
+        if k == 2:  # an eager step on the graph's solver between replays
+            g.step(1, sp)
+            e.step(1, sp)
+            torch.cuda.synchronize()
+    g.close()
+    e.close()
+
+
+def test_autotune_tile_returns_a_candidate():
+    from paper_2002_08733_amd import Solver
+    from paper_2002_08733_amd.autotune import autotune_tile
+    w = W.jittered(10, 3, seed=5, flux="upwind")
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+
+    def make(tile):
+        s = Solver(3, "fp32", "upwind", dt=dt, tile=tile)
+        s.set_mesh(w.verts, w.tets)
+        s.set_material(w.eps, w.mu)
+        s.bind_torch_workspace()
+        return s
+
+    best, times = autotune_tile(make, candidates=(32, 64), steps=5, warmup=2)
+    say(f"[autotune] K={w.nt}: {times} -> tile {best}")
+    assert best in (32, 64) and set(times) == {32, 64}
+    assert all(v > 0 for v in times.values())

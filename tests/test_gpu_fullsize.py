@@ -88,9 +88,9 @@ def test_fullsize_open_pml_rhs_sampled(precision, tol):
     say(f"  rel err {err:.3e}")
     assert err < tol
 
-def _run_steps(w, precision, steps, dt):
+def _run_steps(w, precision, steps, dt, tile=0):
     from paper_2002_08733_amd import Solver
-    s = Solver(w.p, precision, w.flux, dt=dt)
+    s = Solver(w.p, precision, w.flux, dt=dt, tile=tile)
     s.set_mesh(w.verts, w.tets)
     s.set_material(w.eps, w.mu)
     s.bind_torch_workspace()
@@ -117,17 +117,15 @@ def test_fullsize_fp32_vs_fp64_1000_steps():
     assert np.isfinite(err) and err < 1e-5
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_tile_size_independence(precision, monkeypatch):
+def test_tile_size_independence(precision):
     w = W.jittered(12, 3, seed=7, flux="upwind")
     dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
     out = {}
-    for tile in ("32", "64"):
-        monkeypatch.setenv("MDG_TILE", tile)
-        s, E, H = _run_steps(w, precision, 5, dt)
+    for tile in (32, 64):
+        s, E, H = _run_steps(w, precision, 5, dt, tile=tile)
         out[tile] = (E, H, s.query()["tile_size"], s.query()["n_halo"])
         s.close()
-    monkeypatch.delenv("MDG_TILE")
-    (E1, H1, t1, h1), (E2, H2, t2, h2) = out["32"], out["64"]
+    (E1, H1, t1, h1), (E2, H2, t2, h2) = out[32], out[64]
     say(f"[tiles] {precision} K={w.nt}: tile {t1} ({h1} halo faces) vs tile {t2} ({h2} halo faces)")
     assert t1 == 32 and t2 == 64 and h1 != h2
     scale = max(np.abs(E2).max(), np.abs(H2).max())

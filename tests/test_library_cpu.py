@@ -178,3 +178,56 @@ def test_generated_reference_operators(lib, p):
         Tref = np.einsum("q,mq,ql->ml", sw, ps, ph)
         np.testing.assert_allclose(Tg[f], Tref, atol=1e-12 * max(1, np.abs(Tref).max()))
         assert np.all((Tg[f] == 0) == (np.abs(Tref) < 1e-10))
+
+
+def test_instances_host_side(lib):
+    w = W.batched(3, 2, seed=11, nmin=2, nmax=4)
+    first = w.info["first"]
+    s = lib.Solver(2, "fp32", "upwind", tile=32)
+    s.set_mesh(w.verts, w.tets)
+    s.set_instances(first)
+    pos = np.array([d[0] for d in w.dipoles])
+    dr = np.array([d[1] for d in w.dipoles])
+    wave = np.array([[2.0, 1.0, 5.0 / (2 * np.pi)]] * len(w.dipoles))
+    s.set_dipoles(pos, dr, wave, instance=[d[3] for d in w.dipoles])
+    assert s.workspace_size() > 0
+    q = s.query()
+    assert q["n_instances"] == 3 and q["n_dipoles"] == 3 and q["tile_size"] == 32
+    # the instances' elements stay together: no halo face can join two of
+    # them, and the face count is the sum of the instances'
+    nb = sum(12 * int(n) ** 2 for n in w.info["sizes"])
+    assert q["n_faces_boundary"] == nb
+    # errors
+    with pytest.raises(lib.MdgError) as e:
+        s.set_instances(np.array([1, w.nt]))
+    assert e.value.status == lib.MDG_E_ARG
+    with pytest.raises(lib.MdgError) as e:
+        s.set_instances(np.array([0, w.nt - 1]))
+    assert e.value.status == lib.MDG_E_ARG
+    with pytest.raises(lib.MdgError) as e:
+        s.set_instances(np.array([0, 5, 5, w.nt]))
+    assert e.value.status == lib.MDG_E_ARG
+    with pytest.raises(lib.MdgError) as e:
+        s.set_dipoles(pos[:1], dr[:1], wave[:1], instance=[7])
+    assert e.value.status == lib.MDG_E_ARG
+    # a point of instance 0's region that lies outside instance 2's box cannot be found there
+    with pytest.raises(lib.MdgError) as e:
+        s.set_dipoles(np.array([[5.0, 5.0, 5.0]]), dr[:1], wave[:1], instance=[2])
+    assert e.value.status == lib.MDG_E_ARG
+    s.close()
+
+
+def test_instances_must_not_share_faces(lib):
+    v, t = W.kuhn_cube_mesh(2, 0.0, 1.0)
+    s = lib.Solver(1)
+    s.set_mesh(v, t)
+    with pytest.raises(lib.MdgError) as e:
+        s.set_instances(np.array([0, 24, 48]))
+    assert e.value.status == lib.MDG_E_MESH
+    s.close()
+
+
+def test_tile_option_is_validated(lib):
+    with pytest.raises(lib.MdgError) as e:
+        lib.Solver(2, tile=48)
+    assert e.value.status == lib.MDG_E_ARG

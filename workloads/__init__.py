@@ -187,6 +187,37 @@ def jittered(n=32, p=3, seed=2, flux="upwind", amount=0.1):
                     box=(-1.0, 1.0), steps=1000)
 
 
+def batched(n_inst=64, p=3, seed=4, nmin=8, nmax=24, flux="upwind", amount=0.1):
+    """Independent instances for one batched solver. Instance i: [-1,1]^3 with
+    n_i^3 Kuhn cubes, n_i ~ U{nmin..nmax}, interior jitter U(-0.1h, 0.1h), its
+    own eps ~ U[1,4], mu = 1, and a z-directed dipole (f0 = 2, bw = 1) at a
+    point ~ U([-0.5,0.5]^3). The meshes are concatenated with offset vertex
+    ids; info["first"] holds the element range of every instance and each
+    dipole carries its instance index as a fourth entry. rng order per
+    instance: size (drawn first for all), jitter, eps, dipole point."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(nmin, nmax + 1, size=n_inst)
+    V, T, E, dips, first = [], [], [], [], [0]
+    voff = 0
+    for i, n in enumerate(sizes):
+        n = int(n)
+        verts, tets = kuhn_cube_mesh(n, -1.0, 1.0)
+        verts = jitter_interior(verts, -1.0, 1.0, 2.0 / n, amount, rng)
+        E.append(rng.uniform(1.0, 4.0, size=tets.shape[0]))
+        pos = rng.uniform(-0.5, 0.5, size=3)
+        dips.append((pos, np.array([0.0, 0.0, 1.0]), (2.0, 1.0), i))
+        V.append(verts)
+        T.append(tets + voff)
+        voff += verts.shape[0]
+        first.append(first[-1] + tets.shape[0])
+    verts = np.concatenate(V)
+    tets = np.concatenate(T)
+    eps = np.concatenate(E)
+    return Workload(f"batched_{n_inst}x_p{p}", verts, tets, p, eps, np.ones(tets.shape[0]), flux,
+                    dipoles=dips, box=(-1.0, 1.0), steps=500,
+                    info={"first": np.array(first, dtype=np.int64), "sizes": sizes})
+
+
 def pml_profile(centroids, inner=1.0, thickness=0.2, sigma_max=20.0, power=3):
     """Per-element, per-axis damping w_a = sigma_max (d_a/L)^power at the centroid,
     d_a = max(0, |x_a| - inner), L = thickness. Zero inside the inner box."""
