@@ -143,6 +143,96 @@ def traffic_for(kernel_hash, precision):
     return ent.get("bytes_per_launch")
 
 
+def batched_main(args):
+    """64 independent instances on uneven meshes (n_i^3 cubes x 6, n_i ~ U{8..24},
+    jitter 0.1h, own eps ~ U[1,4], a z-dipole each), p=3, upwind, advanced by
+    one launch per RK stage over all instances, the steps replayed from a HIP
+    graph; tile chosen by the autotuner on this workload."""
+    import torch
+    from paper_2002_08733_amd import Solver
+    from paper_2002_08733_amd.autotune import autotune_tile
+    t0 = time.time()
+    w = W.batched(args.instances, 3, seed=4)
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+    log(f"[bench] batched: {args.instances} instances, K={w.nt}, DOF={w.nt * 120}, dt={dt:.3e} "
+        f"(workload {time.time() - t0:.1f} s)")
+    pos = np.array([d[0] for d in w.dipoles])
+    dr = np.array([d[1] for d in w.dipoles])
+    wave = np.array([[d[2][0], d[2][1], 5.0 / (2.0 * np.pi * d[2][1])] for d in w.dipoles])
+    inst = [d[3] for d in w.dipoles]
+
+    def make(prec, tile):
+        s = Solver(3, prec, "upwind", dt=dt, tile=tile)
+        s.set_mesh(w.verts, w.tets)
+        s.set_instances(w.info["first"])
+        s.set_material(w.eps, w.mu)
+        s.set_dipoles(pos, dr, wave, instance=inst)
+        s.bind_torch_workspace()
+        return s
+
+    out_prec = {}
+    stream = torch.cuda.Stream()
+    sp = stream.cuda_stream
+    for prec in (["fp32"] if args.skip_fp64 else ["fp32", "fp64"]):
+        t1 = time.time()
+        tile, tune = autotune_tile(lambda t: make(prec, t), candidates=(32, 64), steps=5, warmup=2)
+        log(f"[bench] {prec}: autotune {tune} -> tile {tile} ({time.time() - t1:.1f} s)")
+        s = make(prec, tile)
+        info = s.query()
+        with torch.cuda.stream(stream):
+            s.step_graph(args.warmup, args.graph_steps, sp)
+        torch.cuda.synchronize()
+        res = {}
+        for mode in ("graph", "eager"):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            with torch.cuda.stream(stream):
+                if mode == "graph":
+                    s.step_graph(args.steps, args.graph_steps, sp)
+                else:
+                    s.step(args.steps, sp)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[mode] = e0.elapsed_time(e1) / 1000.0
+        Wi = s.energy_instances()
+        sec = res["graph"]
+        stages = 4 * args.steps
+        gdof = w.nt * 120 * stages / sec / 1e9
+        achieved = info["bytes_per_stage"] / (sec / stages) / 1e9
+        out_prec[prec] = {"value": gdof, "ms_per_step": 1000 * sec / args.steps,
+                          "us_per_stage": 1e6 * sec / stages,
+                          "eager_ms_per_step": 1000 * res["eager"] / args.steps,
+                          "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                       "algorithmic_bytes_per_launch": info["bytes_per_stage"]},
+                          "tile": tile, "autotune_us_per_step": tune,
+                          "energy_min": float(Wi.min()), "energy_max": float(Wi.max())}
+        log(f"[bench] {prec}: {gdof:.1f} GDOF/s, {1e6 * sec / stages:.1f} us/stage (graph), "
+            f"eager {1e6 * res['eager'] / stages:.1f} us/stage, {100 * achieved / HBM_PEAK_GBS:.1f}% of HBM")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    m = out_prec["fp32"]
+    out = {
+        "metric": "GDOF-updates/s per RK stage at p=3 (FP32 vs FP64) and % of HBM roofline",
+        "value": m["value"], "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {args.instances} instances, n_i^3 cubes x 6 with n_i ~ U{{8..24}} "
+                               "(seed 4), jitter 0.1h, eps~U[1,4], z-dipole each, p=3, upwind, RK4 CFL 0.3, "
+                               "one launch per stage over all instances, HIP-graph replay",
+                   "elements": w.nt, "dof": w.nt * 120, "instances": args.instances, "dt": dt,
+                   "graph_steps": args.graph_steps},
+        "roofline": m["roofline"], "us_per_stage": m["us_per_stage"], "tile": m["tile"],
+        "eager_ms_per_step": m["eager_ms_per_step"], "autotune_us_per_step": m["autotune_us_per_step"],
+    }
+    if "fp64" in out_prec:
+        out["fp64"] = out_prec["fp64"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +246,10 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "batched"],
+                    help="headline: the jittered 196,608-element cube; batched: many instances in one launch")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--graph-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
@@ -165,6 +259,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        if args.steps == 1000:
+            args.steps = 500
+        batched_main(args)
+        return
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
