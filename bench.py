@@ -233,6 +233,53 @@ def batched_main(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_main(args):
+    """Gradient of a probe energy w.r.t. every element's eps by the checkpointed
+    discrete adjoint: 24^3 cubes x 6 = 82,944 jittered tets, p=3, central
+    flux, eps ~ U[1,4], z-dipole, 8 probe elements (the lowest-index tet
+    containing each (+-1/2, +-1/2, +-1/2)), 2000 RK4 steps, checkpoint every
+    100. Reports forward and forward+adjoint times."""
+    import torch
+    from paper_2002_08733_amd import Solver
+    w = W.jittered(24, 3, seed=5, flux="central")
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+    cen = W.tet_centroids(w.verts, w.tets)
+    probes = []
+    for sx in (-0.5, 0.5):
+        for sy in (-0.5, 0.5):
+            for sz in (-0.5, 0.5):
+                probes.append(int(np.argmin(np.sum((cen - np.array([sx, sy, sz])) ** 2, axis=1))))
+    dip = (np.array([[0.0, 0.0, 0.0]]), np.array([[0.0, 0.0, 1.0]]), np.array([[2.0, 1.0, 5.0 / (2 * np.pi)]]))
+    nsteps, every = args.steps if args.steps != 1000 else 2000, 100
+    out_prec = {}
+    for prec in (["fp64"] if args.skip_fp64 is False else []) + ["fp32"]:
+        s = Solver(3, prec, "central", dt=dt)
+        s.set_mesh(w.verts, w.tets)
+        s.set_material(w.eps, w.mu)
+        s.set_dipoles(*dip)
+        s.bind_torch_workspace()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        s.step(nsteps)
+        torch.cuda.synchronize()
+        t_fwd = time.time() - t0
+        s.set_state(np.zeros((w.nt, 3, 20)), np.zeros((w.nt, 3, 20)))
+        t0 = time.time()
+        J, g = s.adjoint_probe_energy(nsteps, every, probes)
+        t_adj = time.time() - t0
+        s.close()
+        out_prec[prec] = {"forward_s": t_fwd, "forward_adjoint_s": t_adj, "ratio": t_adj / t_fwd, "J": J,
+                          "grad_norm": float(np.linalg.norm(g)), "grad_max": float(np.abs(g).max())}
+        log(f"[bench] adjoint {prec}: forward {t_fwd:.2f} s, forward+adjoint {t_adj:.2f} s "
+            f"({t_adj / t_fwd:.1f}x), J={J:.6e}")
+    print(json.dumps({"metric": "probe-energy gradient w.r.t. per-element eps (discrete adjoint)",
+                      "unit": "s", "higher_is_better": False, "n_gpus": 1, "steps": nsteps,
+                      "config": {"workload": "adjoint: 24^3 cubes x 6 = 82944 jittered tets, p=3, central, "
+                                             "eps~U[1,4], z-dipole at the origin, 8 probes, checkpoint every 100",
+                                 "elements": w.nt, "dt": dt, "probes": probes},
+                      "results": out_prec}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,7 +293,7 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--workload", default="headline", choices=["headline", "batched"],
+    ap.add_argument("--workload", default="headline", choices=["headline", "batched", "adjoint"],
                     help="headline: the jittered 196,608-element cube; batched: many instances in one launch")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--graph-steps", type=int, default=10)
@@ -263,6 +310,9 @@ def main():
         if args.steps == 1000:
             args.steps = 500
         batched_main(args)
+        return
+    if args.workload == "adjoint":
+        adjoint_main(args)
         return
 
     if args.calib_copy_mib > 0:

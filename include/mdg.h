@@ -198,6 +198,23 @@ mdg_status mdg_step_graph(mdg_solver* s, int64_t nsteps, int32_t steps_per_graph
 mdg_status mdg_rhs(mdg_solver* s, const double* E, const double* H, const double* P,
                    const double* Q, double t, double* dE, double* dH, double* dP, double* dQ);
 
+/* Probe energy and its gradient with respect to every element's permittivity
+ * (the material of [KS Sec. I]), by the discrete adjoint of the RK4 steps.
+ * From the current state, advances nsteps steps (the solver ends in the
+ * advanced state) accumulating
+ *   J = sum_{n=1..nsteps} dt sum_{T in probes} ||e^n||^2_{L2(T)},
+ * then sweeps the adjoint of every step backwards, recomputing the forward
+ * states of each interval of `every` steps from checkpoints kept on the
+ * device, and returns J and grad_eps[nt] = dJ/deps_T (caller's element order;
+ * FP64 reductions, the state precision of the solver). probes[nprobe] are
+ * element indices. Requires the central flux and no PML elements
+ * (MDG_E_UNSUPPORTED): the stiffness is then skew, so the adjoint operator is
+ * the forward operator negated between mass scalings, and eps enters only
+ * through the mass inverse. Allocates (nsteps/every + every + 11) state
+ * vectors of device memory for the call. Synchronous. */
+mdg_status mdg_adjoint_probe_energy(mdg_solver* s, int64_t nsteps, int32_t every, int32_t nprobe,
+                                     const int64_t* probes, double* J, double* grad_eps, void* stream);
+
 /* Electromagnetic energy W = 1/2 sum_T [(eps e, e)_T + (mu h, h)_T] of the
  * current state, accumulated in FP64 on the device [KS Sec. III]. Synchronous. */
 mdg_status mdg_energy(mdg_solver* s, double* W);

@@ -1,0 +1,58 @@
+"""PyTorch autograd entry for the probe-energy objective.
+
+J(eps) = sum_n dt sum_{T in probes} ||e^n||^2_{L2(T)} along the RK4 trajectory
+of a fixed initial field, with dJ/deps computed by the library's checkpointed
+discrete adjoint (mdg_adjoint_probe_energy). The binding only marshals
+arguments; the forward steps, the adjoint sweep and the reductions run in
+the library's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .mdg import Solver
+
+
+class ProbeEnergyProblem:
+    """Mesh, initial state, sources and run length of the objective; eps is
+    the differentiable input. E0/H0 are covariant coefficients [nt][3][N]
+    (they do not depend on eps). dipoles = (pos[n][3], dir[n][3], wave[n][3])
+    or None."""
+
+    def __init__(self, verts, tets, order, E0, H0, dt, nsteps, every, probes, mu=None, dipoles=None,
+                 precision="fp64"):
+        self.verts, self.tets, self.order = verts, tets, order
+        self.E0, self.H0, self.mu, self.dipoles = E0, H0, mu, dipoles
+        self.dt, self.nsteps, self.every = dt, nsteps, every
+        self.probes = np.asarray(probes, dtype=np.int64)
+        self.precision = precision
+
+    def run(self, eps):
+        s = Solver(self.order, self.precision, "central", dt=self.dt)
+        try:
+            s.set_mesh(self.verts, self.tets)
+            s.set_material(eps, self.mu)
+            if self.dipoles is not None:
+                s.set_dipoles(*self.dipoles)
+            s.bind_torch_workspace()
+            s.set_state(self.E0, self.H0)
+            return s.adjoint_probe_energy(self.nsteps, self.every, self.probes)
+        finally:
+            s.close()
+
+    def __call__(self, eps: torch.Tensor) -> torch.Tensor:
+        return ProbeEnergy.apply(eps, self)
+
+
+class ProbeEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, eps, problem):
+        J, g = problem.run(eps.detach().cpu().double().numpy())
+        ctx.save_for_backward(torch.as_tensor(g, dtype=eps.dtype, device=eps.device))
+        return eps.new_tensor(J)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (g,) = ctx.saved_tensors
+        return gJ * g, None

@@ -41,7 +41,7 @@ def generate():
 
 def build(verbose: bool = True) -> str:
     generate()
-    srcs = [os.path.join(CSRC, f) for f in ("setup.cpp", "stage_kernel.hip", "api.hip")]
+    srcs = [os.path.join(CSRC, f) for f in ("setup.cpp", "stage_kernel.hip", "adjoint_kernel.hip", "api.hip")]
     tmp = LIB + ".tmp"
     _run([HIPCC, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp])
     os.replace(tmp, LIB)

@@ -1,0 +1,184 @@
+// adjoint_kernel.hip -- device kernels of the discrete adjoint of the RK4
+// trajectory (probe-energy objective, gradient w.r.t. per-element eps):
+// state-vector combinations, the probe energy and its derivative, and the
+// per-element gradient accumulation. The operator applications themselves are
+// stage-kernel launches (stage_kernel.hip).
+//
+// All state vectors use the blocked layout of the stage kernel:
+// [K/64][field E,H][3N rows][64], row = component*N + mode. The covariant
+// mass of element T is M_T = eps_T M0_T (E) / mu_T M0_T (H) per mode with
+// M0_T = |det A| A^-1 A^-T = (G0^-1)^-1, G0^-1 the geometry record.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "solver.hpp"
+
+namespace mdg {
+
+// z = a x + b y + c w (x, y, w may be null: then their coefficient is unused)
+template <typename R>
+__global__ __launch_bounds__(256) void comb3_kernel(R* __restrict__ z, double a, const R* __restrict__ x, double b,
+                                                    const R* __restrict__ y, double c, const R* __restrict__ w,
+                                                    int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  if (x) v += a * (double)x[i];
+  if (y) v += b * (double)y[i];
+  if (w) v += c * (double)w[i];
+  z[i] = (R)v;
+}
+
+// M0 of element k from its geometry record
+template <typename R>
+__device__ __forceinline__ void mass0(const R* __restrict__ geo, int64_t k, double (&m)[6]) {
+  const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
+  const double a = gk[G_XX * 64], b = gk[G_XY * 64], c = gk[G_XZ * 64];
+  const double d = gk[G_YY * 64], e = gk[G_YZ * 64], f = gk[G_ZZ * 64];
+  const double det = a * (d * f - e * e) - b * (b * f - e * c) + c * (b * e - d * c);
+  const double id = 1.0 / det;
+  m[0] = (d * f - e * e) * id;  // xx
+  m[1] = (c * e - b * f) * id;  // xy
+  m[2] = (b * e - c * d) * id;  // xz
+  m[3] = (a * f - c * c) * id;  // yy
+  m[4] = (b * c - a * e) * id;  // yz
+  m[5] = (a * d - b * b) * id;  // zz
+}
+
+// (u, v)_{M0, E, T} = sum_l u_l^T M0_T v_l over the E rows of element k
+template <typename R, int N>
+__device__ __forceinline__ double e_dot(const R* __restrict__ u, const R* __restrict__ v, const double (&m)[6],
+                                        int64_t k) {
+  const R* uk = u + (k >> 6) * 6 * N * 64 + (k & 63);
+  const R* vk = v + (k >> 6) * 6 * N * 64 + (k & 63);
+  double s = 0.0;
+  for (int l = 0; l < N; ++l) {
+    const double ux = uk[(0 * N + l) * 64], uy = uk[(1 * N + l) * 64], uz = uk[(2 * N + l) * 64];
+    const double vx = vk[(0 * N + l) * 64], vy = vk[(1 * N + l) * 64], vz = vk[(2 * N + l) * 64];
+    s += ux * (m[0] * vx + m[1] * vy + m[2] * vz) + uy * (m[1] * vx + m[3] * vy + m[4] * vz) +
+         uz * (m[2] * vx + m[4] * vy + m[5] * vz);
+  }
+  return s;
+}
+
+// J += dt sum_{probes} (e, e)_{M0}: one block, fixed summation order
+template <typename R, int N>
+__global__ __launch_bounds__(256) void probe_energy_kernel(const R* __restrict__ u, const R* __restrict__ geo,
+                                                           const int64_t* __restrict__ probes, int np, double dt,
+                                                           double* __restrict__ J) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) {
+    double m[6];
+    mass0(geo, probes[i], m);
+    s += e_dot<R, N>(u, u, m, probes[i]);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J[0] += dt * red[0];
+}
+
+// nu_E += (2 dt / eps_T) u_E on the probe elements (the derivative of the
+// probe energy, mapped by M^-1)
+template <typename R, int N>
+__global__ __launch_bounds__(256) void probe_add_kernel(R* __restrict__ nu, const R* __restrict__ u,
+                                                        const R* __restrict__ geo, const int64_t* __restrict__ probes,
+                                                        int np, double dt) {
+  const int i = blockIdx.x;
+  if (i >= np) return;
+  const int64_t k = probes[i];
+  const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
+  const double f = 2.0 * dt * (double)gk[G_IEPS * 64];
+  const int64_t base = (k >> 6) * 6 * N * 64 + (k & 63);
+  for (int r = threadIdx.x; r < 3 * N; r += 256) nu[base + r * 64] = (R)((double)nu[base + r * 64] + f * (double)u[base + r * 64]);
+}
+
+// g_T -= (a, K)_{M0, E, T} for every element
+template <typename R, int N>
+__global__ __launch_bounds__(256) void grad_acc_kernel(double* __restrict__ g, const R* __restrict__ a,
+                                                       const R* __restrict__ K, const R* __restrict__ geo, int64_t nk) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= nk) return;
+  double m[6];
+  mass0(geo, k, m);
+  g[k] -= e_dot<R, N>(a, K, m, k);
+}
+
+// ---------------------------------------------------------------- launch
+static void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
+                  const void* w, void* stream) {
+  const int64_t n = int64_t(6) * s.N * s.Kpad;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s.opt.precision == MDG_FP32)
+    hipLaunchKernelGGL(comb3_kernel<float>, grid, dim3(256), 0, st, (float*)z, a, (const float*)x, b,
+                       (const float*)y, c, (const float*)w, n);
+  else
+    hipLaunchKernelGGL(comb3_kernel<double>, grid, dim3(256), 0, st, (double*)z, a, (const double*)x, b,
+                       (const double*)y, c, (const double*)w, n);
+  check(hipGetLastError(), "comb3_kernel launch");
+}
+
+#define MDG_BY_ORDER(R, KERNEL, ...)                                                  \
+  switch (s.P) {                                                                      \
+    case 1: hipLaunchKernelGGL((KERNEL<R, 4>), __VA_ARGS__); break;                  \
+    case 2: hipLaunchKernelGGL((KERNEL<R, 10>), __VA_ARGS__); break;                 \
+    case 3: hipLaunchKernelGGL((KERNEL<R, 20>), __VA_ARGS__); break;                 \
+    case 4: hipLaunchKernelGGL((KERNEL<R, 35>), __VA_ARGS__); break;                 \
+    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");                    \
+  }
+
+void launch_probe_energy(const Solver& s, const void* u, const int64_t* probes, int np, double dt, double* J,
+                         void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const void* geo = static_cast<char*>(s.ws) + s.L.geo;
+  if (s.opt.precision == MDG_FP32) {
+    MDG_BY_ORDER(float, probe_energy_kernel, dim3(1), dim3(256), 0, st, (const float*)u, (const float*)geo, probes,
+                 np, dt, J)
+  } else {
+    MDG_BY_ORDER(double, probe_energy_kernel, dim3(1), dim3(256), 0, st, (const double*)u, (const double*)geo,
+                 probes, np, dt, J)
+  }
+  check(hipGetLastError(), "probe_energy_kernel launch");
+}
+
+void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* probes, int np, double dt,
+                      void* stream) {
+  if (np == 0) return;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const void* geo = static_cast<char*>(s.ws) + s.L.geo;
+  if (s.opt.precision == MDG_FP32) {
+    MDG_BY_ORDER(float, probe_add_kernel, dim3(np), dim3(256), 0, st, (float*)nu, (const float*)u, (const float*)geo,
+                 probes, np, dt)
+  } else {
+    MDG_BY_ORDER(double, probe_add_kernel, dim3(np), dim3(256), 0, st, (double*)nu, (const double*)u,
+                 (const double*)geo, probes, np, dt)
+  }
+  check(hipGetLastError(), "probe_add_kernel launch");
+}
+
+void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, void* stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const void* geo = static_cast<char*>(s.ws) + s.L.geo;
+  const dim3 grid((unsigned)((s.K + 255) / 256));
+  if (s.opt.precision == MDG_FP32) {
+    MDG_BY_ORDER(float, grad_acc_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)K,
+                 (const float*)geo, s.K)
+  } else {
+    MDG_BY_ORDER(double, grad_acc_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)K,
+                 (const double*)geo, s.K)
+  }
+  check(hipGetLastError(), "grad_acc_kernel launch");
+}
+#undef MDG_BY_ORDER
+
+}  // namespace mdg

@@ -117,10 +117,50 @@ void read_state(Solver& s, double* E, double* H, double* P, double* Q, size_t of
   }
 }
 
-// set a device clock (t0, n = 0); synchronous
-void set_clock(Solver& s, size_t off, double t0) {
-  const double c[2] = {t0, 0.0};
+// set a device clock (t0, n); synchronous
+void set_clock(Solver& s, size_t off, double t0, double n = 0.0) {
+  const double c[2] = {t0, n};
   hip_check(hipMemcpy(dev(s, off), c, sizeof c, hipMemcpyHostToDevice), "clock");
+}
+
+// device buffers owned by one call, freed on every exit path
+struct DevBufs {
+  std::vector<void*> p;
+  void* get(size_t bytes) {
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) throw Error(MDG_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p.push_back(q);
+    return q;
+  }
+  ~DevBufs() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+
+// Kout = L U (operator without the RK update) at the time t0 + cstage dt of
+// the mdg_rhs clock; the input's halo traces are published into H1 first
+void apply_operator(Solver& s, const void* U, void* Kout, double cstage, bool sources, void* stream) {
+  const DevLayout& L = s.L;
+  launch_publish(s, U, dev(s, L.H1), stream);
+  StageParams sp{};
+  sp.stage = -1;
+  sp.dt = s.dt;
+  sp.cstage = cstage;
+  sp.clock = reinterpret_cast<const double*>(dev(s, L.rhs_clock));
+  sp.sources = sources;
+  sp.Y = dev(s, L.Y);
+  sp.Uin = U;
+  sp.Uout = Kout;
+  sp.ACC = dev(s, L.ACC);
+  sp.aY = dev(s, L.aY);
+  sp.aUin = dev(s, L.aUa);
+  sp.aUout = dev(s, L.aUb);
+  sp.aACC = dev(s, L.aACC);
+  sp.hin = dev(s, L.H1);
+  sp.hout = nullptr;
+  sp.publish = false;
+  launch_stage(s, sp, stream);
 }
 
 void drop_graph(Solver& s) {
@@ -444,6 +484,115 @@ mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double
     sp.publish = false;
     launch_stage(s, sp, nullptr);
     read_state(s, dE, dH, dP, dQ, L.Ub, L.aUb);
+  });
+}
+
+mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every, int32_t nprobe,
+                                     const int64_t* probes, double* J, double* grad_eps, void* stream) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (nsteps < 1 || every < 1) throw Error(MDG_E_ARG, "adjoint: nsteps >= 1 and checkpoint interval >= 1");
+    if (nprobe < 1 || !probes || !J || !grad_eps) throw Error(MDG_E_ARG, "adjoint: probes, J and grad_eps required");
+    if (s.opt.flux != MDG_CENTRAL) throw Error(MDG_E_UNSUPPORTED, "adjoint: central flux only");
+    if (s.Kp > 0) throw Error(MDG_E_UNSUPPORTED, "adjoint: no PML elements");
+    std::vector<int64_t> pin(nprobe);
+    for (int i = 0; i < nprobe; ++i) {
+      if (probes[i] < 0 || probes[i] >= s.nt) throw Error(MDG_E_ARG, "adjoint: probe element out of range");
+      pin[i] = s.iperm[probes[i]];
+    }
+    const size_t SB = size_t(6) * s.N * s.Kpad * s.real_size();  // one state vector
+    const int64_t k = std::min<int64_t>(every, nsteps);
+    const int64_t nseg = (nsteps + k - 1) / k;
+    DevBufs B;
+    std::vector<void*> ck(nseg), seg(k);
+    for (auto& q : ck) q = B.get(SB);
+    for (auto& q : seg) q = B.get(SB);
+    void* K4s[4];
+    for (auto& q : K4s) q = B.get(SB);
+    void* X = B.get(SB);
+    void* nu = B.get(SB);
+    void* a = B.get(SB);
+    void* m = B.get(SB);
+    void* msum = B.get(SB);
+    void* uend = B.get(SB);
+    double* g = static_cast<double*>(B.get(size_t(s.K) * 8));
+    double* Jd = static_cast<double*>(B.get(8));
+    int64_t* pd = static_cast<int64_t*>(B.get(size_t(nprobe) * 8));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(hipMemcpyAsync(pd, pin.data(), pin.size() * 8, hipMemcpyHostToDevice, st), "probes");
+    hip_check(hipMemsetAsync(g, 0, size_t(s.K) * 8, st), "grad");
+    hip_check(hipMemsetAsync(Jd, 0, 8, st), "J");
+    void* Y = dev(s, s.L.Y);
+    const double dt = s.dt;
+    const int64_t nbase = s.nstep;
+    // forward: J and checkpoints u^{j k}
+    publish_if_needed(s, stream);
+    for (int64_t n = 0; n < nsteps; ++n) {
+      if (n % k == 0) hip_check(hipMemcpyAsync(ck[n / k], Y, SB, hipMemcpyDeviceToDevice, st), "checkpoint");
+      enqueue_steps(s, 1, stream);
+      launch_probe_energy(s, Y, pd, nprobe, dt, Jd, stream);
+    }
+    hip_check(hipMemcpyAsync(uend, Y, SB, hipMemcpyDeviceToDevice, st), "state");
+    // reverse: nu = M^-1 lambda; central flux makes the stiffness skew, so
+    // M^-1 L^T M = -L and the adjoint stages apply the operator itself
+    hip_check(hipMemsetAsync(nu, 0, SB, st), "nu");
+    launch_probe_add(s, nu, uend, pd, nprobe, dt, stream);
+    static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int64_t n0 = sgi * k, n1 = std::min(nsteps, n0 + k);
+      // recompute u^{n0 .. n1-1} from the checkpoint with the stepping path
+      hip_check(hipMemcpyAsync(seg[0], ck[sgi], SB, hipMemcpyDeviceToDevice, st), "segment");
+      hip_check(hipMemcpyAsync(Y, ck[sgi], SB, hipMemcpyDeviceToDevice, st), "segment");
+      hip_check(hipStreamSynchronize(st), "sync");
+      set_clock(s, s.L.clock, s.t0, double(nbase + n0));
+      s.halo_valid = false;
+      publish_if_needed(s, stream);
+      for (int64_t j = 1; j < n1 - n0; ++j) {
+        enqueue_steps(s, 1, stream);
+        hip_check(hipMemcpyAsync(seg[j], Y, SB, hipMemcpyDeviceToDevice, st), "segment");
+      }
+      for (int64_t n = n1 - 1; n >= n0; --n) {
+        const void* x = seg[n - n0];
+        hip_check(hipStreamSynchronize(st), "sync");
+        set_clock(s, s.L.rhs_clock, s.t0, double(nbase + n));
+        // forward stage derivatives K_i = F(X_i) at this step
+        apply_operator(s, x, K4s[0], cn[0], true, stream);
+        launch_comb3(s, X, 1.0, x, 0.5 * dt, K4s[0], 0.0, nullptr, stream);
+        apply_operator(s, X, K4s[1], cn[1], true, stream);
+        launch_comb3(s, X, 1.0, x, 0.5 * dt, K4s[1], 0.0, nullptr, stream);
+        apply_operator(s, X, K4s[2], cn[2], true, stream);
+        launch_comb3(s, X, 1.0, x, dt, K4s[2], 0.0, nullptr, stream);
+        apply_operator(s, X, K4s[3], cn[3], true, stream);
+        // adjoint stages: a_i = M^-1 kappa_i, m_i = M^-1 L^T kappa_i = -L a_i
+        launch_comb3(s, a, dt / 6.0, nu, 0.0, nullptr, 0.0, nullptr, stream);  // a4
+        launch_grad_acc(s, g, a, K4s[3], stream);
+        apply_operator(s, a, m, 0.0, false, stream);                              // -m4
+        launch_comb3(s, msum, -1.0, m, 0.0, nullptr, 0.0, nullptr, stream);
+        launch_comb3(s, a, dt / 3.0, nu, -dt, m, 0.0, nullptr, stream);          // a3
+        launch_grad_acc(s, g, a, K4s[2], stream);
+        apply_operator(s, a, m, 0.0, false, stream);                              // -m3
+        launch_comb3(s, msum, 1.0, msum, -1.0, m, 0.0, nullptr, stream);
+        launch_comb3(s, a, dt / 3.0, nu, -0.5 * dt, m, 0.0, nullptr, stream);    // a2
+        launch_grad_acc(s, g, a, K4s[1], stream);
+        apply_operator(s, a, m, 0.0, false, stream);                              // -m2
+        launch_comb3(s, msum, 1.0, msum, -1.0, m, 0.0, nullptr, stream);
+        launch_comb3(s, a, dt / 6.0, nu, -0.5 * dt, m, 0.0, nullptr, stream);    // a1
+        launch_grad_acc(s, g, a, K4s[0], stream);
+        apply_operator(s, a, m, 0.0, false, stream);                              // -m1
+        launch_comb3(s, nu, 1.0, nu, 1.0, msum, -1.0, m, stream);
+        if (n >= 1) launch_probe_add(s, nu, x, pd, nprobe, dt, stream);
+      }
+    }
+    // the solver state is the forward end state
+    hip_check(hipMemcpyAsync(Y, uend, SB, hipMemcpyDeviceToDevice, st), "state");
+    hip_check(hipStreamSynchronize(st), "sync");
+    s.nstep = nbase + nsteps;
+    set_clock(s, s.L.clock, s.t0, double(s.nstep));
+    s.halo_valid = false;
+    std::vector<double> gh(s.K);
+    hip_check(hipMemcpy(gh.data(), g, size_t(s.K) * 8, hipMemcpyDeviceToHost), "grad");
+    hip_check(hipMemcpy(J, Jd, 8, hipMemcpyDeviceToHost), "J");
+    for (int64_t u = 0; u < s.nt; ++u) grad_eps[u] = gh[s.iperm[u]];
   });
 }
 

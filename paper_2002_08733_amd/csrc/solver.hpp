@@ -141,6 +141,7 @@ struct StageParams {
   double dt;
   double cstage;  // c_i: the stage's time is clock t0 + (n + c_i) dt
   const double* clock;
+  bool sources = true;  // add the dipole currents
   // state buffers (E and H together, blocked layout)
   void* Y;
   const void* Uin;
@@ -160,5 +161,14 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream);
 void launch_publish(const Solver& s, const void* U, void* H, void* stream);
 void launch_energy(const Solver& s, const void* Y, void* stream);
 void launch_tick(const Solver& s, void* stream);  // clock n += 1
+
+// ---- adjoint_kernel.hip (state vectors in the blocked layout, E and H)
+void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
+                  const void* w, void* stream);  // z = a x + b y + c w
+void launch_probe_energy(const Solver& s, const void* u, const int64_t* probes, int np, double dt, double* J,
+                         void* stream);  // J += dt sum_probes (e, e)_M0
+void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* probes, int np, double dt,
+                      void* stream);  // nu_E += 2 dt / eps u_E on probes
+void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, void* stream);  // g -= (a, K)_M0,E
 
 }  // namespace mdg

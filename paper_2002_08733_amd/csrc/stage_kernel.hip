@@ -915,7 +915,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.srcnext = reinterpret_cast<const int32_t*>(base + s.L.srcnext);
   a.srcwave = reinterpret_cast<const double*>(base + s.L.srcwave);
   a.clock = sp.clock;
-  a.has_src = s.dips.empty() ? 0 : 1;
+  a.has_src = (sp.sources && !s.dips.empty()) ? 1 : 0;
   const size_t rs = s.real_size();
   a.state_bytes = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
   a.aux_bytes = (uint32_t)(size_t(6) * s.N * s.Kppad * rs);

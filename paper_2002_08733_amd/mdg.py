@@ -76,6 +76,7 @@ SIGNATURES = {
     "mdg_rhs": (_S, [_VP, _D, _D, _D, _D, ctypes.c_double, _D, _D, _D, _D]),
     "mdg_energy": (_S, [_VP, _D]),
     "mdg_energy_instances": (_S, [_VP, _D]),
+    "mdg_adjoint_probe_energy": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _I64, _D, _D, _VP]),
     "mdg_query": (_S, [_VP, ctypes.POINTER(mdg_info)]),
 }
 
@@ -255,6 +256,16 @@ class Solver:
         w = ctypes.c_double()
         self._chk(self.lib.mdg_energy(self.h, ctypes.byref(w)))
         return w.value
+
+    def adjoint_probe_energy(self, nsteps, every, probes, stream=None):
+        """(J, dJ/deps[nt]): probe energy over nsteps steps from the current
+        state and its gradient by the checkpointed discrete adjoint."""
+        pr = np.ascontiguousarray(probes, dtype=np.int64)
+        J = ctypes.c_double()
+        g = np.empty(self.nt)
+        self._chk(self.lib.mdg_adjoint_probe_energy(self.h, int(nsteps), int(every), len(pr),
+                                                    pr.ctypes.data_as(_I64), ctypes.byref(J), _dptr(g), stream))
+        return J.value, g
 
     def energy_instances(self):
         n = self.query()["n_instances"]

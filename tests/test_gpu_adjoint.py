@@ -1,0 +1,137 @@
+"""GPU tests of the adjoint (gradient of the probe energy w.r.t. every
+element's permittivity): against the oracle's matrix adjoint on a tiny mesh,
+against central finite differences of the library's own objective on 16
+elements, independence of the checkpoint interval, and the autograd entry."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_08733_amd import load_library
+    load_library()
+
+
+def _solver(verts, tets, p, eps, dt, precision="fp64", dip=None):
+    from paper_2002_08733_amd import Solver
+    s = Solver(p, precision, "central", dt=dt)
+    s.set_mesh(verts, tets)
+    s.set_material(eps, None)
+    if dip is not None:
+        s.set_dipoles(*dip)
+    s.bind_torch_workspace()
+    return s
+
+
+def _tiny():
+    verts, tets = W.kuhn_cube_mesh(2, 0.0, 1.0)
+    rng = np.random.default_rng(41)
+    verts = W.jitter_interior(verts, 0.0, 1.0, 0.5, 0.1, rng)
+    return verts, tets
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+def test_adjoint_matches_oracle_adjoint(precision, tol):
+    from oracle import OracleDG
+    from oracle.adjoint import adjoint_gradient
+    verts, tets = _tiny()
+    rng = np.random.default_rng(42)
+    eps = rng.uniform(1.0, 4.0, 48)
+    pos, dr = np.array([0.4, 0.45, 0.55]), np.array([0.3, 0.2, 1.0])
+    O = OracleDG(verts, tets, 1, eps=eps, mu=np.ones(48), flux="central",
+                 dipoles=[(pos, dr, lambda t: W.dipole_waveform(t, 2.0, 1.0))])
+    cE0 = 0.3 * rng.standard_normal((48, 3, O.N))
+    cH0 = 0.3 * rng.standard_normal((48, 3, O.N))
+    dt, nsteps, probes = 0.01, 8, np.array([3, 17, 40])
+    Jo, go = adjoint_gradient(O, cE0, cH0, dt, nsteps, probes)
+    dip = (pos[None], dr[None], np.array([[2.0, 1.0, 5.0 / (2 * np.pi)]]))
+    s = _solver(verts, tets, 1, eps, dt, precision, dip)
+    s.set_state(O.to_covariant(cE0), O.to_covariant(cH0))
+    J, g = s.adjoint_probe_energy(nsteps, 3, probes)
+    s.close()
+    eJ = abs(J - Jo) / abs(Jo)
+    eg = np.abs(g - go).max() / np.abs(go).max()
+    say(f"[adjoint vs oracle] {precision}: J {J:.12e} vs {Jo:.12e} ({eJ:.2e}), grad max rel {eg:.2e}")
+    assert eJ < tol and eg < tol
+
+
+def _medium(n=4, p=2, seed=51):
+    w = W.jittered(n, p, seed=seed, flux="central")
+    rng = np.random.default_rng(seed + 1)
+    E0 = 0.2 * rng.standard_normal((w.nt, 3, W.nmodes(p)))
+    H0 = 0.2 * rng.standard_normal((w.nt, 3, W.nmodes(p)))
+    dip = (np.array([[0.1, -0.2, 0.15]]), np.array([[0.0, 0.0, 1.0]]), np.array([[2.0, 1.0, 5.0 / (2 * np.pi)]]))
+    return w, E0, H0, dip
+
+
+def test_adjoint_matches_finite_differences_on_16_elements():
+    w, E0, H0, dip = _medium()
+    dt, nsteps, every = 2e-3, 60, 16
+    probes = np.array([5, 77, 150, 222, 301, 333, 360, 383])
+    s = _solver(w.verts, w.tets, w.p, w.eps, dt, dip=dip)
+    s.set_state(E0, H0)
+    J, g = s.adjoint_probe_energy(nsteps, every, probes)
+    s.close()
+    rng = np.random.default_rng(7)
+    elems = np.unique(np.concatenate([probes, rng.choice(w.nt, 8, replace=False)]))[:16]
+    say(f"[adjoint FD] K={w.nt} p={w.p}, {nsteps} steps, checkpoint every {every}, J={J:.10e}")
+    worst = 0.0
+    for T in elems:
+        h = 1e-6 * w.eps[T]
+        Jpm = []
+        for sgn in (1, -1):
+            e = w.eps.copy()
+            e[T] += sgn * h
+            s = _solver(w.verts, w.tets, w.p, e, dt, dip=dip)
+            s.set_state(E0, H0)
+            Jpm.append(s.adjoint_probe_energy(nsteps, nsteps, probes)[0])
+            s.close()
+        fd = (Jpm[0] - Jpm[1]) / (2 * h)
+        # FD round-off is ~1e-16 |J| / h in absolute terms, so elements whose
+        # gradient is tiny are held to the scale of the whole gradient
+        bound = 1e-5 * abs(fd) + 1e-7 * np.abs(g).max()
+        ratio = abs(g[T] - fd) / bound
+        worst = max(worst, ratio)
+        say(f"  element {T}: adjoint {g[T]:+.8e}  fd {fd:+.8e}  |diff|/bound {ratio:.2f}")
+    assert worst <= 1.0
+
+
+def test_adjoint_checkpoint_interval_independence():
+    w, E0, H0, dip = _medium(5, 3, 61)
+    dt, nsteps = 1e-3, 40
+    probes = np.array([0, 100, 500, 749])
+    out = {}
+    for every in (1, 7, 40):
+        s = _solver(w.verts, w.tets, w.p, w.eps, dt, dip=dip)
+        s.set_state(E0, H0)
+        out[every] = s.adjoint_probe_energy(nsteps, every, probes)
+        E, H, t = s.get_state()
+        assert abs(t - nsteps * dt) < 1e-15
+        s.close()
+    say(f"[adjoint checkpoints] J = {[out[e][0] for e in out]}")
+    for every in (7, 40):
+        assert out[every][0] == out[1][0]
+        assert np.array_equal(out[every][1], out[1][1])
+
+
+def test_autograd_function():
+    import torch
+    from paper_2002_08733_amd.autograd import ProbeEnergyProblem
+    w, E0, H0, dip = _medium()
+    probes = np.array([5, 222])
+    prob = ProbeEnergyProblem(w.verts, w.tets, w.p, E0, H0, 2e-3, 20, 5, probes, dipoles=dip)
+    eps = torch.tensor(w.eps, dtype=torch.float64, requires_grad=True)
+    J = prob(eps)
+    (gt,) = torch.autograd.grad(3.0 * J, eps)
+    Jd, gd = prob.run(w.eps)
+    say(f"[autograd] J={J.item():.10e}")
+    assert J.item() == Jd
+    assert np.array_equal(gt.numpy(), 3.0 * gd)

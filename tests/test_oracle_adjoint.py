@@ -1,0 +1,40 @@
+"""Pins of the oracle's discrete adjoint (test infrastructure for the GPU
+adjoint): its gradient of the probe energy with respect to every element's
+permittivity against central finite differences of the oracle's own RK4
+objective, and its J against the plain trajectory."""
+import numpy as np
+
+import workloads as W
+from oracle import OracleDG
+from oracle.adjoint import adjoint_gradient, probe_objective
+
+
+def _problem(eps):
+    verts, tets = W.kuhn_cube_mesh(2, 0.0, 1.0)
+    rng = np.random.default_rng(41)
+    verts = W.jitter_interior(verts, 0.0, 1.0, 0.5, 0.1, rng)
+    dip = [(np.array([0.4, 0.45, 0.55]), np.array([0.3, 0.2, 1.0]),
+            lambda t: W.dipole_waveform(t, 2.0, 1.0))]
+    return OracleDG(verts, tets, 1, eps=eps, mu=np.ones(len(tets)), flux="central", dipoles=dip)
+
+
+def test_oracle_adjoint_matches_finite_differences():
+    rng = np.random.default_rng(42)
+    eps = rng.uniform(1.0, 4.0, 48)
+    O = _problem(eps)
+    cE0 = 0.3 * rng.standard_normal((48, 3, O.N))
+    cH0 = 0.3 * rng.standard_normal((48, 3, O.N))
+    dt, nsteps, probes = 0.01, 8, np.array([3, 17, 40])
+    J, g = adjoint_gradient(O, cE0, cH0, dt, nsteps, probes)
+    assert abs(J - probe_objective(O, cE0, cH0, dt, nsteps, probes)) < 1e-12 * abs(J)
+    for T in (0, 3, 17, 29, 40, 47):
+        h = 1e-5 * eps[T]
+        ep, em = eps.copy(), eps.copy()
+        ep[T] += h
+        em[T] -= h
+        # the initial state is held in Cartesian coefficients: the fields
+        # themselves are fixed while eps moves
+        Jp = probe_objective(_problem(ep), cE0, cH0, dt, nsteps, probes)
+        Jm = probe_objective(_problem(em), cE0, cH0, dt, nsteps, probes)
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(g[T] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (T, g[T], fd)
