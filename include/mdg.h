@@ -180,9 +180,10 @@ mdg_status mdg_project(mdg_solver* s, int32_t q, const double* Evals, const doub
 
 /* Advance nsteps classic RK4 steps. Asynchronous on `stream` (hipStream_t,
  * NULL = default stream): four stage-kernel launches per step (eight with
- * PML elements) and one clock tick. Source amplitudes are evaluated on the
- * device from a device-side clock (t0 + n dt), so every launch of a step has
- * the same arguments. Kernel faults surface at the next synchronising call. */
+ * PML elements, plus a tiny amplitude kernel per stage when dipoles exist).
+ * Source amplitudes are evaluated on the device from a device-side clock
+ * (t0 + n dt) that the last launch of each step advances, so every launch of
+ * a step has the same arguments. Kernel faults surface at the next synchronising call. */
 mdg_status mdg_step(mdg_solver* s, int64_t nsteps, void* stream);
 
 /* Same result as mdg_step(nsteps), launched as replays of a HIP graph of

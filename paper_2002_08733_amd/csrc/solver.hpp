@@ -54,7 +54,8 @@ struct DevLayout {
   size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
   size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
   size_t geo, nbr, pub, halo_tile, pml;
-  size_t src, srcid, srcnext, srcwave;  // dipoles: coefficients, per-element first dipole, chain, waveforms
+  size_t src, srcid, srcnext, srcwave, srcamp;  // dipoles: coefficients, first dipole per element, chain,
+                                                 // waveforms, amplitudes at the current stage
   size_t clock, rhs_clock;              // device time: (t0, n) of the stepping clock and of mdg_rhs
   size_t eelem;                         // per-element energies (FP64)
   size_t H0, H1;  // halo trace buffers: stage inputs' traces on cross-tile faces (ping-pong)
@@ -141,7 +142,8 @@ struct StageParams {
   double dt;
   double cstage;  // c_i: the stage's time is clock t0 + (n + c_i) dt
   const double* clock;
-  bool sources = true;  // add the dipole currents
+  bool sources = true;    // add the dipole currents
+  double* tick = nullptr;  // device clock to advance by one step in this launch
   // state buffers (E and H together, blocked layout)
   void* Y;
   const void* Uin;
@@ -160,7 +162,6 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream);
 // halo traces of state U (blocked layout) into the halo buffer H
 void launch_publish(const Solver& s, const void* U, void* H, void* stream);
 void launch_energy(const Solver& s, const void* Y, void* stream);
-void launch_tick(const Solver& s, void* stream);  // clock n += 1
 
 // ---- adjoint_kernel.hip (state vectors in the blocked layout, E and H)
 void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,

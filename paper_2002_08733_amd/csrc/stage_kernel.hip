@@ -73,13 +73,13 @@ struct DevArgs {
   const void* src;            // dipole load vectors [ndip][3][N]
   const int32_t* srcid;       // blocked [Kpad/64][64]: first dipole acting on the element, or -1
   const int32_t* srcnext;     // [ndip]: next dipole on the same element, or -1
-  const double* srcwave;      // [ndip][3]: f0, bw, t0
-  const double* clock;        // (t0, n): the stage's time is t0 + (n + cstage) dt
+  const double* srcamp;       // [ndip]: g(t) of every dipole at the stage's time
+  double* tick;               // non-null: advance this device clock (n += 1) once
   uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes;
   int64_t pml_base;
   int32_t tile_begin, ntiles, stage, has_src, publish;
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
-  double bcoef, cdt, dt, cstage;
+  double bcoef, cdt, dt;
 };
 
 // ---- raw buffer access (gfx9 buffer descriptor, bounds-checked by hardware)
@@ -489,6 +489,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const int tl = (b & 7) * (nb >> 3) + (b >> 3);
   if (tl >= a.ntiles) return;  // whole block leaves together
   const int t = a.tile_begin + tl;
+  // the step's clock advances once, from a launch that no other kernel of the
+  // step overlaps (the amplitudes of this stage were evaluated before it)
+  if (a.tick && b == 0 && threadIdx.x == 0) a.tick[1] = a.tick[1] + 1.0;
   const int tile = blockDim.x >> 3;  // 8 lanes per element: 2 roles x 4 parts
   const int tid = threadIdx.x;
   // 2*tile is a multiple of 64, so the part is uniform within a wave
@@ -640,18 +643,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   MDG_SWITCH_Q((lift_all_q<P, Q, R>(lds, role, tile, li, acc)));
 
   // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j, with the
-  // Gaussian-modulated sinusoid g evaluated in FP64 at the stage's time on the
-  // device clock
+  // amplitudes g(t) of the stage's time evaluated just before the launch
   if (a.has_src && role == 0) {
     const Rsrc rS = make_rsrc(a.srcid, a.nbr_bytes / 4);
     int d = bldi(rS, blk_base(el, 1, 4), 0);
     if (d >= 0) {
-      const double t = a.clock[0] + (a.clock[1] + a.cstage) * a.dt;
       const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
       for (; d >= 0; d = a.srcnext[d]) {
-        const double f0 = a.srcwave[3 * d], bw = a.srcwave[3 * d + 1], t0 = a.srcwave[3 * d + 2];
-        const double pi = 3.14159265358979323846, tau = t - t0, sg = 1.0 / (2.0 * pi * bw);
-        const R amp = R(sin(2.0 * pi * f0 * tau) * exp(-tau * tau / (2.0 * sg * sg)));
+        const R amp = R(a.srcamp[d]);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -792,9 +791,18 @@ __global__ __launch_bounds__(256) void energy_kernel(const R* __restrict__ Y, co
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// the device clock of a step sequence: n += 1 after the last stage of a step
-__global__ void tick_kernel(double* clock) {
-  if (threadIdx.x == 0) clock[1] = clock[1] + 1.0;
+// dipole amplitudes at the stage's time t = t0 + (n + cstage) dt of the
+// device clock: the Gaussian-modulated sinusoid
+// g(t) = sin(2 pi f0 (t - tc)) exp(-(t - tc)^2 / (2 s^2)), s = 1/(2 pi bw), in FP64
+__global__ __launch_bounds__(256) void src_amp_kernel(const double* __restrict__ clock, double cstage, double dt,
+                                                      const double* __restrict__ wave, int nd,
+                                                      double* __restrict__ amp) {
+  const int d = blockIdx.x * 256 + threadIdx.x;
+  if (d >= nd) return;
+  const double t = clock[0] + (clock[1] + cstage) * dt;
+  const double pi = 3.14159265358979323846;
+  const double tau = t - wave[3 * d + 2], sg = 1.0 / (2.0 * pi * wave[3 * d + 1]);
+  amp[d] = sin(2.0 * pi * wave[3 * d] * tau) * exp(-tau * tau / (2.0 * sg * sg));
 }
 
 __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ part, int64_t n,
@@ -913,8 +921,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.src = base + s.L.src;
   a.srcid = reinterpret_cast<const int32_t*>(base + s.L.srcid);
   a.srcnext = reinterpret_cast<const int32_t*>(base + s.L.srcnext);
-  a.srcwave = reinterpret_cast<const double*>(base + s.L.srcwave);
-  a.clock = sp.clock;
+  a.srcamp = reinterpret_cast<const double*>(base + s.L.srcamp);
   a.has_src = (sp.sources && !s.dips.empty()) ? 1 : 0;
   const size_t rs = s.real_size();
   a.state_bytes = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
@@ -925,7 +932,6 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
   a.pml_base = s.K0;
   a.stage = sp.stage;
-  a.cstage = sp.cstage;
   a.bcoef = sp.bcoef;
   a.cdt = sp.cdt;
   a.dt = sp.dt;
@@ -933,8 +939,17 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   const bool upw = s.opt.flux == MDG_UPWIND;
   const size_t lds = stage_lds_bytes(s);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // non-PML tiles, then PML tiles
+  if (a.has_src) {
+    const int nd = (int)s.dips.size();
+    hipLaunchKernelGGL(src_amp_kernel, dim3((nd + 255) / 256), dim3(256), 0, st, sp.clock, sp.cstage, sp.dt,
+                       reinterpret_cast<const double*>(base + s.L.srcwave), nd,
+                       reinterpret_cast<double*>(base + s.L.srcamp));
+    hip_check(hipGetLastError(), "src_amp_kernel launch");
+  }
+  // non-PML tiles, then PML tiles; the last launch carries the clock tick
+  const int last = s.ntiles > s.ntiles0 ? 1 : 0;
   for (int part = 0; part < 2; ++part) {
+    a.tick = part == last ? sp.tick : nullptr;
     a.tile_begin = part == 0 ? 0 : (int32_t)s.ntiles0;
     a.elem_begin = part == 0 ? 0 : (int32_t)s.K0;
     a.elem_end = part == 0 ? (int32_t)s.K0 : (int32_t)s.K;
@@ -964,12 +979,6 @@ static void launch_energy_r(const Solver& s, const void* Y, hipStream_t st) {
   hip_check(hipGetLastError(), "energy_kernel launch");
   hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, part, nblk, out);
   hip_check(hipGetLastError(), "energy_final launch");
-}
-
-void launch_tick(const Solver& s, void* stream) {
-  double* clock = reinterpret_cast<double*>(static_cast<char*>(s.ws) + s.L.clock);
-  hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), clock);
-  hip_check(hipGetLastError(), "tick_kernel launch");
 }
 
 void launch_energy(const Solver& s, const void* Y, void* stream) {
