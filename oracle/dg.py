@@ -201,12 +201,14 @@ class OracleDG:
         return hs, es
 
     # ------------------------------------------------------------------ rhs
-    def rhs(self, cE, cH, pE=None, pH=None, t=0.0, elems=None, chunk=4096):
+    def rhs(self, cE, cH, pE=None, pH=None, t=0.0, elems=None, chunk=4096, damping=True):
         """Time derivatives (dcE, dcH, dpE, dpH) of the Cartesian coefficients.
 
         ``elems`` restricts the output to a subset of element indices (rows of
         the returned arrays follow ``elems``); the full state is still read for
         neighbours. pE/pH (PML auxiliaries, Cartesian, [K,3,N]) may be None.
+        damping=False leaves out the PML terms (dpE = dpH = None): the
+        undamped curl, flux and source terms only.
         """
         K, N = self.K, self.N
         idx_all = np.arange(K) if elems is None else np.asarray(elems, dtype=np.int64)
@@ -219,7 +221,7 @@ class OracleDG:
             dE[s:s + chunk] = RE / (self.eps[idx] * self.J[idx])[:, None, None]
             dH[s:s + chunk] = RH / (self.mu[idx] * self.J[idx])[:, None, None]
         dpE = dpH = None
-        if self.omega is not None:
+        if self.omega is not None and damping:
             om = self.omega[idx_all]
             eta, xi = pml_tensors(om)
             pe = np.zeros((len(idx_all), 3, N)) if pE is None else pE[idx_all]
