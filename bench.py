@@ -52,10 +52,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def setup_solver(w, precision, dt, q=4):
+def setup_solver(w, precision, dt, q=4, integrator="rk4"):
     import torch
     from paper_2002_08733_amd import Solver
-    s = Solver(w.p, precision, w.flux, dt=dt)
+    s = Solver(w.p, precision, w.flux, dt=dt, integrator=integrator)
     s.set_mesh(w.verts, w.tets)
     s.set_material(w.eps, w.mu)
     s.bind_torch_workspace()
@@ -280,6 +280,55 @@ def adjoint_main(args):
                       "results": out_prec}), flush=True)
 
 
+def leapfrog_main(args):
+    """The paper's own time scheme [KS Sec. V] on the headline mesh (32^3
+    cubes x 6 = 196,608 jittered tets, p=3, eps ~ U[1,4], PEC, Gaussian pulse)
+    with the central flux, which leap-frog needs: leap-frog at CFL 0.2
+    (dt rho(L) < 1.9 < 2) against RK4 at CFL 0.3 (dt rho(L) < 2.8 < 2 sqrt 2).
+    Reports GDOF-updates/s per step (every DOF updated once per step),
+    simulated time per wall-clock second, and each launch against the HBM
+    roofline (a leap-frog half step moves 9N values per element, an RK4 stage
+    17/4 x 6N)."""
+    import torch
+    w = W.jittered(args.n, 3, seed=2, flux="central")
+    results = {}
+    for prec in ["fp32"] + ([] if args.skip_fp64 else ["fp64"]):
+        for integ, cfl in (("leapfrog", 0.2), ("rk4", 0.3)):
+            dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, cfl)
+            s = setup_solver(w, prec, dt, integrator=integ)
+            info = s.query()
+            W0 = s.energy()
+            sec = time_steps(s, args.steps, args.warmup)
+            W1 = s.energy()
+            launches = (2 if integ == "leapfrog" else 4) * args.steps
+            t_launch = sec / launches
+            achieved = info["bytes_per_stage"] / t_launch / 1e9
+            r = {"cfl": cfl, "dt": dt, "gdof_per_step": w.nt * 120 * args.steps / sec / 1e9,
+                 "sim_time_per_s": args.steps * dt / sec, "ms_per_step": 1000 * sec / args.steps,
+                 "us_per_launch": 1e6 * t_launch,
+                 "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                              "algorithmic_bytes_per_launch": info["bytes_per_stage"]},
+                 "energy_ratio": W1 / W0}
+            results[f"{integ}_{prec}"] = r
+            log(f"[bench] {integ} {prec}: {r['gdof_per_step']:.1f} GDOF/s per step, "
+                f"{r['us_per_launch']:.1f} us/launch ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM), "
+                f"{r['sim_time_per_s']:.2f} time units/s, W1/W0={W1 / W0:.6f}")
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+    lf = results["leapfrog_fp32"]
+    print(json.dumps({"metric": "simulated time per second, leap-frog vs RK4 (central flux, p=3)",
+                      "value": lf["sim_time_per_s"], "unit": "time units/s", "higher_is_better": True,
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": f"jittered cube [-1,1]^3, {args.n}^3 cubes x 6 = {w.nt} tets, p=3, "
+                                             "eps~U[1,4], mu=1, central, PEC, Gaussian pulse; leap-frog CFL 0.2, "
+                                             "RK4 CFL 0.3", "elements": w.nt, "dof": w.nt * 120},
+                      "speedup_vs_rk4_fp32": lf["sim_time_per_s"] / results["rk4_fp32"]["sim_time_per_s"],
+                      "results": results}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,7 +342,7 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--workload", default="headline", choices=["headline", "batched", "adjoint"],
+    ap.add_argument("--workload", default="headline", choices=["headline", "batched", "adjoint", "leapfrog"],
                     help="headline: the jittered 196,608-element cube; batched: many instances in one launch")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--graph-steps", type=int, default=10)
@@ -313,6 +362,9 @@ def main():
         return
     if args.workload == "adjoint":
         adjoint_main(args)
+        return
+    if args.workload == "leapfrog":
+        leapfrog_main(args)
         return
 
     if args.calib_copy_mib > 0:

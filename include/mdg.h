@@ -62,13 +62,13 @@ enum {
 
 enum { MDG_FP64 = 0, MDG_FP32 = 1 };
 enum { MDG_CENTRAL = 0, MDG_UPWIND = 1 };
-enum { MDG_RK4 = 0 };
+enum { MDG_RK4 = 0, MDG_LEAPFROG = 1 };
 
 typedef struct mdg_options {
   int32_t order;      /* polynomial order p, 1..4, same for e and h */
   int32_t precision;  /* MDG_FP64 or MDG_FP32: storage and arithmetic of the state */
   int32_t flux;       /* MDG_CENTRAL [KS eqs. uwc/cwc] or MDG_UPWIND (Riemann flux) */
-  int32_t integrator; /* MDG_RK4 */
+  int32_t integrator; /* MDG_RK4, or MDG_LEAPFROG (central flux only; see mdg_step) */
   double dt;          /* > 0: fixed time step; 0: computed from cfl */
   double cfl;         /* dt = cfl * min_T(2 r_in,T sqrt(eps_T mu_T)) / (p+1)^2 when dt == 0 */
   int32_t tile;       /* elements per stage-kernel workgroup: 32 or 64; 0 = automatic */
@@ -80,7 +80,8 @@ typedef struct mdg_info {
   int64_t n_elements, n_faces_interior, n_faces_boundary, n_pml;
   int64_t n_tiles, n_halo;        /* work decomposition of the stage kernel */
   double dt, time;
-  double bytes_per_stage;         /* algorithmic HBM bytes of one RK stage (all elements) */
+  double bytes_per_stage;         /* algorithmic HBM bytes of one RK stage, or of one
+                                     leap-frog half step (all elements) */
   double flops_per_stage;         /* algorithmic flops of one RK stage (sparse reference ops) */
   int64_t workspace_bytes;        /* device bytes mdg_bind_workspace needs */
   int64_t n_instances;            /* independent instances (mdg_set_instances), >= 1 */
@@ -159,7 +160,8 @@ mdg_status mdg_bind_workspace(mdg_solver* s, void* dev_ptr, size_t bytes, void* 
 /* Set the state from host FP64 arrays E[nt][3][N], H[nt][3][N] (covariant
  * coefficients, caller's element order) and PML auxiliaries P, Q (same layout;
  * NULL = zero; ignored on non-PML elements); t is the time of the state.
- * Synchronous. */
+ * With MDG_LEAPFROG the state is staggered: E and P are taken at t, H and Q
+ * at t + dt/2 (mdg_get_state and mdg_project likewise). Synchronous. */
 mdg_status mdg_set_state(mdg_solver* s, const double* E, const double* H, const double* P,
                          const double* Q, double t);
 
@@ -185,6 +187,15 @@ mdg_status mdg_project(mdg_solver* s, int32_t q, const double* Evals, const doub
  * (t0 + n dt) that the last launch of each step advances, so every launch of
  * a step has the same arguments. Kernel faults surface at the next synchronising call. */
 mdg_status mdg_step(mdg_solver* s, int64_t nsteps, void* stream);
+/* With MDG_LEAPFROG a step is the staggered leap-frog scheme of [KS Sec. V]
+ * instead: e^{n+1} = e^n + dt eps^-1 (curl-terms of h^{n+1/2} - j(t^{n+1/2})),
+ * then h^{n+3/2} = h^{n+1/2} - dt mu^-1 (curl-terms of e^{n+1}), one launch
+ * per half step (two with PML elements), each updating its field in place.
+ * The PML damping terms are taken by the trapezoid rule, which keeps the
+ * scheme explicit (a 2x2 solve per Cartesian component) [KS Sec. V]. Needs
+ * the central flux: without PML the staggered energy
+ * 1/2 (e^n, eps e^n) + 1/2 (h^{n-1/2}, mu h^{n+1/2}) is then conserved to
+ * round-off; stable for dt rho(L) < 2 (a smaller CFL number than RK4's). */
 
 /* Same result as mdg_step(nsteps), launched as replays of a HIP graph of
  * steps_per_graph steps (captured on the first call, kept until the solver
@@ -208,7 +219,7 @@ mdg_status mdg_rhs(mdg_solver* s, const double* E, const double* H, const double
  * states of each interval of `every` steps from checkpoints kept on the
  * device, and returns J and grad_eps[nt] = dJ/deps_T (caller's element order;
  * FP64 reductions, the state precision of the solver). probes[nprobe] are
- * element indices. Requires the central flux and no PML elements
+ * element indices. Requires MDG_RK4, the central flux and no PML elements
  * (MDG_E_UNSUPPORTED): the stiffness is then skew, so the adjoint operator is
  * the forward operator negated between mass scalings, and eps enters only
  * through the mass inverse. Allocates (nsteps/every + every + 11) state

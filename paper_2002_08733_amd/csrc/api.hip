@@ -171,8 +171,43 @@ void drop_graph(Solver& s) {
   s.graph_steps = 0;
 }
 
-// enqueue n RK4 steps (4 or 8 stage launches each; the last advances the clock)
+// n leap-frog steps: the E half (sources at t + dt/2), then the H half, which
+// advances the clock; both update Y (and the PML auxiliaries) in place and
+// share the halo buffer H0
+void enqueue_leapfrog_steps(Solver& s, int64_t nsteps, void* stream) {
+  const DevLayout& L = s.L;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    for (int half = 0; half < 2; ++half) {
+      StageParams sp{};
+      sp.stage = 4 + half;
+      sp.dt = s.dt;
+      sp.cstage = 0.5;
+      sp.clock = reinterpret_cast<const double*>(dev(s, L.clock));
+      sp.sources = half == 0;
+      sp.Y = dev(s, L.Y);
+      sp.Uin = sp.Y;
+      sp.Uout = sp.Y;
+      sp.ACC = dev(s, L.ACC);
+      sp.aY = dev(s, L.aY);
+      sp.aUin = sp.aY;
+      sp.aUout = sp.aY;
+      sp.aACC = dev(s, L.aACC);
+      sp.hin = dev(s, L.H0);
+      sp.hout = dev(s, L.H0);
+      sp.publish = true;
+      if (half == 1) sp.tick = reinterpret_cast<double*>(dev(s, L.clock));
+      launch_stage(s, sp, stream);
+    }
+  }
+}
+
+// enqueue n steps: RK4 (4 or 8 stage launches each; the last advances the
+// clock) or leap-frog
 void enqueue_steps(Solver& s, int64_t nsteps, void* stream) {
+  if (s.opt.integrator == MDG_LEAPFROG) {
+    enqueue_leapfrog_steps(s, nsteps, stream);
+    return;
+  }
   static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
   static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
   const DevLayout& L = s.L;
@@ -228,7 +263,11 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
   if (o->order < 1 || o->order > 4) { g_create_error = "order must be 1..4"; return MDG_E_UNSUPPORTED; }
   if (o->precision != MDG_FP64 && o->precision != MDG_FP32) { g_create_error = "bad precision"; return MDG_E_ARG; }
   if (o->flux != MDG_CENTRAL && o->flux != MDG_UPWIND) { g_create_error = "bad flux"; return MDG_E_ARG; }
-  if (o->integrator != MDG_RK4) { g_create_error = "only MDG_RK4 is available"; return MDG_E_UNSUPPORTED; }
+  if (o->integrator != MDG_RK4 && o->integrator != MDG_LEAPFROG) { g_create_error = "bad integrator"; return MDG_E_ARG; }
+  if (o->integrator == MDG_LEAPFROG && o->flux != MDG_CENTRAL) {
+    g_create_error = "leap-frog needs the central flux";
+    return MDG_E_UNSUPPORTED;
+  }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_create_error = "tile must be 0, 32 or 64"; return MDG_E_ARG; }
   if (o->reserved != 0) { g_create_error = "reserved must be 0"; return MDG_E_ARG; }
   if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
@@ -493,6 +532,7 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     need_bound(s);
     if (nsteps < 1 || every < 1) throw Error(MDG_E_ARG, "adjoint: nsteps >= 1 and checkpoint interval >= 1");
     if (nprobe < 1 || !probes || !J || !grad_eps) throw Error(MDG_E_ARG, "adjoint: probes, J and grad_eps required");
+    if (s.opt.integrator != MDG_RK4) throw Error(MDG_E_UNSUPPORTED, "adjoint: RK4 steps only");
     if (s.opt.flux != MDG_CENTRAL) throw Error(MDG_E_UNSUPPORTED, "adjoint: central flux only");
     if (s.Kp > 0) throw Error(MDG_E_UNSUPPORTED, "adjoint: no PML elements");
     std::vector<int64_t> pin(nprobe);

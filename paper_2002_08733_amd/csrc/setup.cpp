@@ -619,10 +619,13 @@ double bytes_per_stage(const Solver& s) {
   // classic RK4 with fused stages moves 17 state arrays per step (stage 1:
   // 1 read + 2 writes, stages 2-3: 3 reads + 2 writes, stage 4: 3 reads +
   // 1 write) -> 17/4 per stage; plus the geometry record and 4 neighbour codes
+  // A leap-frog half step reads both fields and writes one (9 N reals per
+  // element); a PML element reads and writes one auxiliary field.
   const double rs = (double)s.real_size();
-  const double state = 17.0 / 4.0 * 6.0 * s.N * rs;
+  const bool lf = s.opt.integrator == MDG_LEAPFROG;
+  const double state = (lf ? 9.0 : 17.0 / 4.0 * 6.0) * s.N * rs;
   const double geo = (s.opt.flux == MDG_UPWIND ? 14.0 : 9.0) * rs + 16.0;
-  const double pml = 17.0 / 4.0 * 6.0 * s.N * rs + NPML * rs;
+  const double pml = (lf ? 6.0 : 17.0 / 4.0 * 6.0) * s.N * rs + NPML * rs;
   return s.K * (state + geo) + s.Kp * pml;
 }
 

@@ -136,7 +136,7 @@ double flops_per_stage(const Solver& s);
 
 // ---- stage_kernel.hip
 struct StageParams {
-  int stage;      // 0..3 RK4 stage, -1 = operator output only
+  int stage;      // 0..3 RK4 stage, -1 = operator output only, 4/5 leap-frog E/H half step
   double bcoef;   // b_i
   double cdt;     // c_{i+1} dt (stages 0..2)
   double dt;

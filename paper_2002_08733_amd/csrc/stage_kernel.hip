@@ -77,7 +77,7 @@ struct DevArgs {
   double* tick;               // non-null: advance this device clock (n += 1) once
   uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes;
   int64_t pml_base;
-  int32_t tile_begin, ntiles, stage, has_src, publish;
+  int32_t tile_begin, ntiles, stage, has_src, publish;  // stage: 0..3 RK4, -1 operator, 4/5 leap-frog E/H half
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
   double bcoef, cdt, dt;
 };
@@ -333,21 +333,23 @@ __device__ __forceinline__ void publish_face(const R* stg, int role, int tile, i
 //   stage 1,2:  ACC = a + b k,     Uout = y + c dt k
 //   stage 3:    Y   = y + dt (a + b k)                      (ACC store dropped)
 //   operator:   Uout = k                                    (y = a = 0, c dt = 1)
+//   leap-frog half (stage 4: E, 5: H): Y = y + dt k for the active field, with
+//               y taken from the staged input (the stage input is Y itself)
 struct Epi {
   Rsrc y_rd, a_rd, a_wr, out_wr;
   bool final_stage;
-  double c_out;  // c_{i+1} dt, dt (final) or 1 (operator)
+  double c_out;  // c_{i+1} dt, dt (final, leap-frog) or 1 (operator)
 };
 __device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* ACC, const void* Uout,
                                         uint32_t bytes, double bcoef, double cdt, double dt) {
   Epi e;
-  const bool op = stage < 0;
+  const bool op = stage < 0, lf = stage >= 4;
   e.final_stage = stage == 3;
-  e.y_rd = make_rsrc(Y, op ? 0u : bytes);
+  e.y_rd = make_rsrc(Y, (op || lf) ? 0u : bytes);
   e.a_rd = make_rsrc(ACC, (stage >= 1 && stage <= 3) ? bytes : 0u);
   e.a_wr = make_rsrc(ACC, (stage >= 0 && stage <= 2) ? bytes : 0u);
-  e.out_wr = make_rsrc(e.final_stage ? Y : Uout, bytes);
-  e.c_out = op ? 1.0 : (e.final_stage ? dt : cdt);
+  e.out_wr = make_rsrc((e.final_stage || lf) ? Y : Uout, bytes);
+  e.c_out = op ? 1.0 : ((e.final_stage || lf) ? dt : cdt);
   (void)bcoef;
   return e;
 }
@@ -547,6 +549,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   }
   __syncthreads();  // B0: the tile's input fields are staged
 
+  // leap-frog half: the stage input is the state itself, so the own rows of
+  // the output field come from the staging (no second read of Y), and only
+  // the lanes of the active field store and publish. The other role's lanes
+  // run along and their results are dropped; with the central flux the active
+  // field's derivative reads no trace of its own field, which is what lets the
+  // halves share one halo buffer.
+  const int lf = a.stage >= 4 ? a.stage - 4 : -1;
+  const bool wr = live && (lf < 0 || lf == role);
+  if (lf >= 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int l = part * NQ + q;
+        ypre[c][q] = stg[(role * R3 + c * N + (l < N ? l : N - 1)) * tile + li];
+      }
+  }
+
   // 3. halo: the traces of out-of-tile neighbours were written by those
   // neighbours in the previous stage, as an image of this tile's halo slots.
   // Copy the block into LDS slots 4 tile.. with asynchronous LDS loads
@@ -695,6 +715,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const R wzz = bld<R>(rP, vp, rowb<R>(PM_OM + 2));
     const R ex = wy + wzz - wx, ey = wzz + wx - wy, ez = wx + wy - wzz;
     const R xx = (wx - wy) * (wx - wzz), xy = (wy - wzz) * (wy - wx), xz = (wzz - wx) * (wzz - wy);
+    const Rsrc raW = make_rsrc(a.aYw, lf >= 0 ? a.aux_bytes : 0u);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int l = part * NQ + q;
@@ -709,6 +730,33 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       const R cx = AiT[0] * u[0] + AiT[1] * u[1] + AiT[2] * u[2];
       const R cy = AiT[3] * u[0] + AiT[4] * u[1] + AiT[5] * u[2];
       const R cz = AiT[6] * u[0] + AiT[7] * u[1] + AiT[8] * u[2];
+      if (lf >= 0) {
+        // leap-frog half with the damping terms by the trapezoid rule: per
+        // Cartesian component, with k the undamped derivative and h = dt/2,
+        //   x - c = dt k - h eta (x + c) - h (y + a),  y - a = h xi (x + c) - h w (y + a)
+        // for the new field x and auxiliary y, solved exactly (2x2)
+        const R h = R(0.5) * R(a.dt), dtr = R(a.dt);
+        const R kc[3] = {AiT[0] * acc[0][q] + AiT[1] * acc[1][q] + AiT[2] * acc[2][q],
+                         AiT[3] * acc[0][q] + AiT[4] * acc[1][q] + AiT[5] * acc[2][q],
+                         AiT[6] * acc[0][q] + AiT[7] * acc[1][q] + AiT[8] * acc[2][q]};
+        const R cc[3] = {cx, cy, cz}, et[3] = {ex, ey, ez}, xs[3] = {xx, xy, xz}, wv[3] = {wx, wy, wzz};
+        R xn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const R b1 = fma(dtr, kc[c], fma(-h, fma(et[c], cc[c], qa[c]), cc[c]));
+          const R b2 = fma(h, fma(xs[c], cc[c], -wv[c] * qa[c]), qa[c]);
+          const R p1 = fma(h, et[c], R(1)), p2 = fma(h, wv[c], R(1));
+          const R idet = R(1) / fma(h * h, xs[c], p1 * p2);
+          xn[c] = (p2 * b1 - h * b2) * idet;
+          const R yn = fma(p1, b2, h * xs[c] * b1) * idet;
+          if (wr) bst<R, CP_NT>(yn, raW, va, (uint32_t)(c * N + l) * 64u * RS);
+        }
+        // the new covariant field, stored as is by the epilogue
+        acc[0][q] = AT[0] * xn[0] + AT[1] * xn[1] + AT[2] * xn[2];
+        acc[1][q] = AT[3] * xn[0] + AT[4] * xn[1] + AT[5] * xn[2];
+        acc[2][q] = AT[6] * xn[0] + AT[7] * xn[1] + AT[8] * xn[2];
+        continue;
+      }
       const R y0 = fma(ex, cx, qa[0]), y1 = fma(ey, cy, qa[1]), y2 = fma(ez, cz, qa[2]);
       acc[0][q] -= AT[0] * y0 + AT[1] * y1 + AT[2] * y2;
       acc[1][q] -= AT[3] * y0 + AT[4] * y1 + AT[5] * y2;
@@ -723,14 +771,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // the stored output
   {
     const R cf = R(ef.c_out);
+    const bool direct = PML && lf >= 0;  // the PML block computed the new field
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int l = part * NQ + q;
-        if (l < N)
-          acc[c][q] = rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], vout, (uint32_t)(c * N + l) * 64u * RS,
-                                      bc, cf, live);
+        if (l >= N) continue;
+        const uint32_t so = (uint32_t)(c * N + l) * 64u * RS;
+        if (direct) {
+          if (wr) bst<R, CP_NT>(acc[c][q], ef.out_wr, vout, so);
+        } else {
+          acc[c][q] = rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], vout, so, bc, cf, wr);
+        }
       }
   }
 
@@ -748,7 +801,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         if (l < N) stg[((role * 3 + c) * N + l) * tile + li] = acc[c][q];
       }
     __syncthreads();  // B5
-    if (live && pcode >= 0) {
+    if (wr && pcode >= 0) {
       const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
       MDG_SWITCH_Q((publish_face<P, Q, R>(stg, role, tile, li, rHo, pcode)));
     }

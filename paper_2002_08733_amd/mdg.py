@@ -20,6 +20,7 @@ MDG_OK, MDG_E_ARG, MDG_E_MESH, MDG_E_HIP, MDG_E_OOM, MDG_E_STATE, MDG_E_UNSTABLE
 MDG_FP64, MDG_FP32 = 0, 1
 MDG_CENTRAL, MDG_UPWIND = 0, 1
 MDG_RK4 = 0
+MDG_LEAPFROG = 1
 
 _STATUS = {0: "MDG_OK", -1: "MDG_E_ARG", -2: "MDG_E_MESH", -3: "MDG_E_HIP", -4: "MDG_E_OOM",
            -5: "MDG_E_STATE", -6: "MDG_E_UNSTABLE", -7: "MDG_E_UNSUPPORTED"}
@@ -122,11 +123,14 @@ def _f64(a, shape=None):
 class Solver:
     """One libmdg handle. Methods mirror the C entry points one to one."""
 
-    def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3, tile=0):
+    def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3, tile=0, integrator="rk4"):
         self.lib = load_library()
+        if integrator not in ("rk4", "leapfrog"):
+            raise ValueError("integrator must be 'rk4' or 'leapfrog'")
         o = mdg_options(order=order, precision=MDG_FP32 if precision == "fp32" else MDG_FP64,
                         flux=MDG_UPWIND if flux == "upwind" else MDG_CENTRAL,
-                        integrator=MDG_RK4, dt=float(dt), cfl=float(cfl), tile=int(tile), reserved=0)
+                        integrator=MDG_RK4 if integrator == "rk4" else MDG_LEAPFROG, dt=float(dt), cfl=float(cfl),
+                        tile=int(tile), reserved=0)
         h = _VP()
         st = self.lib.mdg_create(ctypes.byref(o), ctypes.byref(h))
         if st != MDG_OK:

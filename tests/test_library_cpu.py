@@ -231,3 +231,34 @@ def test_tile_option_is_validated(lib):
     with pytest.raises(lib.MdgError) as e:
         lib.Solver(2, tile=48)
     assert e.value.status == lib.MDG_E_ARG
+
+
+def test_integrator_option_is_validated(lib):
+    # leap-frog shares one halo buffer between its halves, which is exact
+    # only when a field's derivative reads no trace of that field (central flux)
+    with pytest.raises(lib.MdgError) as e:
+        lib.Solver(2, flux="upwind", integrator="leapfrog")
+    assert e.value.status == lib.MDG_E_UNSUPPORTED
+    s = lib.Solver(2, flux="central", integrator="leapfrog", dt=1e-3)
+    s.close()
+    o = lib.mdg_options(order=2, precision=lib.MDG_FP64, flux=lib.MDG_CENTRAL, integrator=7, dt=1e-3, cfl=0.0,
+                        tile=0, reserved=0)
+    h = lib._VP()
+    assert lib.load_library().mdg_create(lib.ctypes.byref(o), lib.ctypes.byref(h)) == lib.MDG_E_ARG
+
+
+def test_leapfrog_bytes_per_half_step(lib):
+    # a leap-frog half step reads both fields and writes one: 9/(17/4 * 6) of
+    # an RK4 stage's state traffic
+    verts, tets = W.kuhn_cube_mesh(3)
+    q = {}
+    for integ in ("rk4", "leapfrog"):
+        s = lib.Solver(2, flux="central", integrator=integ, dt=1e-3)
+        s.set_mesh(verts, tets)
+        s.workspace_size()
+        q[integ] = s.query()["bytes_per_stage"]
+        s.close()
+    K, N, rs = len(tets), 10, 8
+    geo = 9 * rs + 16
+    assert q["rk4"] == pytest.approx(K * (17 / 4 * 6 * N * rs + geo))
+    assert q["leapfrog"] == pytest.approx(K * (9 * N * rs + geo))
