@@ -39,15 +39,14 @@ def adjoint_gradient(O, cE0, cH0, dt, nsteps, probes):
     LT = L.T
 
     def src(t):
-        z = np.zeros((K, 3, N))
-        dE, dH, _, _ = O.rhs(z, z, t=t)
+        dE, dH, _, _ = O.rhs(np.zeros((K, 3, N)), np.zeros((K, 3, O.NH)), t=t)
         return np.concatenate([dE.ravel(), dH.ravel()])
 
     def F(x, t):
         return L @ x + src(t)
 
     # probe weights: d/dx of sum_T J_T |e_T|^2 is 2 W x (E rows of probes)
-    w = np.zeros(2 * nE)
+    w = np.zeros(nE + K * 3 * O.NH)
     for T in probes:
         w[T * 3 * N:(T + 1) * 3 * N] = O.J[T]
     x = [np.concatenate([cE0.ravel(), cH0.ravel()])]

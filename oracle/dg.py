@@ -2,8 +2,10 @@
 
 Test infrastructure only (see the package docstring).
 
-Semi-discrete system (paper Sec. III; fields e, h in P_p(T)^3 on every
-tetrahedron T, Cartesian components, scalar basis phi_m^T = phi_m o Phi_T^-1):
+Semi-discrete system (paper Sec. III; fields e in P_pe(T)^3 and h in
+P_ph(T)^3 on every tetrahedron T, Cartesian components, scalar basis
+phi_m^T = phi_m o Phi_T^-1; equal orders by default, the paper's own choice
+pe = ph + 1 with ph given, eqs. triale/trialh):
 
   E, weak curl with numerical flux (eq. uwc):
     (eps d_t e, v)_T = (h, curl v)_T - sum_F (h* x n, v)_F - (j, v)_T
@@ -67,7 +69,11 @@ class OracleDG:
     Parameters
     ----------
     verts[nv,3], tets[nt,4] : mesh (any vertex order inside a tet).
-    p : polynomial order (same for e and h).
+    p : polynomial order of e (and of h unless ph is given).
+    ph : polynomial order of h (default p); the paper pairs e at order ph+1
+         with h at ph (eqs. triale, trialh). Test functions of each equation
+         are those of its own field, so E and H coefficient arrays have
+         N = dim P_p and NH = dim P_ph modes.
     eps, mu : per-element material (> 0).
     flux : "central" or "upwind".
     omega : [nt,3] per-axis PML damping (None = no PML).
@@ -75,14 +81,17 @@ class OracleDG:
     """
 
     def __init__(self, verts, tets, p, eps=None, mu=None, flux="central", omega=None,
-                 dipoles=()):
+                 dipoles=(), ph=None):
         self.verts = np.asarray(verts, dtype=np.float64)
         # canonical frame (only for the covariant conversions): ascending id
         self.tets = np.sort(np.asarray(tets, dtype=np.int64), axis=1)
         self.K = self.tets.shape[0]
         self.p = p
-        self.basis = Dubiner(p)
+        self.ph = p if ph is None else int(ph)
+        self.basis = Dubiner(p)  # e (and its test functions)
         self.N = self.basis.N
+        self.basis_h = self.basis if self.ph == p else Dubiner(self.ph)  # h
+        self.NH = self.basis_h.N
         self.eps = np.ones(self.K) if eps is None else np.asarray(eps, dtype=np.float64)
         self.mu = np.ones(self.K) if mu is None else np.asarray(mu, dtype=np.float64)
         if flux not in ("central", "upwind"):
@@ -103,11 +112,14 @@ class OracleDG:
         for (pos, d, g) in dipoles:
             k = self.locate(np.asarray(pos, dtype=np.float64))
             self.dipoles.append((k, np.asarray(pos, dtype=np.float64), np.asarray(d, dtype=np.float64), g))
-        q = p + 1
+        # every integrand is a product of two fields/test functions of degree
+        # <= max(p, ph): rules exact to degree 2 max(p, ph) (2q - 1 >= that)
+        q = max(p, self.ph) + 1
         self.vq, self.vw = tet_quadrature(q)
         self.fq, self.fw = tri_quadrature(q)
         self.phi_vq = self.basis.eval(self.vq)  # [Q, N]
         self.grad_vq = self.basis.grad(self.vq)  # [Q, 3, N]
+        self.phih_vq = self.basis_h.eval(self.vq)  # [Q, NH]
 
     # ------------------------------------------------------------------ mesh
     def _faces(self):
@@ -161,16 +173,18 @@ class OracleDG:
         return np.einsum("kij,kim->kjm", self.A, c)
 
     def eval_at(self, coef, k, x):
-        """Field of element(s) k at physical points x[...,3] -> [...,3]."""
+        """Field of element(s) k at physical points x[...,3] -> [...,3]; the
+        basis (of e or of h) follows the coefficient count."""
         r = np.einsum("...ij,...j->...i", self.Ainv[k], x - self.b[k])
-        ph = self.basis.eval(r)
+        ph = (self.basis if coef.shape[2] == self.N else self.basis_h).eval(r)
         return np.einsum("...m,...im->...i", ph, coef[k])
 
-    def project(self, fn, q=None):
-        """L2 projection of a physical vector field fn(x[...,3]) -> c[K,3,N]."""
+    def project(self, fn, q=None, field="e"):
+        """L2 projection of a physical vector field fn(x[...,3]) onto the space
+        of e (c[K,3,N]) or, with field="h", of h (c[K,3,NH])."""
         q = self.p + 6 if q is None else q
         rq, w = tet_quadrature(q)
-        ph = self.basis.eval(rq)  # [Q,N]
+        ph = (self.basis if field == "e" else self.basis_h).eval(rq)  # [Q,N]
         x = self.b[:, None, :] + np.einsum("kij,qj->kqi", self.A, rq)  # [K,Q,3]
         F = fn(x)  # [K,Q,3]
         # (1/J) int_T F phi_m = sum_q w_q F(x_q) phi_m(r_q)
@@ -210,10 +224,10 @@ class OracleDG:
         damping=False leaves out the PML terms (dpE = dpH = None): the
         undamped curl, flux and source terms only.
         """
-        K, N = self.K, self.N
+        K, N, NH = self.K, self.N, self.NH
         idx_all = np.arange(K) if elems is None else np.asarray(elems, dtype=np.int64)
         dE = np.zeros((len(idx_all), 3, N))
-        dH = np.zeros((len(idx_all), 3, N))
+        dH = np.zeros((len(idx_all), 3, NH))
         Z = np.sqrt(self.mu / self.eps)
         for s in range(0, len(idx_all), chunk):
             idx = idx_all[s:s + chunk]
@@ -225,7 +239,7 @@ class OracleDG:
             om = self.omega[idx_all]
             eta, xi = pml_tensors(om)
             pe = np.zeros((len(idx_all), 3, N)) if pE is None else pE[idx_all]
-            ph = np.zeros((len(idx_all), 3, N)) if pH is None else pH[idx_all]
+            ph = np.zeros((len(idx_all), 3, NH)) if pH is None else pH[idx_all]
             e = cE[idx_all]
             h = cH[idx_all]
             ep = self.eps[idx_all][:, None, None]
@@ -243,14 +257,14 @@ class OracleDG:
         AinvT = np.transpose(self.Ainv[idx], (0, 2, 1))  # grad phi = A^-T grad_hat
         # ---------------- volume terms (physical quadrature)
         G = np.einsum("kab,qbm->kqam", AinvT, self.grad_vq)  # [n,Q,3,N]
-        ph = self.phi_vq  # [Q,N]
-        hq = np.einsum("kim,qm->kqi", cH[idx], ph)  # [n,Q,3]
+        phh = self.phih_vq  # [Q,NH]
+        hq = np.einsum("kim,qm->kqi", cH[idx], phh)  # [n,Q,3]
         wJ = self.vw[None, :] * J[:, None]  # [n,Q]
         # E weak: (h, curl(phi_m e_i)) = e_i . (h x grad phi_m)
         RE = np.einsum("ijl,kqj,kqlm->kim", LEVI_CIVITA, wJ[:, :, None] * hq, G, optimize=True)
         # H strong: -(curl e, phi_m e_i), curl e = sum_n grad phi_n x c_n
         curl_e = np.einsum("ijl,kqjn,kln->kqi", LEVI_CIVITA, G, cE[idx], optimize=True)  # [n,Q,3]
-        RH = -np.einsum("kqi,qm->kim", wJ[:, :, None] * curl_e, ph)
+        RH = -np.einsum("kqi,qm->kim", wJ[:, :, None] * curl_e, phh)
         # ---------------- face terms (physical face quadrature)
         s1 = self.fq[:, 0]
         s2 = self.fq[:, 1]
@@ -261,17 +275,18 @@ class OracleDG:
             x = xa[:, None] + s1[None, :, None] * (xb - xa)[:, None] + s2[None, :, None] * (xc - xa)[:, None]
             wq = self.fw[None, :] * self.area2[idx, f][:, None]  # [n,Qf]
             nrm = np.broadcast_to(self.normal[idx, f][:, None, :], x.shape)
-            phi_own = self.basis.eval(np.einsum("kij,kqj->kqi", self.Ainv[idx], x - self.b[idx][:, None]))
+            r_own = np.einsum("kij,kqj->kqi", self.Ainv[idx], x - self.b[idx][:, None])
+            phi_own = self.basis.eval(r_own)
+            phih_own = self.basis_h.eval(r_own)
             e_m = np.einsum("kqm,kim->kqi", phi_own, cE[idx])
-            h_m = np.einsum("kqm,kim->kqi", phi_own, cH[idx])
+            h_m = np.einsum("kqm,kim->kqi", phih_own, cH[idx])
             side = self.nbr_side[idx, f]
             has = side >= 0
             knb = np.where(has, side // 4, idx)
             # neighbour values at the same physical points via its inverse map
             r_nb = np.einsum("kij,kqj->kqi", self.Ainv[knb], x - self.b[knb][:, None])
-            phi_nb = self.basis.eval(r_nb)
-            e_p = np.einsum("kqm,kim->kqi", phi_nb, cE[knb])
-            h_p = np.einsum("kqm,kim->kqi", phi_nb, cH[knb])
+            e_p = np.einsum("kqm,kim->kqi", self.basis.eval(r_nb), cE[knb])
+            h_p = np.einsum("kqm,kim->kqi", self.basis_h.eval(r_nb), cH[knb])
             # PEC ghost
             en = np.sum(nrm * e_m, axis=-1, keepdims=True)
             e_ghost = -e_m + 2.0 * nrm * en
@@ -283,7 +298,7 @@ class OracleDG:
             FE = -np.cross(hs, nrm)
             FH = np.cross(es - e_m, nrm)
             RE += np.einsum("kqi,kqm->kim", wq[:, :, None] * FE, phi_own)
-            RH += np.einsum("kqi,kqm->kim", wq[:, :, None] * FH, phi_own)
+            RH += np.einsum("kqi,kqm->kim", wq[:, :, None] * FH, phih_own)
         # ---------------- point current source: -(j, phi_m e_i)
         for (k0, pos, d, g) in self.dipoles:
             sel = np.nonzero(idx == k0)[0]
@@ -370,8 +385,8 @@ class OracleDG:
     # ------------------------------------------------------ global operator
     def assemble(self):
         """Dense operator L (Cartesian, E then H, no PML/source) for tiny meshes."""
-        K, N = self.K, self.N
-        n = 2 * K * 3 * N
+        K, N, NH = self.K, self.N, self.NH
+        n = K * 3 * (N + NH)
         Lm = np.zeros((n, n))
         dips = self.dipoles
         self.dipoles = []
@@ -380,7 +395,7 @@ class OracleDG:
                 v = np.zeros(n)
                 v[col] = 1.0
                 cE = v[: K * 3 * N].reshape(K, 3, N)
-                cH = v[K * 3 * N:].reshape(K, 3, N)
+                cH = v[K * 3 * N:].reshape(K, 3, NH)
                 dE, dH, _, _ = self.rhs(cE, cH)
                 Lm[:, col] = np.concatenate([dE.ravel(), dH.ravel()])
         finally:
@@ -389,7 +404,7 @@ class OracleDG:
 
     def mass_diag(self):
         """Diagonal of the Cartesian mass matrix (E then H)."""
-        K, N = self.K, self.N
+        K, N, NH = self.K, self.N, self.NH
         mE = np.repeat(self.eps * self.J, 3 * N)
-        mH = np.repeat(self.mu * self.J, 3 * N)
+        mH = np.repeat(self.mu * self.J, 3 * NH)
         return np.concatenate([mE, mH])
