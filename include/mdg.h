@@ -29,6 +29,11 @@
  *    corrected to an orthonormal polynomial basis: the middle factor carries
  *    (1-x)^j and the last Jacobi weight is (2i+2j+2, 0)).
  *  - PML auxiliaries p, q use the same covariant expansion as e, h.
+ *  - Mixed orders (mdg_options.mixed = 1): e and p carry N = dim P_{p+1}
+ *    modes, h and q carry NH = dim P_p modes, so every H/Q array below is
+ *    [nt][3][NH]. The P_p modes are the first NH modes of P_{p+1} (total
+ *    degree first), which the library uses to run the mixed system as the
+ *    order-(p+1) system with the modes NH.. of h held at zero.
  *  - All host arrays are row-major, caller-owned and only read (or written)
  *    during the call. Device memory is owned by the caller (see
  *    mdg_bind_workspace) or, if the caller passes NULL there, by the library.
@@ -65,14 +70,15 @@ enum { MDG_CENTRAL = 0, MDG_UPWIND = 1 };
 enum { MDG_RK4 = 0, MDG_LEAPFROG = 1 };
 
 typedef struct mdg_options {
-  int32_t order;      /* polynomial order p, 1..4, same for e and h */
+  int32_t order;      /* polynomial order p, 1..4 (of h; of e too unless mixed) */
   int32_t precision;  /* MDG_FP64 or MDG_FP32: storage and arithmetic of the state */
   int32_t flux;       /* MDG_CENTRAL [KS eqs. uwc/cwc] or MDG_UPWIND (Riemann flux) */
   int32_t integrator; /* MDG_RK4, or MDG_LEAPFROG (central flux only; see mdg_step) */
   double dt;          /* > 0: fixed time step; 0: computed from cfl */
   double cfl;         /* dt = cfl * min_T(2 r_in,T sqrt(eps_T mu_T)) / (p+1)^2 when dt == 0 */
   int32_t tile;       /* elements per stage-kernel workgroup: 32 or 64; 0 = automatic */
-  int32_t reserved;   /* must be 0 */
+  int32_t mixed;      /* 0: e and h at order p; 1: e at order p+1, h at order p, the paper's
+                         pairing [KS eqs. triale, trialh] (then p <= 3) */
 } mdg_options;
 
 typedef struct mdg_info {
@@ -86,6 +92,7 @@ typedef struct mdg_info {
   int64_t workspace_bytes;        /* device bytes mdg_bind_workspace needs */
   int64_t n_instances;            /* independent instances (mdg_set_instances), >= 1 */
   int64_t n_dipoles;
+  int32_t order_h, nmodes_h;      /* order and modes of h (order, nmodes refer to e) */
 } mdg_info;
 
 /* Create a solver. opts is copied. *out receives the handle (NULL on error). */

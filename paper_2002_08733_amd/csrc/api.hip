@@ -105,14 +105,13 @@ void read_state(Solver& s, double* E, double* H, double* P, double* Q, size_t of
     download(s, off, size_t(6) * s.N * s.Kpad, buf);
     unpack_state(s, buf, E, H);
   }
-  const size_t n = size_t(s.nt) * 3 * s.N;
   if (P || Q) {
     if (s.Kp > 0) {
       download(s, aoff, size_t(6) * s.N * s.Kppad, buf);
       unpack_aux(s, buf, P, Q);
     } else {
-      if (P) std::memset(P, 0, n * sizeof(double));
-      if (Q) std::memset(Q, 0, n * sizeof(double));
+      if (P) std::memset(P, 0, size_t(s.nt) * 3 * s.N * sizeof(double));
+      if (Q) std::memset(Q, 0, size_t(s.nt) * 3 * s.NH * sizeof(double));
     }
   }
 }
@@ -260,7 +259,11 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
   *out = nullptr;
   g_create_error.clear();
   if (!o) { g_create_error = "NULL options"; return MDG_E_ARG; }
-  if (o->order < 1 || o->order > 4) { g_create_error = "order must be 1..4"; return MDG_E_UNSUPPORTED; }
+  if (o->mixed != 0 && o->mixed != 1) { g_create_error = "mixed must be 0 or 1"; return MDG_E_ARG; }
+  if (o->order < 1 || o->order + o->mixed > 4) {
+    g_create_error = "order must be 1..4 (1..3 with mixed orders)";
+    return MDG_E_UNSUPPORTED;
+  }
   if (o->precision != MDG_FP64 && o->precision != MDG_FP32) { g_create_error = "bad precision"; return MDG_E_ARG; }
   if (o->flux != MDG_CENTRAL && o->flux != MDG_UPWIND) { g_create_error = "bad flux"; return MDG_E_ARG; }
   if (o->integrator != MDG_RK4 && o->integrator != MDG_LEAPFROG) { g_create_error = "bad integrator"; return MDG_E_ARG; }
@@ -269,14 +272,14 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
     return MDG_E_UNSUPPORTED;
   }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_create_error = "tile must be 0, 32 or 64"; return MDG_E_ARG; }
-  if (o->reserved != 0) { g_create_error = "reserved must be 0"; return MDG_E_ARG; }
   if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
   mdg_solver* h = new (std::nothrow) mdg_solver();
   if (!h) return MDG_E_OOM;
   h->s.opt = *o;
-  h->s.P = o->order;
-  h->s.N = nmodes3(o->order);
-  h->s.NF = nmodes2(o->order);
+  h->s.P = o->order + o->mixed;
+  h->s.N = nmodes3(h->s.P);
+  h->s.NF = nmodes2(h->s.P);
+  h->s.NH = nmodes3(o->order);
   *out = h;
   return MDG_OK;
 }
@@ -432,9 +435,8 @@ mdg_status mdg_project(mdg_solver* h, int32_t q, const double* Ev, const double*
     need_bound(s);
     if (q < 1 || q > 16) throw Error(MDG_E_ARG, "q must be 1..16");
     std::vector<double> ce, ch;
-    const size_t n = size_t(s.nt) * 3 * s.N;
-    if (Ev) project_fields(s, q, Ev, ce); else ce.assign(n, 0.0);
-    if (Hv) project_fields(s, q, Hv, ch); else ch.assign(n, 0.0);
+    if (Ev) project_fields(s, q, Ev, s.N, ce); else ce.assign(size_t(s.nt) * 3 * s.N, 0.0);
+    if (Hv) project_fields(s, q, Hv, s.NH, ch); else ch.assign(size_t(s.nt) * 3 * s.NH, 0.0);
     write_state(s, ce.data(), ch.data(), nullptr, nullptr, s.L.Y, s.L.aY);
     s.halo_valid = false;
     s.t0 = t;
@@ -671,6 +673,8 @@ mdg_status mdg_query(mdg_solver* h, mdg_info* info) {
     std::memset(info, 0, sizeof(*info));
     info->order = s.P;
     info->nmodes = s.N;
+    info->order_h = s.P - (s.NH < s.N ? 1 : 0);
+    info->nmodes_h = s.NH;
     info->nfacemodes = s.NF;
     info->precision = s.opt.precision;
     info->flux = s.opt.flux;

@@ -516,15 +516,20 @@ void projection_points(const Solver& s, int q, double* xyz) {
   }
 }
 
-void project_fields(const Solver& s, int q, const double* vals, std::vector<double>& coef) {
+void project_fields(const Solver& s, int q, const double* vals, int N, std::vector<double>& coef) {
   // Cartesian L2 projection c_l = (1/|det A|) int_T F phi_l = sum_q w_q F(x_q) phi^_l(r^_q),
-  // then covariant coefficients u_l = A^T c_l.
+  // then covariant coefficients u_l = A^T c_l, for the first N modes (the
+  // projection onto a lower order space is the truncation: orthonormal,
+  // degree-ordered modes)
   std::vector<double> pts, w;
   tet_rule<double>(q, pts, w);
   const size_t Q = w.size();
-  const int N = s.N;
-  std::vector<double> phi(Q * N);
-  for (size_t i = 0; i < Q; ++i) dubiner3<double>(s.P, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], &phi[i * N], nullptr);
+  const int NP = s.N;
+  std::vector<double> phall(NP), phi(Q * N);
+  for (size_t i = 0; i < Q; ++i) {
+    dubiner3<double>(s.P, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], phall.data(), nullptr);
+    for (int l = 0; l < N; ++l) phi[i * N + l] = phall[l];
+  }
   coef.assign(size_t(s.nt) * 3 * N, 0.0);
   std::vector<double> c(3 * N);
   for (int64_t k = 0; k < s.nt; ++k) {
@@ -541,25 +546,31 @@ void project_fields(const Solver& s, int q, const double* vals, std::vector<doub
   }
 }
 
+// host arrays: E [nt][3][N], H [nt][3][NH]; device rows c*N + l per field,
+// the rows l >= NH of h zero
 void pack_state(const Solver& s, const double* E, const double* H, std::vector<double>& out) {
-  const int N = s.N, R3 = 3 * N;
+  const int N = s.N, NH = s.NH, R3 = 3 * N;
   out.assign(size_t(6) * N * s.Kpad, 0.0);
   for (int64_t k = 0; k < s.K; ++k) {
     const int64_t u = s.perm[k];
-    for (int j = 0; j < R3; ++j) {
-      if (E) out[blk_index(k, j, 2 * R3)] = E[u * R3 + j];
-      if (H) out[blk_index(k, R3 + j, 2 * R3)] = H[u * R3 + j];
+    for (int c = 0; c < 3; ++c) {
+      if (E)
+        for (int l = 0; l < N; ++l) out[blk_index(k, c * N + l, 2 * R3)] = E[(u * 3 + c) * N + l];
+      if (H)
+        for (int l = 0; l < NH; ++l) out[blk_index(k, R3 + c * N + l, 2 * R3)] = H[(u * 3 + c) * NH + l];
     }
   }
 }
 
 void unpack_state(const Solver& s, const std::vector<double>& in, double* E, double* H) {
-  const int N = s.N, R3 = 3 * N;
+  const int N = s.N, NH = s.NH, R3 = 3 * N;
   for (int64_t k = 0; k < s.K; ++k) {
     const int64_t u = s.perm[k];
-    for (int j = 0; j < R3; ++j) {
-      if (E) E[u * R3 + j] = in[blk_index(k, j, 2 * R3)];
-      if (H) H[u * R3 + j] = in[blk_index(k, R3 + j, 2 * R3)];
+    for (int c = 0; c < 3; ++c) {
+      if (E)
+        for (int l = 0; l < N; ++l) E[(u * 3 + c) * N + l] = in[blk_index(k, c * N + l, 2 * R3)];
+      if (H)
+        for (int l = 0; l < NH; ++l) H[(u * 3 + c) * NH + l] = in[blk_index(k, R3 + c * N + l, 2 * R3)];
     }
   }
 }
@@ -572,14 +583,15 @@ void pack_aux(const Solver& s, const double* P, const double* Q, std::vector<dou
   for (int which = 0; which < 2; ++which) {
     const double* in = which == 0 ? P : Q;
     if (!in) continue;
+    const int Nw = which == 0 ? N : s.NH;  // host modes of this field
     for (int64_t k = s.K0; k < s.K; ++k) {
       const int64_t u = s.perm[k], pk = k - s.K0;
       const double* Ai = &s.Ainv[9 * u];
       const double m = which == 0 ? s.eps[u] : s.mu[u];
-      for (int l = 0; l < N; ++l)
+      for (int l = 0; l < Nw; ++l)
         for (int j = 0; j < 3; ++j) {
           double v = 0;
-          for (int i = 0; i < 3; ++i) v += Ai[3 * i + j] * in[(u * 3 + i) * N + l];
+          for (int i = 0; i < 3; ++i) v += Ai[3 * i + j] * in[(u * 3 + i) * Nw + l];
           out[blk_index(pk, which * R3 + j * N + l, 2 * R3)] = v / m;
         }
     }
@@ -591,16 +603,17 @@ void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, doubl
   for (int which = 0; which < 2; ++which) {
     double* out = which == 0 ? P : Q;
     if (!out) continue;
-    std::fill(out, out + size_t(s.nt) * R3, 0.0);
+    const int Nw = which == 0 ? N : s.NH;
+    std::fill(out, out + size_t(s.nt) * 3 * Nw, 0.0);
     for (int64_t k = s.K0; k < s.K; ++k) {
       const int64_t u = s.perm[k], pk = k - s.K0;
       const double* A = &s.A[9 * u];
       const double m = which == 0 ? s.eps[u] : s.mu[u];
-      for (int l = 0; l < N; ++l)
+      for (int l = 0; l < Nw; ++l)
         for (int j = 0; j < 3; ++j) {
           double v = 0;
           for (int i = 0; i < 3; ++i) v += A[3 * i + j] * in[blk_index(pk, which * R3 + i * N + l, 2 * R3)];
-          out[(u * 3 + j) * N + l] = v * m;
+          out[(u * 3 + j) * Nw + l] = v * m;
         }
     }
   }
@@ -619,13 +632,15 @@ double bytes_per_stage(const Solver& s) {
   // classic RK4 with fused stages moves 17 state arrays per step (stage 1:
   // 1 read + 2 writes, stages 2-3: 3 reads + 2 writes, stage 4: 3 reads +
   // 1 write) -> 17/4 per stage; plus the geometry record and 4 neighbour codes
-  // A leap-frog half step reads both fields and writes one (9 N reals per
-  // element); a PML element reads and writes one auxiliary field.
+  // A leap-frog half step reads both fields and writes one (on average
+  // 4.5 (N + NH) reals per element); a PML element reads and writes one
+  // auxiliary field. With mixed orders only the NH modes of h count.
   const double rs = (double)s.real_size();
   const bool lf = s.opt.integrator == MDG_LEAPFROG;
-  const double state = (lf ? 9.0 : 17.0 / 4.0 * 6.0) * s.N * rs;
+  const double nn = double(s.N + s.NH);
+  const double state = (lf ? 4.5 : 17.0 / 4.0 * 3.0) * nn * rs;
   const double geo = (s.opt.flux == MDG_UPWIND ? 14.0 : 9.0) * rs + 16.0;
-  const double pml = (lf ? 6.0 : 17.0 / 4.0 * 6.0) * s.N * rs + NPML * rs;
+  const double pml = (lf ? 3.0 : 17.0 / 4.0 * 3.0) * nn * rs + NPML * rs;
   return s.K * (state + geo) + s.Kp * pml;
 }
 

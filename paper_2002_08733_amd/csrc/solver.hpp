@@ -65,7 +65,8 @@ struct DevLayout {
 
 struct Solver {
   mdg_options opt{};
-  int P = 0, N = 0, NF = 0;
+  int P = 0, N = 0, NF = 0;  // order, modes and face modes of the kernel (of e)
+  int NH = 0;                // modes of h: N, or dim P_{P-1} with mixed orders
   std::string err;
   // ---- mesh (caller's element order, canonical vertex order)
   int64_t nv = 0, nt = 0;
@@ -123,7 +124,7 @@ int tile_size_for(int P, bool fp32);
 size_t stage_lds_bytes(const Solver& s);
 constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
 void projection_points(const Solver& s, int q, double* xyz);
-void project_fields(const Solver& s, int q, const double* vals, std::vector<double>& coef);
+void project_fields(const Solver& s, int q, const double* vals, int N, std::vector<double>& coef);
 // state conversion between the caller's FP64 [nt][3][N] arrays and the
 // internal blocked layout (as double); auxiliaries are stored as A^-T P / eps
 // (P) and A^-T Q / mu (Q).

@@ -79,6 +79,7 @@ struct DevArgs {
   int64_t pml_base;
   int32_t tile_begin, ntiles, stage, has_src, publish;  // stage: 0..3 RK4, -1 operator, 4/5 leap-frog E/H half
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
+  int32_t nh;                    // modes of h: N, or fewer with mixed orders (the rest stay zero)
   double bcoef, cdt, dt;
 };
 
@@ -478,9 +479,12 @@ constexpr int waves_per_eu() { return sizeof(R) == 4 ? 4 : 2; }
     default: { constexpr int Q = 3; __VA_ARGS__; } break; \
   }
 
-template <typename R, int P, bool UPW, bool PML>
+// LF: leap-frog half steps (stage 4/5), central flux only; the RK4 and
+// operator launches use LF = false, for which every leap-frog branch folds away
+template <typename R, int P, bool UPW, bool PML, bool LF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
     DevArgs a) {
+  static_assert(!(LF && UPW), "leap-frog halves need the central flux");
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
   constexpr int SS = slot_stride<NF>();
   constexpr uint32_t RS = sizeof(R);
@@ -552,12 +556,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // leap-frog half: the stage input is the state itself, so the own rows of
   // the output field come from the staging (no second read of Y), and only
   // the lanes of the active field store and publish. The other role's lanes
-  // run along and their results are dropped; with the central flux the active
-  // field's derivative reads no trace of its own field, which is what lets the
-  // halves share one halo buffer.
-  const int lf = a.stage >= 4 ? a.stage - 4 : -1;
-  const bool wr = live && (lf < 0 || lf == role);
-  if (lf >= 0) {
+  // run along and their results are dropped (skipping their work gains
+  // nothing: the launch is bound by the workgroup's chain of loads and
+  // barriers, and with 32-element tiles the two roles share waves). With the
+  // central flux the active field's derivative reads no trace of its own
+  // field, which is what lets the halves share one halo buffer.
+  const int lf = LF ? a.stage - 4 : -1;
+  const bool wr = live && (!LF || lf == role);
+  if (LF) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -692,6 +698,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     acc[2][q] = mf * fma(gxz, x, fma(gyz, y, gzz * z));
   }
 
+  // mixed orders: h lives in the lower-order space, whose modes are the first
+  // nh of this basis; its other modes get no derivative (they stay zero), and
+  // the PML terms below then leave them at zero too
+  if (a.nh < N && role == 1) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (part * NQ + q >= a.nh) acc[0][q] = acc[1][q] = acc[2][q] = R(0);
+  }
+
   const R bc = R(a.bcoef);
   const int stage = a.stage;
   // rows of this part: row(c, q) = c*N + part*NQ + q, skipped past N
@@ -715,7 +730,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const R wzz = bld<R>(rP, vp, rowb<R>(PM_OM + 2));
     const R ex = wy + wzz - wx, ey = wzz + wx - wy, ez = wx + wy - wzz;
     const R xx = (wx - wy) * (wx - wzz), xy = (wy - wzz) * (wy - wx), xz = (wzz - wx) * (wzz - wy);
-    const Rsrc raW = make_rsrc(a.aYw, lf >= 0 ? a.aux_bytes : 0u);
+    const Rsrc raW = make_rsrc(a.aYw, LF ? a.aux_bytes : 0u);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int l = part * NQ + q;
@@ -730,7 +745,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       const R cx = AiT[0] * u[0] + AiT[1] * u[1] + AiT[2] * u[2];
       const R cy = AiT[3] * u[0] + AiT[4] * u[1] + AiT[5] * u[2];
       const R cz = AiT[6] * u[0] + AiT[7] * u[1] + AiT[8] * u[2];
-      if (lf >= 0) {
+      if (LF) {
         // leap-frog half with the damping terms by the trapezoid rule: per
         // Cartesian component, with k the undamped derivative and h = dt/2,
         //   x - c = dt k - h eta (x + c) - h (y + a),  y - a = h xi (x + c) - h w (y + a)
@@ -771,7 +786,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // the stored output
   {
     const R cf = R(ef.c_out);
-    const bool direct = PML && lf >= 0;  // the PML block computed the new field
+    const bool direct = PML && LF;  // the PML block computed the new field
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -916,26 +931,30 @@ static void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <typename R, int P, bool UPW, bool PML>
+template <typename R, int P, bool UPW, bool PML, bool LF>
 static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
   const int grid = (a.ntiles + 7) / 8 * 8;
   if (lds > 64 * 1024) {
-    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML>),
+    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
               "hipFuncSetAttribute(dynamic LDS)");
   }
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML>), dim3(grid), dim3(8 * tile), lds, st, a);
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF>), dim3(grid), dim3(8 * tile), lds, st, a);
   hip_check(hipGetLastError(), "stage_kernel launch");
 }
 
 template <typename R, int P>
 static void launch_p(const DevArgs& a, bool upw, bool pml, int tile, size_t lds, hipStream_t st) {
-  if (upw) {
-    if (pml) launch_one<R, P, true, true>(a, tile, lds, st);
-    else launch_one<R, P, true, false>(a, tile, lds, st);
+  if (a.stage >= 4) {  // leap-frog half (central flux, checked at creation)
+    if (upw) throw Error(MDG_E_UNSUPPORTED, "leap-frog needs the central flux");
+    if (pml) launch_one<R, P, false, true, true>(a, tile, lds, st);
+    else launch_one<R, P, false, false, true>(a, tile, lds, st);
+  } else if (upw) {
+    if (pml) launch_one<R, P, true, true, false>(a, tile, lds, st);
+    else launch_one<R, P, true, false, false>(a, tile, lds, st);
   } else {
-    if (pml) launch_one<R, P, false, true>(a, tile, lds, st);
-    else launch_one<R, P, false, false>(a, tile, lds, st);
+    if (pml) launch_one<R, P, false, true, false>(a, tile, lds, st);
+    else launch_one<R, P, false, false, false>(a, tile, lds, st);
   }
 }
 
@@ -984,6 +1003,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.pml_bytes = (uint32_t)(size_t(NPML) * s.Kppad * rs);
   a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
   a.pml_base = s.K0;
+  a.nh = s.NH;
   a.stage = sp.stage;
   a.bcoef = sp.bcoef;
   a.cdt = sp.cdt;

@@ -35,7 +35,7 @@ class MdgError(RuntimeError):
 class mdg_options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("flux", ctypes.c_int32),
                 ("integrator", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("mixed", ctypes.c_int32)]
 
 
 class mdg_info(ctypes.Structure):
@@ -47,7 +47,7 @@ class mdg_info(ctypes.Structure):
                 ("dt", ctypes.c_double), ("time", ctypes.c_double),
                 ("bytes_per_stage", ctypes.c_double), ("flops_per_stage", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_int64), ("n_instances", ctypes.c_int64),
-                ("n_dipoles", ctypes.c_int64)]
+                ("n_dipoles", ctypes.c_int64), ("order_h", ctypes.c_int32), ("nmodes_h", ctypes.c_int32)]
 
 
 _lib = None
@@ -123,21 +123,26 @@ def _f64(a, shape=None):
 class Solver:
     """One libmdg handle. Methods mirror the C entry points one to one."""
 
-    def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3, tile=0, integrator="rk4"):
+    def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3, tile=0, integrator="rk4",
+                 mixed=False):
+        """order: polynomial order of h (and of e, unless mixed: then e is one
+        order higher, the paper's pairing)."""
         self.lib = load_library()
         if integrator not in ("rk4", "leapfrog"):
             raise ValueError("integrator must be 'rk4' or 'leapfrog'")
         o = mdg_options(order=order, precision=MDG_FP32 if precision == "fp32" else MDG_FP64,
                         flux=MDG_UPWIND if flux == "upwind" else MDG_CENTRAL,
                         integrator=MDG_RK4 if integrator == "rk4" else MDG_LEAPFROG, dt=float(dt), cfl=float(cfl),
-                        tile=int(tile), reserved=0)
+                        tile=int(tile), mixed=1 if mixed else 0)
         h = _VP()
         st = self.lib.mdg_create(ctypes.byref(o), ctypes.byref(h))
         if st != MDG_OK:
             raise MdgError(st, self.lib.mdg_last_error(None).decode())
         self.h = h
         self.order = order
-        self.nmodes = (order + 1) * (order + 2) * (order + 3) // 6
+        pe = order + (1 if mixed else 0)
+        self.nmodes = (pe + 1) * (pe + 2) * (pe + 3) // 6  # of e (and p)
+        self.nmodes_h = (order + 1) * (order + 2) * (order + 3) // 6  # of h (and q)
         self.nt = 0
         self._ws = None
 
@@ -160,6 +165,9 @@ class Solver:
 
     def _shape(self):
         return (self.nt, 3, self.nmodes)
+
+    def _shape_h(self):
+        return (self.nt, 3, self.nmodes_h)
 
     # ----------------------------------------------------------------- setup
     def set_mesh(self, verts, tets):
@@ -215,15 +223,15 @@ class Solver:
 
     # ----------------------------------------------------------------- state
     def set_state(self, E, H, P=None, Q=None, t=0.0):
-        s = self._shape()
-        E, H, P, Q = (_f64(x, s) for x in (E, H, P, Q))
+        s, sh = self._shape(), self._shape_h()
+        E, H, P, Q = _f64(E, s), _f64(H, sh), _f64(P, s), _f64(Q, sh)
         self._chk(self.lib.mdg_set_state(self.h, _dptr(E), _dptr(H), _dptr(P), _dptr(Q), float(t)))
 
     def get_state(self, aux=False):
-        s = self._shape()
-        E, H = np.empty(s), np.empty(s)
+        s, sh = self._shape(), self._shape_h()
+        E, H = np.empty(s), np.empty(sh)
         P = np.empty(s) if aux else None
-        Q = np.empty(s) if aux else None
+        Q = np.empty(sh) if aux else None
         t = ctypes.c_double()
         self._chk(self.lib.mdg_get_state(self.h, _dptr(E), _dptr(H), _dptr(P), _dptr(Q), ctypes.byref(t)))
         return (E, H, P, Q, t.value) if aux else (E, H, t.value)
@@ -247,11 +255,11 @@ class Solver:
         self._chk(self.lib.mdg_step_graph(self.h, int(nsteps), int(steps_per_graph), stream))
 
     def rhs(self, E, H, P=None, Q=None, t=0.0, aux=False):
-        s = self._shape()
-        E, H, P, Q = (_f64(x, s) for x in (E, H, P, Q))
-        dE, dH = np.empty(s), np.empty(s)
+        s, sh = self._shape(), self._shape_h()
+        E, H, P, Q = _f64(E, s), _f64(H, sh), _f64(P, s), _f64(Q, sh)
+        dE, dH = np.empty(s), np.empty(sh)
         dP = np.empty(s) if aux else None
-        dQ = np.empty(s) if aux else None
+        dQ = np.empty(sh) if aux else None
         self._chk(self.lib.mdg_rhs(self.h, _dptr(E), _dptr(H), _dptr(P), _dptr(Q), float(t),
                                    _dptr(dE), _dptr(dH), _dptr(dP), _dptr(dQ)))
         return (dE, dH, dP, dQ) if aux else (dE, dH)

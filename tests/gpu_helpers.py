@@ -53,10 +53,10 @@ def rel_energy_err(O, aE, aH, bE, bH, aP=None, aQ=None, bP=None, bQ=None):
     (Cartesian coefficients)."""
     J, e, m = O.J[:, None, None], O.eps[:, None, None], O.mu[:, None, None]
 
-    def nrm2(E, H, P, Q):
-        v = np.sum(J * (e * E * E + m * H * H))
+    def nrm2(E, H, P, Q):  # E, P and H, Q may differ in modes (mixed orders)
+        v = np.sum(J * e * E * E) + np.sum(J * m * H * H)
         if P is not None:
-            v += np.sum(J * (P * P / e + Q * Q / m))
+            v += np.sum(J * P * P / e) + np.sum(J * Q * Q / m)
         return v
 
     dP = None if aP is None else aP - bP

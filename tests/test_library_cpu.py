@@ -242,7 +242,7 @@ def test_integrator_option_is_validated(lib):
     s = lib.Solver(2, flux="central", integrator="leapfrog", dt=1e-3)
     s.close()
     o = lib.mdg_options(order=2, precision=lib.MDG_FP64, flux=lib.MDG_CENTRAL, integrator=7, dt=1e-3, cfl=0.0,
-                        tile=0, reserved=0)
+                        tile=0, mixed=0)
     h = lib._VP()
     assert lib.load_library().mdg_create(lib.ctypes.byref(o), lib.ctypes.byref(h)) == lib.MDG_E_ARG
 
@@ -262,3 +262,27 @@ def test_leapfrog_bytes_per_half_step(lib):
     geo = 9 * rs + 16
     assert q["rk4"] == pytest.approx(K * (17 / 4 * 6 * N * rs + geo))
     assert q["leapfrog"] == pytest.approx(K * (9 * N * rs + geo))
+
+
+def test_mixed_order_option(lib):
+    with pytest.raises(lib.MdgError) as e:
+        lib.Solver(4, mixed=True)  # e would need order 5
+    assert e.value.status == lib.MDG_E_UNSUPPORTED
+    o = lib.mdg_options(order=2, precision=lib.MDG_FP64, flux=lib.MDG_CENTRAL, integrator=0, dt=1e-3, cfl=0.0,
+                        tile=0, mixed=2)
+    h = lib._VP()
+    assert lib.load_library().mdg_create(lib.ctypes.byref(o), lib.ctypes.byref(h)) == lib.MDG_E_ARG
+    s = lib.Solver(2, mixed=True, dt=1e-3)
+    q = s.query()
+    assert (q["order"], q["nmodes"], q["order_h"], q["nmodes_h"]) == (3, 20, 2, 10)
+    # algorithmic bytes count the modes of h at its own order
+    verts, tets = W.kuhn_cube_mesh(2)
+    s.set_mesh(verts, tets)
+    s.workspace_size()
+    geo = 9 * 8 + 16
+    assert s.query()["bytes_per_stage"] == pytest.approx(len(tets) * (17 / 4 * 3 * (20 + 10) * 8 + geo))
+    s.close()
+    s = lib.Solver(2, dt=1e-3)
+    q = s.query()
+    assert (q["order"], q["nmodes"], q["order_h"], q["nmodes_h"]) == (2, 10, 2, 10)
+    s.close()
