@@ -14,13 +14,24 @@ the stiffness A does not depend on eps, so dK_i/d eps_T at fixed X_i is
 -(1/eps_T) times the E rows of K_i on element T. The time integrator is the
 oracle's classic RK4 and the operator the oracle's (central flux, no PML).
 Pinned by central finite differences of J (tests/test_oracle_adjoint.py).
+
+With PML elements the state also carries the auxiliaries (p_E, p_H), in the
+oracle's unscaled Cartesian form, which start at zero. Per Cartesian
+component a of element T,
+  d_t e = R_E / (eps J) - eta_a e - p_E / eps,   d_t p_E = -w_a p_E + eps xi_a e,
+with R_E (curl, flux, current) free of eps for the central flux, so at fixed
+state dF_E/deps_T = -(F_E + eta e)/eps_T and dF_pE/deps_T = xi e on the rows
+of T, zero elsewhere. The adjoint sweep uses the transposed assembled
+operator including the auxiliary rows.
 """
 import numpy as np
 
 
 def probe_objective(O, cE0, cH0, dt, nsteps, probes):
-    """J along the oracle's RK4 trajectory from (cE0, cH0) at t = 0."""
-    s = [cE0, cH0, None, None]
+    """J along the oracle's RK4 trajectory from (cE0, cH0) at t = 0 (PML
+    auxiliaries, if any, from zero)."""
+    pml = O.omega is not None
+    s = [cE0, cH0, np.zeros_like(cE0) if pml else None, np.zeros_like(cH0) if pml else None]
     t = 0.0
     J = 0.0
     Jt = O.J[probes]
@@ -31,25 +42,57 @@ def probe_objective(O, cE0, cH0, dt, nsteps, probes):
     return J
 
 
+def _assemble_with_aux(O):
+    """Dense operator on (e, h, p_E, p_H) (no sources), for tiny meshes."""
+    K, N, NH = O.K, O.N, O.NH
+    sizes = [K * 3 * N, K * 3 * NH, K * 3 * N, K * 3 * NH]
+    cuts = np.cumsum([0] + sizes)
+    n = cuts[-1]
+    Lm = np.zeros((n, n))
+    dips = O.dipoles
+    O.dipoles = []
+    try:
+        for col in range(n):
+            v = np.zeros(n)
+            v[col] = 1.0
+            parts = [v[cuts[i]:cuts[i + 1]].reshape(K, 3, -1) for i in range(4)]
+            d = O.rhs(*parts)
+            Lm[:, col] = np.concatenate([x.ravel() for x in d])
+    finally:
+        O.dipoles = dips
+    return Lm
+
+
 def adjoint_gradient(O, cE0, cH0, dt, nsteps, probes):
     """(J, dJ/deps[K]) by the discrete adjoint of RK4 with the assembled operator."""
     K, N = O.K, O.N
     nE = K * 3 * N
-    L = O.assemble()  # no sources, E rows then H rows
+    pml = O.omega is not None
+    if pml:
+        from .dg import pml_tensors
+        L = _assemble_with_aux(O)
+        eta, xi = pml_tensors(O.omega)
+        nEH = nE + K * 3 * O.NH
+    else:
+        L = O.assemble()  # no sources, E rows then H rows
     LT = L.T
+    ntot = L.shape[0]
 
     def src(t):
-        dE, dH, _, _ = O.rhs(np.zeros((K, 3, N)), np.zeros((K, 3, O.NH)), t=t)
-        return np.concatenate([dE.ravel(), dH.ravel()])
+        dE, dH, _, _ = O.rhs(np.zeros((K, 3, N)), np.zeros((K, 3, O.NH)), t=t, damping=False)
+        v = np.zeros(ntot)
+        v[:nE] = dE.ravel()
+        v[nE:nE + dH.size] = dH.ravel()
+        return v
 
     def F(x, t):
         return L @ x + src(t)
 
     # probe weights: d/dx of sum_T J_T |e_T|^2 is 2 W x (E rows of probes)
-    w = np.zeros(nE + K * 3 * O.NH)
+    w = np.zeros(ntot)
     for T in probes:
         w[T * 3 * N:(T + 1) * 3 * N] = O.J[T]
-    x = [np.concatenate([cE0.ravel(), cH0.ravel()])]
+    x = [np.concatenate([cE0.ravel(), cH0.ravel(), np.zeros(ntot - nE - cH0.size)])]
     J = 0.0
     for n in range(nsteps):
         t = n * dt
@@ -78,8 +121,16 @@ def adjoint_gradient(O, cE0, cH0, dt, nsteps, probes):
         mu2 = LT @ kap2
         kap1 = dt / 6.0 * lam + 0.5 * dt * mu2
         mu1 = LT @ kap1
-        for kap, kk in ((kap1, k1), (kap2, k2), (kap3, k3), (kap4, k4)):
-            grad -= np.bincount(erow, weights=kap[:nE] * kk[:nE], minlength=K) / O.eps
+        stages = ((kap1, k1, xn), (kap2, k2, xn + 0.5 * dt * k1), (kap3, k3, xn + 0.5 * dt * k2),
+                  (kap4, k4, xn + dt * k3))
+        for kap, kk, X in stages:
+            dFE = kk[:nE]
+            if pml:
+                e = X[:nE].reshape(K, 3, N)
+                dFE = dFE + (eta[:, :, None] * e).ravel()
+                # p_E rows: dF/deps_T = xi e
+                grad += np.bincount(erow, weights=kap[nEH:nEH + nE] * (xi[:, :, None] * e).ravel(), minlength=K)
+            grad -= np.bincount(erow, weights=kap[:nE] * dFE, minlength=K) / O.eps
         lam = lam + mu1 + mu2 + mu3 + mu4
         if n >= 1:
             lam = lam + 2.0 * dt * w * xn

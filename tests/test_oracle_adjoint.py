@@ -9,13 +9,13 @@ from oracle import OracleDG
 from oracle.adjoint import adjoint_gradient, probe_objective
 
 
-def _problem(eps):
+def _problem(eps, omega=None):
     verts, tets = W.kuhn_cube_mesh(2, 0.0, 1.0)
     rng = np.random.default_rng(41)
     verts = W.jitter_interior(verts, 0.0, 1.0, 0.5, 0.1, rng)
     dip = [(np.array([0.4, 0.45, 0.55]), np.array([0.3, 0.2, 1.0]),
             lambda t: W.dipole_waveform(t, 2.0, 1.0))]
-    return OracleDG(verts, tets, 1, eps=eps, mu=np.ones(len(tets)), flux="central", dipoles=dip)
+    return OracleDG(verts, tets, 1, eps=eps, mu=np.ones(len(tets)), flux="central", dipoles=dip, omega=omega)
 
 
 def test_oracle_adjoint_matches_finite_differences():
@@ -38,3 +38,33 @@ def test_oracle_adjoint_matches_finite_differences():
         Jm = probe_objective(_problem(em), cE0, cH0, dt, nsteps, probes)
         fd = (Jp - Jm) / (2 * h)
         assert abs(g[T] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (T, g[T], fd)
+
+
+def test_oracle_adjoint_with_pml_matches_finite_differences():
+    """PML elements (per-axis poles, one axis undamped on some): eps enters
+    the curl terms, eta/xi couplings and the auxiliary equation; the
+    auxiliaries start at zero."""
+    rng = np.random.default_rng(43)
+    eps = rng.uniform(1.0, 4.0, 48)
+    omega = np.zeros((48, 3))
+    sel = rng.random(48) < 0.5
+    omega[sel] = rng.uniform(1.0, 8.0, (sel.sum(), 3))
+    omega[sel & (rng.random(48) < 0.4), 2] = 0.0
+    O = _problem(eps, omega)
+    cE0 = 0.3 * rng.standard_normal((48, 3, O.N))
+    cH0 = 0.3 * rng.standard_normal((48, 3, O.N))
+    dt, nsteps, probes = 0.01, 8, np.array([3, 17, 40])
+    J, g = adjoint_gradient(O, cE0, cH0, dt, nsteps, probes)
+    assert abs(J - probe_objective(O, cE0, cH0, dt, nsteps, probes)) < 1e-12 * abs(J)
+    checked = 0
+    for T in (0, 3, 17, 29, 40, 47) + tuple(np.flatnonzero(sel)[:4]):
+        h = 1e-5 * eps[T]
+        ep, em = eps.copy(), eps.copy()
+        ep[T] += h
+        em[T] -= h
+        Jp = probe_objective(_problem(ep, omega), cE0, cH0, dt, nsteps, probes)
+        Jm = probe_objective(_problem(em, omega), cE0, cH0, dt, nsteps, probes)
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(g[T] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (T, g[T], fd)
+        checked += int(sel[T])
+    assert checked >= 4
