@@ -98,6 +98,46 @@ __global__ __launch_bounds__(256) void probe_add_kernel(R* __restrict__ nu, cons
   for (int r = threadIdx.x; r < 3 * N; r += 256) nu[base + r * 64] = (R)((double)nu[base + r * 64] + f * (double)u[base + r * 64]);
 }
 
+// g_T -= (a, A^T (eta c + q))_{M0, E, T} on PML elements, c = A^-T x_E and
+// q the scaled Cartesian auxiliary of the stage input: the damping part of
+// the stage derivative, which does not scale with 1/eps (with it, g_T gets
+// -(a, K_curl)_M0 where K_curl = K + A^T (eta c + q) is the part that does)
+template <typename R, int N>
+__global__ __launch_bounds__(256) void grad_pml_kernel(double* __restrict__ g, const R* __restrict__ a,
+                                                       const R* __restrict__ x, const R* __restrict__ xa,
+                                                       const R* __restrict__ geo, const R* __restrict__ pml,
+                                                       int64_t K0, int64_t Kp) {
+  const int64_t pk = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (pk >= Kp) return;
+  const int64_t k = K0 + pk;
+  double m[6];
+  mass0(geo, k, m);
+  const R* pr = pml + (pk >> 6) * NPML * 64 + (pk & 63);
+  double AT[9], AiT[9];
+  for (int i = 0; i < 9; ++i) {
+    AT[i] = pr[(PM_AT + i) * 64];
+    AiT[i] = pr[(PM_AIT + i) * 64];
+  }
+  const double wx = pr[(PM_OM + 0) * 64], wy = pr[(PM_OM + 1) * 64], wz = pr[(PM_OM + 2) * 64];
+  const double eta[3] = {wy + wz - wx, wz + wx - wy, wx + wy - wz};
+  const R* xk = x + (k >> 6) * 6 * N * 64 + (k & 63);
+  const R* qk = xa + (pk >> 6) * 6 * N * 64 + (pk & 63);
+  const R* ak = a + (k >> 6) * 6 * N * 64 + (k & 63);
+  double s = 0.0;
+  for (int l = 0; l < N; ++l) {
+    double u[3], y[3], z[3], v[3];
+    for (int c = 0; c < 3; ++c) u[c] = xk[(c * N + l) * 64];
+    for (int i = 0; i < 3; ++i)
+      y[i] = eta[i] * (AiT[3 * i] * u[0] + AiT[3 * i + 1] * u[1] + AiT[3 * i + 2] * u[2]) +
+             (double)qk[(i * N + l) * 64];
+    for (int c = 0; c < 3; ++c) z[c] = AT[3 * c] * y[0] + AT[3 * c + 1] * y[1] + AT[3 * c + 2] * y[2];
+    for (int c = 0; c < 3; ++c) v[c] = ak[(c * N + l) * 64];
+    s += v[0] * (m[0] * z[0] + m[1] * z[1] + m[2] * z[2]) + v[1] * (m[1] * z[0] + m[3] * z[1] + m[4] * z[2]) +
+         v[2] * (m[2] * z[0] + m[4] * z[1] + m[5] * z[2]);
+  }
+  g[k] -= s;
+}
+
 // g_T -= (a, K)_{M0, E, T} for every element
 template <typename R, int N>
 __global__ __launch_bounds__(256) void grad_acc_kernel(double* __restrict__ g, const R* __restrict__ a,
@@ -115,8 +155,9 @@ static void check(hipError_t e, const char* what) {
 }
 
 void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
-                  const void* w, void* stream) {
-  const int64_t n = int64_t(6) * s.N * s.Kpad;
+                  const void* w, void* stream, bool aux) {
+  const int64_t n = int64_t(6) * s.N * (aux ? s.Kppad : s.Kpad);
+  if (n == 0) return;
   const dim3 grid((unsigned)((n + 255) / 256));
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (s.opt.precision == MDG_FP32)
@@ -178,6 +219,21 @@ void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, v
                  (const double*)geo, s.K)
   }
   check(hipGetLastError(), "grad_acc_kernel launch");
+}
+void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, void* stream) {
+  if (s.Kp == 0) return;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const void* geo = static_cast<char*>(s.ws) + s.L.geo;
+  const void* pml = static_cast<char*>(s.ws) + s.L.pml;
+  const dim3 grid((unsigned)((s.Kp + 255) / 256));
+  if (s.opt.precision == MDG_FP32) {
+    MDG_BY_ORDER(float, grad_pml_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)x,
+                 (const float*)xa, (const float*)geo, (const float*)pml, s.K0, s.Kp)
+  } else {
+    MDG_BY_ORDER(double, grad_pml_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)x,
+                 (const double*)xa, (const double*)geo, (const double*)pml, s.K0, s.Kp)
+  }
+  check(hipGetLastError(), "grad_pml_kernel launch");
 }
 #undef MDG_BY_ORDER
 

@@ -137,9 +137,13 @@ struct DevBufs {
   }
 };
 
-// Kout = L U (operator without the RK update) at the time t0 + cstage dt of
-// the mdg_rhs clock; the input's halo traces are published into H1 first
-void apply_operator(Solver& s, const void* U, void* Kout, double cstage, bool sources, void* stream) {
+// Kout = L U (operator without the RK update), or with adj the adjoint
+// operator in the mass inner product, at the time t0 + cstage dt of the
+// mdg_rhs clock; PML auxiliaries are read from aU and written to aK (the
+// stage scratch pair when null); the input's halo traces are published into
+// H1 first
+void apply_operator(Solver& s, const void* U, void* Kout, double cstage, bool sources, void* stream,
+                    const void* aU = nullptr, void* aK = nullptr, bool adj = false) {
   const DevLayout& L = s.L;
   launch_publish(s, U, dev(s, L.H1), stream);
   StageParams sp{};
@@ -148,13 +152,14 @@ void apply_operator(Solver& s, const void* U, void* Kout, double cstage, bool so
   sp.cstage = cstage;
   sp.clock = reinterpret_cast<const double*>(dev(s, L.rhs_clock));
   sp.sources = sources;
+  sp.adj = adj;
   sp.Y = dev(s, L.Y);
   sp.Uin = U;
   sp.Uout = Kout;
   sp.ACC = dev(s, L.ACC);
   sp.aY = dev(s, L.aY);
-  sp.aUin = dev(s, L.aUa);
-  sp.aUout = dev(s, L.aUb);
+  sp.aUin = aU ? aU : dev(s, L.aUa);
+  sp.aUout = aK ? aK : dev(s, L.aUb);
   sp.aACC = dev(s, L.aACC);
   sp.hin = dev(s, L.H1);
   sp.hout = nullptr;
@@ -536,97 +541,132 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     if (nprobe < 1 || !probes || !J || !grad_eps) throw Error(MDG_E_ARG, "adjoint: probes, J and grad_eps required");
     if (s.opt.integrator != MDG_RK4) throw Error(MDG_E_UNSUPPORTED, "adjoint: RK4 steps only");
     if (s.opt.flux != MDG_CENTRAL) throw Error(MDG_E_UNSUPPORTED, "adjoint: central flux only");
-    if (s.Kp > 0) throw Error(MDG_E_UNSUPPORTED, "adjoint: no PML elements");
     std::vector<int64_t> pin(nprobe);
     for (int i = 0; i < nprobe; ++i) {
       if (probes[i] < 0 || probes[i] >= s.nt) throw Error(MDG_E_ARG, "adjoint: probe element out of range");
       pin[i] = s.iperm[probes[i]];
     }
-    const size_t SB = size_t(6) * s.N * s.Kpad * s.real_size();  // one state vector
+    // a state vector: fields (blocked layout) and, with PML elements, the
+    // auxiliaries of the PML elements
+    const bool pml = s.Kp > 0;
+    const size_t SB = size_t(6) * s.N * s.Kpad * s.real_size();
+    const size_t SA = pml ? size_t(6) * s.N * s.Kppad * s.real_size() : 0;
+    struct SV {
+      void* u = nullptr;
+      void* q = nullptr;
+    };
+    DevBufs B;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto alloc = [&]() {
+      SV v;
+      v.u = B.get(SB);
+      if (pml) v.q = B.get(SA);
+      return v;
+    };
+    auto copy = [&](SV d, SV x) {
+      hip_check(hipMemcpyAsync(d.u, x.u, SB, hipMemcpyDeviceToDevice, st), "adjoint copy");
+      if (pml) hip_check(hipMemcpyAsync(d.q, x.q, SA, hipMemcpyDeviceToDevice, st), "adjoint copy");
+    };
+    // z = a x + b y + c w
+    auto comb = [&](SV z, double a, SV x, double b = 0.0, const SV* y = nullptr, double c = 0.0,
+                    const SV* w = nullptr) {
+      launch_comb3(s, z.u, a, x.u, b, y ? y->u : nullptr, c, w ? w->u : nullptr, stream);
+      if (pml) launch_comb3(s, z.q, a, x.q, b, y ? y->q : nullptr, c, w ? w->q : nullptr, stream, true);
+    };
+    auto op = [&](SV in, SV out, double cstage, bool sources, bool adj) {
+      apply_operator(s, in.u, out.u, cstage, sources, stream, in.q, out.q, adj);
+    };
     const int64_t k = std::min<int64_t>(every, nsteps);
     const int64_t nseg = (nsteps + k - 1) / k;
-    DevBufs B;
-    std::vector<void*> ck(nseg), seg(k);
-    for (auto& q : ck) q = B.get(SB);
-    for (auto& q : seg) q = B.get(SB);
-    void* K4s[4];
-    for (auto& q : K4s) q = B.get(SB);
-    void* X = B.get(SB);
-    void* nu = B.get(SB);
-    void* a = B.get(SB);
-    void* m = B.get(SB);
-    void* msum = B.get(SB);
-    void* uend = B.get(SB);
+    std::vector<SV> ck(nseg), seg(k);
+    for (auto& q : ck) q = alloc();
+    for (auto& q : seg) q = alloc();
+    SV K4s[4];
+    for (auto& q : K4s) q = alloc();
+    const SV X = alloc(), nu = alloc(), a = alloc(), m = alloc(), msum = alloc(), uend = alloc();
+    SV state;
+    state.u = dev(s, s.L.Y);
+    state.q = pml ? dev(s, s.L.aY) : nullptr;
     double* g = static_cast<double*>(B.get(size_t(s.K) * 8));
     double* Jd = static_cast<double*>(B.get(8));
     int64_t* pd = static_cast<int64_t*>(B.get(size_t(nprobe) * 8));
-    hipStream_t st = static_cast<hipStream_t>(stream);
     hip_check(hipMemcpyAsync(pd, pin.data(), pin.size() * 8, hipMemcpyHostToDevice, st), "probes");
     hip_check(hipMemsetAsync(g, 0, size_t(s.K) * 8, st), "grad");
     hip_check(hipMemsetAsync(Jd, 0, 8, st), "J");
-    void* Y = dev(s, s.L.Y);
     const double dt = s.dt;
     const int64_t nbase = s.nstep;
     // forward: J and checkpoints u^{j k}
     publish_if_needed(s, stream);
     for (int64_t n = 0; n < nsteps; ++n) {
-      if (n % k == 0) hip_check(hipMemcpyAsync(ck[n / k], Y, SB, hipMemcpyDeviceToDevice, st), "checkpoint");
+      if (n % k == 0) copy(ck[n / k], state);
       enqueue_steps(s, 1, stream);
-      launch_probe_energy(s, Y, pd, nprobe, dt, Jd, stream);
+      launch_probe_energy(s, state.u, pd, nprobe, dt, Jd, stream);
     }
-    hip_check(hipMemcpyAsync(uend, Y, SB, hipMemcpyDeviceToDevice, st), "state");
-    // reverse: nu = M^-1 lambda; central flux makes the stiffness skew, so
-    // M^-1 L^T M = -L and the adjoint stages apply the operator itself
-    hip_check(hipMemsetAsync(nu, 0, SB, st), "nu");
-    launch_probe_add(s, nu, uend, pd, nprobe, dt, stream);
+    copy(uend, state);
+    // reverse sweep in nu = M^-1 lambda (M: the mass, auxiliaries weighted
+    // like their field): every adjoint stage is one adjoint operator call
+    // m_i = L* a_i, L* = M^-1 L^T M, which the stage kernel evaluates
+    // directly (skew part negated, PML couplings transposed)
+    hip_check(hipMemsetAsync(nu.u, 0, SB, st), "nu");
+    if (pml) hip_check(hipMemsetAsync(nu.q, 0, SA, st), "nu");
+    launch_probe_add(s, nu.u, uend.u, pd, nprobe, dt, stream);
+    // g -= (a_i, K_i)_M0 over the E rows, K_i without its damping part on
+    // PML elements (only the rest scales with 1/eps); X_i is the stage input
+    auto grad = [&](SV ai, SV Ki, SV Xi) {
+      launch_grad_acc(s, g, ai.u, Ki.u, stream);
+      if (pml) launch_grad_pml(s, g, ai.u, Xi.u, Xi.q, stream);
+    };
     static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
       const int64_t n0 = sgi * k, n1 = std::min(nsteps, n0 + k);
       // recompute u^{n0 .. n1-1} from the checkpoint with the stepping path
-      hip_check(hipMemcpyAsync(seg[0], ck[sgi], SB, hipMemcpyDeviceToDevice, st), "segment");
-      hip_check(hipMemcpyAsync(Y, ck[sgi], SB, hipMemcpyDeviceToDevice, st), "segment");
+      copy(seg[0], ck[sgi]);
+      copy(state, ck[sgi]);
       hip_check(hipStreamSynchronize(st), "sync");
       set_clock(s, s.L.clock, s.t0, double(nbase + n0));
       s.halo_valid = false;
       publish_if_needed(s, stream);
       for (int64_t j = 1; j < n1 - n0; ++j) {
         enqueue_steps(s, 1, stream);
-        hip_check(hipMemcpyAsync(seg[j], Y, SB, hipMemcpyDeviceToDevice, st), "segment");
+        copy(seg[j], state);
       }
       for (int64_t n = n1 - 1; n >= n0; --n) {
-        const void* x = seg[n - n0];
+        const SV x = seg[n - n0];
         hip_check(hipStreamSynchronize(st), "sync");
         set_clock(s, s.L.rhs_clock, s.t0, double(nbase + n));
         // forward stage derivatives K_i = F(X_i) at this step
-        apply_operator(s, x, K4s[0], cn[0], true, stream);
-        launch_comb3(s, X, 1.0, x, 0.5 * dt, K4s[0], 0.0, nullptr, stream);
-        apply_operator(s, X, K4s[1], cn[1], true, stream);
-        launch_comb3(s, X, 1.0, x, 0.5 * dt, K4s[1], 0.0, nullptr, stream);
-        apply_operator(s, X, K4s[2], cn[2], true, stream);
-        launch_comb3(s, X, 1.0, x, dt, K4s[2], 0.0, nullptr, stream);
-        apply_operator(s, X, K4s[3], cn[3], true, stream);
-        // adjoint stages: a_i = M^-1 kappa_i, m_i = M^-1 L^T kappa_i = -L a_i
-        launch_comb3(s, a, dt / 6.0, nu, 0.0, nullptr, 0.0, nullptr, stream);  // a4
-        launch_grad_acc(s, g, a, K4s[3], stream);
-        apply_operator(s, a, m, 0.0, false, stream);                              // -m4
-        launch_comb3(s, msum, -1.0, m, 0.0, nullptr, 0.0, nullptr, stream);
-        launch_comb3(s, a, dt / 3.0, nu, -dt, m, 0.0, nullptr, stream);          // a3
-        launch_grad_acc(s, g, a, K4s[2], stream);
-        apply_operator(s, a, m, 0.0, false, stream);                              // -m3
-        launch_comb3(s, msum, 1.0, msum, -1.0, m, 0.0, nullptr, stream);
-        launch_comb3(s, a, dt / 3.0, nu, -0.5 * dt, m, 0.0, nullptr, stream);    // a2
-        launch_grad_acc(s, g, a, K4s[1], stream);
-        apply_operator(s, a, m, 0.0, false, stream);                              // -m2
-        launch_comb3(s, msum, 1.0, msum, -1.0, m, 0.0, nullptr, stream);
-        launch_comb3(s, a, dt / 6.0, nu, -0.5 * dt, m, 0.0, nullptr, stream);    // a1
-        launch_grad_acc(s, g, a, K4s[0], stream);
-        apply_operator(s, a, m, 0.0, false, stream);                              // -m1
-        launch_comb3(s, nu, 1.0, nu, 1.0, msum, -1.0, m, stream);
-        if (n >= 1) launch_probe_add(s, nu, x, pd, nprobe, dt, stream);
+        op(x, K4s[0], cn[0], true, false);
+        comb(X, 1.0, x, 0.5 * dt, &K4s[0]);
+        op(X, K4s[1], cn[1], true, false);
+        comb(X, 1.0, x, 0.5 * dt, &K4s[1]);
+        op(X, K4s[2], cn[2], true, false);
+        comb(X, 1.0, x, dt, &K4s[2]);
+        op(X, K4s[3], cn[3], true, false);
+        // adjoint stages (X holds X_4 here; the others are rebuilt for the
+        // PML part of the gradient)
+        comb(a, dt / 6.0, nu);  // a4
+        grad(a, K4s[3], X);
+        op(a, m, 0.0, false, true);  // m4
+        comb(msum, 1.0, m);
+        comb(a, dt / 3.0, nu, dt, &m);  // a3
+        if (pml) comb(X, 1.0, x, 0.5 * dt, &K4s[1]);
+        grad(a, K4s[2], X);
+        op(a, m, 0.0, false, true);  // m3
+        comb(msum, 1.0, msum, 1.0, &m);
+        comb(a, dt / 3.0, nu, 0.5 * dt, &m);  // a2
+        if (pml) comb(X, 1.0, x, 0.5 * dt, &K4s[0]);
+        grad(a, K4s[1], X);
+        op(a, m, 0.0, false, true);  // m2
+        comb(msum, 1.0, msum, 1.0, &m);
+        comb(a, dt / 6.0, nu, 0.5 * dt, &m);  // a1
+        grad(a, K4s[0], x);
+        op(a, m, 0.0, false, true);  // m1
+        comb(nu, 1.0, nu, 1.0, &msum, 1.0, &m);
+        if (n >= 1) launch_probe_add(s, nu.u, x.u, pd, nprobe, dt, stream);
       }
     }
     // the solver state is the forward end state
-    hip_check(hipMemcpyAsync(Y, uend, SB, hipMemcpyDeviceToDevice, st), "state");
+    copy(state, uend);
     hip_check(hipStreamSynchronize(st), "sync");
     s.nstep = nbase + nsteps;
     set_clock(s, s.L.clock, s.t0, double(s.nstep));

@@ -158,6 +158,7 @@ struct StageParams {
   const void* hin;
   void* hout;
   bool publish;  // write the output's halo traces (false for the operator-only call)
+  bool adj = false;  // operator calls: the adjoint operator in the mass inner product
 };
 void launch_stage(const Solver& s, const StageParams& sp, void* stream);
 // halo traces of state U (blocked layout) into the halo buffer H
@@ -165,12 +166,15 @@ void launch_publish(const Solver& s, const void* U, void* H, void* stream);
 void launch_energy(const Solver& s, const void* Y, void* stream);
 
 // ---- adjoint_kernel.hip (state vectors in the blocked layout, E and H)
+// z = a x + b y + c w over a state vector (aux = false) or a PML auxiliary vector
 void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
-                  const void* w, void* stream);  // z = a x + b y + c w
+                  const void* w, void* stream, bool aux = false);
 void launch_probe_energy(const Solver& s, const void* u, const int64_t* probes, int np, double dt, double* J,
                          void* stream);  // J += dt sum_probes (e, e)_M0
 void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* probes, int np, double dt,
                       void* stream);  // nu_E += 2 dt / eps u_E on probes
 void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, void* stream);  // g -= (a, K)_M0,E
+// PML elements: g -= (a, A^T (eta A^-T x_E + xa_E))_M0,E for stage input (x, xa)
+void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, void* stream);
 
 }  // namespace mdg

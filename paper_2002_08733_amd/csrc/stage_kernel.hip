@@ -80,6 +80,7 @@ struct DevArgs {
   int32_t tile_begin, ntiles, stage, has_src, publish;  // stage: 0..3 RK4, -1 operator, 4/5 leap-frog E/H half
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
   int32_t nh;                    // modes of h: N, or fewer with mixed orders (the rest stay zero)
+  int32_t adj;                   // 1: adjoint operator (operator calls without sources)
   double bcoef, cdt, dt;
 };
 
@@ -596,7 +597,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const R* vin_lds = stg + (1 - role) * R3 * tile + li;
   auto vl = [&](int c, int l) { return vin_lds[(c * N + l) * tile]; };
   const R g = role ? R(-1) : R(1);
-  const R sgn = bld<R>(rG, vgeo, rowb<R>(G_SIGN));
+  // sign(det A); the adjoint operator negates the skew part (volume curl and
+  // the averaged face term), which both carry this factor
+  const R sgn = (a.adj ? R(-1) : R(1)) * bld<R>(rG, vgeo, rowb<R>(G_SIGN));
   R acc[3][NQ];
   {
     R t0[NF], t1[NF];
@@ -730,6 +733,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const R wzz = bld<R>(rP, vp, rowb<R>(PM_OM + 2));
     const R ex = wy + wzz - wx, ey = wzz + wx - wy, ez = wx + wy - wzz;
     const R xx = (wx - wy) * (wx - wzz), xy = (wy - wzz) * (wy - wx), xz = (wzz - wx) * (wzz - wy);
+    // couplings u <- -q and q <- xi c; the adjoint in the mass inner product
+    // (auxiliary weighted like its field, in Cartesian components) swaps
+    // them: u <- xi q and q <- -c (the eta and w terms are self-adjoint)
+    const R ux = a.adj ? -xx : R(1), uy = a.adj ? -xy : R(1), uz = a.adj ? -xz : R(1);
+    const R qx = a.adj ? R(-1) : xx, qy = a.adj ? R(-1) : xy, qz = a.adj ? R(-1) : xz;
     const Rsrc raW = make_rsrc(a.aYw, LF ? a.aux_bytes : 0u);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -772,11 +780,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         acc[2][q] = AT[6] * xn[0] + AT[7] * xn[1] + AT[8] * xn[2];
         continue;
       }
-      const R y0 = fma(ex, cx, qa[0]), y1 = fma(ey, cy, qa[1]), y2 = fma(ez, cz, qa[2]);
+      const R y0 = fma(ex, cx, ux * qa[0]), y1 = fma(ey, cy, uy * qa[1]), y2 = fma(ez, cz, uz * qa[2]);
       acc[0][q] -= AT[0] * y0 + AT[1] * y1 + AT[2] * y2;
       acc[1][q] -= AT[3] * y0 + AT[4] * y1 + AT[5] * y2;
       acc[2][q] -= AT[6] * y0 + AT[7] * y1 + AT[8] * y2;
-      const R k[3] = {fma(xx, cx, -wx * qa[0]), fma(xy, cy, -wy * qa[1]), fma(xz, cz, -wzz * qa[2])};
+      const R k[3] = {fma(qx, cx, -wx * qa[0]), fma(qy, cy, -wy * qa[1]), fma(qz, cz, -wzz * qa[2])};
 #pragma unroll
       for (int c = 0; c < 3; ++c) rk_store<R>(ea, k[c], va, (uint32_t)(c * N + l) * 64u * RS, bc, ca, live);
     }
@@ -1004,6 +1012,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
   a.pml_base = s.K0;
   a.nh = s.NH;
+  a.adj = sp.adj ? 1 : 0;
   a.stage = sp.stage;
   a.bcoef = sp.bcoef;
   a.cdt = sp.cdt;

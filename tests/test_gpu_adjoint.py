@@ -1,7 +1,8 @@
 """GPU tests of the adjoint (gradient of the probe energy w.r.t. every
 element's permittivity): against the oracle's matrix adjoint on a tiny mesh,
 against central finite differences of the library's own objective on 16
-elements, independence of the checkpoint interval, and the autograd entry."""
+elements (both also with PML elements, and the finite differences with mixed
+orders), independence of the checkpoint interval, and the autograd entry."""
 import numpy as np
 import pytest
 
@@ -20,11 +21,13 @@ def _gpu():
     load_library()
 
 
-def _solver(verts, tets, p, eps, dt, precision="fp64", dip=None):
+def _solver(verts, tets, p, eps, dt, precision="fp64", dip=None, omega=None, mixed=False):
     from paper_2002_08733_amd import Solver
-    s = Solver(p, precision, "central", dt=dt)
+    s = Solver(p, precision, "central", dt=dt, mixed=mixed)
     s.set_mesh(verts, tets)
     s.set_material(eps, None)
+    if omega is not None:
+        s.set_pml(omega)
     if dip is not None:
         s.set_dipoles(*dip)
     s.bind_torch_workspace()
@@ -38,28 +41,38 @@ def _tiny():
     return verts, tets
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
-def test_adjoint_matches_oracle_adjoint(precision, tol):
+def _tiny_omega(rng):
+    omega = np.zeros((48, 3))
+    sel = rng.random(48) < 0.5
+    omega[sel] = rng.uniform(1.0, 8.0, (sel.sum(), 3))
+    omega[sel & (rng.random(48) < 0.4), 2] = 0.0
+    return omega
+
+
+@pytest.mark.parametrize("precision,tol,pml", [("fp64", 1e-10, False), ("fp32", 2e-4, False),
+                                               ("fp64", 1e-10, True), ("fp32", 2e-4, True)])
+def test_adjoint_matches_oracle_adjoint(precision, tol, pml):
     from oracle import OracleDG
     from oracle.adjoint import adjoint_gradient
     verts, tets = _tiny()
     rng = np.random.default_rng(42)
     eps = rng.uniform(1.0, 4.0, 48)
+    omega = _tiny_omega(rng) if pml else None
     pos, dr = np.array([0.4, 0.45, 0.55]), np.array([0.3, 0.2, 1.0])
-    O = OracleDG(verts, tets, 1, eps=eps, mu=np.ones(48), flux="central",
+    O = OracleDG(verts, tets, 1, eps=eps, mu=np.ones(48), flux="central", omega=omega,
                  dipoles=[(pos, dr, lambda t: W.dipole_waveform(t, 2.0, 1.0))])
     cE0 = 0.3 * rng.standard_normal((48, 3, O.N))
     cH0 = 0.3 * rng.standard_normal((48, 3, O.N))
     dt, nsteps, probes = 0.01, 8, np.array([3, 17, 40])
     Jo, go = adjoint_gradient(O, cE0, cH0, dt, nsteps, probes)
     dip = (pos[None], dr[None], np.array([[2.0, 1.0, 5.0 / (2 * np.pi)]]))
-    s = _solver(verts, tets, 1, eps, dt, precision, dip)
+    s = _solver(verts, tets, 1, eps, dt, precision, dip, omega)
     s.set_state(O.to_covariant(cE0), O.to_covariant(cH0))
     J, g = s.adjoint_probe_energy(nsteps, 3, probes)
     s.close()
     eJ = abs(J - Jo) / abs(Jo)
     eg = np.abs(g - go).max() / np.abs(go).max()
-    say(f"[adjoint vs oracle] {precision}: J {J:.12e} vs {Jo:.12e} ({eJ:.2e}), grad max rel {eg:.2e}")
+    say(f"[adjoint vs oracle] {precision} pml={pml}: J {J:.12e} vs {Jo:.12e} ({eJ:.2e}), grad max rel {eg:.2e}")
     assert eJ < tol and eg < tol
 
 
@@ -72,17 +85,39 @@ def _medium(n=4, p=2, seed=51):
     return w, E0, H0, dip
 
 
-def test_adjoint_matches_finite_differences_on_16_elements():
+@pytest.mark.parametrize("case", ["plain", "pml", "mixed_pml"])
+def test_adjoint_matches_finite_differences_on_16_elements(case):
     w, E0, H0, dip = _medium()
+    omega, mixed = None, case == "mixed_pml"
+    if case != "plain":
+        # a damped slab (x > 0.4), one axis undamped on part of it
+        c = W.tet_centroids(w.verts, w.tets)
+        omega = np.zeros((w.nt, 3))
+        sel = c[:, 0] > 0.4
+        omega[sel, 0] = 6.0 * ((c[sel, 0] - 0.4) / 0.6) ** 2
+        omega[sel, 1] = 2.0
+        omega[sel & (c[:, 2] > 0.0), 2] = 1.5
+    if mixed:  # e at order 2, h at order 1
+        H0 = H0[:, :, :W.nmodes(w.p - 1)]
     dt, nsteps, every = 2e-3, 60, 16
     probes = np.array([5, 77, 150, 222, 301, 333, 360, 383])
-    s = _solver(w.verts, w.tets, w.p, w.eps, dt, dip=dip)
-    s.set_state(E0, H0)
+    p = w.p - 1 if mixed else w.p
+
+    def make(eps):
+        s = _solver(w.verts, w.tets, p, eps, dt, dip=dip, omega=omega, mixed=mixed)
+        s.set_state(E0, H0)
+        return s
+
+    s = make(w.eps)
     J, g = s.adjoint_probe_energy(nsteps, every, probes)
+    npml = s.query()["n_pml"]
     s.close()
     rng = np.random.default_rng(7)
     elems = np.unique(np.concatenate([probes, rng.choice(w.nt, 8, replace=False)]))[:16]
-    say(f"[adjoint FD] K={w.nt} p={w.p}, {nsteps} steps, checkpoint every {every}, J={J:.10e}")
+    if omega is not None:  # half of the checked elements damped
+        damped = np.flatnonzero(omega.any(axis=1))
+        elems = np.unique(np.concatenate([elems[:8], rng.choice(damped, 8, replace=False)]))
+    say(f"[adjoint FD] {case}: K={w.nt} ({npml} PML) p={w.p}, {nsteps} steps, checkpoint every {every}, J={J:.10e}")
     worst = 0.0
     for T in elems:
         h = 1e-6 * w.eps[T]
@@ -90,8 +125,7 @@ def test_adjoint_matches_finite_differences_on_16_elements():
         for sgn in (1, -1):
             e = w.eps.copy()
             e[T] += sgn * h
-            s = _solver(w.verts, w.tets, w.p, e, dt, dip=dip)
-            s.set_state(E0, H0)
+            s = make(e)
             Jpm.append(s.adjoint_probe_energy(nsteps, nsteps, probes)[0])
             s.close()
         fd = (Jpm[0] - Jpm[1]) / (2 * h)
