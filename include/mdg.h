@@ -217,6 +217,15 @@ mdg_status mdg_step_graph(mdg_solver* s, int64_t nsteps, int32_t steps_per_graph
 mdg_status mdg_rhs(mdg_solver* s, const double* E, const double* H, const double* P,
                    const double* Q, double t, double* dE, double* dH, double* dP, double* dQ);
 
+/* Probe energy alone: advances nsteps steps (RK4 or leap-frog) from the
+ * current state accumulating on the device
+ *   J = sum_{n=1..nsteps} dt sum_{T in probes} ||e^n||^2_{L2(T)}
+ * (the objective of mdg_adjoint_probe_energy; element indices probes[nprobe]
+ * in the caller's order), written to *J. The solver ends in the advanced
+ * state. Synchronous. */
+mdg_status mdg_probe_energy(mdg_solver* s, int64_t nsteps, int32_t nprobe, const int64_t* probes, double* J,
+                            void* stream);
+
 /* Probe energy and its gradient with respect to every element's permittivity
  * (the material of [KS Sec. I]), by the discrete adjoint of the RK4 steps.
  * From the current state, advances nsteps steps (the solver ends in the

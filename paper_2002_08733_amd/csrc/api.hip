@@ -533,6 +533,34 @@ mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double
   });
 }
 
+mdg_status mdg_probe_energy(mdg_solver* h, int64_t nsteps, int32_t nprobe, const int64_t* probes, double* J,
+                            void* stream) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (nsteps < 0) throw Error(MDG_E_ARG, "probe energy: nsteps >= 0");
+    if (nprobe < 1 || !probes || !J) throw Error(MDG_E_ARG, "probe energy: probes and J required");
+    std::vector<int64_t> pin(nprobe);
+    for (int i = 0; i < nprobe; ++i) {
+      if (probes[i] < 0 || probes[i] >= s.nt) throw Error(MDG_E_ARG, "probe energy: element out of range");
+      pin[i] = s.iperm[probes[i]];
+    }
+    DevBufs B;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* Jd = static_cast<double*>(B.get(8));
+    int64_t* pd = static_cast<int64_t*>(B.get(size_t(nprobe) * 8));
+    hip_check(hipMemcpyAsync(pd, pin.data(), pin.size() * 8, hipMemcpyHostToDevice, st), "probes");
+    hip_check(hipMemsetAsync(Jd, 0, 8, st), "J");
+    publish_if_needed(s, stream);
+    for (int64_t n = 0; n < nsteps; ++n) {
+      enqueue_steps(s, 1, stream);
+      launch_probe_energy(s, dev(s, s.L.Y), pd, nprobe, s.dt, Jd, stream);
+    }
+    hip_check(hipStreamSynchronize(st), "sync");
+    s.nstep += nsteps;
+    hip_check(hipMemcpy(J, Jd, 8, hipMemcpyDeviceToHost), "J");
+  });
+}
+
 mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every, int32_t nprobe,
                                      const int64_t* probes, double* J, double* grad_eps, void* stream) {
   return guarded(h, [&](Solver& s) {

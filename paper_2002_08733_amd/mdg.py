@@ -78,6 +78,7 @@ SIGNATURES = {
     "mdg_energy": (_S, [_VP, _D]),
     "mdg_energy_instances": (_S, [_VP, _D]),
     "mdg_adjoint_probe_energy": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _I64, _D, _D, _VP]),
+    "mdg_probe_energy": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, _I64, _D, _VP]),
     "mdg_query": (_S, [_VP, ctypes.POINTER(mdg_info)]),
 }
 
@@ -268,6 +269,14 @@ class Solver:
         w = ctypes.c_double()
         self._chk(self.lib.mdg_energy(self.h, ctypes.byref(w)))
         return w.value
+
+    def probe_energy(self, nsteps, probes, stream=None):
+        """J = sum_n dt sum_probes ||e^n||^2 over nsteps steps from the current state."""
+        pr = np.ascontiguousarray(probes, dtype=np.int64)
+        J = ctypes.c_double()
+        self._chk(self.lib.mdg_probe_energy(self.h, int(nsteps), len(pr), pr.ctypes.data_as(_I64),
+                                            ctypes.byref(J), stream))
+        return J.value
 
     def adjoint_probe_energy(self, nsteps, every, probes, stream=None):
         """(J, dJ/deps[nt]): probe energy over nsteps steps from the current

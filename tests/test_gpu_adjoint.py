@@ -156,6 +156,59 @@ def test_adjoint_checkpoint_interval_independence():
         assert np.array_equal(out[every][1], out[1][1])
 
 
+def test_adjoint_fullsize_pml_against_finite_differences():
+    """The adjoint configuration at full size, FP64: 24^3 cubes x 6 = 82,944
+    tets with a PML 3 cubes thick (57.8% of the elements), p=3, central
+    flux, z-dipole, 8 probes, 2000 steps, checkpoint every 100; central
+    differences (delta = 1e-6 eps) of the forward objective on the 8 probe
+    elements and 8 random ones (seed 5)."""
+    from paper_2002_08733_amd import Solver
+    w = W.adjoint_pml()
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+    probes = w.info["probes"]
+    d = w.dipoles[0]
+    dip = (d[0][None], d[1][None], np.array([[d[2][0], d[2][1], 5.0 / (2 * np.pi * d[2][1])]]))
+    nsteps = 2000
+
+    def make(eps):
+        s = Solver(3, "fp64", "central", dt=dt)
+        s.set_mesh(w.verts, w.tets)
+        s.set_material(eps, w.mu)
+        s.set_pml(w.omega)
+        s.set_dipoles(*dip)
+        s.bind_torch_workspace()
+        return s
+
+    s = make(w.eps)
+    say(f"[adjoint full size] K={w.nt} ({s.query()['n_pml']} PML), {nsteps} steps, checkpoint every 100")
+    J, g = s.adjoint_probe_energy(nsteps, 100, probes)
+    s.close()
+    s = make(w.eps)
+    Jf = s.probe_energy(nsteps, probes)
+    s.close()
+    say(f"  J = {J:.12e} (forward only {Jf:.12e}), |grad| max {np.abs(g).max():.3e}")
+    assert J == Jf
+    rng = np.random.default_rng(5)
+    elems = np.concatenate([probes, rng.choice(w.nt, 8, replace=False)])
+    worst = 0.0
+    for T in elems:
+        h = 1e-6 * w.eps[T]
+        Jpm = []
+        for sgn in (1, -1):
+            e = w.eps.copy()
+            e[T] += sgn * h
+            s = make(e)
+            Jpm.append(s.probe_energy(nsteps, probes))
+            s.close()
+        fd = (Jpm[0] - Jpm[1]) / (2 * h)
+        bound = 1e-5 * abs(fd) + 1e-7 * np.abs(g).max()
+        ratio = abs(g[T] - fd) / bound
+        worst = max(worst, ratio)
+        say(f"  element {T} ({'PML' if w.omega[T].any() else 'inner'}): adjoint {g[T]:+.8e}  fd {fd:+.8e}  "
+            f"|diff|/bound {ratio:.2f}")
+    assert worst <= 1.0
+
+
 def test_autograd_function():
     import torch
     from paper_2002_08733_amd.autograd import ProbeEnergyProblem

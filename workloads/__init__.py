@@ -245,6 +245,31 @@ def open_pml(n=48, p=3, layers=4, inner=1.0, sigma_max=20.0, flux="upwind"):
                                       "sigma_max": sigma_max, "dipole_tet": t0})
 
 
+def containing_tet(verts, tets, x, tol=1e-12):
+    """Lowest-index tet whose closure contains the point x (barycentric test)."""
+    X = verts[tets]  # [nt,4,3]
+    A = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+    lam = np.linalg.solve(A, (np.asarray(x, dtype=np.float64)[None, :] - X[:, 0])[:, :, None])[:, :, 0]
+    bary = np.concatenate([1.0 - lam.sum(axis=1, keepdims=True), lam], axis=1)
+    idx = np.flatnonzero(np.all(bary >= -tol, axis=1))
+    if idx.size == 0:
+        raise ValueError("point outside the mesh")
+    return int(idx[0])
+
+
+def adjoint_pml(n=24, p=3, layers=3):
+    """The adjoint workload: open_pml with n^3 cubes (inner [-1,1]^3 of n-2*layers
+    cubes per axis plus a PML ``layers`` cubes thick), central flux, the z-dipole
+    at the origin, and 8 probe elements: the lowest-index tet containing each
+    point (+-1/2, +-1/2, +-1/2)."""
+    w = open_pml(n, p, layers=layers, flux="central")
+    probes = [containing_tet(w.verts, w.tets, np.array([sx, sy, sz]))
+              for sx in (-0.5, 0.5) for sy in (-0.5, 0.5) for sz in (-0.5, 0.5)]
+    w.info["probes"] = np.array(probes, dtype=np.int64)
+    w.name = f"adjoint_pml_n{n}_p{p}"
+    return w
+
+
 def cfl_dt(verts, tets, eps, mu, p, cfl):
     """Explicit step from a CFL number: dt = cfl * min_T(2 r_in sqrt(eps mu)) / (p+1)^2,
     r_in = 3|T| / (sum of face areas). Mesh geometry only (no DG arithmetic)."""
