@@ -226,7 +226,8 @@ void setup_dipoles(Solver& s, int n, const int32_t* inst, const double* pos, con
 size_t stage_lds_bytes(const Solver& s) {
   // trace slots of the tile's faces and of its halo, plus 16 bytes of slack
   // for the 16-byte granules of the halo copy
-  return (4ull * s.NF + 1) * (4ull * s.tile + s.hmax) * s.real_size() + 16;
+  const size_t rs = s.real_size();
+  return ((4ull * s.NF + 1) * 4ull * s.tile + 2ull * halo_role_reals(s.NF, (int)rs) * s.hmax) * rs + 16;
 }
 
 int tile_size_for(int P, bool fp32) {
@@ -331,7 +332,7 @@ void finalize(Solver& s) {
     s.halo_tile.assign(2 * s.ntiles, 0);
     s.hmax = 0;
     s.nhalo = 0;
-    const int64_t SS = 4 * s.NF + 1;         // reals per trace slot
+    const int64_t SH = 2 * halo_role_reals(s.NF, (int)rs);  // reals per halo slot
     const int64_t align = 64 / (int64_t)rs;  // halo blocks start on 64-byte boundaries
     int64_t hoff = 0;
     struct HE { int32_t fn; int64_t kn; int64_t k; int f; };
@@ -358,12 +359,12 @@ void finalize(Solver& s) {
       });
       for (size_t h = 0; h < ents.size(); ++h) {
         NB(ents[h].f, ents[h].k) = (int32_t)(4 * tile + h);
-        PUB(ents[h].fn, ents[h].kn) = (int32_t)(hoff + (int64_t)h * SS);
+        PUB(ents[h].fn, ents[h].kn) = (int32_t)(hoff + (int64_t)h * SH);
       }
       const int64_t nh = (int64_t)ents.size();
       s.halo_tile[2 * t] = (int32_t)hoff;
       s.halo_tile[2 * t + 1] = (int32_t)nh;
-      hoff = (hoff + nh * SS + align - 1) / align * align;
+      hoff = (hoff + nh * SH + align - 1) / align * align;
       if (hoff >= (int64_t(1) << 31)) throw Error(MDG_E_UNSUPPORTED, "mesh too large: halo buffer exceeds 2^31 reals");
       s.nhalo += nh;
       s.hmax = std::max<int>(s.hmax, (int)nh);

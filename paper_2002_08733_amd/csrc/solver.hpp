@@ -120,6 +120,11 @@ void setup_dipoles(Solver& s, int n, const int32_t* inst, const double* pos, con
 void finalize(Solver& s);  // ordering, tiles, halo, geometry records, layout
 double cfl_dt(const Solver& s);
 int tile_size_for(int P, bool fp32);
+// Halo trace slots: the two tangential traces of one field (2 NF reals) are
+// padded to a multiple of 16 bytes, so a slot holds 2 hrr reals and every
+// field block starts 16-byte aligned (the publishing lane writes it with
+// 16-byte stores). In-tile slots keep the odd stride 4 NF + 1.
+inline int halo_role_reals(int NF, int rs) { return (2 * NF * rs + 15) / 16 * 16 / rs; }
 // dynamic LDS of one stage-kernel workgroup: the face-trace exchange
 size_t stage_lds_bytes(const Solver& s);
 constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // gfx950 LDS per workgroup

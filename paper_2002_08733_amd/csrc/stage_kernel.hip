@@ -300,6 +300,43 @@ template <int NF>
 __device__ __forceinline__ int lbase(int slot, int role) { return slot * slot_stride<NF>() + role * 2 * NF; }
 template <int NF>
 constexpr int loff(int k, int m) { return k * NF + m; }
+// halo slots (index 4 tile + h): field blocks of hrr reals, 16-byte aligned
+template <int NF, typename R>
+constexpr int hrr() { return (2 * NF * (int)sizeof(R) + 15) / 16 * 16 / (int)sizeof(R); }
+// LDS offset of field `role`'s traces in slot `slot` (in-tile or halo)
+template <int NF, typename R>
+__device__ __forceinline__ int slot_base(int slot, int role, int tile) {
+  const int h = slot - 4 * tile;
+  return h < 0 ? lbase<NF>(slot, role) : 4 * tile * slot_stride<NF>() + (2 * h + role) * hrr<NF, R>();
+}
+// stores the NV consecutive reals v at byte offset vo (16-byte aligned) of r
+template <typename R, int NV>
+__device__ __forceinline__ void bst_run(const R (&v)[NV], Rsrc r, uint32_t vo) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  constexpr int ND = NV * (int)sizeof(R) / 4;
+  uint32_t w[ND];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    if constexpr (sizeof(R) == 4) {
+      w[i] = __builtin_bit_cast(uint32_t, v[i]);
+    } else {
+      const u32x2 d = __builtin_bit_cast(u32x2, v[i]);
+      w[2 * i] = d.x;
+      w[2 * i + 1] = d.y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i + 4 <= ND; i += 4) {
+    const u32x4 q = {w[i], w[i + 1], w[i + 2], w[i + 3]};
+    __builtin_amdgcn_raw_buffer_store_b128(q, r, vo, (uint32_t)(4 * i), 0);
+  }
+  if constexpr (ND % 4 >= 2) {
+    const u32x2 q = {w[ND / 4 * 4], w[ND / 4 * 4 + 1]};
+    __builtin_amdgcn_raw_buffer_store_b64(q, r, vo, (uint32_t)(4 * (ND / 4 * 4)), 0);
+  }
+  if constexpr (ND % 2 == 1) __builtin_amdgcn_raw_buffer_store_b32(w[ND - 1], r, vo, (uint32_t)(4 * (ND - 1)), 0);
+}
 
 // components of a field that enter the tangential trace on face F
 template <int F>
@@ -319,13 +356,16 @@ __device__ __forceinline__ void publish_face(const R* stg, int role, int tile, i
     for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((role * 3 + c) * N + l) * tile + li] : R(0);
   R t0[NF], t1[NF];
   face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
-  // a field's traces feed the neighbour lanes of the other role
-  const uint32_t base = (uint32_t)(code + (1 - role) * 2 * NF) * (uint32_t)sizeof(R);
+  // a field's traces feed the neighbour lanes of the other role; the field
+  // block of the halo slot is 16-byte aligned, so it goes out in 16-byte stores
+  const uint32_t base = (uint32_t)(code + (1 - role) * hrr<NF, R>()) * (uint32_t)sizeof(R);
+  R v[2 * NF];
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
-    bst<R>(t0[m], rH, base, (uint32_t)(m * sizeof(R)));
-    bst<R>(t1[m], rH, base, (uint32_t)((NF + m) * sizeof(R)));
+    v[m] = t0[m];
+    v[NF + m] = t1[m];
   }
+  bst_run<R, 2 * NF>(v, rH, base);
 }
 
 // RK4 stage epilogue, one code path for every stage. The descriptors select
@@ -407,7 +447,7 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   const int sn = has ? code : so;
   const R fin = has ? R(1) : g;
   const R* own = lds + lbase<NF>(so, role);
-  const R* nbr = lds + lbase<NF>(sn, role);
+  const R* nbr = lds + slot_base<NF, R>(sn, role, tile);
   const R om = role ? R(1) - wz : wz;  // own weight of the averaged input field
   const R rsign = (F == 0 || F == 2) ? R(1) : R(-1);  // sigma^_f = (+,-,+,-)
   const R c = -g * rsign * sgn;
@@ -424,7 +464,7 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   }
   if constexpr (UPW) {
     const R* own_o = lds + lbase<NF>(so, 1 - role);
-    const R* nbr_o = lds + lbase<NF>(sn, 1 - role);
+    const R* nbr_o = lds + slot_base<NF, R>(sn, 1 - role, tile);
     R g11, g12, g22;
     face_metric_rt<R>(F, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
     const R idet = R(1) / sqrt(g11 * g22 - g12 * g12);
@@ -581,7 +621,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   {
     typedef __attribute__((address_space(3))) unsigned char lds_byte;
     const int hoff = a.halo_tile[2 * t], nh = a.halo_tile[2 * t + 1];
-    const uint32_t nbytes = ((uint32_t)nh * SS * RS + 15u) & ~15u;
+    const uint32_t nbytes = ((uint32_t)nh * 2u * hrr<NF, R>() * RS + 15u) & ~15u;
     const Rsrc rH = make_rsrc(a.hin, a.hbuf_bytes);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6), nwv = blockDim.x >> 6;
     lds_byte* dst = (lds_byte*)smem_raw + 4u * (uint32_t)tile * SS * RS;
@@ -901,7 +941,7 @@ __device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], 
   constexpr int NF = Ops<P>::NF;
   R t0[NF], t1[NF];
   face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
-  const uint32_t base = (uint32_t)(code + (1 - fld) * 2 * NF) * (uint32_t)sizeof(R);
+  const uint32_t base = (uint32_t)(code + (1 - fld) * hrr<NF, R>()) * (uint32_t)sizeof(R);
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
     bst<R>(t0[m], rH, base, (uint32_t)(m * sizeof(R)));
