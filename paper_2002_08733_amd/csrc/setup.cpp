@@ -230,6 +230,12 @@ size_t stage_lds_bytes(const Solver& s) {
   return ((4ull * s.NF + 1) * 4ull * s.tile + 2ull * halo_role_reals(s.NF, (int)rs) * s.hmax) * rs + 16;
 }
 
+size_t lf_lds_bytes(const Solver& s) {
+  const size_t rs = s.real_size();
+  const size_t slots = (2ull * s.NF + 1) * 4ull * s.tile + 2ull * halo_role_reals(s.NF, (int)rs) * s.hmax;
+  return std::max<size_t>(slots, 3ull * s.N * s.tile) * rs + 16;
+}
+
 int tile_size_for(int P, bool fp32) {
   // elements per workgroup (eight lanes each: 2 fields x 4 parts, so 2*tile
   // must be a multiple of the 64-lane wave); the trace exchange in LDS needs
@@ -302,6 +308,10 @@ void finalize(Solver& s) {
   const bool fp32 = s.opt.precision == MDG_FP32;
   const size_t rs = s.real_size();
   int tile0 = tile_size_for(s.P, fp32);
+  // leap-frog: 64-element tiles let the half steps give all lanes to the
+  // active field (the operator calls then may use a larger workgroup LDS)
+  const bool lf = s.opt.integrator == MDG_LEAPFROG;
+  if (lf) tile0 = 64;
   const bool forced = s.opt.tile != 0;  // a caller's choice (e.g. an autotuner)
   if (forced) tile0 = s.opt.tile;
   for (int tile = tile0;; tile /= 2) {
@@ -374,6 +384,7 @@ void finalize(Solver& s) {
     // the default choice keeps two workgroups per CU; a forced tile only has
     // to fit the LDS of one workgroup
     if (lds <= 64 * 1024 || (forced && lds <= LDS_MAX_BYTES)) break;
+    if (lf && tile == 64 && lf_lds_bytes(s) <= LDS_MAX_BYTES / 2 && lds <= LDS_MAX_BYTES) break;
     if (tile <= 32) {
       // up to 160 KiB per workgroup on gfx950 (checked against the device at bind time)
       if (lds <= LDS_MAX_BYTES) break;

@@ -127,6 +127,9 @@ int tile_size_for(int P, bool fp32);
 inline int halo_role_reals(int NF, int rs) { return (2 * NF * rs + 15) / 16 * 16 / rs; }
 // dynamic LDS of one stage-kernel workgroup: the face-trace exchange
 size_t stage_lds_bytes(const Solver& s);
+// leap-frog halves with four lanes per element (64-element tiles): the input
+// field staged, compact in-tile slots, the same halo slots
+size_t lf_lds_bytes(const Solver& s);
 constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
 void projection_points(const Solver& s, int q, double* xyz);
 void project_fields(const Solver& s, int q, const double* vals, int N, std::vector<double>& coef);

@@ -294,20 +294,24 @@ __device__ __forceinline__ void volume_q(const V& v, R gs, R (&acc)[3][nq<P>()])
 // [role][k][m] = 4 NF reals, padded to an odd stride so that consecutive lanes
 // (consecutive slots) hit distinct banks. A lane keeps one base address per
 // slot; role, k and m become immediate offsets.
-template <int NF>
-constexpr int slot_stride() { return 4 * NF + 1; }
-template <int NF>
-__device__ __forceinline__ int lbase(int slot, int role) { return slot * slot_stride<NF>() + role * 2 * NF; }
+// C (compact): leap-frog halves with one field per workgroup keep only that
+// field's input traces in the in-tile slots (stride 2 NF + 1)
+template <int NF, bool C = false>
+constexpr int slot_stride() { return C ? 2 * NF + 1 : 4 * NF + 1; }
+template <int NF, bool C = false>
+__device__ __forceinline__ int lbase(int slot, int role) {
+  return slot * slot_stride<NF, C>() + (C ? 0 : role * 2 * NF);
+}
 template <int NF>
 constexpr int loff(int k, int m) { return k * NF + m; }
 // halo slots (index 4 tile + h): field blocks of hrr reals, 16-byte aligned
 template <int NF, typename R>
 constexpr int hrr() { return (2 * NF * (int)sizeof(R) + 15) / 16 * 16 / (int)sizeof(R); }
 // LDS offset of field `role`'s traces in slot `slot` (in-tile or halo)
-template <int NF, typename R>
+template <int NF, typename R, bool C = false>
 __device__ __forceinline__ int slot_base(int slot, int role, int tile) {
   const int h = slot - 4 * tile;
-  return h < 0 ? lbase<NF>(slot, role) : 4 * tile * slot_stride<NF>() + (2 * h + role) * hrr<NF, R>();
+  return h < 0 ? lbase<NF, C>(slot, role) : 4 * tile * slot_stride<NF, C>() + (2 * h + role) * hrr<NF, R>();
 }
 // stores the NV consecutive reals v at byte offset vo (16-byte aligned) of r
 template <typename R, int NV>
@@ -347,13 +351,13 @@ constexpr bool face_needs(int c) {
 // trace of a field on face F from the LDS output staging [role][3N][tile],
 // stored to its halo-buffer slot: [input role of the field][k][m]
 template <int P, int F, typename R>
-__device__ __forceinline__ void publish_face(const R* stg, int role, int tile, int li, Rsrc rH, int code) {
+__device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int tile, int li, Rsrc rH, int code) {
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
   R w[3][N];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((role * 3 + c) * N + l) * tile + li] : R(0);
+    for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((sf * 3 + c) * N + l) * tile + li] : R(0);
   R t0[NF], t1[NF];
   face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
   // a field's traces feed the neighbour lanes of the other role; the field
@@ -376,18 +380,19 @@ __device__ __forceinline__ void publish_face(const R* stg, int role, int tile, i
 //   stage 3:    Y   = y + dt (a + b k)                      (ACC store dropped)
 //   operator:   Uout = k                                    (y = a = 0, c dt = 1)
 //   leap-frog half (stage 4: E, 5: H): Y = y + dt k for the active field, with
-//               y taken from the staged input (the stage input is Y itself)
+//               y taken from the staged input (the stage input is Y itself) or,
+//               with four lanes per element, loaded like the RK4 operands
 struct Epi {
   Rsrc y_rd, a_rd, a_wr, out_wr;
   bool final_stage;
   double c_out;  // c_{i+1} dt, dt (final, leap-frog) or 1 (operator)
 };
 __device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* ACC, const void* Uout,
-                                        uint32_t bytes, double bcoef, double cdt, double dt) {
+                                        uint32_t bytes, double bcoef, double cdt, double dt, bool y_staged) {
   Epi e;
   const bool op = stage < 0, lf = stage >= 4;
   e.final_stage = stage == 3;
-  e.y_rd = make_rsrc(Y, (op || lf) ? 0u : bytes);
+  e.y_rd = make_rsrc(Y, (op || (lf && y_staged)) ? 0u : bytes);
   e.a_rd = make_rsrc(ACC, (stage >= 1 && stage <= 3) ? bytes : 0u);
   e.a_wr = make_rsrc(ACC, (stage >= 0 && stage <= 2) ? bytes : 0u);
   e.out_wr = make_rsrc((e.final_stage || lf) ? Y : Uout, bytes);
@@ -434,7 +439,7 @@ __device__ __forceinline__ void face_metric_rt(int F, R gxx, R gxy, R gxz, R gyy
 // flux coefficients of face F in the face basis: the lift of the face term
 // is sum_m T_F[m][l] (t^1 A1[m] + t^2 A2[m]). No reference matrix enters, so
 // the face index is a runtime (wave-uniform) value.
-template <int P, bool UPW, typename R>
+template <int P, bool UPW, typename R, bool C = false>
 __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, int tile, int li, int code, R g,
                                                R sgn, R wz, R Z, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz,
                                                R (&A1)[Ops<P>::NF], R (&A2)[Ops<P>::NF]) {
@@ -446,8 +451,8 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   const bool has = code >= 0;
   const int sn = has ? code : so;
   const R fin = has ? R(1) : g;
-  const R* own = lds + lbase<NF>(so, role);
-  const R* nbr = lds + slot_base<NF, R>(sn, role, tile);
+  const R* own = lds + lbase<NF, C>(so, role);
+  const R* nbr = lds + slot_base<NF, R, C>(sn, role, tile);
   const R om = role ? R(1) - wz : wz;  // own weight of the averaged input field
   const R rsign = (F == 0 || F == 2) ? R(1) : R(-1);  // sigma^_f = (+,-,+,-)
   const R c = -g * rsign * sgn;
@@ -463,8 +468,8 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
     A2[m] = -c * xw0;
   }
   if constexpr (UPW) {
-    const R* own_o = lds + lbase<NF>(so, 1 - role);
-    const R* nbr_o = lds + slot_base<NF, R>(sn, 1 - role, tile);
+    const R* own_o = lds + lbase<NF, C>(so, 1 - role);
+    const R* nbr_o = lds + slot_base<NF, R, C>(sn, 1 - role, tile);
     R g11, g12, g22;
     face_metric_rt<R>(F, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
     const R idet = R(1) / sqrt(g11 * g22 - g12 * g12);
@@ -485,13 +490,13 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
 
 // lift of all four faces onto the modes of part Q; the flux coefficients of
 // face F of this element were published in its slot F*tile + li
-template <int P, int Q, typename R>
+template <int P, int Q, typename R, bool C = false>
 __device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int li, R (&acc)[3][nq<P>()]) {
   constexpr int NF = Ops<P>::NF;
 #define MDG_LIFT_FACE(F)                                                   \
   {                                                                        \
     asm volatile("" ::: "memory");                                         \
-    const R* s_ = lds + lbase<NF>((F) * tile + li, role);                  \
+    const R* s_ = lds + lbase<NF, C>((F) * tile + li, role);               \
     R A1[NF], A2[NF];                                                      \
     _Pragma("unroll") for (int m = 0; m < NF; ++m) {                       \
       A1[m] = s_[loff<NF>(0, m)];                                          \
@@ -521,13 +526,17 @@ constexpr int waves_per_eu() { return sizeof(R) == 4 ? 4 : 2; }
   }
 
 // LF: leap-frog half steps (stage 4/5), central flux only; the RK4 and
-// operator launches use LF = false, for which every leap-frog branch folds away
-template <typename R, int P, bool UPW, bool PML, bool LF>
+// operator launches use LF = 0, for which every leap-frog branch folds away.
+// LF = 1 keeps eight lanes per element (both roles, one of them idle);
+// LF = 2 (64-element tiles) gives every lane to the active field: four lanes
+// per element and compact slots, so that four workgroups share a CU.
+template <typename R, int P, bool UPW, bool PML, int LF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
     DevArgs a) {
   static_assert(!(LF && UPW), "leap-frog halves need the central flux");
+  constexpr bool C = LF == 2;
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
-  constexpr int SS = slot_stride<NF>();
+  constexpr int SS = slot_stride<NF, C>();
   constexpr uint32_t RS = sizeof(R);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
@@ -539,13 +548,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // the step's clock advances once, from a launch that no other kernel of the
   // step overlaps (the amplitudes of this stage were evaluated before it)
   if (a.tick && b == 0 && threadIdx.x == 0) a.tick[1] = a.tick[1] + 1.0;
-  const int tile = blockDim.x >> 3;  // 8 lanes per element: 2 roles x 4 parts
+  // 8 lanes per element (2 roles x 4 parts), or 4 (the active role's parts)
+  const int tile = blockDim.x >> (C ? 2 : 3);
   const int tid = threadIdx.x;
-  // 2*tile is a multiple of 64, so the part is uniform within a wave
-  const int part = __builtin_amdgcn_readfirstlane(tid / (2 * tile));
-  const int rem = tid - part * 2 * tile;
-  const int role = rem >= tile;
-  const int li = rem - role * tile;
+  // the lanes of one part are a multiple of 64, so the part is uniform in a wave
+  const int part = __builtin_amdgcn_readfirstlane(tid / (C ? tile : 2 * tile));
+  const int rem = tid - part * (C ? tile : 2 * tile);
+  const int role = C ? a.stage - 4 : (rem >= tile);
+  const int li = rem - (C ? 0 : role * tile);
   const int start = a.elem_begin + tl * tile;
   const int cnt = min(tile, a.elem_end - start);
   // Lanes past the end of a partial tile compute on padding (arrays are padded
@@ -575,7 +585,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 
   // 2. RK operands of this part's output rows, issued now so that their
   // latency overlaps the trace, volume and flux work (absent operands read as 0)
-  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt);
+  // (with four lanes per element no lane stages the output field, and the
+  // compact slots leave no room for it beside the halo slots)
+  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt, LF == 1);
   R ypre[3][NQ], apre[3][NQ];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -590,7 +602,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 #pragma unroll
   for (int i = 0; i < RQ; ++i) {
     const int r = part * RQ + i;
-    if (r < R3) stg[((1 - role) * R3 + r) * tile + li] = vq[i];
+    if (r < R3) stg[((C ? 0 : 1 - role) * R3 + r) * tile + li] = vq[i];
   }
   __syncthreads();  // B0: the tile's input fields are staged
 
@@ -604,7 +616,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // field, which is what lets the halves share one halo buffer.
   const int lf = LF ? a.stage - 4 : -1;
   const bool wr = live && (!LF || lf == role);
-  if (LF) {
+  if (LF == 1) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -634,7 +646,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // 4. trace of the input field on face `part` and the volume term of the
   // part's modes, both reading the input field from the staging (not held in
   // registers, which keeps the register budget at five waves per SIMD)
-  const R* vin_lds = stg + (1 - role) * R3 * tile + li;
+  const R* vin_lds = stg + (C ? 0 : 1 - role) * R3 * tile + li;
   auto vl = [&](int c, int l) { return vin_lds[(c * N + l) * tile]; };
   const R g = role ? R(-1) : R(1);
   // sign(det A); the adjoint operator negates the skew part (volume curl and
@@ -651,7 +663,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 #pragma unroll
       for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(acc[c][i]));
     __syncthreads();  // B0': every lane has read the staging
-    R* d = lds + lbase<NF>(part * tile + li, role);
+    R* d = lds + lbase<NF, C>(part * tile + li, role);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
       d[loff<NF>(0, m)] = t0[m];
@@ -695,11 +707,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // 7. flux coefficients of face `part`
   {
     R A1[NF], A2[NF];
-    face_flux_coef<P, UPW, R>(part, lds, role, tile, li, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz, gzz, A1,
-                              A2);
+    face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz, gzz,
+                                 A1, A2);
     __syncthreads();  // B2: every flux read of this tile is done
     // publish the flux coefficients of face `part` in its own slot
-    R* d = lds + lbase<NF>(part * tile + li, role);
+    R* d = lds + lbase<NF, C>(part * tile + li, role);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
       d[loff<NF>(0, m)] = A1[m];
@@ -709,7 +721,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   __syncthreads();  // B3
 
   // 8. lift of the four faces onto this part's modes
-  MDG_SWITCH_Q((lift_all_q<P, Q, R>(lds, role, tile, li, acc)));
+  MDG_SWITCH_Q((lift_all_q<P, Q, R, C>(lds, role, tile, li, acc)));
 
   // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j, with the
   // amplitudes g(t) of the stage's time evaluated just before the launch
@@ -759,7 +771,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const Rsrc rP = make_rsrc(a.pml, a.pml_bytes);
     const uint32_t vp = blk_base(pk, NPML, RS);
     const Rsrc raU = make_rsrc(a.aUin, a.aux_bytes);
-    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.aux_bytes, a.bcoef, a.cdt, a.dt);
+    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.aux_bytes, a.bcoef, a.cdt, a.dt, false);
     const R ca = R(ea.c_out);
     const uint32_t va = blk_base(pk, 2 * R3, RS) + role * rowb<R>(R3);
     R AT[9], AiT[9];
@@ -855,18 +867,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // face Q of its element into the neighbour tile's halo block
   if (a.publish) {
     __syncthreads();  // B4: the lifts are done with the trace area
-    R* stg = lds;     // [role][3N][tile]
+    R* stg = lds;     // [role][3N][tile] ([active field][3N][tile] with four lanes per element)
+    const int sf = C ? 0 : role;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int l = part * NQ + q;
-        if (l < N) stg[((role * 3 + c) * N + l) * tile + li] = acc[c][q];
+        if (l < N) stg[((sf * 3 + c) * N + l) * tile + li] = acc[c][q];
       }
     __syncthreads();  // B5
     if (wr && pcode >= 0) {
       const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
-      MDG_SWITCH_Q((publish_face<P, Q, R>(stg, role, tile, li, rHo, pcode)));
+      MDG_SWITCH_Q((publish_face<P, Q, R>(stg, sf, role, tile, li, rHo, pcode)));
     }
   }
 }
@@ -979,7 +992,7 @@ static void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <typename R, int P, bool UPW, bool PML, bool LF>
+template <typename R, int P, bool UPW, bool PML, int LF>
 static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
   const int grid = (a.ntiles + 7) / 8 * 8;
   if (lds > 64 * 1024) {
@@ -987,7 +1000,7 @@ static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
               "hipFuncSetAttribute(dynamic LDS)");
   }
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF>), dim3(grid), dim3(8 * tile), lds, st, a);
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF>), dim3(grid), dim3((LF == 2 ? 4 : 8) * tile), lds, st, a);
   hip_check(hipGetLastError(), "stage_kernel launch");
 }
 
@@ -995,14 +1008,19 @@ template <typename R, int P>
 static void launch_p(const DevArgs& a, bool upw, bool pml, int tile, size_t lds, hipStream_t st) {
   if (a.stage >= 4) {  // leap-frog half (central flux, checked at creation)
     if (upw) throw Error(MDG_E_UNSUPPORTED, "leap-frog needs the central flux");
-    if (pml) launch_one<R, P, false, true, true>(a, tile, lds, st);
-    else launch_one<R, P, false, false, true>(a, tile, lds, st);
+    if (tile % 64 == 0) {  // four lanes per element
+      if (pml) launch_one<R, P, false, true, 2>(a, tile, lds, st);
+      else launch_one<R, P, false, false, 2>(a, tile, lds, st);
+    } else {
+      if (pml) launch_one<R, P, false, true, 1>(a, tile, lds, st);
+      else launch_one<R, P, false, false, 1>(a, tile, lds, st);
+    }
   } else if (upw) {
-    if (pml) launch_one<R, P, true, true, false>(a, tile, lds, st);
-    else launch_one<R, P, true, false, false>(a, tile, lds, st);
+    if (pml) launch_one<R, P, true, true, 0>(a, tile, lds, st);
+    else launch_one<R, P, true, false, 0>(a, tile, lds, st);
   } else {
-    if (pml) launch_one<R, P, false, true, false>(a, tile, lds, st);
-    else launch_one<R, P, false, false, false>(a, tile, lds, st);
+    if (pml) launch_one<R, P, false, true, 0>(a, tile, lds, st);
+    else launch_one<R, P, false, false, 0>(a, tile, lds, st);
   }
 }
 
@@ -1059,7 +1077,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.dt = sp.dt;
   const bool fp32 = s.opt.precision == MDG_FP32;
   const bool upw = s.opt.flux == MDG_UPWIND;
-  const size_t lds = stage_lds_bytes(s);
+  const size_t lds = (sp.stage >= 4 && s.tile % 64 == 0) ? lf_lds_bytes(s) : stage_lds_bytes(s);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (a.has_src) {
     const int nd = (int)s.dips.size();
