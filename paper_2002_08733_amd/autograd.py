@@ -18,21 +18,26 @@ class ProbeEnergyProblem:
     """Mesh, initial state, sources and run length of the objective; eps is
     the differentiable input. E0/H0 are covariant coefficients [nt][3][N]
     (they do not depend on eps). dipoles = (pos[n][3], dir[n][3], wave[n][3])
-    or None."""
+    or None; omega[nt][3] per-axis PML damping or None (the PML starts at
+    rest); mixed pairs e at order+1 with h at order (H0 then has the modes of
+    h's order)."""
 
     def __init__(self, verts, tets, order, E0, H0, dt, nsteps, every, probes, mu=None, dipoles=None,
-                 precision="fp64"):
+                 precision="fp64", omega=None, mixed=False):
         self.verts, self.tets, self.order = verts, tets, order
         self.E0, self.H0, self.mu, self.dipoles = E0, H0, mu, dipoles
+        self.omega, self.mixed = omega, mixed
         self.dt, self.nsteps, self.every = dt, nsteps, every
         self.probes = np.asarray(probes, dtype=np.int64)
         self.precision = precision
 
     def run(self, eps):
-        s = Solver(self.order, self.precision, "central", dt=self.dt)
+        s = Solver(self.order, self.precision, "central", dt=self.dt, mixed=self.mixed)
         try:
             s.set_mesh(self.verts, self.tets)
             s.set_material(eps, self.mu)
+            if self.omega is not None:
+                s.set_pml(self.omega)
             if self.dipoles is not None:
                 s.set_dipoles(*self.dipoles)
             s.bind_torch_workspace()

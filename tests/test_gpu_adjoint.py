@@ -209,16 +209,30 @@ def test_adjoint_fullsize_pml_against_finite_differences():
     assert worst <= 1.0
 
 
-def test_autograd_function():
+@pytest.mark.parametrize("pml", [False, True])
+def test_autograd_function(pml):
     import torch
     from paper_2002_08733_amd.autograd import ProbeEnergyProblem
     w, E0, H0, dip = _medium()
     probes = np.array([5, 222])
-    prob = ProbeEnergyProblem(w.verts, w.tets, w.p, E0, H0, 2e-3, 20, 5, probes, dipoles=dip)
+    omega = None
+    if pml:
+        c = W.tet_centroids(w.verts, w.tets)
+        omega = np.zeros((w.nt, 3))
+        omega[c[:, 0] > 0.4] = 3.0
+    prob = ProbeEnergyProblem(w.verts, w.tets, w.p, E0, H0, 2e-3, 20, 5, probes, dipoles=dip, omega=omega)
     eps = torch.tensor(w.eps, dtype=torch.float64, requires_grad=True)
     J = prob(eps)
     (gt,) = torch.autograd.grad(3.0 * J, eps)
     Jd, gd = prob.run(w.eps)
-    say(f"[autograd] J={J.item():.10e}")
+    say(f"[autograd] pml={pml}: J={J.item():.10e}")
     assert J.item() == Jd
     assert np.array_equal(gt.numpy(), 3.0 * gd)
+    # the same objective through the library directly, finite differences on one element
+    T = 222
+    h = 1e-6 * w.eps[T]
+    e1, e2 = w.eps.copy(), w.eps.copy()
+    e1[T] += h
+    e2[T] -= h
+    fd = (prob.run(e1)[0] - prob.run(e2)[0]) / (2 * h)
+    assert abs(gd[T] - fd) <= 1e-5 * abs(fd) + 1e-7 * np.abs(gd).max()

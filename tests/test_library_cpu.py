@@ -102,6 +102,13 @@ def test_error_paths(lib):
     with pytest.raises(lib.MdgError) as e:
         s.step(1)
     assert e.value.status == lib.MDG_E_STATE
+    # objective and adjoint need a bound workspace too (no device call is made)
+    with pytest.raises(lib.MdgError) as e:
+        s.probe_energy(3, [0, 1])
+    assert e.value.status == lib.MDG_E_STATE
+    with pytest.raises(lib.MdgError) as e:
+        s.adjoint_probe_energy(3, 1, [0])
+    assert e.value.status == lib.MDG_E_STATE
     with pytest.raises(lib.MdgError) as e:
         s.set_dipoles(np.array([[5.0, 5.0, 5.0]]), np.array([[0, 0, 1.0]]), np.array([[2.0, 1.0, 0.4]]))
     assert e.value.status == lib.MDG_E_ARG
