@@ -23,6 +23,13 @@ with R_E (curl, flux, current) free of eps for the central flux, so at fixed
 state dF_E/deps_T = -(F_E + eta e)/eps_T and dF_pE/deps_T = xi e on the rows
 of T, zero elsewhere. The adjoint sweep uses the transposed assembled
 operator including the auxiliary rows.
+
+Upwind flux: eps also enters the face weights through Z = sqrt(mu/eps), on
+every face of T and in the neighbours' equations. There dF/deps_T at fixed
+state is taken by central differences of the oracle's operator (relative
+step 1e-5, on the rows of T and its neighbours, the only ones it touches);
+the same route reproduces the analytic derivative above for the central
+flux (pinned in tests/test_oracle_adjoint.py).
 """
 import numpy as np
 
@@ -63,11 +70,23 @@ def _assemble_with_aux(O):
     return Lm
 
 
-def adjoint_gradient(O, cE0, cH0, dt, nsteps, probes):
-    """(J, dJ/deps[K]) by the discrete adjoint of RK4 with the assembled operator."""
+def _with_eps(O, eps):
+    """The same problem with another permittivity."""
+    from .dg import OracleDG
+    return OracleDG(O.verts, O.tets, O.p, eps=eps, mu=O.mu, flux=O.flux, omega=O.omega,
+                    dipoles=[(pos, d, g) for (_, pos, d, g) in O.dipoles], ph=O.ph)
+
+
+def adjoint_gradient(O, cE0, cH0, dt, nsteps, probes, deps=None):
+    """(J, dJ/deps[K]) by the discrete adjoint of RK4 with the assembled operator.
+    deps: "analytic" (central flux only) or "fd" (differences of the operator);
+    default analytic for the central flux, fd for the upwind flux."""
     K, N = O.K, O.N
     nE = K * 3 * N
     pml = O.omega is not None
+    deps = deps or ("analytic" if O.flux == "central" else "fd")
+    if deps == "analytic" and O.flux != "central":
+        raise ValueError("the analytic eps-derivative holds for the central flux only")
     if pml:
         from .dg import pml_tensors
         L = _assemble_with_aux(O)
@@ -106,6 +125,32 @@ def adjoint_gradient(O, cE0, cH0, dt, nsteps, probes):
     grad = np.zeros(K)
     lam = 2.0 * dt * w * x[nsteps]
     erow = np.repeat(np.arange(K), 3 * N)  # element of each E row
+    if deps == "fd":
+        # per element: the perturbed problems, the element and its neighbours,
+        # and their rows in the state vector (blocks e, h[, p_E, p_H])
+        NH = O.NH
+        blocks = [(0, N), (nE, NH)] + ([(nE + K * 3 * NH, N), (2 * nE + K * 3 * NH, NH)] if pml else [])
+        fd = []
+        for T in range(K):
+            el = np.array([T] + [sd // 4 for sd in O.nbr_side[T] if sd >= 0], dtype=np.int64)
+            rows = np.concatenate([off + (el[:, None] * 3 * nb + np.arange(3 * nb)[None, :]).ravel()
+                                   for off, nb in blocks])
+            h = 1e-5 * O.eps[T]
+            ep, em = O.eps.copy(), O.eps.copy()
+            ep[T] += h
+            em[T] -= h
+            fd.append((el, rows, h, _with_eps(O, ep), _with_eps(O, em)))
+
+        def split(X):
+            parts, off = [], 0
+            for nb in (N, NH) + ((N, NH) if pml else ()):
+                parts.append(X[off:off + K * 3 * nb].reshape(K, 3, nb))
+                off += K * 3 * nb
+            return parts + [None, None] * (not pml)
+
+        def dF_rows(Op, X, t, el):
+            d = Op.rhs(*split(X), t=t, elems=el)
+            return np.concatenate([v.ravel() for v in d if v is not None])
     for n in range(nsteps - 1, -1, -1):
         t = n * dt
         xn = x[n]
@@ -123,6 +168,12 @@ def adjoint_gradient(O, cE0, cH0, dt, nsteps, probes):
         mu1 = LT @ kap1
         stages = ((kap1, k1, xn), (kap2, k2, xn + 0.5 * dt * k1), (kap3, k3, xn + 0.5 * dt * k2),
                   (kap4, k4, xn + dt * k3))
+        if deps == "fd":
+            for (kap, kk, X), ts in zip(stages, (t, t + 0.5 * dt, t + 0.5 * dt, t + dt)):
+                for T, (el, rows, h, Op, Om) in enumerate(fd):
+                    dF = (dF_rows(Op, X, ts, el) - dF_rows(Om, X, ts, el)) / (2.0 * h)
+                    grad[T] += float(np.dot(kap[rows], dF))
+            stages = ()
         for kap, kk, X in stages:
             dFE = kk[:nE]
             if pml:
