@@ -235,12 +235,14 @@ mdg_status mdg_probe_energy(mdg_solver* s, int64_t nsteps, int32_t nprobe, const
  * states of each interval of `every` steps from checkpoints kept on the
  * device, and returns J and grad_eps[nt] = dJ/deps_T (caller's element order;
  * FP64 reductions, the state precision of the solver). probes[nprobe] are
- * element indices. Requires MDG_RK4 and the central flux (MDG_E_UNSUPPORTED):
- * the curl part of the stiffness is then skew, so the adjoint operator in
- * the mass inner product is the forward one with that part negated and the
- * PML couplings of [KS Sec. IV] transposed, and eps enters only through the
- * mass inverse of the curl part (the PML equations are written for P/eps and
- * Q/mu, whose values at the start are held fixed: zero for a PML at rest).
+ * element indices. Requires MDG_RK4 (MDG_E_UNSUPPORTED). The averaged part
+ * of the face terms and the volume curl are skew, the upwind penalties
+ * symmetric, so the adjoint operator in the mass inner product is the forward
+ * one with the skew part negated and the PML couplings of [KS Sec. IV]
+ * transposed. eps enters through the mass inverse of the curl part (the PML
+ * equations are written for P/eps and Q/mu, whose values at the start are
+ * held fixed: zero for a PML at rest) and, with the upwind flux, through the
+ * face impedances sqrt(mu/eps) of every face of an element.
  * Allocates (nsteps/every + every + 10) state vectors (fields and PML
  * auxiliaries) of device memory for the call. Synchronous. */
 mdg_status mdg_adjoint_probe_energy(mdg_solver* s, int64_t nsteps, int32_t every, int32_t nprobe,

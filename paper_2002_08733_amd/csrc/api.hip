@@ -374,6 +374,8 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
     hip_check(hipStreamSynchronize(st), "sync");
     upload(s, s.geo, s.L.geo, st);
     hip_check(hipMemcpyAsync(dev(s, s.L.nbr), s.nbr_code.data(), s.nbr_code.size() * 4, hipMemcpyHostToDevice, st), "nbr");
+    hip_check(hipMemcpyAsync(dev(s, s.L.nbrg), s.nbr_glob.data(), s.nbr_glob.size() * 4, hipMemcpyHostToDevice, st),
+              "nbrg");
     hip_check(hipMemcpyAsync(dev(s, s.L.pub), s.pub_code.data(), s.pub_code.size() * 4, hipMemcpyHostToDevice, st), "pub");
     hip_check(hipMemcpyAsync(dev(s, s.L.halo_tile), s.halo_tile.data(), s.halo_tile.size() * 4, hipMemcpyHostToDevice, st), "halo");
     hip_check(hipStreamSynchronize(st), "sync");
@@ -568,7 +570,6 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     if (nsteps < 1 || every < 1) throw Error(MDG_E_ARG, "adjoint: nsteps >= 1 and checkpoint interval >= 1");
     if (nprobe < 1 || !probes || !J || !grad_eps) throw Error(MDG_E_ARG, "adjoint: probes, J and grad_eps required");
     if (s.opt.integrator != MDG_RK4) throw Error(MDG_E_UNSUPPORTED, "adjoint: RK4 steps only");
-    if (s.opt.flux != MDG_CENTRAL) throw Error(MDG_E_UNSUPPORTED, "adjoint: central flux only");
     std::vector<int64_t> pin(nprobe);
     for (int i = 0; i < nprobe; ++i) {
       if (probes[i] < 0 || probes[i] >= s.nt) throw Error(MDG_E_ARG, "adjoint: probe element out of range");
@@ -576,7 +577,7 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     }
     // a state vector: fields (blocked layout) and, with PML elements, the
     // auxiliaries of the PML elements
-    const bool pml = s.Kp > 0;
+    const bool pml = s.Kp > 0, upw = s.opt.flux == MDG_UPWIND;
     const size_t SB = size_t(6) * s.N * s.Kpad * s.real_size();
     const size_t SA = pml ? size_t(6) * s.N * s.Kppad * s.real_size() : 0;
     struct SV {
@@ -640,9 +641,11 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     launch_probe_add(s, nu.u, uend.u, pd, nprobe, dt, stream);
     // g -= (a_i, K_i)_M0 over the E rows, K_i without its damping part on
     // PML elements (only the rest scales with 1/eps); X_i is the stage input
+    // with the upwind flux the face impedances depend on eps too: g += (a_i, dA/deps X_i)
     auto grad = [&](SV ai, SV Ki, SV Xi) {
       launch_grad_acc(s, g, ai.u, Ki.u, stream);
       if (pml) launch_grad_pml(s, g, ai.u, Xi.u, Xi.q, stream);
+      if (upw) launch_grad_upw(s, g, ai.u, Xi.u, stream);
     };
     static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
@@ -671,18 +674,18 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
         comb(X, 1.0, x, dt, &K4s[2]);
         op(X, K4s[3], cn[3], true, false);
         // adjoint stages (X holds X_4 here; the others are rebuilt for the
-        // PML part of the gradient)
+        // PML and upwind parts of the gradient)
         comb(a, dt / 6.0, nu);  // a4
         grad(a, K4s[3], X);
         op(a, m, 0.0, false, true);  // m4
         comb(msum, 1.0, m);
         comb(a, dt / 3.0, nu, dt, &m);  // a3
-        if (pml) comb(X, 1.0, x, 0.5 * dt, &K4s[1]);
+        if (pml || upw) comb(X, 1.0, x, 0.5 * dt, &K4s[1]);
         grad(a, K4s[2], X);
         op(a, m, 0.0, false, true);  // m3
         comb(msum, 1.0, msum, 1.0, &m);
         comb(a, dt / 3.0, nu, 0.5 * dt, &m);  // a2
-        if (pml) comb(X, 1.0, x, 0.5 * dt, &K4s[0]);
+        if (pml || upw) comb(X, 1.0, x, 0.5 * dt, &K4s[0]);
         grad(a, K4s[1], X);
         op(a, m, 0.0, false, true);  // m2
         comb(msum, 1.0, msum, 1.0, &m);

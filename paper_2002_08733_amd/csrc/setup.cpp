@@ -336,6 +336,12 @@ void finalize(Solver& s) {
     // the neighbour itself into tile t's block of the halo buffer, at the
     // offset recorded in the neighbour's publish code.
     s.nbr_code.assign(4 * s.Kpad, -1);
+    s.nbr_glob.assign(4 * s.Kpad, -1);
+    for (int64_t k = 0; k < s.K; ++k)
+      for (int f = 0; f < 4; ++f) {
+        const int64_t sd = s.side[4 * s.perm[k] + f];
+        if (sd >= 0) s.nbr_glob[4 * k + f] = (int32_t)(4 * s.iperm[sd / 4] + sd % 4);
+      }
     s.pub_code.assign(4 * s.Kpad, -1);
     auto NB = [&](int f, int64_t k) -> int32_t& { return s.nbr_code[blk_index(k, f, 4)]; };
     auto PUB = [&](int f, int64_t k) -> int32_t& { return s.pub_code[blk_index(k, f, 4)]; };
@@ -466,6 +472,7 @@ void finalize(Solver& s) {
   L.aACC = off; off = align256(off + afield);
   L.geo = off; off = align256(off + size_t(NGEO) * s.Kpad * rs);
   L.nbr = off; off = align256(off + size_t(4) * s.Kpad * 4);
+  L.nbrg = off; off = align256(off + size_t(4) * s.Kpad * 4);
   L.pub = off; off = align256(off + size_t(4) * s.Kpad * 4);
   L.halo_tile = off; off = align256(off + size_t(2) * s.ntiles * 4);
   L.H0 = off; off = align256(off + size_t(s.hbuf_reals) * rs);

@@ -54,6 +54,7 @@ struct DevLayout {
   size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
   size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
   size_t geo, nbr, pub, halo_tile, pml;
+  size_t nbrg;  // [Kpad][4] int32: neighbour element * 4 + its face, -1 = PEC (adjoint of the upwind flux)
   size_t src, srcid, srcnext, srcwave, srcamp;  // dipoles: coefficients, first dipole per element, chain,
                                                  // waveforms, amplitudes at the current stage
   size_t clock, rhs_clock;              // device time: (t0, n) of the stepping clock and of mdg_rhs
@@ -89,6 +90,7 @@ struct Solver {
   int hmax = 0;
   std::vector<int32_t> tile_start, tile_count;
   std::vector<int32_t> nbr_code;   // blocked [Kpad/64][4][64]: trace slot of the face's neighbour, -1 = PEC
+  std::vector<int32_t> nbr_glob;   // [Kpad][4]: neighbour element * 4 + face (sorted order), -1 = PEC
   std::vector<int32_t> pub_code;   // blocked [Kpad/64][4][64]: halo-buffer offset (reals) of the face's trace, or -1
   std::vector<int32_t> halo_tile;  // [ntiles][2]: halo block offset (reals), halo slot count
   int64_t hbuf_reals = 0;
@@ -184,5 +186,8 @@ void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* p
 void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, void* stream);  // g -= (a, K)_M0,E
 // PML elements: g -= (a, A^T (eta A^-T x_E + xa_E))_M0,E for stage input (x, xa)
 void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, void* stream);
+// upwind flux: g += (a, dA/deps x), the impedance dependence of the face terms
+// (stage_kernel.hip, where the face operators live)
+void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, void* stream);
 
 }  // namespace mdg

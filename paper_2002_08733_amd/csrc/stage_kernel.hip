@@ -987,6 +987,115 @@ __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t st
   if (code[3] >= 0) publish_face_global<P, 3, R>(w, fld, rH, code[3]);
 }
 
+// ------------------------------------------------- adjoint, upwind flux
+// The upwind face terms depend on eps through the impedances Z = sqrt(mu/eps)
+// of the two elements of a face: the own weight of the averaged input field
+// (E rows: Z-/(Z- + Z+), H rows: Z+/(Z- + Z+)) and the penalty factor (E rows:
+// 1/(Z- + Z+), H rows: Z- Z+/(Z- + Z+)); PEC faces mirror the element (weights
+// 1/2, penalties 1/(2 Z) and Z/2). For the discrete adjoint, g_T gets
+// dZ_T/deps_T times the derivative by Z_T of (a, A x) over the faces of T: the
+// face terms of T's own equations and those of its neighbours' equations, for
+// both fields. A x is the stage derivative before the mass inverse, a the
+// adjoint stage vector, x the stage input; in the face basis (a, face term)
+// = sum_m tau_1(a)[m] A1[m] + tau_2(a)[m] A2[m] (the lift is the transposed
+// trace). Runs in FP64 on either state precision.
+
+// traces of field fld (0: E, 1: H) of element e on face F (runtime)
+template <typename R, int P>
+__device__ void traces_rt(const R* __restrict__ u, int64_t e, int fld, int F, double (&t0)[Ops<P>::NF],
+                          double (&t1)[Ops<P>::NF]) {
+  constexpr int N = Ops<P>::N;
+  const R* ue = u + (e >> 6) * 6 * N * 64 + (e & 63) + fld * 3 * N * 64;
+  auto v = [&](int c, int l) { return (double)ue[(c * N + l) * 64]; };
+  switch (F) {
+    case 0: face_trace<P, 0, double>(v, t0, t1); break;
+    case 1: face_trace<P, 1, double>(v, t0, t1); break;
+    case 2: face_trace<P, 2, double>(v, t0, t1); break;
+    default: face_trace<P, 3, double>(v, t0, t1); break;
+  }
+}
+
+// d/dZ of (a, A x) for the face terms of element e's equations on its face F
+// whose other side is (en, fn) (PEC: en = e, fn = F), given dom / dpen, the
+// derivatives of the own weight and of the penalty factor, for field role r
+template <typename R, int P>
+__device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, const R* __restrict__ geo,
+                           int64_t e, int F, int64_t en, int fn, bool has, int r, double dom, double dpen) {
+  constexpr int NF = Ops<P>::NF;
+  const double g = r ? -1.0 : 1.0;
+  const double fin = has ? 1.0 : g, fout = has ? 1.0 : -g;  // PEC mirror of the input / output field
+  const R* ge = geo + (e >> 6) * NGEO * 64 + (e & 63);
+  const double rsign = (F == 0 || F == 2) ? 1.0 : -1.0;
+  const double c = -g * rsign * (double)ge[G_SIGN * 64];
+  double g11, g12, g22;
+  face_metric_rt<double>(F, ge[G_XX * 64], ge[G_XY * 64], ge[G_XZ * 64], ge[G_YY * 64], ge[G_YZ * 64],
+                         ge[G_ZZ * 64], g11, g12, g22);
+  const double idet = 1.0 / sqrt(g11 * g22 - g12 * g12);
+  const double W11 = g22 * idet, W12 = -g12 * idet, W22 = g11 * idet;
+  double ta0[NF], ta1[NF], v0[NF], v1[NF];
+  traces_rt<R, P>(a, e, r, F, ta0, ta1);  // the adjoint of the output field
+  double s_avg = 0.0, s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+  // averaged input field: d(A1, A2)/dom = c (xm1 - xp1, -(xm0 - xp0))
+  traces_rt<R, P>(x, e, 1 - r, F, v0, v1);
+  for (int m = 0; m < NF; ++m) s_avg += ta0[m] * v1[m] - ta1[m] * v0[m];
+  traces_rt<R, P>(x, en, 1 - r, fn, v0, v1);
+  for (int m = 0; m < NF; ++m) s_avg -= fin * (ta0[m] * v1[m] - ta1[m] * v0[m]);
+  // penalty on the jump of the output field: d(A1, A2)/dpen = W (j0, j1)
+  traces_rt<R, P>(x, en, r, fn, v0, v1);
+  for (int m = 0; m < NF; ++m) {
+    s00 += fout * ta0[m] * v0[m];
+    s01 += fout * ta0[m] * v1[m];
+    s10 += fout * ta1[m] * v0[m];
+    s11 += fout * ta1[m] * v1[m];
+  }
+  traces_rt<R, P>(x, e, r, F, v0, v1);
+  for (int m = 0; m < NF; ++m) {
+    s00 -= ta0[m] * v0[m];
+    s01 -= ta0[m] * v1[m];
+    s10 -= ta1[m] * v0[m];
+    s11 -= ta1[m] * v1[m];
+  }
+  return dom * c * s_avg + dpen * (W11 * s00 + W12 * s01 + W12 * s10 + W22 * s11);
+}
+
+template <typename R, int P>
+__global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout, const R* __restrict__ a,
+                                                      const R* __restrict__ x, const R* __restrict__ geo,
+                                                      const int32_t* __restrict__ nbrg, int64_t K) {
+  const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (k >= K) return;
+  const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
+  const double Z = gk[G_Z * 64], eps = 1.0 / (double)gk[G_IEPS * 64];
+  double sum = 0.0;
+  for (int F = 0; F < 4; ++F) {
+    const int code = nbrg[4 * k + F];
+    const bool has = code >= 0;
+    const int64_t kn = has ? code >> 2 : k;
+    const int fn = has ? (code & 3) : F;
+    const double Zn = has ? (double)geo[(kn >> 6) * NGEO * 64 + (kn & 63) + G_Z * 64] : Z;
+    const double S = Z + Zn, S2 = S * S;
+    for (int r = 0; r < 2; ++r) {
+      // own equations: weight and penalty by Z_T (= Z-)
+      double dom, dpen;
+      if (has) {
+        dom = r ? -Zn / S2 : Zn / S2;
+        dpen = r ? Zn * Zn / S2 : -1.0 / S2;
+      } else {
+        dom = 0.0;
+        dpen = r ? 0.5 : -0.5 / (Z * Z);
+      }
+      sum += upw_side<R, P>(a, x, geo, k, F, kn, fn, has, r, dom, dpen);
+      // the neighbour's equations, where T is the other side (Z_T = Z+)
+      if (has) {
+        const double dom2 = r ? Zn / S2 : -Zn / S2;
+        const double dpen2 = r ? Zn * Zn / S2 : -1.0 / S2;
+        sum += upw_side<R, P>(a, x, geo, kn, fn, k, F, true, r, dom2, dpen2);
+      }
+    }
+  }
+  gout[k] += -0.5 * Z / eps * sum;  // dZ/deps = -Z / (2 eps)
+}
+
 // ---------------------------------------------------------------- launch
 static void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -1153,6 +1262,27 @@ void launch_publish(const Solver& s, const void* U, void* H, void* stream) {
   if (s.nhalo == 0) return;
   if (s.opt.precision == MDG_FP32) launch_publish_r<float>(s, U, H, st);
   else launch_publish_r<double>(s, U, H, st);
+}
+
+void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, void* stream) {
+  char* base = static_cast<char*>(s.ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid((unsigned)((s.K + 63) / 64));
+  const int32_t* nb = reinterpret_cast<const int32_t*>(base + s.L.nbrg);
+  const void* geo = base + s.L.geo;
+#define MDG_UPW(R, P)                                                                                     \
+  hipLaunchKernelGGL((grad_upw_kernel<R, P>), grid, dim3(64), 0, st, g, (const R*)a, (const R*)x,           \
+                     (const R*)geo, nb, s.K)
+  const bool fp32 = s.opt.precision == MDG_FP32;
+  switch (s.P) {
+    case 1: if (fp32) MDG_UPW(float, 1); else MDG_UPW(double, 1); break;
+    case 2: if (fp32) MDG_UPW(float, 2); else MDG_UPW(double, 2); break;
+    case 3: if (fp32) MDG_UPW(float, 3); else MDG_UPW(double, 3); break;
+    case 4: if (fp32) MDG_UPW(float, 4); else MDG_UPW(double, 4); break;
+    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
+  }
+#undef MDG_UPW
+  hip_check(hipGetLastError(), "grad_upw_kernel launch");
 }
 
 }  // namespace mdg

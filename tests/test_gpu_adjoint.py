@@ -21,11 +21,12 @@ def _gpu():
     load_library()
 
 
-def _solver(verts, tets, p, eps, dt, precision="fp64", dip=None, omega=None, mixed=False):
+def _solver(verts, tets, p, eps, dt, precision="fp64", dip=None, omega=None, mixed=False, flux="central",
+            mu=None):
     from paper_2002_08733_amd import Solver
-    s = Solver(p, precision, "central", dt=dt, mixed=mixed)
+    s = Solver(p, precision, flux, dt=dt, mixed=mixed)
     s.set_mesh(verts, tets)
-    s.set_material(eps, None)
+    s.set_material(eps, mu)
     if omega is not None:
         s.set_pml(omega)
     if dip is not None:
@@ -49,9 +50,13 @@ def _tiny_omega(rng):
     return omega
 
 
-@pytest.mark.parametrize("precision,tol,pml", [("fp64", 1e-10, False), ("fp32", 2e-4, False),
-                                               ("fp64", 1e-10, True), ("fp32", 2e-4, True)])
-def test_adjoint_matches_oracle_adjoint(precision, tol, pml):
+@pytest.mark.parametrize("precision,tol,pml,flux", [
+    ("fp64", 1e-10, False, "central"), ("fp32", 2e-4, False, "central"),
+    ("fp64", 1e-10, True, "central"), ("fp32", 2e-4, True, "central"),
+    # the oracle takes the upwind impedance derivative by differences of its
+    # operator (relative step 1e-5): agreement to ~1e-9 is what it can show
+    ("fp64", 1e-7, False, "upwind"), ("fp64", 1e-7, True, "upwind"), ("fp32", 2e-4, True, "upwind")])
+def test_adjoint_matches_oracle_adjoint(precision, tol, pml, flux):
     from oracle import OracleDG
     from oracle.adjoint import adjoint_gradient
     verts, tets = _tiny()
@@ -59,20 +64,22 @@ def test_adjoint_matches_oracle_adjoint(precision, tol, pml):
     eps = rng.uniform(1.0, 4.0, 48)
     omega = _tiny_omega(rng) if pml else None
     pos, dr = np.array([0.4, 0.45, 0.55]), np.array([0.3, 0.2, 1.0])
-    O = OracleDG(verts, tets, 1, eps=eps, mu=np.ones(48), flux="central", omega=omega,
+    mu = np.linspace(1.0, 2.0, 48)
+    O = OracleDG(verts, tets, 1, eps=eps, mu=mu, flux=flux, omega=omega,
                  dipoles=[(pos, dr, lambda t: W.dipole_waveform(t, 2.0, 1.0))])
     cE0 = 0.3 * rng.standard_normal((48, 3, O.N))
     cH0 = 0.3 * rng.standard_normal((48, 3, O.N))
     dt, nsteps, probes = 0.01, 8, np.array([3, 17, 40])
     Jo, go = adjoint_gradient(O, cE0, cH0, dt, nsteps, probes)
     dip = (pos[None], dr[None], np.array([[2.0, 1.0, 5.0 / (2 * np.pi)]]))
-    s = _solver(verts, tets, 1, eps, dt, precision, dip, omega)
+    s = _solver(verts, tets, 1, eps, dt, precision, dip, omega, flux=flux, mu=mu)
     s.set_state(O.to_covariant(cE0), O.to_covariant(cH0))
     J, g = s.adjoint_probe_energy(nsteps, 3, probes)
     s.close()
     eJ = abs(J - Jo) / abs(Jo)
     eg = np.abs(g - go).max() / np.abs(go).max()
-    say(f"[adjoint vs oracle] {precision} pml={pml}: J {J:.12e} vs {Jo:.12e} ({eJ:.2e}), grad max rel {eg:.2e}")
+    say(f"[adjoint vs oracle] {precision} {flux} pml={pml}: J {J:.12e} vs {Jo:.12e} ({eJ:.2e}), "
+        f"grad max rel {eg:.2e}")
     assert eJ < tol and eg < tol
 
 
@@ -85,10 +92,11 @@ def _medium(n=4, p=2, seed=51):
     return w, E0, H0, dip
 
 
-@pytest.mark.parametrize("case", ["plain", "pml", "mixed_pml"])
+@pytest.mark.parametrize("case", ["plain", "pml", "mixed_pml", "upwind_pml"])
 def test_adjoint_matches_finite_differences_on_16_elements(case):
     w, E0, H0, dip = _medium()
     omega, mixed = None, case == "mixed_pml"
+    flux = "upwind" if case.startswith("upwind") else "central"
     if case != "plain":
         # a damped slab (x > 0.4), one axis undamped on part of it
         c = W.tet_centroids(w.verts, w.tets)
@@ -104,7 +112,7 @@ def test_adjoint_matches_finite_differences_on_16_elements(case):
     p = w.p - 1 if mixed else w.p
 
     def make(eps):
-        s = _solver(w.verts, w.tets, p, eps, dt, dip=dip, omega=omega, mixed=mixed)
+        s = _solver(w.verts, w.tets, p, eps, dt, dip=dip, omega=omega, mixed=mixed, flux=flux)
         s.set_state(E0, H0)
         return s
 
