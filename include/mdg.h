@@ -79,6 +79,10 @@ typedef struct mdg_options {
   int32_t tile;       /* elements per stage-kernel workgroup: 32 or 64; 0 = automatic */
   int32_t mixed;      /* 0: e and h at order p; 1: e at order p+1, h at order p, the paper's
                          pairing [KS eqs. triale, trialh] (then p <= 3) */
+  double sip_alpha;   /* > 0: symmetric interior penalty surface unknown h_s on every face
+                         [KS Sec. III, eqs. jmp_var_def, 1st_weak_equation, weak_penalty]
+                         with alpha_F = sip_alpha (p+1)(p+3)/3 |F| / min(|T|, |T'|);
+                         0: none. Central flux and equal orders only (see mdg_set_sip_state) */
 } mdg_options;
 
 typedef struct mdg_info {
@@ -175,6 +179,33 @@ mdg_status mdg_set_state(mdg_solver* s, const double* E, const double* H, const 
 /* Copy the state back to host FP64 arrays (same layout; P, Q may be NULL;
  * zero on non-PML elements). Synchronises the device. *t may be NULL. */
 mdg_status mdg_get_state(mdg_solver* s, double* E, double* H, double* P, double* Q, double* t);
+
+/* SIP surface unknown (mdg_options.sip_alpha > 0) [KS Sec. III]. On every face
+ * F a tangential field h_s of degree p evolves by
+ *   (mu_F/alpha_F) (d_t h_s, psi)_F = ([[e]], psi)_F,
+ *   [[e]] = n_T x (e_T - e_T') (either side T; n_T x e_T on PEC faces),
+ * and adds -(h_s x n_T, v)_F to the E equation of both elements of F
+ * [KS eqs. jmp_var_def, 1st_weak_equation, weak_penalty], with
+ * mu_F = (mu_T + mu_T')/2 (mu_T on PEC faces), no PML damping of h_s. The
+ * block system is then skew and W + 1/2 sum_F (mu_F/alpha_F) (h_s, h_s)_F is
+ * conserved by the semi-discrete system (mdg_energy reports W alone). With
+ * MDG_LEAPFROG h_s is staggered with h (at t + dt/2). dt from cfl does not
+ * account for the penalty: choose cfl (or dt) for it.
+ * Layout S[nt][4][2][NF] (caller's element order, NF = (p+1)(p+2)/2): face f
+ * of element t is the face opposite the element's f-th vertex in the element
+ * frame (vertices by ascending global id); its vertices a < b < c (global id)
+ * parametrise it as x = x_a + s1 (x_b - x_a) + s2 (x_c - x_a), and
+ *   (h_s . t_k)(s) = sum_m S[t][f][k][m] psi_m(s1, s2),  t_1 = x_b - x_a, t_2 = x_c - x_a,
+ *   psi_ij = sqrt(2 (2i+1)(i+j+1)) P_i^(0,0)(2 s2/(1-s1) - 1) (1-s1)^i P_j^(2i+1,0)(2 s1 - 1),
+ * modes by total degree i+j, then i. Both elements of a face hold a copy; the
+ * library updates both from the same data, so they agree to round-off.
+ * mdg_set_state and mdg_project set h_s to zero; mdg_set_sip_state then sets
+ * it (both copies of a face should be equal). Not available (MDG_E_UNSUPPORTED)
+ * with the upwind flux, mixed orders or instances (mdg_create, or the first
+ * call that finalises the setup), in mdg_rhs and in the probe-energy and
+ * adjoint calls, and in these two calls without sip_alpha. Synchronous. */
+mdg_status mdg_set_sip_state(mdg_solver* s, const double* S);
+mdg_status mdg_get_sip_state(mdg_solver* s, double* S);
 
 /* Physical points where a field must be sampled for mdg_project: q^3 points
  * per element (collapsed Gauss-Legendre rule of order q, 1 <= q <= 16).

@@ -116,6 +116,18 @@ void read_state(Solver& s, double* E, double* H, double* P, double* Q, size_t of
   }
 }
 
+// a new state starts with a zero SIP unknown
+void clear_sip(Solver& s) {
+  if (!s.sip()) return;
+  std::vector<double> z;
+  pack_sip(s, nullptr, z);
+  upload(s, z, s.L.sY, nullptr);
+}
+
+void no_sip(const Solver& s, const char* what) {
+  if (s.sip()) throw Error(MDG_E_UNSUPPORTED, std::string(what) + ": not available with the SIP unknown");
+}
+
 // set a device clock (t0, n); synchronous
 void set_clock(Solver& s, size_t off, double t0, double n = 0.0) {
   const double c[2] = {t0, n};
@@ -196,6 +208,10 @@ void enqueue_leapfrog_steps(Solver& s, int64_t nsteps, void* stream) {
       sp.aUin = sp.aY;
       sp.aUout = sp.aY;
       sp.aACC = dev(s, L.aACC);
+      sp.sY = dev(s, L.sY);
+      sp.sUin = sp.sY;
+      sp.sUout = sp.sY;
+      sp.sACC = dev(s, L.sACC);
       sp.hin = dev(s, L.H0);
       sp.hout = dev(s, L.H0);
       sp.publish = true;
@@ -229,6 +245,8 @@ void enqueue_steps(Solver& s, int64_t nsteps, void* stream) {
       const size_t outb = i == 1 ? L.Ub : L.Ua;
       const size_t ain = i == 0 ? L.aY : (i == 2 ? L.aUb : L.aUa);
       const size_t aout = i == 1 ? L.aUb : L.aUa;
+      const size_t sin = i == 0 ? L.sY : (i == 2 ? L.sUb : L.sUa);
+      const size_t sout = i == 1 ? L.sUb : L.sUa;
       sp.Y = dev(s, L.Y);
       sp.Uin = dev(s, in);
       sp.Uout = dev(s, outb);
@@ -237,6 +255,10 @@ void enqueue_steps(Solver& s, int64_t nsteps, void* stream) {
       sp.aUin = dev(s, ain);
       sp.aUout = dev(s, aout);
       sp.aACC = dev(s, L.aACC);
+      sp.sY = dev(s, L.sY);
+      sp.sUin = dev(s, sin);
+      sp.sUout = dev(s, sout);
+      sp.sACC = dev(s, L.sACC);
       // halo traces of the stage input in, of the stage output out; after
       // the last stage H0 again holds the traces of Y
       sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
@@ -277,6 +299,11 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
     return MDG_E_UNSUPPORTED;
   }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_create_error = "tile must be 0, 32 or 64"; return MDG_E_ARG; }
+  if (!(o->sip_alpha >= 0) || !std::isfinite(o->sip_alpha)) { g_create_error = "sip_alpha must be >= 0"; return MDG_E_ARG; }
+  if (o->sip_alpha > 0 && (o->flux != MDG_CENTRAL || o->mixed)) {
+    g_create_error = "the SIP unknown needs the central flux and equal orders";
+    return MDG_E_UNSUPPORTED;
+  }
   if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
   mdg_solver* h = new (std::nothrow) mdg_solver();
   if (!h) return MDG_E_OOM;
@@ -413,6 +440,7 @@ mdg_status mdg_set_state(mdg_solver* h, const double* E, const double* H, const 
     need_bound(s);
     if (!E || !H) throw Error(MDG_E_ARG, "E and H are required");
     write_state(s, E, H, P, Q, s.L.Y, s.L.aY);
+    clear_sip(s);
     s.halo_valid = false;
     s.t0 = t;
     s.nstep = 0;
@@ -425,6 +453,29 @@ mdg_status mdg_get_state(mdg_solver* h, double* E, double* H, double* P, double*
     need_bound(s);
     read_state(s, E, H, P, Q, s.L.Y, s.L.aY);
     if (t) *t = s.time();
+  });
+}
+
+mdg_status mdg_set_sip_state(mdg_solver* h, const double* S) {
+  return guarded(h, [&](Solver& s) {
+    if (!s.sip()) throw Error(MDG_E_UNSUPPORTED, "set_sip_state: the solver has no SIP unknown (sip_alpha = 0)");
+    need_bound(s);
+    if (!S) throw Error(MDG_E_ARG, "set_sip_state: NULL S");
+    std::vector<double> buf;
+    pack_sip(s, S, buf);
+    upload(s, buf, s.L.sY, nullptr);
+  });
+}
+
+mdg_status mdg_get_sip_state(mdg_solver* h, double* S) {
+  return guarded(h, [&](Solver& s) {
+    if (!s.sip()) throw Error(MDG_E_UNSUPPORTED, "get_sip_state: the solver has no SIP unknown (sip_alpha = 0)");
+    need_bound(s);
+    if (!S) throw Error(MDG_E_ARG, "get_sip_state: NULL S");
+    hip_check(hipDeviceSynchronize(), "synchronize");
+    std::vector<double> buf;
+    download(s, s.L.sY, size_t(8) * s.NF * s.Kpad, buf);
+    unpack_sip(s, buf, S);
   });
 }
 
@@ -445,6 +496,7 @@ mdg_status mdg_project(mdg_solver* h, int32_t q, const double* Ev, const double*
     if (Ev) project_fields(s, q, Ev, s.N, ce); else ce.assign(size_t(s.nt) * 3 * s.N, 0.0);
     if (Hv) project_fields(s, q, Hv, s.NH, ch); else ch.assign(size_t(s.nt) * 3 * s.NH, 0.0);
     write_state(s, ce.data(), ch.data(), nullptr, nullptr, s.L.Y, s.L.aY);
+    clear_sip(s);
     s.halo_valid = false;
     s.t0 = t;
     s.nstep = 0;
@@ -507,6 +559,7 @@ mdg_status mdg_step_graph(mdg_solver* h, int64_t nsteps, int32_t steps_per_graph
 mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double* P, const double* Q, double t,
                    double* dE, double* dH, double* dP, double* dQ) {
   return guarded(h, [&](Solver& s) {
+    no_sip(s, "rhs");
     need_bound(s);
     if (!E || !H || !dE || !dH) throw Error(MDG_E_ARG, "E, H, dE, dH are required");
     const DevLayout& L = s.L;
@@ -538,6 +591,7 @@ mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double
 mdg_status mdg_probe_energy(mdg_solver* h, int64_t nsteps, int32_t nprobe, const int64_t* probes, double* J,
                             void* stream) {
   return guarded(h, [&](Solver& s) {
+    no_sip(s, "probe energy");
     need_bound(s);
     if (nsteps < 0) throw Error(MDG_E_ARG, "probe energy: nsteps >= 0");
     if (nprobe < 1 || !probes || !J) throw Error(MDG_E_ARG, "probe energy: probes and J required");
@@ -566,6 +620,7 @@ mdg_status mdg_probe_energy(mdg_solver* h, int64_t nsteps, int32_t nprobe, const
 mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every, int32_t nprobe,
                                      const int64_t* probes, double* J, double* grad_eps, void* stream) {
   return guarded(h, [&](Solver& s) {
+    no_sip(s, "adjoint");
     need_bound(s);
     if (nsteps < 1 || every < 1) throw Error(MDG_E_ARG, "adjoint: nsteps >= 1 and checkpoint interval >= 1");
     if (nprobe < 1 || !probes || !J || !grad_eps) throw Error(MDG_E_ARG, "adjoint: probes, J and grad_eps required");

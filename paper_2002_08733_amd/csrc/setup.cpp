@@ -262,6 +262,8 @@ static uint64_t spread21(uint64_t v) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 void finalize(Solver& s) {
+  if (s.sip() && s.inst_first.size() > 2)
+    throw Error(MDG_E_UNSUPPORTED, "the SIP unknown is not available with instances");
   if (s.nt == 0) throw Error(MDG_E_STATE, "no mesh");
   const int64_t nt = s.nt;
   std::vector<char> ispml(nt, 0);
@@ -443,6 +445,30 @@ void finalize(Solver& s) {
         G(G_WZ0 + f, k) = Zm / (Zm + Zp);
       }
     }
+    if (s.sip()) {
+      // alpha_F / mu_F of each face: alpha_F = alpha0 (p+1)(p+3)/3 |F| / min(|T|, |T'|),
+      // mu_F the mean of the two sides (the element's own on PEC faces); both
+      // sides evaluate the same expression in the same order
+      const int p = s.P;
+      for (int f = 0; f < 4; ++f) {
+        const int64_t sd = s.side[4 * u + f];
+        int fv[3];
+        face_vertices(f, fv);
+        const double* xa = &s.xyz[3 * s.tet[4 * u + fv[0]]];
+        const double* xb = &s.xyz[3 * s.tet[4 * u + fv[1]]];
+        const double* xc = &s.xyz[3 * s.tet[4 * u + fv[2]]];
+        double t1[3], t2[3];
+        for (int i = 0; i < 3; ++i) { t1[i] = xb[i] - xa[i]; t2[i] = xc[i] - xa[i]; }
+        const double cx = t1[1] * t2[2] - t1[2] * t2[1], cy = t1[2] * t2[0] - t1[0] * t2[2],
+                     cz = t1[0] * t2[1] - t1[1] * t2[0];
+        const double area = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        const double vm = std::fabs(s.det[u]) / 6.0;
+        const double vo = sd < 0 ? vm : std::fabs(s.det[sd / 4]) / 6.0;
+        const double alpha = s.opt.sip_alpha * (p + 1) * (p + 3) / 3.0 * area / std::min(vm, vo);
+        const double muF = sd < 0 ? s.mu[u] : 0.5 * (s.mu[u] + s.mu[sd / 4]);
+        G(G_SIP0 + f, k) = alpha / muF;
+      }
+    }
   }
   // PML records: A^T, A^-T (row-major) and the damping
   s.pmlrec.assign(size_t(NPML) * s.Kppad, 0.0);
@@ -470,6 +496,11 @@ void finalize(Solver& s) {
   L.aUa = off; off = align256(off + afield);
   L.aUb = off; off = align256(off + afield);
   L.aACC = off; off = align256(off + afield);
+  const size_t sfield = s.sip() ? size_t(8) * s.NF * s.Kpad * rs : 0;
+  L.sY = off; off = align256(off + sfield);
+  L.sUa = off; off = align256(off + sfield);
+  L.sUb = off; off = align256(off + sfield);
+  L.sACC = off; off = align256(off + sfield);
   L.geo = off; off = align256(off + size_t(NGEO) * s.Kpad * rs);
   L.nbr = off; off = align256(off + size_t(4) * s.Kpad * 4);
   L.nbrg = off; off = align256(off + size_t(4) * s.Kpad * 4);
@@ -491,7 +522,7 @@ void finalize(Solver& s) {
   L.epart = off; off = align256(off + nblk * 8);
   L.eout = off; off = align256(off + 8);
   L.total = off;
-  if (field >= (size_t(1) << 32) || size_t(NGEO) * s.Kpad * rs >= (size_t(1) << 32))
+  if (field >= (size_t(1) << 32) || sfield >= (size_t(1) << 32) || size_t(NGEO) * s.Kpad * rs >= (size_t(1) << 32))
     throw Error(MDG_E_UNSUPPORTED, "mesh too large: a state array exceeds 4 GiB");
   s.finalized = true;
 }
@@ -638,6 +669,24 @@ void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, doubl
   }
 }
 
+void pack_sip(const Solver& s, const double* S, std::vector<double>& out) {
+  const int R8 = 8 * s.NF;
+  out.assign(size_t(R8) * s.Kpad, 0.0);
+  if (!S) return;
+  for (int64_t k = 0; k < s.K; ++k) {
+    const int64_t u = s.perm[k];
+    for (int r = 0; r < R8; ++r) out[blk_index(k, r, R8)] = S[u * R8 + r];
+  }
+}
+
+void unpack_sip(const Solver& s, const std::vector<double>& in, double* S) {
+  const int R8 = 8 * s.NF;
+  for (int64_t k = 0; k < s.K; ++k) {
+    const int64_t u = s.perm[k];
+    for (int r = 0; r < R8; ++r) S[u * R8 + r] = in[blk_index(k, r, R8)];
+  }
+}
+
 static void nnz_of(int P, int& nd, int& nf) {
   switch (P) {
     case 1: nd = ref::Ops<1>::nnzD; nf = ref::Ops<1>::nnzT; break;
@@ -660,7 +709,11 @@ double bytes_per_stage(const Solver& s) {
   const double state = (lf ? 4.5 : 17.0 / 4.0 * 3.0) * nn * rs;
   const double geo = (s.opt.flux == MDG_UPWIND ? 14.0 : 9.0) * rs + 16.0;
   const double pml = (lf ? 3.0 : 17.0 / 4.0 * 3.0) * nn * rs + NPML * rs;
-  return s.K * (state + geo) + s.Kp * pml;
+  // SIP: 8 NF surface values per element streamed like the state (the E
+  // half of a leap-frog step reads them, the H half reads and writes them)
+  // plus the four face rows of the geometry record
+  const double sip = s.sip() ? (lf ? 12.0 : 17.0 / 4.0 * 8.0) * s.NF * rs + 4.0 * rs : 0.0;
+  return s.K * (state + geo + sip) + s.Kp * pml;
 }
 
 double flops_per_stage(const Solver& s) {

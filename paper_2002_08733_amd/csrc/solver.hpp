@@ -27,6 +27,9 @@ enum GeoRow {
   G_WZ0, G_WZ1, G_WZ2, G_WZ3,              // Z-/(Z- + Z+) per local face (1/2 on PEC faces)
   NGEO
 };
+// With the SIP surface unknown (central flux only) the four face rows of the
+// upwind weights hold alpha_F / mu_F of each local face instead.
+constexpr int G_SIP0 = G_WZ0;
 // Per-PML-element record rows.
 enum PmlRow { PM_AT = 0, PM_AIT = 9, PM_OM = 18, NPML = 21 };
 
@@ -53,6 +56,7 @@ inline size_t blk_index(int64_t e, int row, int rows_per_block) {
 struct DevLayout {
   size_t Y, Ua, Ub, ACC;      // E and H together: [K/64][2][3N][64]
   size_t aY, aUa, aUb, aACC;  // PML auxiliaries P~, Q~: [Kp/64][2][3N][64]
+  size_t sY, sUa, sUb, sACC;  // SIP surface unknown, one copy per element face: [K/64][4][2][NF][64]
   size_t geo, nbr, pub, halo_tile, pml;
   size_t nbrg;  // [Kpad][4] int32: neighbour element * 4 + its face, -1 = PEC (adjoint of the upwind flux)
   size_t src, srcid, srcnext, srcwave, srcamp;  // dipoles: coefficients, first dipole per element, chain,
@@ -110,6 +114,7 @@ struct Solver {
   void* graph = nullptr;       // hipGraph_t
   int graph_steps = 0;
   size_t real_size() const { return opt.precision == MDG_FP32 ? 4 : 8; }
+  bool sip() const { return opt.sip_alpha > 0; }
 };
 
 // ---- setup.cpp
@@ -141,6 +146,9 @@ void project_fields(const Solver& s, int q, const double* vals, int N, std::vect
 void pack_state(const Solver& s, const double* E, const double* H, std::vector<double>& out);
 void unpack_state(const Solver& s, const std::vector<double>& in, double* E, double* H);
 void pack_aux(const Solver& s, const double* P, const double* Q, std::vector<double>& out);
+// SIP unknown: caller's S[nt][4][2][NF] <-> blocked [Kpad/64][8 NF][64]
+void pack_sip(const Solver& s, const double* S, std::vector<double>& out);
+void unpack_sip(const Solver& s, const std::vector<double>& in, double* S);
 void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, double* Q);
 double bytes_per_stage(const Solver& s);
 double flops_per_stage(const Solver& s);
@@ -164,6 +172,11 @@ struct StageParams {
   const void* aUin;
   void* aUout;
   void* aACC;
+  // SIP surface unknown (ignored without it): base, stage input/output, accumulator
+  void* sY = nullptr;
+  const void* sUin = nullptr;
+  void* sUout = nullptr;
+  void* sACC = nullptr;
   // halo traces (see Solver::pub_code): read for the input, written for the output
   const void* hin;
   void* hout;

@@ -63,6 +63,10 @@ struct DevArgs {
   void* aUout;
   void* aACC;
   void* aYw;
+  const void* sY;     // SIP surface unknown [K/64][face][k][NF][64]: RK base (leap-frog: updated in place)
+  const void* sUin;   // stage input
+  void* sUout;        // next stage input / operator output
+  void* sACC;         // RK accumulator
   const void* geo;
   const int32_t* nbr;
   const int32_t* pub;        // publish codes: halo-buffer offset of each face's trace, or -1
@@ -75,7 +79,7 @@ struct DevArgs {
   const int32_t* srcnext;     // [ndip]: next dipole on the same element, or -1
   const double* srcamp;       // [ndip]: g(t) of every dipole at the stage's time
   double* tick;               // non-null: advance this device clock (n += 1) once
-  uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes;
+  uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes, sip_bytes;
   int64_t pml_base;
   int32_t tile_begin, ntiles, stage, has_src, publish;  // stage: 0..3 RK4, -1 operator, 4/5 leap-frog E/H half
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
@@ -530,10 +534,15 @@ constexpr int waves_per_eu() { return sizeof(R) == 4 ? 4 : 2; }
 // LF = 1 keeps eight lanes per element (both roles, one of them idle);
 // LF = 2 (64-element tiles) gives every lane to the active field: four lanes
 // per element and compact slots, so that four workgroups share a CU.
-template <typename R, int P, bool UPW, bool PML, int LF>
+// SIP: the symmetric interior penalty surface unknown h_s of every face
+// (central flux): part Q of the E lanes adds h_s of face Q to the averaged h
+// trace, part Q of the H lanes advances h_s of face Q from the jump of the e
+// traces (one copy per element face; both sides compute the same update).
+template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
     DevArgs a) {
   static_assert(!(LF && UPW), "leap-frog halves need the central flux");
+  static_assert(!(SIP && UPW), "the SIP unknown comes with the central flux");
   constexpr bool C = LF == 2;
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
   constexpr int SS = slot_stride<NF, C>();
@@ -684,6 +693,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     Z = bld<R>(rG, vgeo, rowb<R>(G_Z));
     wz = bld<R>(rG, vgeo, rowb<R>(G_WZ0 + part));
   }
+  R sipc = 0;  // alpha_F / mu_F of face `part`
+  if constexpr (SIP) sipc = bld<R>(rG, vgeo, rowb<R>(G_SIP0 + part));
   const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
   const Rsrc rN = make_rsrc(a.nbr, a.nbr_bytes);
   const int code = bldi(rN, blk_base(el, 4, 4), (uint32_t)part * 256u);
@@ -709,6 +720,46 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     R A1[NF], A2[NF];
     face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz, gzz,
                                  A1, A2);
+    if constexpr (SIP) {
+      // face `part` of this element: sig = sign((t^1 x t^2) . n_out), rows
+      // (part, k, m) of the element's surface block
+      const R sig = ((part == 0 || part == 2) ? R(1) : R(-1)) * sgn;
+      const uint32_t vs = blk_base(el, 8 * NF, RS);
+      const int srow = part * 2 * NF;
+      if (role == 0) {
+        // E: -(h_s x n, v)_F has the form of the averaged h term, so the
+        // edge-tangent components of h_s add to the averaged traces
+        const Rsrc rS = make_rsrc(a.sUin, a.sip_bytes);
+#pragma unroll
+        for (int m = 0; m < NF; ++m) {
+          const R s0 = bld<R>(rS, vs, rowb<R>(srow + m));
+          const R s1 = bld<R>(rS, vs, rowb<R>(srow + NF + m));
+          A1[m] = fma(-sig, s1, A1[m]);
+          A2[m] = fma(sig, s0, A2[m]);
+        }
+      } else {
+        // h_s: (mu/alpha) sqrt(det g) g^-1 d_t S = [-sig D_2; sig D_1] with
+        // D_k the face coefficients of (e- - e+) . t^k (e+ = 0 on PEC faces);
+        // the physical metric g is |det A| g^, whose Jacobian cancels
+        R g11, g12, g22;
+        face_metric_rt<R>(part, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
+        const R fs = sipc / sqrt(g11 * g22 - g12 * g12);
+        const bool has = code >= 0;
+        const R* own = lds + lbase<NF, C>(part * tile + li, 1);
+        const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile);
+        const R hn = has ? R(1) : R(0);
+        const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip_bytes, a.bcoef, a.cdt, a.dt, false);
+        const R cs = R(es.c_out), bs = R(a.bcoef);
+#pragma unroll
+        for (int m = 0; m < NF; ++m) {
+          const R d0 = fma(-hn, nbr[loff<NF>(0, m)], own[loff<NF>(0, m)]);
+          const R d1 = fma(-hn, nbr[loff<NF>(1, m)], own[loff<NF>(1, m)]);
+          const R v1 = -sig * d1, v2 = sig * d0;
+          rk_store<R>(es, fs * fma(g11, v1, g12 * v2), vs, rowb<R>(srow + m), bs, cs, wr);
+          rk_store<R>(es, fs * fma(g12, v1, g22 * v2), vs, rowb<R>(srow + NF + m), bs, cs, wr);
+        }
+      }
+    }
     __syncthreads();  // B2: every flux read of this tile is done
     // publish the flux coefficients of face `part` in its own slot
     R* d = lds + lbase<NF, C>(part * tile + li, role);
@@ -1101,45 +1152,54 @@ static void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <typename R, int P, bool UPW, bool PML, int LF>
+template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false>
 static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
   const int grid = (a.ntiles + 7) / 8 * 8;
   if (lds > 64 * 1024) {
-    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF>),
+    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
               "hipFuncSetAttribute(dynamic LDS)");
   }
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF>), dim3(grid), dim3((LF == 2 ? 4 : 8) * tile), lds, st, a);
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP>), dim3(grid), dim3((LF == 2 ? 4 : 8) * tile), lds, st,
+                     a);
   hip_check(hipGetLastError(), "stage_kernel launch");
 }
 
+// central-flux launches with or without the SIP unknown
+template <typename R, int P, bool PML, int LF>
+static void launch_c(const DevArgs& a, bool sip, int tile, size_t lds, hipStream_t st) {
+  if (sip) launch_one<R, P, false, PML, LF, true>(a, tile, lds, st);
+  else launch_one<R, P, false, PML, LF, false>(a, tile, lds, st);
+}
+
 template <typename R, int P>
-static void launch_p(const DevArgs& a, bool upw, bool pml, int tile, size_t lds, hipStream_t st) {
+static void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
+  if (upw && sip) throw Error(MDG_E_UNSUPPORTED, "the SIP unknown needs the central flux");
   if (a.stage >= 4) {  // leap-frog half (central flux, checked at creation)
     if (upw) throw Error(MDG_E_UNSUPPORTED, "leap-frog needs the central flux");
     if (tile % 64 == 0) {  // four lanes per element
-      if (pml) launch_one<R, P, false, true, 2>(a, tile, lds, st);
-      else launch_one<R, P, false, false, 2>(a, tile, lds, st);
+      if (pml) launch_c<R, P, true, 2>(a, sip, tile, lds, st);
+      else launch_c<R, P, false, 2>(a, sip, tile, lds, st);
     } else {
-      if (pml) launch_one<R, P, false, true, 1>(a, tile, lds, st);
-      else launch_one<R, P, false, false, 1>(a, tile, lds, st);
+      if (pml) launch_c<R, P, true, 1>(a, sip, tile, lds, st);
+      else launch_c<R, P, false, 1>(a, sip, tile, lds, st);
     }
   } else if (upw) {
     if (pml) launch_one<R, P, true, true, 0>(a, tile, lds, st);
     else launch_one<R, P, true, false, 0>(a, tile, lds, st);
   } else {
-    if (pml) launch_one<R, P, false, true, 0>(a, tile, lds, st);
-    else launch_one<R, P, false, false, 0>(a, tile, lds, st);
+    if (pml) launch_c<R, P, true, 0>(a, sip, tile, lds, st);
+    else launch_c<R, P, false, 0>(a, sip, tile, lds, st);
   }
 }
 
 template <typename R>
-static void launch_r(int P, const DevArgs& a, bool upw, bool pml, int tile, size_t lds, hipStream_t st) {
+static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
   switch (P) {
-    case 1: launch_p<R, 1>(a, upw, pml, tile, lds, st); break;
-    case 2: launch_p<R, 2>(a, upw, pml, tile, lds, st); break;
-    case 3: launch_p<R, 3>(a, upw, pml, tile, lds, st); break;
-    case 4: launch_p<R, 4>(a, upw, pml, tile, lds, st); break;
+    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, st); break;
+    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, st); break;
+    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, st); break;
+    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
 }
@@ -1157,6 +1217,10 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.aUin = sp.aUin;
   a.aUout = sp.aUout;
   a.aACC = sp.aACC;
+  a.sY = sp.sY;
+  a.sUin = sp.sUin;
+  a.sUout = sp.sUout;
+  a.sACC = sp.sACC;
   a.geo = base + s.L.geo;
   a.nbr = reinterpret_cast<const int32_t*>(base + s.L.nbr);
   a.pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
@@ -1177,6 +1241,9 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.nbr_bytes = (uint32_t)(size_t(4) * s.Kpad * 4);
   a.pml_bytes = (uint32_t)(size_t(NPML) * s.Kppad * rs);
   a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
+  a.sip_bytes = s.sip() ? (uint32_t)(size_t(8) * s.NF * s.Kpad * rs) : 0u;
+  if (s.sip() && !(sp.sY && sp.sUin && (sp.stage >= 3 || sp.sUout) && (sp.stage < 0 || sp.stage > 3 || sp.sACC)))
+    throw Error(MDG_E_STATE, "SIP launch without its surface buffers");
   a.pml_base = s.K0;
   a.nh = s.NH;
   a.adj = sp.adj ? 1 : 0;
@@ -1204,8 +1271,8 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
     a.elem_end = part == 0 ? (int32_t)s.K0 : (int32_t)s.K;
     a.ntiles = part == 0 ? (int32_t)s.ntiles0 : (int32_t)(s.ntiles - s.ntiles0);
     if (a.ntiles == 0) continue;
-    if (fp32) launch_r<float>(s.P, a, upw, part == 1, s.tile, lds, st);
-    else launch_r<double>(s.P, a, upw, part == 1, s.tile, lds, st);
+    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, st);
+    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, st);
   }
 }
 

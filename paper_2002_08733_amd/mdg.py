@@ -35,7 +35,7 @@ class MdgError(RuntimeError):
 class mdg_options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("flux", ctypes.c_int32),
                 ("integrator", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("tile", ctypes.c_int32), ("mixed", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("mixed", ctypes.c_int32), ("sip_alpha", ctypes.c_double)]
 
 
 class mdg_info(ctypes.Structure):
@@ -70,6 +70,8 @@ SIGNATURES = {
     "mdg_bind_workspace": (_S, [_VP, _VP, ctypes.c_size_t, _VP]),
     "mdg_set_state": (_S, [_VP, _D, _D, _D, _D, ctypes.c_double]),
     "mdg_get_state": (_S, [_VP, _D, _D, _D, _D, _D]),
+    "mdg_set_sip_state": (_S, [_VP, _D]),
+    "mdg_get_sip_state": (_S, [_VP, _D]),
     "mdg_projection_points": (_S, [_VP, ctypes.c_int32, _I64, _D]),
     "mdg_project": (_S, [_VP, ctypes.c_int32, _D, _D, ctypes.c_double]),
     "mdg_step": (_S, [_VP, ctypes.c_int64, _VP]),
@@ -125,16 +127,17 @@ class Solver:
     """One libmdg handle. Methods mirror the C entry points one to one."""
 
     def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3, tile=0, integrator="rk4",
-                 mixed=False):
+                 mixed=False, sip_alpha=0.0):
         """order: polynomial order of h (and of e, unless mixed: then e is one
-        order higher, the paper's pairing)."""
+        order higher, the paper's pairing). sip_alpha > 0 adds the SIP
+        surface unknown (central flux, equal orders)."""
         self.lib = load_library()
         if integrator not in ("rk4", "leapfrog"):
             raise ValueError("integrator must be 'rk4' or 'leapfrog'")
         o = mdg_options(order=order, precision=MDG_FP32 if precision == "fp32" else MDG_FP64,
                         flux=MDG_UPWIND if flux == "upwind" else MDG_CENTRAL,
                         integrator=MDG_RK4 if integrator == "rk4" else MDG_LEAPFROG, dt=float(dt), cfl=float(cfl),
-                        tile=int(tile), mixed=1 if mixed else 0)
+                        tile=int(tile), mixed=1 if mixed else 0, sip_alpha=float(sip_alpha))
         h = _VP()
         st = self.lib.mdg_create(ctypes.byref(o), ctypes.byref(h))
         if st != MDG_OK:
@@ -144,6 +147,7 @@ class Solver:
         pe = order + (1 if mixed else 0)
         self.nmodes = (pe + 1) * (pe + 2) * (pe + 3) // 6  # of e (and p)
         self.nmodes_h = (order + 1) * (order + 2) * (order + 3) // 6  # of h (and q)
+        self.nfacemodes = (pe + 1) * (pe + 2) // 2
         self.nt = 0
         self._ws = None
 
@@ -236,6 +240,16 @@ class Solver:
         t = ctypes.c_double()
         self._chk(self.lib.mdg_get_state(self.h, _dptr(E), _dptr(H), _dptr(P), _dptr(Q), ctypes.byref(t)))
         return (E, H, P, Q, t.value) if aux else (E, H, t.value)
+
+    def set_sip_state(self, S):
+        """SIP unknown S[nt][4][2][NF] (see mdg_set_sip_state)."""
+        S = _f64(S, (self.nt, 4, 2, self.nfacemodes))
+        self._chk(self.lib.mdg_set_sip_state(self.h, _dptr(S)))
+
+    def get_sip_state(self):
+        S = np.empty((self.nt, 4, 2, self.nfacemodes))
+        self._chk(self.lib.mdg_get_sip_state(self.h, _dptr(S)))
+        return S
 
     def projection_points(self, q):
         n = ctypes.c_int64()

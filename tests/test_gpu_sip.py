@@ -1,0 +1,188 @@
+"""GPU parity of the SIP surface unknown [KS Sec. III, eqs. jmp_var_def,
+1st_weak_equation, weak_penalty] against the oracle (oracle/sip.py).
+
+* RK4 trajectories (FP64, FP32) from random e, h, h_s with PML elements, a
+  dipole and uneven materials, on meshes of several tiles with a ragged tail.
+* The paper's own scheme: leap-frog with h_s beside h, PML damping by the
+  trapezoid rule, a dipole (FP64, FP32).
+* The two copies of each interior face's h_s stay equal to round-off, the
+  staggered energy with the h_s term is conserved over 200 leap-frog steps,
+  and the result does not depend on the tile size.
+* set_state clears h_s; set/get round trip.
+
+Errors are relative, in the energy norm of the whole state (e, h, h_s, p, q)
+of the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import dipole_args, oracle_dipoles, say, unit_jittered
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_08733_amd import load_library
+    load_library()
+
+
+def _pair(verts, tets, p, precision, eps, mu, alpha0, dt, omega=None, dipoles=(), integrator="rk4", tile=0):
+    from oracle import OracleDG
+    from oracle.sip import SipDG
+    from paper_2002_08733_amd import Solver
+    s = Solver(p, precision, "central", dt=dt, integrator=integrator, sip_alpha=alpha0, tile=tile)
+    s.set_mesh(verts, tets)
+    s.set_material(eps, mu)
+    if omega is not None:
+        s.set_pml(omega)
+    if dipoles:
+        s.set_dipoles(*dipole_args(dipoles))
+    s.bind_torch_workspace()
+    O = OracleDG(verts, tets, p, eps=eps, mu=mu, flux="central", omega=omega, dipoles=oracle_dipoles(dipoles))
+    return s, SipDG(O, alpha0)
+
+
+def _pml_omega(verts, tets, rng):
+    c = W.tet_centroids(verts, tets)
+    omega = np.zeros((len(tets), 3))
+    sel = c[:, 0] > 0.6
+    omega[sel] = rng.uniform(1.0, 5.0, (sel.sum(), 3))
+    omega[sel & (c[:, 1] < 0.3), 2] = 0.0
+    return omega, sel
+
+
+def _dip():
+    return [(np.array([0.45, 0.5, 0.52]), np.array([0.1, 0.3, 0.95]), (2.0, 1.0))]
+
+
+def _rel(S, got, want):
+    """Relative error in the oracle's energy norm; got/want = (e, h, h_s[faces], p, q)."""
+    d = [None if a is None else a - b for a, b in zip(got, want)]
+    num = S.energy(d[0], d[1], d[2])
+    den = S.energy(want[0], want[1], want[2])
+    if want[3] is not None:
+        O = S.O
+        J = O.J[:, None, None]
+        for a, b, m in ((d[3], want[3], O.eps), (d[4], want[4], O.mu)):
+            num += 0.5 * np.sum(J * a * a / m[:, None, None])
+            den += 0.5 * np.sum(J * b * b / m[:, None, None])
+    return float(np.sqrt(num / den))
+
+
+def _random_state(S, rng, pml=None):
+    O = S.O
+    K, N = O.K, O.N
+    E, H = rng.standard_normal((K, 3, N)), rng.standard_normal((K, 3, N))
+    Sf = rng.standard_normal((S.nfaces, 2, S.NF))
+    P = Q = None
+    if pml is not None:
+        P, Q = rng.standard_normal((K, 3, N)), rng.standard_normal((K, 3, N))
+        P[~pml] = 0.0
+        Q[~pml] = 0.0
+    return E, H, Sf, P, Q
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_sip_rk4_trajectory_with_pml_and_dipole(precision, tol):
+    verts, tets, eps, mu = unit_jittered(4, 71)
+    rng = np.random.default_rng(72)
+    omega, pml = _pml_omega(verts, tets, rng)
+    dt = W.cfl_dt(verts, tets, eps, mu, 3, 0.1)
+    s, S = _pair(verts, tets, 3, precision, eps, mu, 1.5, dt, omega, _dip())
+    E, H, Sf, P, Q = _random_state(S, rng, pml)
+    O = S.O
+    cov = O.to_covariant
+    s.set_state(cov(E), cov(H), cov(P), cov(Q), t=0.5)
+    s.set_sip_state(S.to_sides(Sf))
+    q = s.query()
+    say(f"[SIP RK4] p=3 {precision}: K={O.K} ({pml.sum()} PML), {S.nfaces} faces, {q['n_tiles']} tiles, dt={dt:.3e}")
+    s.step(6)
+    gE, gH, gP, gQ, t = s.get_state(aux=True)
+    gS = s.get_sip_state()
+    s.close()
+    (oE, oH, oS, oP, oQ), to = S.rk4_run(E, H, Sf, P, Q, t0=0.5, dt=dt, nsteps=6)
+    cv = O.to_cartesian
+    err = _rel(S, (cv(gE), cv(gH), S.from_sides(gS), cv(gP), cv(gQ)), (oE, oH, oS, oP, oQ))
+    # the other copy of every interior face
+    other = np.stack([gS[o // 4, o % 4] for (_, _, o) in S.sides if o >= 0])
+    first = np.stack([gS[k, f] for (k, f, o) in S.sides if o >= 0])
+    dcopy = np.abs(other - first).max() / np.abs(first).max()
+    say(f"  rel err {err:.3e}, copies of interior faces differ by {dcopy:.2e}")
+    assert abs(t - to) < 1e-12 and err < tol
+    assert dcopy < (1e-13 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_sip_leapfrog_trapezoid_pml(precision, tol):
+    verts, tets, eps, mu = unit_jittered(5, 73)
+    rng = np.random.default_rng(74)
+    omega, pml = _pml_omega(verts, tets, rng)
+    dt = W.cfl_dt(verts, tets, eps, mu, 3, 0.05)
+    s, S = _pair(verts, tets, 3, precision, eps, mu, 1.0, dt, omega, _dip(), integrator="leapfrog")
+    E, H, Sf, P, Q = _random_state(S, rng, pml)
+    O = S.O
+    cov = O.to_covariant
+    s.set_state(cov(E), cov(H), cov(P), cov(Q), t=0.6)
+    s.set_sip_state(S.to_sides(Sf))
+    s.step(15)
+    gE, gH, gP, gQ, _ = s.get_state(aux=True)
+    gS = s.get_sip_state()
+    s.close()
+    oE, oH, oS, oP, oQ, _ = S.leapfrog_run(E, H, Sf, P, Q, t0=0.6, dt=dt, nsteps=15)
+    cv = O.to_cartesian
+    err = _rel(S, (cv(gE), cv(gH), S.from_sides(gS), cv(gP), cv(gQ)), (oE, oH, oS, oP, oQ))
+    say(f"[SIP leap-frog] p=3 {precision}: K={O.K} ({pml.sum()} PML), 15 steps: rel err {err:.3e}")
+    assert err < tol
+
+
+def test_sip_leapfrog_staggered_energy_and_tiles():
+    verts, tets, eps, mu = unit_jittered(5, 75)
+    dt = W.cfl_dt(verts, tets, eps, mu, 2, 0.05)
+    rng = np.random.default_rng(76)
+    out = {}
+    for tile in (32, 64):
+        s, S = _pair(verts, tets, 2, "fp64", eps, mu, 2.0, dt, integrator="leapfrog", tile=tile)
+        O = S.O
+        E, H, Sf, _, _ = _random_state(S, np.random.default_rng(77))
+        s.set_state(O.to_covariant(E), O.to_covariant(H))
+        s.set_sip_state(S.to_sides(Sf))
+        cv = O.to_cartesian
+
+        def w_next():
+            _, Hp, _ = s.get_state()
+            Sp = S.from_sides(s.get_sip_state())
+            s.step(1)
+            e, h, _ = s.get_state()
+            return S.staggered_energy(cv(e), cv(Hp), cv(h), Sp, S.from_sides(s.get_sip_state()))
+
+        W1 = w_next()
+        s.step(200)
+        W2 = w_next()
+        out[tile] = s.get_state()[:2] + (s.get_sip_state(), s.query()["n_halo"])
+        s.close()
+        say(f"[SIP leap-frog energy] tile {tile}: W {W1:.15e} -> {W2:.15e} ({(W2 - W1) / W1:.1e})")
+        assert abs(W2 - W1) < 1e-12 * W1
+    (E1, H1, S1, h1), (E2, H2, S2, h2) = out[32], out[64]
+    d = max(np.abs(E1 - E2).max(), np.abs(H1 - H2).max(), np.abs(S1 - S2).max())
+    say(f"  tiles 32 vs 64: halo faces {h1} vs {h2}, max difference {d:.2e}")
+    assert h1 != h2 and d < 1e-11 * max(np.abs(E2).max(), np.abs(S2).max())
+
+
+def test_sip_state_roundtrip_and_reset():
+    verts, tets, eps, mu = unit_jittered(3, 78)
+    s, S = _pair(verts, tets, 2, "fp64", eps, mu, 1.0, 1e-3)
+    rng = np.random.default_rng(79)
+    K = len(tets)
+    Ss = rng.standard_normal((K, 4, 2, S.NF))
+    E = rng.standard_normal((K, 3, 10))
+    s.set_state(E, E)
+    s.set_sip_state(Ss)
+    assert np.array_equal(s.get_sip_state(), Ss)
+    s.set_state(E, E)  # a new state starts with h_s = 0
+    assert not s.get_sip_state().any()
+    s.close()

@@ -293,3 +293,46 @@ def test_mixed_order_option(lib):
     q = s.query()
     assert (q["order"], q["nmodes"], q["order_h"], q["nmodes_h"]) == (2, 10, 2, 10)
     s.close()
+
+
+def test_sip_option_and_host_side_errors(lib):
+    verts, tets = W.kuhn_cube_mesh(2)
+    # the SIP unknown comes with the central flux and equal orders
+    for kw in ({"flux": "upwind"}, {"mixed": True}):
+        with pytest.raises(lib.MdgError) as e:
+            lib.Solver(2, dt=1e-3, sip_alpha=1.0, **kw)
+        assert e.value.status == lib.MDG_E_UNSUPPORTED
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(lib.MdgError) as e:
+            lib.Solver(2, dt=1e-3, sip_alpha=bad)
+        assert e.value.status == lib.MDG_E_ARG
+    # state calls on a solver without it; instances; operator-only calls
+    s = lib.Solver(2, dt=1e-3)
+    s.set_mesh(verts, tets)
+    with pytest.raises(lib.MdgError) as e:
+        s.get_sip_state()
+    assert e.value.status == lib.MDG_E_UNSUPPORTED
+    s.close()
+    s = lib.Solver(2, dt=1e-3, sip_alpha=1.0)
+    s.set_mesh(np.concatenate([verts, verts + 5.0]), np.concatenate([tets, tets + len(verts)]))
+    s.set_instances([0, len(tets), 2 * len(tets)])
+    with pytest.raises(lib.MdgError) as e:
+        s.workspace_size()
+    assert e.value.status == lib.MDG_E_UNSUPPORTED
+    s.close()
+    s = lib.Solver(2, dt=1e-3, sip_alpha=1.0)
+    s.set_mesh(verts, tets)
+    K, N = len(tets), 10
+    z = np.zeros((K, 3, N))
+    for call in (lambda: s.rhs(z, z), lambda: s.probe_energy(2, [0]), lambda: s.adjoint_probe_energy(2, 1, [0])):
+        with pytest.raises(lib.MdgError) as e:
+            call()
+        assert e.value.status == lib.MDG_E_UNSUPPORTED
+    # algorithmic bytes: 8 NF surface values per element streamed like the
+    # state, plus the four face rows of the geometry record
+    s.workspace_size()
+    NF, rs = 6, 8
+    geo = 9 * rs + 16
+    want = K * (17 / 4 * 6 * N * rs + geo + 17 / 4 * 8 * NF * rs + 4 * rs)
+    assert s.query()["bytes_per_stage"] == pytest.approx(want)
+    s.close()
