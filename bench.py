@@ -52,11 +52,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def setup_solver(w, precision, dt, q=4, integrator="rk4", mixed=False):
+def setup_solver(w, precision, dt, q=4, integrator="rk4", mixed=False, sip_alpha=0.0):
     import torch
     from paper_2002_08733_amd import Solver
     # mixed: e at the workload's order, h one order lower
-    s = Solver(w.p - (1 if mixed else 0), precision, w.flux, dt=dt, integrator=integrator, mixed=mixed)
+    s = Solver(w.p - (1 if mixed else 0), precision, w.flux, dt=dt, integrator=integrator, mixed=mixed,
+               sip_alpha=sip_alpha)
     s.set_mesh(w.verts, w.tets)
     s.set_material(w.eps, w.mu)
     s.bind_torch_workspace()
@@ -288,19 +289,23 @@ def leapfrog_main(args):
     cubes x 6 = 196,608 jittered tets, p=3, eps ~ U[1,4], PEC, Gaussian pulse)
     with the central flux, which leap-frog needs: leap-frog at CFL 0.2
     (dt rho(L) < 1.9 < 2) against RK4 at CFL 0.3 (dt rho(L) < 2.8 < 2 sqrt 2),
-    and the paper's mixed pairing (e at order 3, h at order 2) by leap-frog.
-    Reports GDOF-updates/s per step (every DOF updated once per step),
+    the paper's mixed pairing (e at order 3, h at order 2) by leap-frog, and
+    leap-frog with the SIP surface unknown (alpha0 = 1, 80 more unknowns per
+    element, h_s starting at zero). Reports GDOF-updates/s per step of the
+    e and h DOF (every DOF updated once per step),
     simulated time per wall-clock second, and each launch against the HBM
     roofline (a leap-frog half step moves 4.5 (N + NH) values per element, an
-    RK4 stage 17/4 x 3 (N + NH))."""
+    RK4 stage 17/4 x 3 (N + NH); SIP adds 12 NF per half step)."""
     import torch
     w = W.jittered(args.n, 3, seed=2, flux="central")
     results = {}
     for prec in ["fp32"] + ([] if args.skip_fp64 else ["fp64"]):
-        for name, integ, cfl, mixed in (("leapfrog", "leapfrog", 0.2, False), ("rk4", "rk4", 0.3, False),
-                                        ("leapfrog_mixed", "leapfrog", 0.2, True)):
+        for name, integ, cfl, mixed, sip in (("leapfrog", "leapfrog", 0.2, False, 0.0),
+                                             ("rk4", "rk4", 0.3, False, 0.0),
+                                             ("leapfrog_mixed", "leapfrog", 0.2, True, 0.0),
+                                             ("leapfrog_sip", "leapfrog", 0.2, False, 1.0)):
             dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, cfl)
-            s = setup_solver(w, prec, dt, integrator=integ, mixed=mixed)
+            s = setup_solver(w, prec, dt, integrator=integ, mixed=mixed, sip_alpha=sip)
             info = s.query()
             W0 = s.energy()
             sec = time_steps(s, args.steps, args.warmup)
@@ -330,7 +335,8 @@ def leapfrog_main(args):
                       "data": "synthetic",
                       "config": {"workload": f"jittered cube [-1,1]^3, {args.n}^3 cubes x 6 = {w.nt} tets, p=3, "
                                              "eps~U[1,4], mu=1, central, PEC, Gaussian pulse; leap-frog CFL 0.2, "
-                                             "RK4 CFL 0.3; leapfrog_mixed: e order 3, h order 2",
+                                             "RK4 CFL 0.3; leapfrog_mixed: e order 3, h order 2; "
+                                             "leapfrog_sip: SIP unknown, alpha0 = 1",
                                  "elements": w.nt, "dof": w.nt * 120},
                       "speedup_vs_rk4_fp32": lf["sim_time_per_s"] / results["rk4_fp32"]["sim_time_per_s"],
                       "results": results}), flush=True)
