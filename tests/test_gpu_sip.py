@@ -8,7 +8,8 @@
 * The two copies of each interior face's h_s stay equal to round-off, the
   staggered energy with the h_s term is conserved over 200 leap-frog steps,
   and the result does not depend on the tile size.
-* set_state clears h_s; set/get round trip.
+* set_state clears h_s; set/get round trip; HIP-graph replay of SIP steps
+  equals eager stepping (several replays with eager work between them).
 
 Errors are relative, in the energy norm of the whole state (e, h, h_s, p, q)
 of the oracle.
@@ -186,3 +187,31 @@ def test_sip_state_roundtrip_and_reset():
     s.set_state(E, E)  # a new state starts with h_s = 0
     assert not s.get_sip_state().any()
     s.close()
+
+
+def test_sip_graph_replay_matches_eager():
+    import torch
+    verts, tets, eps, mu = unit_jittered(4, 80)
+    dt = W.cfl_dt(verts, tets, eps, mu, 3, 0.1)
+    rng = np.random.default_rng(81)
+    stream = torch.cuda.Stream()  # default priority
+    sp = stream.cuda_stream
+    pair = [_pair(verts, tets, 3, "fp32", eps, mu, 1.0, dt) for _ in range(2)]
+    g, e = pair[0][0], pair[1][0]
+    S = pair[0][1]
+    E, H, Sf, _, _ = _random_state(S, rng)
+    for x in (g, e):
+        x.set_state(S.O.to_covariant(E), S.O.to_covariant(H), t=0.2)
+        x.set_sip_state(S.to_sides(Sf))
+    for n in (9, 4, 7):
+        with torch.cuda.stream(stream):
+            g.step_graph(n, 4, sp)
+            e.step(n, sp)
+        stream.synchronize()
+        same = np.array_equal(g.get_sip_state(), e.get_sip_state()) and all(
+            np.array_equal(a, b) for a, b in zip(g.get_state(), e.get_state()))
+        say(f"[SIP graph] after {n} more steps: graph == eager: {same}")
+        assert same
+        g.energy()
+    g.close()
+    e.close()

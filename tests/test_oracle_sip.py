@@ -20,6 +20,9 @@ eqs. jmp_var_def, 1st_weak_equation, weak_penalty].
 * Consistency: a global polynomial field of degree <= p has no jumps, so
   d_t h_s = 0 on every interior face.
 * Leap-frog with h_s beside h conserves the staggered energy to round-off.
+* Purpose: on the unit PEC cube the central scheme has spurious
+  eigenfrequencies; with the surface unknown the low spectrum is exactly the
+  cavity's.
 """
 import numpy as np
 import pytest
@@ -149,3 +152,44 @@ def test_leapfrog_with_sip_conserves_staggered_energy():
         if n == 0:
             cE, cH, Sv, _, _, _ = S.leapfrog_run(cE, cH, Sv, dt=dt, nsteps=30)
     assert abs(Ws[1] - Ws[0]) < 1e-12 * Ws[0] and abs(Ws[2] - Ws[0]) < 1e-12 * Ws[0]
+
+
+def test_sip_clears_spurious_modes_of_the_cavity():
+    """The purpose of the SIP unknown [KS Sec. III]: the central scheme's
+    spectrum on the unit PEC cube (6 Kuhn tets, p=3) has eigenfrequencies
+    that belong to no cavity mode (below the lowest one, pi sqrt 2); with the
+    surface unknown (alpha0 = 1) every eigenfrequency below 6.5 lies within 3%
+    of a cavity mode pi sqrt(l^2+m^2+n^2) with its multiplicity (three near
+    pi sqrt 2, two near pi sqrt 3), and the spectrum stays on the imaginary
+    axis (skew system)."""
+    verts, tets = W.kuhn_cube_mesh(1, 0.0, 1.0)
+    O = OracleDG(verts, tets, 3)
+    S = SipDG(O, 1.0)
+    K, N = O.K, O.N
+    ne, ns = K * 3 * N, S.nfaces * 2 * S.NF
+
+    def freqs(with_sip):
+        n = 2 * ne + (ns if with_sip else 0)
+        A = np.zeros((n, n))
+        for c in range(n):
+            v = np.zeros(n)
+            v[c] = 1.0
+            E, H = v[:ne].reshape(K, 3, N), v[ne:2 * ne].reshape(K, 3, N)
+            if with_sip:
+                dE, dH, dS, _, _ = S.rhs(E, H, v[2 * ne:].reshape(S.nfaces, 2, S.NF))
+                A[:, c] = np.concatenate([dE.ravel(), dH.ravel(), dS.ravel()])
+            else:
+                dE, dH, _, _ = O.rhs(E, H)
+                A[:, c] = np.concatenate([dE.ravel(), dH.ravel()])
+        ev = np.linalg.eigvals(A)
+        assert np.abs(ev.real).max() < 1e-10 * np.abs(ev.imag).max()
+        return np.sort(ev.imag[ev.imag > 1e-8])
+
+    lowest = np.pi * np.sqrt(2.0)
+    plain = freqs(False)
+    assert np.sum(plain < 0.97 * lowest) >= 2  # spurious: below every cavity mode
+    w = freqs(True)
+    w = w[w < 6.5]
+    cavity = np.array([lowest] * 3 + [np.pi * np.sqrt(3.0)] * 2)
+    assert len(w) == len(cavity)
+    assert np.all(np.abs(w / cavity - 1.0) < 0.03)
