@@ -9,8 +9,9 @@ System (central flux, PEC boundaries, optional PML and dipoles from OracleDG):
   (mu d_t h, w)_T  = [central terms of OracleDG]
   (mu_F/alpha_F) (d_t h_s, psi)_F = ([[e]]_F, psi)_F   for every face F
 
-with h_s a tangential field of degree p on every face. Readings (the paper
-leaves them open or garbled):
+with h_s a tangential field on every face of the degree p_h of h (p with
+equal orders; in the paper's mixed pairing, e at order p and h at p-1, it
+is p-1). Readings (the paper leaves them open or garbled):
 
 * jump: [[e]]_F = n_T x (e_T - e_T'), the same from either side T, T' of an
   interior face; on a PEC face [[e]]_F = n_T x e_T (the jump against the
@@ -18,9 +19,10 @@ leaves them open or garbled):
   skew ((e, h, h_s) rows [0 C C_F; -C^T 0 0; -C_F^T 0 0]), so that
   W = 1/2 (eps e, e) + 1/2 (mu h, h) + 1/2 sum_F (mu_F/alpha_F) (h_s, h_s)_F
   is conserved (pinned in tests/test_oracle_sip.py).
-* penalty: alpha_F = alpha0 (p+1)(p+3)/3 |F| / min(|T|, |T'|) (the trace
-  inverse-inequality scaling of the cited lower bounds; one user constant
-  alpha0 > 0); mu_F = (mu_T + mu_T')/2 (mu_T on PEC faces).
+* penalty: alpha_F = alpha0 (p+1)(p+3)/3 |F| / min(|T|, |T'|), p the order
+  of e, whose jump is penalised (the trace inverse-inequality scaling of the
+  cited lower bounds; one user constant alpha0 > 0); mu_F = (mu_T + mu_T')/2
+  (mu_T on PEC faces).
 * PML elements: h_s carries no damping (the penalty term is consistent, so
   it needs none).
 
@@ -65,17 +67,17 @@ def face_basis(p, s):
 
 
 class SipDG:
-    """SIP extension of an OracleDG with the central flux (equal orders)."""
+    """SIP extension of an OracleDG with the central flux (h_s of the order of h)."""
 
     def __init__(self, O, alpha0):
-        if O.flux != "central" or O.ph != O.p:
-            raise ValueError("SIP oracle: central flux, equal orders")
+        if O.flux != "central":
+            raise ValueError("SIP oracle: central flux")
         if not alpha0 > 0:
             raise ValueError("alpha0 > 0")
         self.O = O
         self.alpha0 = float(alpha0)
         p = O.p
-        self.NF = (p + 1) * (p + 2) // 2
+        self.NF = (O.ph + 1) * (O.ph + 2) // 2  # face space of h_s: degree p_h
         K = O.K
         # unique faces, numbered by their first (element, face) side
         fid = -np.ones((K, 4), dtype=np.int64)
@@ -94,7 +96,7 @@ class SipDG:
         self.nfaces = len(sides)
         vol = O.J / 6.0
         self.fq, self.fw = tri_quadrature(p + 2)
-        self.psi = face_basis(p, self.fq)  # [Qf, NF]
+        self.psi = face_basis(O.ph, self.fq)  # [Qf, NF]
         NF = self.NF
         self.alpha = np.zeros(self.nfaces)
         self.muF = np.zeros(self.nfaces)

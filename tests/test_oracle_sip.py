@@ -193,3 +193,38 @@ def test_sip_clears_spurious_modes_of_the_cavity():
     cavity = np.array([lowest] * 3 + [np.pi * np.sqrt(3.0)] * 2)
     assert len(w) == len(cavity)
     assert np.all(np.abs(w / cavity - 1.0) < 0.03)
+
+
+def test_sip_with_mixed_orders():
+    """The paper's pairing (e at order p+1, h and h_s at order p): the block
+    system stays skew, global polynomials of e's degree have no jumps, and
+    leap-frog conserves the staggered energy."""
+    verts, tets, eps, mu, rng = _mesh(17)
+    O = OracleDG(verts, tets, 3, eps=eps, mu=mu, ph=2)
+    S = SipDG(O, 1.5)
+    assert S.NF == 6  # h_s in P_2 of each face
+    K = O.K
+    cE, cH = rng.standard_normal((K, 3, O.N)), rng.standard_normal((K, 3, O.NH))
+    Sv = rng.standard_normal((S.nfaces, 2, S.NF))
+    dE, dH, dS, _, _ = S.rhs(cE, cH, Sv)
+    J = O.J[:, None, None]
+    a = np.sum(J * eps[:, None, None] * cE * dE)
+    b = np.sum(J * mu[:, None, None] * cH * dH)
+    c = sum(float(Sv[F].ravel() @ S.mass[F] @ dS[F].ravel()) for F in range(S.nfaces))
+    scale = abs(a) + abs(b) + abs(c)
+    assert abs(c) > 1e-2 * scale and abs(a + b + c) < 1e-13 * scale
+
+    def fe(x):
+        return np.stack([x[..., 1] ** 2 * x[..., 2], x[..., 0] - x[..., 2] ** 3, x[..., 0] * x[..., 1] * x[..., 2]],
+                        axis=-1)
+
+    _, _, dS0, _, _ = S.rhs(O.project(fe), np.zeros((K, 3, O.NH)), np.zeros_like(Sv))
+    inner = np.array([o >= 0 for (_, _, o) in S.sides])
+    assert np.abs(dS0[inner]).max() < 1e-11
+    dt = 0.2 * W.cfl_dt(verts, tets, eps, mu, 3, 0.2)
+    e1, h1, s1, _, _, _ = S.leapfrog_run(cE, cH, Sv, dt=dt, nsteps=1)
+    W1 = S.staggered_energy(e1, cH, h1, Sv, s1)
+    e2, h2, s2, _, _, _ = S.leapfrog_run(e1, h1, s1, dt=dt, nsteps=20)
+    e3, h3, s3, _, _, _ = S.leapfrog_run(e2, h2, s2, dt=dt, nsteps=1)
+    W2 = S.staggered_energy(e3, h2, h3, s2, s3)
+    assert abs(W2 - W1) < 1e-12 * W1
