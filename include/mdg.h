@@ -81,8 +81,9 @@ typedef struct mdg_options {
                          pairing [KS eqs. triale, trialh] (then p <= 3) */
   double sip_alpha;   /* > 0: symmetric interior penalty surface unknown h_s on every face
                          [KS Sec. III, eqs. jmp_var_def, 1st_weak_equation, weak_penalty]
-                         with alpha_F = sip_alpha (p+1)(p+3)/3 |F| / min(|T|, |T'|);
-                         0: none. Central flux and equal orders only (see mdg_set_sip_state) */
+                         with alpha_F = sip_alpha (p+1)(p+3)/3 |F| / min(|T|, |T'|), p the
+                         order of e;
+                         0: none. Central flux only (see mdg_set_sip_state) */
 } mdg_options;
 
 typedef struct mdg_info {
@@ -191,6 +192,7 @@ mdg_status mdg_get_state(mdg_solver* s, double* E, double* H, double* P, double*
  * conserved by the semi-discrete system (mdg_energy reports W alone). With
  * MDG_LEAPFROG h_s is staggered with h (at t + dt/2). dt from cfl does not
  * account for the penalty: choose cfl (or dt) for it.
+ * h_s has the order p of h (also with mixed orders, the paper's pairing).
  * Layout S[nt][4][2][NF] (caller's element order, NF = (p+1)(p+2)/2): face f
  * of element t is the face opposite the element's f-th vertex in the element
  * frame (vertices by ascending global id); its vertices a < b < c (global id)
@@ -201,7 +203,7 @@ mdg_status mdg_get_state(mdg_solver* s, double* E, double* H, double* P, double*
  * library updates both from the same data, so they agree to round-off.
  * mdg_set_state and mdg_project set h_s to zero; mdg_set_sip_state then sets
  * it (both copies of a face should be equal). Not available (MDG_E_UNSUPPORTED)
- * with the upwind flux, mixed orders or instances (mdg_create, or the first
+ * with the upwind flux or instances (mdg_create, or the first
  * call that finalises the setup), in mdg_rhs and in the probe-energy and
  * adjoint calls, and in these two calls without sip_alpha. Synchronous. */
 mdg_status mdg_set_sip_state(mdg_solver* s, const double* S);

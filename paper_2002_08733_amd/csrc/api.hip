@@ -300,8 +300,8 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
   }
   if (o->tile != 0 && o->tile != 32 && o->tile != 64) { g_create_error = "tile must be 0, 32 or 64"; return MDG_E_ARG; }
   if (!(o->sip_alpha >= 0) || !std::isfinite(o->sip_alpha)) { g_create_error = "sip_alpha must be >= 0"; return MDG_E_ARG; }
-  if (o->sip_alpha > 0 && (o->flux != MDG_CENTRAL || o->mixed)) {
-    g_create_error = "the SIP unknown needs the central flux and equal orders";
+  if (o->sip_alpha > 0 && o->flux != MDG_CENTRAL) {
+    g_create_error = "the SIP unknown needs the central flux";
     return MDG_E_UNSUPPORTED;
   }
   if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
@@ -312,6 +312,7 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
   h->s.N = nmodes3(h->s.P);
   h->s.NF = nmodes2(h->s.P);
   h->s.NH = nmodes3(o->order);
+  h->s.NFH = nmodes2(o->order);
   *out = h;
   return MDG_OK;
 }

@@ -669,21 +669,25 @@ void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, doubl
   }
 }
 
+// host rows (face, k, m < NFH) <-> device rows (face * 2 + k) * NF + m; with
+// mixed orders the face modes NFH.. of the kernel's order stay zero
 void pack_sip(const Solver& s, const double* S, std::vector<double>& out) {
-  const int R8 = 8 * s.NF;
+  const int R8 = 8 * s.NF, NFH = s.NFH;
   out.assign(size_t(R8) * s.Kpad, 0.0);
   if (!S) return;
   for (int64_t k = 0; k < s.K; ++k) {
     const int64_t u = s.perm[k];
-    for (int r = 0; r < R8; ++r) out[blk_index(k, r, R8)] = S[u * R8 + r];
+    for (int fk = 0; fk < 8; ++fk)
+      for (int m = 0; m < NFH; ++m) out[blk_index(k, fk * s.NF + m, R8)] = S[(u * 8 + fk) * NFH + m];
   }
 }
 
 void unpack_sip(const Solver& s, const std::vector<double>& in, double* S) {
-  const int R8 = 8 * s.NF;
+  const int R8 = 8 * s.NF, NFH = s.NFH;
   for (int64_t k = 0; k < s.K; ++k) {
     const int64_t u = s.perm[k];
-    for (int r = 0; r < R8; ++r) S[u * R8 + r] = in[blk_index(k, r, R8)];
+    for (int fk = 0; fk < 8; ++fk)
+      for (int m = 0; m < NFH; ++m) S[(u * 8 + fk) * NFH + m] = in[blk_index(k, fk * s.NF + m, R8)];
   }
 }
 
@@ -712,7 +716,7 @@ double bytes_per_stage(const Solver& s) {
   // SIP: 8 NF surface values per element streamed like the state (the E
   // half of a leap-frog step reads them, the H half reads and writes them)
   // plus the four face rows of the geometry record
-  const double sip = s.sip() ? (lf ? 12.0 : 17.0 / 4.0 * 8.0) * s.NF * rs + 4.0 * rs : 0.0;
+  const double sip = s.sip() ? (lf ? 12.0 : 17.0 / 4.0 * 8.0) * s.NFH * rs + 4.0 * rs : 0.0;
   return s.K * (state + geo + sip) + s.Kp * pml;
 }
 

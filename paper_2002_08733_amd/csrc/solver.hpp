@@ -72,6 +72,7 @@ struct Solver {
   mdg_options opt{};
   int P = 0, N = 0, NF = 0;  // order, modes and face modes of the kernel (of e)
   int NH = 0;                // modes of h: N, or dim P_{P-1} with mixed orders
+  int NFH = 0;               // face modes of the SIP unknown (degree of h): NF, or dim P_{P-1}(F)
   std::string err;
   // ---- mesh (caller's element order, canonical vertex order)
   int64_t nv = 0, nt = 0;
@@ -146,7 +147,7 @@ void project_fields(const Solver& s, int q, const double* vals, int N, std::vect
 void pack_state(const Solver& s, const double* E, const double* H, std::vector<double>& out);
 void unpack_state(const Solver& s, const std::vector<double>& in, double* E, double* H);
 void pack_aux(const Solver& s, const double* P, const double* Q, std::vector<double>& out);
-// SIP unknown: caller's S[nt][4][2][NF] <-> blocked [Kpad/64][8 NF][64]
+// SIP unknown: caller's S[nt][4][2][NFH] <-> blocked [Kpad/64][8 NF][64] (rows of modes >= NFH zero)
 void pack_sip(const Solver& s, const double* S, std::vector<double>& out);
 void unpack_sip(const Solver& s, const std::vector<double>& in, double* S);
 void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, double* Q);

@@ -84,6 +84,7 @@ struct DevArgs {
   int32_t tile_begin, ntiles, stage, has_src, publish;  // stage: 0..3 RK4, -1 operator, 4/5 leap-frog E/H half
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
   int32_t nh;                    // modes of h: N, or fewer with mixed orders (the rest stay zero)
+  int32_t nfh;                   // face modes of the SIP unknown: NF, or fewer with mixed orders
   int32_t adj;                   // 1: adjoint operator (operator calls without sources)
   double bcoef, cdt, dt;
 };
@@ -752,8 +753,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const R cs = R(es.c_out), bs = R(a.bcoef);
 #pragma unroll
         for (int m = 0; m < NF; ++m) {
-          const R d0 = fma(-hn, nbr[loff<NF>(0, m)], own[loff<NF>(0, m)]);
-          const R d1 = fma(-hn, nbr[loff<NF>(1, m)], own[loff<NF>(1, m)]);
+          // with mixed orders h_s lives in the lower-order face space, whose
+          // modes are the first nfh of this basis: the others get no derivative
+          const R keep = m < a.nfh ? R(1) : R(0);
+          const R d0 = keep * fma(-hn, nbr[loff<NF>(0, m)], own[loff<NF>(0, m)]);
+          const R d1 = keep * fma(-hn, nbr[loff<NF>(1, m)], own[loff<NF>(1, m)]);
           const R v1 = -sig * d1, v2 = sig * d0;
           rk_store<R>(es, fs * fma(g11, v1, g12 * v2), vs, rowb<R>(srow + m), bs, cs, wr);
           rk_store<R>(es, fs * fma(g12, v1, g22 * v2), vs, rowb<R>(srow + NF + m), bs, cs, wr);
@@ -1246,6 +1250,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
     throw Error(MDG_E_STATE, "SIP launch without its surface buffers");
   a.pml_base = s.K0;
   a.nh = s.NH;
+  a.nfh = s.NFH;
   a.adj = sp.adj ? 1 : 0;
   a.stage = sp.stage;
   a.bcoef = sp.bcoef;

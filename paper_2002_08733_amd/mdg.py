@@ -130,7 +130,7 @@ class Solver:
                  mixed=False, sip_alpha=0.0):
         """order: polynomial order of h (and of e, unless mixed: then e is one
         order higher, the paper's pairing). sip_alpha > 0 adds the SIP
-        surface unknown (central flux, equal orders)."""
+        surface unknown (central flux)."""
         self.lib = load_library()
         if integrator not in ("rk4", "leapfrog"):
             raise ValueError("integrator must be 'rk4' or 'leapfrog'")
@@ -147,7 +147,7 @@ class Solver:
         pe = order + (1 if mixed else 0)
         self.nmodes = (pe + 1) * (pe + 2) * (pe + 3) // 6  # of e (and p)
         self.nmodes_h = (order + 1) * (order + 2) * (order + 3) // 6  # of h (and q)
-        self.nfacemodes = (pe + 1) * (pe + 2) // 2
+        self.nfacemodes = (order + 1) * (order + 2) // 2  # of the SIP unknown (order of h)
         self.nt = 0
         self._ws = None
 

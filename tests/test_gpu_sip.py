@@ -8,6 +8,8 @@
 * The two copies of each interior face's h_s stay equal to round-off, the
   staggered energy with the h_s term is conserved over 200 leap-frog steps,
   and the result does not depend on the tile size.
+* Mixed orders (e at p+1, h and h_s at p) with RK4, and the paper's whole
+  scheme: mixed orders, leap-frog, trapezoid PML, a dipole and h_s.
 * set_state clears h_s; set/get round trip; HIP-graph replay of SIP steps
   equals eager stepping (several replays with eager work between them).
 
@@ -32,11 +34,13 @@ def _gpu():
     load_library()
 
 
-def _pair(verts, tets, p, precision, eps, mu, alpha0, dt, omega=None, dipoles=(), integrator="rk4", tile=0):
+def _pair(verts, tets, p, precision, eps, mu, alpha0, dt, omega=None, dipoles=(), integrator="rk4", tile=0,
+          mixed=False):
+    """Library solver and oracle; with mixed, e at order p + 1 and h, h_s at p."""
     from oracle import OracleDG
     from oracle.sip import SipDG
     from paper_2002_08733_amd import Solver
-    s = Solver(p, precision, "central", dt=dt, integrator=integrator, sip_alpha=alpha0, tile=tile)
+    s = Solver(p, precision, "central", dt=dt, integrator=integrator, sip_alpha=alpha0, tile=tile, mixed=mixed)
     s.set_mesh(verts, tets)
     s.set_material(eps, mu)
     if omega is not None:
@@ -44,8 +48,11 @@ def _pair(verts, tets, p, precision, eps, mu, alpha0, dt, omega=None, dipoles=()
     if dipoles:
         s.set_dipoles(*dipole_args(dipoles))
     s.bind_torch_workspace()
-    O = OracleDG(verts, tets, p, eps=eps, mu=mu, flux="central", omega=omega, dipoles=oracle_dipoles(dipoles))
-    return s, SipDG(O, alpha0)
+    O = OracleDG(verts, tets, p + (1 if mixed else 0), eps=eps, mu=mu, flux="central", omega=omega,
+                 dipoles=oracle_dipoles(dipoles), ph=p)
+    S = SipDG(O, alpha0)
+    assert (s.nmodes, s.nmodes_h, s.nfacemodes) == (O.N, O.NH, S.NF)
+    return s, S
 
 
 def _pml_omega(verts, tets, rng):
@@ -77,12 +84,12 @@ def _rel(S, got, want):
 
 def _random_state(S, rng, pml=None):
     O = S.O
-    K, N = O.K, O.N
-    E, H = rng.standard_normal((K, 3, N)), rng.standard_normal((K, 3, N))
+    K, N, NH = O.K, O.N, O.NH
+    E, H = rng.standard_normal((K, 3, N)), rng.standard_normal((K, 3, NH))
     Sf = rng.standard_normal((S.nfaces, 2, S.NF))
     P = Q = None
     if pml is not None:
-        P, Q = rng.standard_normal((K, 3, N)), rng.standard_normal((K, 3, N))
+        P, Q = rng.standard_normal((K, 3, N)), rng.standard_normal((K, 3, NH))
         P[~pml] = 0.0
         Q[~pml] = 0.0
     return E, H, Sf, P, Q
@@ -139,6 +146,51 @@ def test_sip_leapfrog_trapezoid_pml(precision, tol):
     err = _rel(S, (cv(gE), cv(gH), S.from_sides(gS), cv(gP), cv(gQ)), (oE, oH, oS, oP, oQ))
     say(f"[SIP leap-frog] p=3 {precision}: K={O.K} ({pml.sum()} PML), 15 steps: rel err {err:.3e}")
     assert err < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_sip_mixed_orders_the_papers_scheme(precision, tol):
+    """e at order 3, h and h_s at order 2, leap-frog with the PML damping by
+    the trapezoid rule, a dipole and the SIP unknown: the paper's scheme."""
+    verts, tets, eps, mu = unit_jittered(5, 82)
+    rng = np.random.default_rng(83)
+    omega, pml = _pml_omega(verts, tets, rng)
+    dt = W.cfl_dt(verts, tets, eps, mu, 3, 0.05)
+    s, S = _pair(verts, tets, 2, precision, eps, mu, 1.0, dt, omega, _dip(), integrator="leapfrog", mixed=True)
+    E, H, Sf, P, Q = _random_state(S, rng, pml)
+    O = S.O
+    cov = O.to_covariant
+    s.set_state(cov(E), cov(H), cov(P), cov(Q), t=0.6)
+    s.set_sip_state(S.to_sides(Sf))
+    s.step(12)
+    gE, gH, gP, gQ, _ = s.get_state(aux=True)
+    gS = s.get_sip_state()
+    s.close()
+    oE, oH, oS, oP, oQ, _ = S.leapfrog_run(E, H, Sf, P, Q, t0=0.6, dt=dt, nsteps=12)
+    cv = O.to_cartesian
+    err = _rel(S, (cv(gE), cv(gH), S.from_sides(gS), cv(gP), cv(gQ)), (oE, oH, oS, oP, oQ))
+    say(f"[SIP mixed leap-frog] e3/h2/h_s2 {precision}: K={O.K} ({pml.sum()} PML), 12 steps: rel err {err:.3e}")
+    assert err < tol
+
+
+def test_sip_mixed_rk4():
+    verts, tets, eps, mu = unit_jittered(4, 84)
+    rng = np.random.default_rng(85)
+    dt = W.cfl_dt(verts, tets, eps, mu, 3, 0.1)
+    s, S = _pair(verts, tets, 2, "fp64", eps, mu, 2.0, dt, mixed=True)
+    E, H, Sf, _, _ = _random_state(S, rng)
+    O = S.O
+    s.set_state(O.to_covariant(E), O.to_covariant(H), t=0.1)
+    s.set_sip_state(S.to_sides(Sf))
+    s.step(6)
+    gE, gH, _ = s.get_state()
+    gS = s.get_sip_state()
+    s.close()
+    (oE, oH, oS, _, _), _ = S.rk4_run(E, H, Sf, t0=0.1, dt=dt, nsteps=6)
+    cv = O.to_cartesian
+    err = _rel(S, (cv(gE), cv(gH), S.from_sides(gS), None, None), (oE, oH, oS, None, None))
+    say(f"[SIP mixed RK4] e3/h2/h_s2 fp64: rel err {err:.3e}")
+    assert err < 1e-12
 
 
 def test_sip_leapfrog_staggered_energy_and_tiles():

@@ -297,11 +297,10 @@ def test_mixed_order_option(lib):
 
 def test_sip_option_and_host_side_errors(lib):
     verts, tets = W.kuhn_cube_mesh(2)
-    # the SIP unknown comes with the central flux and equal orders
-    for kw in ({"flux": "upwind"}, {"mixed": True}):
-        with pytest.raises(lib.MdgError) as e:
-            lib.Solver(2, dt=1e-3, sip_alpha=1.0, **kw)
-        assert e.value.status == lib.MDG_E_UNSUPPORTED
+    # the SIP unknown comes with the central flux
+    with pytest.raises(lib.MdgError) as e:
+        lib.Solver(2, dt=1e-3, sip_alpha=1.0, flux="upwind")
+    assert e.value.status == lib.MDG_E_UNSUPPORTED
     for bad in (-1.0, float("nan"), float("inf")):
         with pytest.raises(lib.MdgError) as e:
             lib.Solver(2, dt=1e-3, sip_alpha=bad)
@@ -334,5 +333,13 @@ def test_sip_option_and_host_side_errors(lib):
     NF, rs = 6, 8
     geo = 9 * rs + 16
     want = K * (17 / 4 * 6 * N * rs + geo + 17 / 4 * 8 * NF * rs + 4 * rs)
+    assert s.query()["bytes_per_stage"] == pytest.approx(want)
+    s.close()
+    # mixed orders (e order 3, h order 2): h_s has the face modes of order 2
+    s = lib.Solver(2, dt=1e-3, sip_alpha=1.0, mixed=True, integrator="leapfrog")
+    s.set_mesh(verts, tets)
+    s.workspace_size()
+    assert s.nfacemodes == 6
+    want = K * (4.5 * (20 + 10) * rs + geo + 12 * 6 * rs + 4 * rs)
     assert s.query()["bytes_per_stage"] == pytest.approx(want)
     s.close()
