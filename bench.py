@@ -414,8 +414,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the element-block sharding "
+              "across GPUs is a design, not an implemented path", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
