@@ -2,7 +2,8 @@
 1st_weak_equation, weak_penalty] against the oracle (oracle/sip.py).
 
 * RK4 trajectories (FP64, FP32) from random e, h, h_s with PML elements, a
-  dipole and uneven materials, on meshes of several tiles with a ragged tail.
+  dipole and uneven materials, on meshes of several tiles with a ragged tail;
+  FP64 RK4 at orders 1, 2 and 4 as well.
 * The paper's own scheme: leap-frog with h_s beside h, PML damping by the
   trapezoid rule, a dipole (FP64, FP32).
 * The two copies of each interior face's h_s stay equal to round-off, the
@@ -267,3 +268,24 @@ def test_sip_graph_replay_matches_eager():
         g.energy()
     g.close()
     e.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_sip_rk4_other_orders(p):
+    verts, tets, eps, mu = unit_jittered(3, 86 + p)
+    rng = np.random.default_rng(90 + p)
+    dt = W.cfl_dt(verts, tets, eps, mu, p, 0.1)
+    s, S = _pair(verts, tets, p, "fp64", eps, mu, 1.0, dt)
+    E, H, Sf, _, _ = _random_state(S, rng)
+    O = S.O
+    s.set_state(O.to_covariant(E), O.to_covariant(H))
+    s.set_sip_state(S.to_sides(Sf))
+    s.step(4)
+    gE, gH, _ = s.get_state()
+    gS = s.get_sip_state()
+    s.close()
+    (oE, oH, oS, _, _), _ = S.rk4_run(E, H, Sf, dt=dt, nsteps=4)
+    cv = O.to_cartesian
+    err = _rel(S, (cv(gE), cv(gH), S.from_sides(gS), None, None), (oE, oH, oS, None, None))
+    say(f"[SIP RK4] p={p} fp64: K={O.K}, NF={S.NF}: rel err {err:.3e}")
+    assert err < 1e-12
