@@ -9,6 +9,8 @@
 * The two copies of each interior face's h_s stay equal to round-off, the
   staggered energy with the h_s term is conserved over 200 leap-frog steps,
   and the result does not depend on the tile size.
+* Full size (the benchmark's SIP configuration): staggered energy with the
+  h_s term conserved and both copies of every face equal.
 * Mixed orders (e at p+1, h and h_s at p) with RK4, and the paper's whole
   scheme: mixed orders, leap-frog, trapezoid PML, a dipole and h_s.
 * set_state clears h_s; set/get round trip; HIP-graph replay of SIP steps
@@ -289,3 +291,97 @@ def test_sip_rk4_other_orders(p):
     err = _rel(S, (cv(gE), cv(gH), S.from_sides(gS), None, None), (oE, oH, oS, None, None))
     say(f"[SIP RK4] p={p} fp64: K={O.K}, NF={S.NF}: rel err {err:.3e}")
     assert err < 1e-12
+
+
+# ------------------------------------------------------------ full size
+_FACE_VERTS = ((1, 2, 3), (0, 2, 3), (0, 1, 3), (0, 1, 2))
+
+
+def _fullsize_tables(verts, tets, mu, p, alpha0):
+    """Closed-form quantities of the staggered energy on every element side
+    (vectorised for the full mesh; the face mass (mu_F/alpha_F) sqrt(det g)
+    g^-1 (x) I is pinned against the oracle's quadrature in
+    test_oracle_sip.py): the side weight c = w (mu_F/alpha_F) |t1 x t2| with
+    w = 1/2 on interior faces (both copies) and 1 on PEC faces, g^-1, the
+    other side (element * 4 + face, or -1), and A^-1, J per element."""
+    T = np.sort(np.asarray(tets, dtype=np.int64), axis=1)
+    X = np.asarray(verts, dtype=np.float64)[T]
+    A = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+    J = np.abs(np.linalg.det(A))
+    K = len(T)
+    keys = np.stack([T[:, list(fv)] for fv in _FACE_VERTS], axis=1).reshape(-1, 3)
+    _, inv = np.unique(keys, axis=0, return_inverse=True)
+    inv = inv.ravel()
+    order = np.argsort(inv, kind="stable")
+    srt = inv[order]
+    pair = np.nonzero(srt[1:] == srt[:-1])[0]
+    other = -np.ones(4 * K, dtype=np.int64)
+    other[order[pair]] = order[pair + 1]
+    other[order[pair + 1]] = order[pair]
+    other = other.reshape(K, 4)
+    t1 = np.stack([X[:, fv[1]] - X[:, fv[0]] for fv in _FACE_VERTS], axis=1)
+    t2 = np.stack([X[:, fv[2]] - X[:, fv[0]] for fv in _FACE_VERTS], axis=1)
+    cr = np.linalg.norm(np.cross(t1, t2), axis=-1)
+    has = other >= 0
+    kn = np.where(has, other // 4, np.arange(K)[:, None])
+    alpha = alpha0 * (p + 1) * (p + 3) / 3.0 * 0.5 * cr / np.minimum(J[:, None], J[kn]) * 6.0
+    muF = 0.5 * (mu[:, None] + mu[kn])
+    c = np.where(has, 0.5, 1.0) * muF / alpha * cr
+    g11, g12, g22 = (t1 * t1).sum(-1), (t1 * t2).sum(-1), (t2 * t2).sum(-1)
+    det = g11 * g22 - g12 * g12
+    ginv = np.stack([np.stack([g22, -g12], -1), np.stack([-g12, g11], -1)], -2) / det[..., None, None]
+    return c, ginv, other, np.linalg.inv(A), J
+
+
+def _fullsize_staggered_energy(tab, eps, mu, E, Hp, Hn, Sp, Sn):
+    c, ginv, _, Ainv, J = tab
+    cart = lambda u: np.einsum("kji,kjm->kim", Ainv, u)  # noqa: E731
+    cE, cHp, cHn = cart(E), cart(Hp), cart(Hn)
+    We = 0.5 * np.sum(J * eps * np.sum(cE * cE, axis=(1, 2)))
+    Wh = 0.5 * np.sum(J * mu * np.sum(cHp * cHn, axis=(1, 2)))
+    Ws = 0.5 * np.sum(c * np.einsum("kfam,kfab,kfbm->kf", Sp, ginv, Sn))
+    return We + Wh + Ws, Ws
+
+
+def test_sip_fullsize_leapfrog_properties():
+    """The benchmark's SIP configuration (196,608-element jittered cube, p=3,
+    central flux, leap-frog at CFL 0.2, alpha0 = 1, same launches), FP64:
+    the staggered energy with the h_s term is conserved, and the two copies
+    of every interior face's h_s agree (properties that hold at any size)."""
+    from paper_2002_08733_amd import Solver
+    w = W.jittered(32, 3, seed=2, flux="central")
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, 3, 0.2)
+    s = Solver(3, "fp64", "central", dt=dt, integrator="leapfrog", sip_alpha=1.0)
+    s.set_mesh(w.verts, w.tets)
+    s.set_material(w.eps, w.mu)
+    s.bind_torch_workspace()
+    rng = np.random.default_rng(93)
+    K = w.nt
+    # a rough state, so that the jumps and the penalty coupling are large
+    s.set_state(rng.standard_normal((K, 3, 20)), rng.standard_normal((K, 3, 20)))
+    tab = _fullsize_tables(w.verts, w.tets, w.mu, 3, 1.0)
+    say(f"[SIP full size] K={K} p=3 fp64 leap-frog CFL 0.2, alpha0 = 1")
+
+    def w_next():
+        _, Hp, _ = s.get_state()
+        Sp = s.get_sip_state()
+        s.step(1)
+        E, Hn, _ = s.get_state()
+        Sn = s.get_sip_state()
+        Wt, Ws = _fullsize_staggered_energy(tab, w.eps, w.mu, E, Hp, Hn, Sp, Sn)
+        return Wt, Ws, Sn
+
+    s.step(20)
+    W1, Ws1, _ = w_next()
+    s.step(100)
+    W2, Ws2, Sn = w_next()
+    s.close()
+    other = tab[2]
+    k, f = np.nonzero(other >= 0)
+    o = other[k, f]
+    dcopy = np.abs(Sn[k, f] - Sn[o // 4, o % 4]).max() / np.abs(Sn).max()
+    say(f"  W {W1:.15e} -> {W2:.15e} ({(W2 - W1) / W1:.1e}), h_s share {Ws1 / W1:.2e}, "
+        f"copies differ by {dcopy:.1e}")
+    assert Ws1 > 1e-3 * W1  # the surface unknown carries energy
+    assert abs(W2 - W1) < 1e-11 * W1
+    assert dcopy < 1e-12
