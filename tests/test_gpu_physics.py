@@ -16,6 +16,9 @@ coefficient difference over the inner box at t = 1.25, 2.5, 3.25 and 4,
 relative to the largest norm of the reference field there (the outgoing
 pulse, at t = 1.25). For the graded profile the continuum estimate is
 exp(-2 sigma_max L / 4): 0.7% for 4 layers.
+
+Also: a step far beyond the stability limit is reported as MDG_E_UNSTABLE
+by the energy calls.
 """
 import numpy as np
 import pytest
@@ -90,3 +93,29 @@ def test_pml_reflection_falls_with_thickness():
             f"{refs[-1]:.3e}")
     assert all(a > 2.0 * b for a, b in zip(refs, refs[1:])), refs
     assert refs[-1] < 0.02
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_unstable_step_is_reported(precision):
+    """A time step far beyond the stability limit (RK4: dt rho(L) <= 2 sqrt 2)
+    makes the state overflow; mdg_energy and mdg_energy_instances report
+    MDG_E_UNSTABLE instead of a number. The condition comes from ordinary
+    arithmetic (overflow to inf/nan), nothing faults."""
+    from paper_2002_08733_amd import Solver
+    from paper_2002_08733_amd.mdg import MDG_E_UNSTABLE, MdgError
+    verts, tets = W.kuhn_cube_mesh(2, 0.0, 1.0)
+    ones = np.ones(len(tets))
+    dt = 60.0 * W.cfl_dt(verts, tets, ones, ones, 3, 0.3)
+    s = Solver(3, precision, "upwind", dt=dt)
+    s.set_mesh(verts, tets)
+    s.bind_torch_workspace()
+    rng = np.random.default_rng(31)
+    s.set_state(rng.standard_normal((len(tets), 3, 20)), rng.standard_normal((len(tets), 3, 20)))
+    W0 = s.energy()
+    s.step(200)
+    for call in (s.energy, s.energy_instances):
+        with pytest.raises(MdgError) as e:
+            call()
+        assert e.value.status == MDG_E_UNSTABLE
+    say(f"[unstable] {precision}: W0 = {W0:.3e}, 200 steps at 60x the CFL step -> MDG_E_UNSTABLE")
+    s.close()
