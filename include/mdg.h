@@ -204,10 +204,19 @@ mdg_status mdg_get_state(mdg_solver* s, double* E, double* H, double* P, double*
  * mdg_set_state and mdg_project set h_s to zero; mdg_set_sip_state then sets
  * it (both copies of a face should be equal). Not available (MDG_E_UNSUPPORTED)
  * with the upwind flux or instances (mdg_create, or the first
- * call that finalises the setup), in mdg_rhs and in the probe-energy and
+ * call that finalises the setup), in mdg_rhs (see mdg_rhs_sip) and in the probe-energy and
  * adjoint calls, and in these two calls without sip_alpha. Synchronous. */
 mdg_status mdg_set_sip_state(mdg_solver* s, const double* S);
 mdg_status mdg_get_sip_state(mdg_solver* s, double* S);
+
+/* mdg_rhs with the SIP unknown (mdg_options.sip_alpha > 0): time derivatives
+ * (dE, dH, dS, dP, dQ) of the state (E, H, S, P, Q) at time t, S and dS in
+ * the layout of mdg_set_sip_state [KS Sec. III, eqs. 1st_weak_equation,
+ * weak_penalty]. S == NULL means zero; dS, P, Q, dP, dQ may be NULL. The
+ * solver state is not modified (stage scratch is). MDG_E_UNSUPPORTED without
+ * sip_alpha (use mdg_rhs). Synchronous. */
+mdg_status mdg_rhs_sip(mdg_solver* s, const double* E, const double* H, const double* S, const double* P,
+                       const double* Q, double t, double* dE, double* dH, double* dS, double* dP, double* dQ);
 
 /* Physical points where a field must be sampled for mdg_project: q^3 points
  * per element (collapsed Gauss-Legendre rule of order q, 1 <= q <= 16).

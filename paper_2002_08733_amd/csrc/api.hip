@@ -277,6 +277,50 @@ void publish_if_needed(Solver& s, void* stream) {
   }
 }
 
+// one operator application from host arrays (the SIP unknown from S, zero
+// when null); the input's halo traces go to H1, so H0 keeps those of Y
+void host_rhs(Solver& s, const double* E, const double* H, const double* S, const double* P, const double* Q,
+              double t, double* dE, double* dH, double* dS, double* dP, double* dQ) {
+  need_bound(s);
+  if (!E || !H || !dE || !dH) throw Error(MDG_E_ARG, "E, H, dE, dH are required");
+  const DevLayout& L = s.L;
+  write_state(s, E, H, P, Q, L.Ua, L.aUa);
+  if (s.sip()) {
+    std::vector<double> buf;
+    pack_sip(s, S, buf);
+    upload(s, buf, L.sUa, nullptr);
+  }
+  StageParams sp{};
+  sp.stage = -1;
+  sp.dt = s.dt;
+  sp.cstage = 0.0;
+  set_clock(s, L.rhs_clock, t);
+  sp.clock = reinterpret_cast<const double*>(dev(s, L.rhs_clock));
+  sp.Y = dev(s, L.Y);
+  sp.Uin = dev(s, L.Ua);
+  sp.Uout = dev(s, L.Ub);
+  sp.ACC = dev(s, L.ACC);
+  sp.aY = dev(s, L.aY);
+  sp.aUin = dev(s, L.aUa);
+  sp.aUout = dev(s, L.aUb);
+  sp.aACC = dev(s, L.aACC);
+  sp.sY = dev(s, L.sY);
+  sp.sUin = dev(s, L.sUa);
+  sp.sUout = dev(s, L.sUb);
+  sp.sACC = dev(s, L.sACC);
+  launch_publish(s, dev(s, L.Ua), dev(s, L.H1), nullptr);
+  sp.hin = dev(s, L.H1);
+  sp.hout = nullptr;
+  sp.publish = false;
+  launch_stage(s, sp, nullptr);
+  read_state(s, dE, dH, dP, dQ, L.Ub, L.aUb);
+  if (s.sip() && dS) {
+    std::vector<double> buf;
+    download(s, L.sUb, size_t(8) * s.NF * s.Kpad, buf);
+    unpack_sip(s, buf, dS);
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -557,35 +601,19 @@ mdg_status mdg_step_graph(mdg_solver* h, int64_t nsteps, int32_t steps_per_graph
   });
 }
 
+mdg_status mdg_rhs_sip(mdg_solver* h, const double* E, const double* H, const double* S, const double* P,
+                       const double* Q, double t, double* dE, double* dH, double* dS, double* dP, double* dQ) {
+  return guarded(h, [&](Solver& s) {
+    if (!s.sip()) throw Error(MDG_E_UNSUPPORTED, "rhs_sip: the solver has no SIP unknown (use mdg_rhs)");
+    host_rhs(s, E, H, S, P, Q, t, dE, dH, dS, dP, dQ);
+  });
+}
+
 mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double* P, const double* Q, double t,
                    double* dE, double* dH, double* dP, double* dQ) {
   return guarded(h, [&](Solver& s) {
-    no_sip(s, "rhs");
-    need_bound(s);
-    if (!E || !H || !dE || !dH) throw Error(MDG_E_ARG, "E, H, dE, dH are required");
-    const DevLayout& L = s.L;
-    write_state(s, E, H, P, Q, L.Ua, L.aUa);
-    StageParams sp{};
-    sp.stage = -1;
-    sp.dt = s.dt;
-    sp.cstage = 0.0;
-    set_clock(s, L.rhs_clock, t);
-    sp.clock = reinterpret_cast<const double*>(dev(s, L.rhs_clock));
-    sp.Y = dev(s, L.Y);
-    sp.Uin = dev(s, L.Ua);
-    sp.Uout = dev(s, L.Ub);
-    sp.ACC = dev(s, L.ACC);
-    sp.aY = dev(s, L.aY);
-    sp.aUin = dev(s, L.aUa);
-    sp.aUout = dev(s, L.aUb);
-    sp.aACC = dev(s, L.aACC);
-    // the input's halo traces go to H1, so H0 keeps the traces of Y
-    launch_publish(s, dev(s, L.Ua), dev(s, L.H1), nullptr);
-    sp.hin = dev(s, L.H1);
-    sp.hout = nullptr;
-    sp.publish = false;
-    launch_stage(s, sp, nullptr);
-    read_state(s, dE, dH, dP, dQ, L.Ub, L.aUb);
+    no_sip(s, "rhs (use mdg_rhs_sip)");
+    host_rhs(s, E, H, nullptr, P, Q, t, dE, dH, nullptr, dP, dQ);
   });
 }
 

@@ -77,6 +77,7 @@ SIGNATURES = {
     "mdg_step": (_S, [_VP, ctypes.c_int64, _VP]),
     "mdg_step_graph": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, _VP]),
     "mdg_rhs": (_S, [_VP, _D, _D, _D, _D, ctypes.c_double, _D, _D, _D, _D]),
+    "mdg_rhs_sip": (_S, [_VP, _D, _D, _D, _D, _D, ctypes.c_double, _D, _D, _D, _D, _D]),
     "mdg_energy": (_S, [_VP, _D]),
     "mdg_energy_instances": (_S, [_VP, _D]),
     "mdg_adjoint_probe_energy": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _I64, _D, _D, _VP]),
@@ -278,6 +279,17 @@ class Solver:
         self._chk(self.lib.mdg_rhs(self.h, _dptr(E), _dptr(H), _dptr(P), _dptr(Q), float(t),
                                    _dptr(dE), _dptr(dH), _dptr(dP), _dptr(dQ)))
         return (dE, dH, dP, dQ) if aux else (dE, dH)
+
+    def rhs_sip(self, E, H, S=None, P=None, Q=None, t=0.0, aux=False):
+        """Operator with the SIP unknown: (dE, dH, dS) or, with aux, (dE, dH, dS, dP, dQ)."""
+        s, sh, ss = self._shape(), self._shape_h(), (self.nt, 4, 2, self.nfacemodes)
+        E, H, S, P, Q = _f64(E, s), _f64(H, sh), _f64(S, ss), _f64(P, s), _f64(Q, sh)
+        dE, dH, dS = np.empty(s), np.empty(sh), np.empty(ss)
+        dP = np.empty(s) if aux else None
+        dQ = np.empty(sh) if aux else None
+        self._chk(self.lib.mdg_rhs_sip(self.h, _dptr(E), _dptr(H), _dptr(S), _dptr(P), _dptr(Q), float(t),
+                                       _dptr(dE), _dptr(dH), _dptr(dS), _dptr(dP), _dptr(dQ)))
+        return (dE, dH, dS, dP, dQ) if aux else (dE, dH, dS)
 
     def energy(self):
         w = ctypes.c_double()

@@ -1,6 +1,8 @@
 """GPU parity of the SIP surface unknown [KS Sec. III, eqs. jmp_var_def,
 1st_weak_equation, weak_penalty] against the oracle (oracle/sip.py).
 
+* One operator application (mdg_rhs_sip; equal and mixed orders) with PML
+  elements, a dipole and uneven materials.
 * RK4 trajectories (FP64, FP32) from random e, h, h_s with PML elements, a
   dipole and uneven materials, on meshes of several tiles with a ragged tail;
   FP64 RK4 at orders 1, 2 and 4 as well.
@@ -96,6 +98,33 @@ def _random_state(S, rng, pml=None):
         P[~pml] = 0.0
         Q[~pml] = 0.0
     return E, H, Sf, P, Q
+
+
+@pytest.mark.parametrize("precision,tol,mixed", [("fp64", 1e-12, False), ("fp32", 2e-5, False),
+                                                 ("fp64", 1e-12, True)])
+def test_sip_operator_parity(precision, tol, mixed):
+    """One operator application (mdg_rhs_sip) against the oracle: PML
+    elements, a dipole at its time, uneven materials, several tiles."""
+    verts, tets, eps, mu = unit_jittered(4, 94)
+    rng = np.random.default_rng(95)
+    omega, pml = _pml_omega(verts, tets, rng)
+    s, S = _pair(verts, tets, 2 if mixed else 3, precision, eps, mu, 1.3, 1e-3, omega, _dip(), mixed=mixed)
+    E, H, Sf, P, Q = _random_state(S, rng, pml)
+    O = S.O
+    cov, cv = O.to_covariant, O.to_cartesian
+    t = 0.8
+    dE, dH, dS, dP, dQ = s.rhs_sip(cov(E), cov(H), S.to_sides(Sf), cov(P), cov(Q), t=t, aux=True)
+    s.close()
+    oE, oH, oS, oP, oQ = S.rhs(E, H, Sf, P, Q, t=t)
+    oP[~pml] = 0.0
+    oQ[~pml] = 0.0
+    err = _rel(S, (cv(dE), cv(dH), S.from_sides(dS), cv(dP), cv(dQ)), (oE, oH, oS, oP, oQ))
+    other = np.stack([dS[o // 4, o % 4] for (_, _, o) in S.sides if o >= 0])
+    first = np.stack([dS[k, f] for (k, f, o) in S.sides if o >= 0])
+    dcopy = np.abs(other - first).max() / np.abs(first).max()
+    say(f"[SIP rhs] {'e3/h2' if mixed else 'p=3'} {precision}: K={O.K} ({pml.sum()} PML): rel err {err:.3e}, "
+        f"copies {dcopy:.1e}")
+    assert err < tol and dcopy < (1e-13 if precision == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])

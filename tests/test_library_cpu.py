@@ -308,9 +308,11 @@ def test_sip_option_and_host_side_errors(lib):
     # state calls on a solver without it; instances; operator-only calls
     s = lib.Solver(2, dt=1e-3)
     s.set_mesh(verts, tets)
-    with pytest.raises(lib.MdgError) as e:
-        s.get_sip_state()
-    assert e.value.status == lib.MDG_E_UNSUPPORTED
+    z = np.zeros((len(tets), 3, 10))
+    for call in (s.get_sip_state, lambda: s.rhs_sip(z, z)):
+        with pytest.raises(lib.MdgError) as e:
+            call()
+        assert e.value.status == lib.MDG_E_UNSUPPORTED
     s.close()
     s = lib.Solver(2, dt=1e-3, sip_alpha=1.0)
     s.set_mesh(np.concatenate([verts, verts + 5.0]), np.concatenate([tets, tets + len(verts)]))
