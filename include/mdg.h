@@ -204,8 +204,10 @@ mdg_status mdg_get_state(mdg_solver* s, double* E, double* H, double* P, double*
  * mdg_set_state and mdg_project set h_s to zero; mdg_set_sip_state then sets
  * it (both copies of a face should be equal). Not available (MDG_E_UNSUPPORTED)
  * with the upwind flux or instances (mdg_create, or the first
- * call that finalises the setup), in mdg_rhs (see mdg_rhs_sip) and in the probe-energy and
- * adjoint calls, and in these two calls without sip_alpha. Synchronous. */
+ * call that finalises the setup) and in mdg_rhs (see mdg_rhs_sip); the
+ * state calls return it without sip_alpha. The probe-energy and adjoint
+ * calls carry h_s along (the adjoint negates its skew couplings like the
+ * others). Synchronous. */
 mdg_status mdg_set_sip_state(mdg_solver* s, const double* S);
 mdg_status mdg_get_sip_state(mdg_solver* s, double* S);
 

@@ -155,8 +155,8 @@ static void check(hipError_t e, const char* what) {
 }
 
 void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
-                  const void* w, void* stream, bool aux) {
-  const int64_t n = int64_t(6) * s.N * (aux ? s.Kppad : s.Kpad);
+                  const void* w, void* stream, int kind) {
+  const int64_t n = kind == 2 ? int64_t(8) * s.NF * s.Kpad : int64_t(6) * s.N * (kind == 1 ? s.Kppad : s.Kpad);
   if (n == 0) return;
   const dim3 grid((unsigned)((n + 255) / 256));
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -155,7 +155,8 @@ struct DevBufs {
 // stage scratch pair when null); the input's halo traces are published into
 // H1 first
 void apply_operator(Solver& s, const void* U, void* Kout, double cstage, bool sources, void* stream,
-                    const void* aU = nullptr, void* aK = nullptr, bool adj = false) {
+                    const void* aU = nullptr, void* aK = nullptr, bool adj = false, const void* sU = nullptr,
+                    void* sK = nullptr) {
   const DevLayout& L = s.L;
   launch_publish(s, U, dev(s, L.H1), stream);
   StageParams sp{};
@@ -173,6 +174,10 @@ void apply_operator(Solver& s, const void* U, void* Kout, double cstage, bool so
   sp.aUin = aU ? aU : dev(s, L.aUa);
   sp.aUout = aK ? aK : dev(s, L.aUb);
   sp.aACC = dev(s, L.aACC);
+  sp.sY = dev(s, L.sY);
+  sp.sUin = sU ? sU : dev(s, L.sUa);
+  sp.sUout = sK ? sK : dev(s, L.sUb);
+  sp.sACC = dev(s, L.sACC);
   sp.hin = dev(s, L.H1);
   sp.hout = nullptr;
   sp.publish = false;
@@ -620,7 +625,6 @@ mdg_status mdg_rhs(mdg_solver* h, const double* E, const double* H, const double
 mdg_status mdg_probe_energy(mdg_solver* h, int64_t nsteps, int32_t nprobe, const int64_t* probes, double* J,
                             void* stream) {
   return guarded(h, [&](Solver& s) {
-    no_sip(s, "probe energy");
     need_bound(s);
     if (nsteps < 0) throw Error(MDG_E_ARG, "probe energy: nsteps >= 0");
     if (nprobe < 1 || !probes || !J) throw Error(MDG_E_ARG, "probe energy: probes and J required");
@@ -649,7 +653,6 @@ mdg_status mdg_probe_energy(mdg_solver* h, int64_t nsteps, int32_t nprobe, const
 mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every, int32_t nprobe,
                                      const int64_t* probes, double* J, double* grad_eps, void* stream) {
   return guarded(h, [&](Solver& s) {
-    no_sip(s, "adjoint");
     need_bound(s);
     if (nsteps < 1 || every < 1) throw Error(MDG_E_ARG, "adjoint: nsteps >= 1 and checkpoint interval >= 1");
     if (nprobe < 1 || !probes || !J || !grad_eps) throw Error(MDG_E_ARG, "adjoint: probes, J and grad_eps required");
@@ -659,14 +662,16 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
       if (probes[i] < 0 || probes[i] >= s.nt) throw Error(MDG_E_ARG, "adjoint: probe element out of range");
       pin[i] = s.iperm[probes[i]];
     }
-    // a state vector: fields (blocked layout) and, with PML elements, the
-    // auxiliaries of the PML elements
-    const bool pml = s.Kp > 0, upw = s.opt.flux == MDG_UPWIND;
+    // a state vector: fields (blocked layout), with PML elements the
+    // auxiliaries of the PML elements, with SIP the surface unknown
+    const bool pml = s.Kp > 0, upw = s.opt.flux == MDG_UPWIND, sip = s.sip();
     const size_t SB = size_t(6) * s.N * s.Kpad * s.real_size();
     const size_t SA = pml ? size_t(6) * s.N * s.Kppad * s.real_size() : 0;
+    const size_t SS = sip ? size_t(8) * s.NF * s.Kpad * s.real_size() : 0;
     struct SV {
       void* u = nullptr;
       void* q = nullptr;
+      void* s = nullptr;
     };
     DevBufs B;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -674,20 +679,27 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
       SV v;
       v.u = B.get(SB);
       if (pml) v.q = B.get(SA);
+      if (sip) v.s = B.get(SS);
       return v;
     };
     auto copy = [&](SV d, SV x) {
       hip_check(hipMemcpyAsync(d.u, x.u, SB, hipMemcpyDeviceToDevice, st), "adjoint copy");
       if (pml) hip_check(hipMemcpyAsync(d.q, x.q, SA, hipMemcpyDeviceToDevice, st), "adjoint copy");
+      if (sip) hip_check(hipMemcpyAsync(d.s, x.s, SS, hipMemcpyDeviceToDevice, st), "adjoint copy");
     };
     // z = a x + b y + c w
     auto comb = [&](SV z, double a, SV x, double b = 0.0, const SV* y = nullptr, double c = 0.0,
                     const SV* w = nullptr) {
       launch_comb3(s, z.u, a, x.u, b, y ? y->u : nullptr, c, w ? w->u : nullptr, stream);
-      if (pml) launch_comb3(s, z.q, a, x.q, b, y ? y->q : nullptr, c, w ? w->q : nullptr, stream, true);
+      if (pml) launch_comb3(s, z.q, a, x.q, b, y ? y->q : nullptr, c, w ? w->q : nullptr, stream, 1);
+      if (sip) launch_comb3(s, z.s, a, x.s, b, y ? y->s : nullptr, c, w ? w->s : nullptr, stream, 2);
     };
+    // with SIP, the adjoint flag negates its couplings too (the block system
+    // is skew in the mass inner product that weights h_s with M_{mu/alpha}),
+    // and eps enters them only through the E mass inverse, so the gradient
+    // terms below need nothing more
     auto op = [&](SV in, SV out, double cstage, bool sources, bool adj) {
-      apply_operator(s, in.u, out.u, cstage, sources, stream, in.q, out.q, adj);
+      apply_operator(s, in.u, out.u, cstage, sources, stream, in.q, out.q, adj, in.s, out.s);
     };
     const int64_t k = std::min<int64_t>(every, nsteps);
     const int64_t nseg = (nsteps + k - 1) / k;
@@ -700,6 +712,7 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     SV state;
     state.u = dev(s, s.L.Y);
     state.q = pml ? dev(s, s.L.aY) : nullptr;
+    state.s = sip ? dev(s, s.L.sY) : nullptr;
     double* g = static_cast<double*>(B.get(size_t(s.K) * 8));
     double* Jd = static_cast<double*>(B.get(8));
     int64_t* pd = static_cast<int64_t*>(B.get(size_t(nprobe) * 8));
@@ -722,6 +735,7 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     // directly (skew part negated, PML couplings transposed)
     hip_check(hipMemsetAsync(nu.u, 0, SB, st), "nu");
     if (pml) hip_check(hipMemsetAsync(nu.q, 0, SA, st), "nu");
+    if (sip) hip_check(hipMemsetAsync(nu.s, 0, SS, st), "nu");
     launch_probe_add(s, nu.u, uend.u, pd, nprobe, dt, stream);
     // g -= (a_i, K_i)_M0 over the E rows, K_i without its damping part on
     // PML elements (only the rest scales with 1/eps); X_i is the stage input

@@ -190,9 +190,10 @@ void launch_publish(const Solver& s, const void* U, void* H, void* stream);
 void launch_energy(const Solver& s, const void* Y, void* stream);
 
 // ---- adjoint_kernel.hip (state vectors in the blocked layout, E and H)
-// z = a x + b y + c w over a state vector (aux = false) or a PML auxiliary vector
+// z = a x + b y + c w over a state vector (kind 0), a PML auxiliary vector
+// (kind 1) or the SIP unknown (kind 2)
 void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
-                  const void* w, void* stream, bool aux = false);
+                  const void* w, void* stream, int kind = 0);
 void launch_probe_energy(const Solver& s, const void* u, const int64_t* probes, int np, double dt, double* J,
                          void* stream);  // J += dt sum_probes (e, e)_M0
 void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* probes, int np, double dt,

@@ -2,7 +2,8 @@
 element's permittivity): against the oracle's matrix adjoint on a tiny mesh,
 against central finite differences of the library's own objective on 16
 elements (both also with PML elements, and the finite differences with mixed
-orders), independence of the checkpoint interval, and the autograd entry."""
+orders, the upwind flux and the SIP unknown), independence of the checkpoint
+interval, and the autograd entry."""
 import numpy as np
 import pytest
 
@@ -22,9 +23,9 @@ def _gpu():
 
 
 def _solver(verts, tets, p, eps, dt, precision="fp64", dip=None, omega=None, mixed=False, flux="central",
-            mu=None):
+            mu=None, sip_alpha=0.0):
     from paper_2002_08733_amd import Solver
-    s = Solver(p, precision, flux, dt=dt, mixed=mixed)
+    s = Solver(p, precision, flux, dt=dt, mixed=mixed, sip_alpha=sip_alpha)
     s.set_mesh(verts, tets)
     s.set_material(eps, mu)
     if omega is not None:
@@ -92,10 +93,11 @@ def _medium(n=4, p=2, seed=51):
     return w, E0, H0, dip
 
 
-@pytest.mark.parametrize("case", ["plain", "pml", "mixed_pml", "upwind_pml"])
+@pytest.mark.parametrize("case", ["plain", "pml", "mixed_pml", "upwind_pml", "sip_pml", "mixed_sip_pml"])
 def test_adjoint_matches_finite_differences_on_16_elements(case):
     w, E0, H0, dip = _medium()
-    omega, mixed = None, case == "mixed_pml"
+    omega, mixed = None, case.startswith("mixed")
+    sip = 1.0 if "sip" in case else 0.0  # the SIP unknown starts at zero
     flux = "upwind" if case.startswith("upwind") else "central"
     if case != "plain":
         # a damped slab (x > 0.4), one axis undamped on part of it
@@ -112,7 +114,7 @@ def test_adjoint_matches_finite_differences_on_16_elements(case):
     p = w.p - 1 if mixed else w.p
 
     def make(eps):
-        s = _solver(w.verts, w.tets, p, eps, dt, dip=dip, omega=omega, mixed=mixed, flux=flux)
+        s = _solver(w.verts, w.tets, p, eps, dt, dip=dip, omega=omega, mixed=mixed, flux=flux, sip_alpha=sip)
         s.set_state(E0, H0)
         return s
 
