@@ -203,8 +203,7 @@ mdg_status mdg_get_state(mdg_solver* s, double* E, double* H, double* P, double*
  * library updates both from the same data, so they agree to round-off.
  * mdg_set_state and mdg_project set h_s to zero; mdg_set_sip_state then sets
  * it (both copies of a face should be equal). Not available (MDG_E_UNSUPPORTED)
- * with the upwind flux or instances (mdg_create, or the first
- * call that finalises the setup) and in mdg_rhs (see mdg_rhs_sip); the
+ * with the upwind flux (mdg_create) and in mdg_rhs (see mdg_rhs_sip); the
  * state calls return it without sip_alpha. The probe-energy and adjoint
  * calls carry h_s along (the adjoint negates its skew couplings like the
  * others). Synchronous. */

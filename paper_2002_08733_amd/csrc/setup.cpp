@@ -262,8 +262,6 @@ static uint64_t spread21(uint64_t v) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 void finalize(Solver& s) {
-  if (s.sip() && s.inst_first.size() > 2)
-    throw Error(MDG_E_UNSUPPORTED, "the SIP unknown is not available with instances");
   if (s.nt == 0) throw Error(MDG_E_STATE, "no mesh");
   const int64_t nt = s.nt;
   std::vector<char> ispml(nt, 0);

@@ -7,6 +7,7 @@ launches, HIP-graph replay of the step sequence, and the tile autotuner.
 * Graph replay against eager stepping, replayed several times with eager
   work and synchronisations in between; every replay is checked.
 * The autotuner returns one of its candidates, with a timing for each.
+* Instances with the SIP unknown reproduce their individual runs.
 """
 import numpy as np
 import pytest
@@ -86,6 +87,44 @@ def test_batch_matches_individual_runs(precision):
         assert abs(t - ti) < 1e-15
         assert d_energy < (1e-12 if precision == "fp64" else 1e-5)
     assert worst < (1e-13 if precision == "fp64" else 1e-5)
+
+
+def test_batch_with_sip_matches_individual_runs():
+    """Instances with the SIP unknown (central flux): every instance of the
+    batch, h_s included, reproduces its run on its own."""
+    from paper_2002_08733_amd import Solver
+    w = W.batched(3, 3, seed=23, nmin=2, nmax=4)
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.2)
+
+    def make(verts, tets, eps, mu, dips, inst=None, first=None):
+        r = Solver(3, "fp64", "central", dt=dt, sip_alpha=1.0)
+        r.set_mesh(verts, tets)
+        if first is not None:
+            r.set_instances(first)
+        r.set_material(eps, mu)
+        r.set_dipoles(np.array([d[0] for d in dips]), np.array([d[1] for d in dips]),
+                      np.array([_wave(d) for d in dips]), instance=inst)
+        r.bind_torch_workspace()
+        return r
+
+    s = make(w.verts, w.tets, w.eps, w.mu, w.dipoles, [d[3] for d in w.dipoles], w.info["first"])
+    s.step(25)
+    E, H, _ = s.get_state()
+    S = s.get_sip_state()
+    s.close()
+    first = w.info["first"]
+    for i in range(3):
+        v, tt, eps, mu, d = _instance(w, i)
+        r = make(v, tt, eps, mu, [d])
+        r.step(25)
+        Ei, Hi, _ = r.get_state()
+        Si = r.get_sip_state()
+        r.close()
+        sl = slice(first[i], first[i + 1])
+        diff = max(np.abs(E[sl] - Ei).max(), np.abs(H[sl] - Hi).max(), np.abs(S[sl] - Si).max())
+        scale = max(np.abs(Ei).max(), np.abs(Si).max())
+        say(f"[batched SIP] instance {i}: max difference {diff / scale:.2e} (|h_s| max {np.abs(Si).max():.2e})")
+        assert np.abs(Si).max() > 0 and diff < 1e-13 * scale
 
 
 def test_batch_instance_against_oracle():

@@ -315,13 +315,6 @@ def test_sip_option_and_host_side_errors(lib):
         assert e.value.status == lib.MDG_E_UNSUPPORTED
     s.close()
     s = lib.Solver(2, dt=1e-3, sip_alpha=1.0)
-    s.set_mesh(np.concatenate([verts, verts + 5.0]), np.concatenate([tets, tets + len(verts)]))
-    s.set_instances([0, len(tets), 2 * len(tets)])
-    with pytest.raises(lib.MdgError) as e:
-        s.workspace_size()
-    assert e.value.status == lib.MDG_E_UNSUPPORTED
-    s.close()
-    s = lib.Solver(2, dt=1e-3, sip_alpha=1.0)
     s.set_mesh(verts, tets)
     K, N = len(tets), 10
     z = np.zeros((K, 3, N))
