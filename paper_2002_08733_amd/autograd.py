@@ -20,19 +20,21 @@ class ProbeEnergyProblem:
     (they do not depend on eps). dipoles = (pos[n][3], dir[n][3], wave[n][3])
     or None; omega[nt][3] per-axis PML damping or None (the PML starts at
     rest); mixed pairs e at order+1 with h at order (H0 then has the modes of
-    h's order)."""
+    h's order); flux is "central" or "upwind"; sip_alpha > 0 adds the SIP
+    surface unknown (central flux, starting at zero)."""
 
     def __init__(self, verts, tets, order, E0, H0, dt, nsteps, every, probes, mu=None, dipoles=None,
-                 precision="fp64", omega=None, mixed=False):
+                 precision="fp64", omega=None, mixed=False, flux="central", sip_alpha=0.0):
         self.verts, self.tets, self.order = verts, tets, order
         self.E0, self.H0, self.mu, self.dipoles = E0, H0, mu, dipoles
         self.omega, self.mixed = omega, mixed
+        self.flux, self.sip_alpha = flux, sip_alpha
         self.dt, self.nsteps, self.every = dt, nsteps, every
         self.probes = np.asarray(probes, dtype=np.int64)
         self.precision = precision
 
     def run(self, eps):
-        s = Solver(self.order, self.precision, "central", dt=self.dt, mixed=self.mixed)
+        s = Solver(self.order, self.precision, self.flux, dt=self.dt, mixed=self.mixed, sip_alpha=self.sip_alpha)
         try:
             s.set_mesh(self.verts, self.tets)
             s.set_material(eps, self.mu)

@@ -219,23 +219,26 @@ def test_adjoint_fullsize_pml_against_finite_differences():
     assert worst <= 1.0
 
 
-@pytest.mark.parametrize("pml", [False, True])
-def test_autograd_function(pml):
+@pytest.mark.parametrize("case", ["plain", "pml", "upwind_pml", "sip_pml"])
+def test_autograd_function(case):
     import torch
     from paper_2002_08733_amd.autograd import ProbeEnergyProblem
     w, E0, H0, dip = _medium()
     probes = np.array([5, 222])
     omega = None
+    pml = case != "plain"
     if pml:
         c = W.tet_centroids(w.verts, w.tets)
         omega = np.zeros((w.nt, 3))
         omega[c[:, 0] > 0.4] = 3.0
-    prob = ProbeEnergyProblem(w.verts, w.tets, w.p, E0, H0, 2e-3, 20, 5, probes, dipoles=dip, omega=omega)
+    prob = ProbeEnergyProblem(w.verts, w.tets, w.p, E0, H0, 2e-3, 20, 5, probes, dipoles=dip, omega=omega,
+                              flux="upwind" if case.startswith("upwind") else "central",
+                              sip_alpha=1.0 if case.startswith("sip") else 0.0)
     eps = torch.tensor(w.eps, dtype=torch.float64, requires_grad=True)
     J = prob(eps)
     (gt,) = torch.autograd.grad(3.0 * J, eps)
     Jd, gd = prob.run(w.eps)
-    say(f"[autograd] pml={pml}: J={J.item():.10e}")
+    say(f"[autograd] {case}: J={J.item():.10e}")
     assert J.item() == Jd
     assert np.array_equal(gt.numpy(), 3.0 * gd)
     # the same objective through the library directly, finite differences on one element
