@@ -518,9 +518,12 @@ __device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int
 
 // Occupancy: LDS (4 NF + 1 reals per element and face) admits 2 workgroups
 // per CU; with 8 lanes per element that is 16 waves (FP32, tile 64) or 8
-// waves (FP64, tile 32) per CU, so registers are capped at 128 / 256.
-template <typename R>
-constexpr int waves_per_eu() { return sizeof(R) == 4 ? 4 : 2; }
+// waves (FP64, tile 32) per CU, so registers are capped at 128 / 256. At
+// p = 4 FP32 (32-element tiles) LDS admits 3 workgroups (12 waves), so the
+// cap is 168 registers: the tighter one only forced spills without adding a
+// wave. (FP64 at p = 4 needs more than the 256 architectural registers.)
+template <typename R, int P>
+constexpr int waves_per_eu() { return sizeof(R) == 4 ? (P >= 4 ? 3 : 4) : 2; }
 
 #define MDG_SWITCH_Q(...)                     \
   switch (part) {                             \
@@ -540,7 +543,7 @@ constexpr int waves_per_eu() { return sizeof(R) == 4 ? 4 : 2; }
 // trace, part Q of the H lanes advances h_s of face Q from the jump of the e
 // traces (one copy per element face; both sides compute the same update).
 template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R>()))) void stage_kernel(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R, P>()))) void stage_kernel(
     DevArgs a) {
   static_assert(!(LF && UPW), "leap-frog halves need the central flux");
   static_assert(!(SIP && UPW), "the SIP unknown comes with the central flux");

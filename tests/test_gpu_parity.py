@@ -82,6 +82,16 @@ def test_rhs_parity_fp32(flux):
 
 
 @pytest.mark.parametrize("flux", ["central", "upwind"])
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_rhs_parity_fp32_other_orders(flux, p):
+    say(f"[rhs fp32] flux={flux} p={p} mesh=unit n=3 jittered")
+    verts, tets, eps, mu = unit_jittered(3, 30 + p)
+    err = _rhs_case(verts, tets, p, flux, eps, mu, precision="fp32")
+    say(f"  rel err {err:.3e}")
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("flux", ["central", "upwind"])
 def test_rhs_parity_pml_fp64(flux):
     say(f"[rhs pml fp64] flux={flux}")
     w = W.open_pml(n=12, p=2, layers=3, flux=flux)
