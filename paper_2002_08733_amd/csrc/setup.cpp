@@ -231,8 +231,9 @@ size_t stage_lds_bytes(const Solver& s) {
 }
 
 size_t lf_lds_bytes(const Solver& s) {
+  // compact in-tile slots and the halo block of the active role only
   const size_t rs = s.real_size();
-  const size_t slots = (2ull * s.NF + 1) * 4ull * s.tile + 2ull * halo_role_reals(s.NF, (int)rs) * s.hmax;
+  const size_t slots = (2ull * s.NF + 1) * 4ull * s.tile + 1ull * halo_role_reals(s.NF, (int)rs) * s.hmax;
   return std::max<size_t>(slots, 3ull * s.N * s.tile) * rs + 16;
 }
 
@@ -348,7 +349,9 @@ void finalize(Solver& s) {
     s.halo_tile.assign(2 * s.ntiles, 0);
     s.hmax = 0;
     s.nhalo = 0;
-    const int64_t SH = 2 * halo_role_reals(s.NF, (int)rs);  // reals per halo slot
+    // one region per reading role, each a sequence of per-tile blocks of
+    // SH reals per slot; a pub code is the slot's offset inside a region
+    const int64_t SH = halo_role_reals(s.NF, (int)rs);
     const int64_t align = 64 / (int64_t)rs;  // halo blocks start on 64-byte boundaries
     int64_t hoff = 0;
     struct HE { int32_t fn; int64_t kn; int64_t k; int f; };
@@ -385,7 +388,8 @@ void finalize(Solver& s) {
       s.nhalo += nh;
       s.hmax = std::max<int>(s.hmax, (int)nh);
     }
-    s.hbuf_reals = std::max<int64_t>(hoff, align);
+    s.hreg = std::max<int64_t>(hoff, align);
+    s.hbuf_reals = 2 * s.hreg;
     const size_t lds = stage_lds_bytes(s);
     // the default choice keeps two workgroups per CU; a forced tile only has
     // to fit the LDS of one workgroup

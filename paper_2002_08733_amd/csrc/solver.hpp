@@ -98,7 +98,8 @@ struct Solver {
   std::vector<int32_t> nbr_glob;   // [Kpad][4]: neighbour element * 4 + face (sorted order), -1 = PEC
   std::vector<int32_t> pub_code;   // blocked [Kpad/64][4][64]: halo-buffer offset (reals) of the face's trace, or -1
   std::vector<int32_t> halo_tile;  // [ntiles][2]: halo block offset (reals), halo slot count
-  int64_t hbuf_reals = 0;
+  int64_t hbuf_reals = 0;         // both regions of one halo buffer
+  int64_t hreg = 0;               // reals of one region (the traces one role reads)
   bool halo_valid = false;         // H0 holds the traces of Y
   std::vector<double> geo;     // blocked [Kpad/64][NGEO][64]
   std::vector<double> pmlrec;  // blocked [Kppad/64][NPML][64]
@@ -129,9 +130,10 @@ void finalize(Solver& s);  // ordering, tiles, halo, geometry records, layout
 double cfl_dt(const Solver& s);
 int tile_size_for(int P, bool fp32);
 // Halo trace slots: the two tangential traces of one field (2 NF reals) are
-// padded to a multiple of 16 bytes, so a slot holds 2 hrr reals and every
-// field block starts 16-byte aligned (the publishing lane writes it with
-// 16-byte stores). In-tile slots keep the odd stride 4 NF + 1.
+// padded to a multiple of 16 bytes (hrr reals), so every slot starts 16-byte
+// aligned (the publishing lane writes it with 16-byte stores). The halo
+// buffer holds one region per reading role; a tile's block in each region
+// has one slot per halo face. In-tile slots keep the odd stride 4 NF + 1.
 inline int halo_role_reals(int NF, int rs) { return (2 * NF * rs + 15) / 16 * 16 / rs; }
 // dynamic LDS of one stage-kernel workgroup: the face-trace exchange
 size_t stage_lds_bytes(const Solver& s);

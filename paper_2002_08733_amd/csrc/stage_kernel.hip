@@ -85,6 +85,7 @@ struct DevArgs {
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
   int32_t nh;                    // modes of h: N, or fewer with mixed orders (the rest stay zero)
   int32_t nfh;                   // face modes of the SIP unknown: NF, or fewer with mixed orders
+  int32_t hreg;                  // reals of one field's region of the halo buffers
   int32_t adj;                   // 1: adjoint operator (operator calls without sources)
   double bcoef, cdt, dt;
 };
@@ -309,14 +310,20 @@ __device__ __forceinline__ int lbase(int slot, int role) {
 }
 template <int NF>
 constexpr int loff(int k, int m) { return k * NF + m; }
-// halo slots (index 4 tile + h): field blocks of hrr reals, 16-byte aligned
+// halo slots (index 4 tile + h): hrr reals per slot and field, 16-byte
+// aligned. The halo buffers hold one region per reading role (region r: the
+// traces that the role-r lanes read), each a sequence of per-tile blocks of
+// nh slots; the LDS halo area is [region 0 block][region 1 block], or only
+// the block of the active role with four lanes per element
 template <int NF, typename R>
 constexpr int hrr() { return (2 * NF * (int)sizeof(R) + 15) / 16 * 16 / (int)sizeof(R); }
-// LDS offset of field `role`'s traces in slot `slot` (in-tile or halo)
+// LDS offset of field `role`'s traces in slot `slot` (in-tile or halo; nh:
+// the tile's halo slots)
 template <int NF, typename R, bool C = false>
-__device__ __forceinline__ int slot_base(int slot, int role, int tile) {
+__device__ __forceinline__ int slot_base(int slot, int role, int tile, int nh) {
   const int h = slot - 4 * tile;
-  return h < 0 ? lbase<NF, C>(slot, role) : 4 * tile * slot_stride<NF, C>() + (2 * h + role) * hrr<NF, R>();
+  return h < 0 ? lbase<NF, C>(slot, role)
+               : 4 * tile * slot_stride<NF, C>() + ((C ? 0 : role * nh) + h) * hrr<NF, R>();
 }
 // stores the NV consecutive reals v at byte offset vo (16-byte aligned) of r
 template <typename R, int NV>
@@ -356,7 +363,8 @@ constexpr bool face_needs(int c) {
 // trace of a field on face F from the LDS output staging [role][3N][tile],
 // stored to its halo-buffer slot: [input role of the field][k][m]
 template <int P, int F, typename R>
-__device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int tile, int li, Rsrc rH, int code) {
+__device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int tile, int li, Rsrc rH, int code,
+                                             int hreg) {
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
   R w[3][N];
 #pragma unroll
@@ -365,9 +373,9 @@ __device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int
     for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((sf * 3 + c) * N + l) * tile + li] : R(0);
   R t0[NF], t1[NF];
   face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
-  // a field's traces feed the neighbour lanes of the other role; the field
-  // block of the halo slot is 16-byte aligned, so it goes out in 16-byte stores
-  const uint32_t base = (uint32_t)(code + (1 - role) * hrr<NF, R>()) * (uint32_t)sizeof(R);
+  // a field's traces feed the neighbour lanes of the other role (the region
+  // of that role); the slot is 16-byte aligned, so it goes out in 16-byte stores
+  const uint32_t base = (uint32_t)(code + (1 - role) * hreg) * (uint32_t)sizeof(R);
   R v[2 * NF];
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
@@ -445,7 +453,7 @@ __device__ __forceinline__ void face_metric_rt(int F, R gxx, R gxy, R gxz, R gyy
 // is sum_m T_F[m][l] (t^1 A1[m] + t^2 A2[m]). No reference matrix enters, so
 // the face index is a runtime (wave-uniform) value.
 template <int P, bool UPW, typename R, bool C = false>
-__device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, int tile, int li, int code, R g,
+__device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, int tile, int li, int hn, int code, R g,
                                                R sgn, R wz, R Z, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz,
                                                R (&A1)[Ops<P>::NF], R (&A2)[Ops<P>::NF]) {
   constexpr int NF = Ops<P>::NF;
@@ -457,7 +465,7 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   const int sn = has ? code : so;
   const R fin = has ? R(1) : g;
   const R* own = lds + lbase<NF, C>(so, role);
-  const R* nbr = lds + slot_base<NF, R, C>(sn, role, tile);
+  const R* nbr = lds + slot_base<NF, R, C>(sn, role, tile, hn);
   const R om = role ? R(1) - wz : wz;  // own weight of the averaged input field
   const R rsign = (F == 0 || F == 2) ? R(1) : R(-1);  // sigma^_f = (+,-,+,-)
   const R c = -g * rsign * sgn;
@@ -474,7 +482,7 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   }
   if constexpr (UPW) {
     const R* own_o = lds + lbase<NF, C>(so, 1 - role);
-    const R* nbr_o = lds + slot_base<NF, R, C>(sn, 1 - role, tile);
+    const R* nbr_o = lds + slot_base<NF, R, C>(sn, 1 - role, tile, hn);
     R g11, g12, g22;
     face_metric_rt<R>(F, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
     const R idet = R(1) / sqrt(g11 * g22 - g12 * g12);
@@ -643,16 +651,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // neighbours in the previous stage, as an image of this tile's halo slots.
   // Copy the block into LDS slots 4 tile.. with asynchronous LDS loads
   // (16 bytes per lane, no registers involved); waited for before barrier 1.
+  const int hn = a.halo_tile[2 * t + 1];  // halo slots of this tile
   {
     typedef __attribute__((address_space(3))) unsigned char lds_byte;
-    const int hoff = a.halo_tile[2 * t], nh = a.halo_tile[2 * t + 1];
-    const uint32_t nbytes = ((uint32_t)nh * 2u * hrr<NF, R>() * RS + 15u) & ~15u;
+    const int hoff = a.halo_tile[2 * t];
+    // the tile's block in each region (hrr reals per slot: a multiple of 16 bytes)
+    const uint32_t rb = (uint32_t)hn * hrr<NF, R>() * RS, jump = (uint32_t)a.hreg * RS;
+    const uint32_t nbytes = C ? rb : 2u * rb;
     const Rsrc rH = make_rsrc(a.hin, a.hbuf_bytes);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6), nwv = blockDim.x >> 6;
     lds_byte* dst = (lds_byte*)smem_raw + 4u * (uint32_t)tile * SS * RS;
     for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
       const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
-      if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rH, dst + c * 1024u, 16, vo, (uint32_t)hoff * RS, 0, 0);
+      const uint32_t src = C ? vo + (uint32_t)role * jump : (vo < rb ? vo : vo - rb + jump);
+      if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rH, dst + c * 1024u, 16, src, (uint32_t)hoff * RS, 0, 0);
     }
   }
 
@@ -722,8 +734,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // 7. flux coefficients of face `part`
   {
     R A1[NF], A2[NF];
-    face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz, gzz,
-                                 A1, A2);
+    face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, hn, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz,
+                                 gzz, A1, A2);
     if constexpr (SIP) {
       // face `part` of this element: sig = sign((t^1 x t^2) . n_out), rows
       // (part, k, m) of the element's surface block
@@ -750,7 +762,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const R fs = sipc / sqrt(g11 * g22 - g12 * g12);
         const bool has = code >= 0;
         const R* own = lds + lbase<NF, C>(part * tile + li, 1);
-        const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile);
+        const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile, hn);
         const R hn = has ? R(1) : R(0);
         const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip_bytes, a.bcoef, a.cdt, a.dt, false);
         const R cs = R(es.c_out), bs = R(a.bcoef);
@@ -937,7 +949,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     __syncthreads();  // B5
     if (wr && pcode >= 0) {
       const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
-      MDG_SWITCH_Q((publish_face<P, Q, R>(stg, sf, role, tile, li, rHo, pcode)));
+      MDG_SWITCH_Q((publish_face<P, Q, R>(stg, sf, role, tile, li, rHo, pcode, a.hreg)));
     }
   }
 }
@@ -1008,11 +1020,12 @@ __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ p
 // of their own outputs): one lane per element and field, every face with a
 // cross-tile neighbour.
 template <int P, int F, typename R>
-__device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], int fld, Rsrc rH, int code) {
+__device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], int fld, Rsrc rH, int code,
+                                                    int hreg) {
   constexpr int NF = Ops<P>::NF;
   R t0[NF], t1[NF];
   face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
-  const uint32_t base = (uint32_t)(code + (1 - fld) * hrr<NF, R>()) * (uint32_t)sizeof(R);
+  const uint32_t base = (uint32_t)(code + (1 - fld) * hreg) * (uint32_t)sizeof(R);
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
     bst<R>(t0[m], rH, base, (uint32_t)(m * sizeof(R)));
@@ -1022,7 +1035,8 @@ __device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], 
 
 template <typename R, int P>
 __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t state_bytes, const int32_t* pub,
-                                                      uint32_t pub_bytes, void* H, uint32_t hbuf_bytes, int K) {
+                                                      uint32_t pub_bytes, void* H, uint32_t hbuf_bytes, int K,
+                                                      int hreg) {
   constexpr int N = Ops<P>::N, R3 = 3 * N;
   constexpr uint32_t RS = sizeof(R);
   const int gid = blockIdx.x * 256 + threadIdx.x;
@@ -1039,10 +1053,10 @@ __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t st
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int l = 0; l < N; ++l) w[c][l] = bld<R>(rU, vo, rowb<R>(c * N + l));
-  if (code[0] >= 0) publish_face_global<P, 0, R>(w, fld, rH, code[0]);
-  if (code[1] >= 0) publish_face_global<P, 1, R>(w, fld, rH, code[1]);
-  if (code[2] >= 0) publish_face_global<P, 2, R>(w, fld, rH, code[2]);
-  if (code[3] >= 0) publish_face_global<P, 3, R>(w, fld, rH, code[3]);
+  if (code[0] >= 0) publish_face_global<P, 0, R>(w, fld, rH, code[0], hreg);
+  if (code[1] >= 0) publish_face_global<P, 1, R>(w, fld, rH, code[1], hreg);
+  if (code[2] >= 0) publish_face_global<P, 2, R>(w, fld, rH, code[2], hreg);
+  if (code[3] >= 0) publish_face_global<P, 3, R>(w, fld, rH, code[3], hreg);
 }
 
 // ------------------------------------------------- adjoint, upwind flux
@@ -1254,6 +1268,7 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.pml_base = s.K0;
   a.nh = s.NH;
   a.nfh = s.NFH;
+  a.hreg = (int32_t)s.hreg;
   a.adj = sp.adj ? 1 : 0;
   a.stage = sp.stage;
   a.bcoef = sp.bcoef;
@@ -1320,13 +1335,13 @@ static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_
   const uint32_t pb = (uint32_t)(size_t(4) * s.Kpad * 4);
   const uint32_t hb = (uint32_t)(size_t(s.hbuf_reals) * rs);
   const int32_t* pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
-  const int K = (int)s.K;
+  const int K = (int)s.K, hreg = (int)s.hreg;
   const dim3 grid((unsigned)((2 * s.K + 255) / 256));
   switch (s.P) {
-    case 1: hipLaunchKernelGGL((publish_kernel<R, 1>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
-    case 2: hipLaunchKernelGGL((publish_kernel<R, 2>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
-    case 3: hipLaunchKernelGGL((publish_kernel<R, 3>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
-    case 4: hipLaunchKernelGGL((publish_kernel<R, 4>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K); break;
+    case 1: hipLaunchKernelGGL((publish_kernel<R, 1>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
+    case 2: hipLaunchKernelGGL((publish_kernel<R, 2>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
+    case 3: hipLaunchKernelGGL((publish_kernel<R, 3>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
+    case 4: hipLaunchKernelGGL((publish_kernel<R, 4>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
   hip_check(hipGetLastError(), "publish_kernel launch");
