@@ -41,11 +41,14 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2002_08733_amd", "csrc", "stage_kernel.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2002_08733_amd", "csrc", f) for f in ("stage_kernel.hpp", "stage_kernel.hip")]
 
 
 def kernel_source_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -68,44 +71,102 @@ def setup_solver(w, precision, dt, q=4, integrator="rk4", mixed=False, sip_alpha
     return s
 
 
-def time_steps(s, steps, warmup):
+REPS = 5            # timed repetitions; the median is reported
+MIN_WARM_S = 0.5    # warm-up continues until this much stepping has run
+
+
+def time_steps(s, steps, warmup, reps=REPS, min_warm_s=MIN_WARM_S):
+    """Median wall time (HIP events on the launch stream) of `steps` steps
+    over `reps` repetitions, after `warmup` steps and then more, until at
+    least `min_warm_s` of stepping has run (the GPU clocks settle). Returns
+    (median seconds, all repetitions, warm-up steps run)."""
     import torch
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
-    s.step(warmup, sp)
+    t0 = time.time()
+    warm = 0
+    if warmup > 0:
+        s.step(warmup, sp)
+        warm += warmup
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    s.step(steps, sp)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1000.0  # seconds
+    while time.time() - t0 < min_warm_s:
+        n = max(steps, 20)
+        s.step(n, sp)
+        torch.cuda.synchronize()
+        warm += n
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s.step(steps, sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1000.0)
+    return float(np.median(times)), times, warm
+
+
+def _oracle_worker(verts, tets, p, eps, mu, flux, idx, barrier, out):
+    """One host process: builds the oracle on the whole mesh (single BLAS
+    thread), waits for its siblings, then times one operator application on
+    its element subset; reports (start, end) wall-clock stamps."""
+    from threadpoolctl import threadpool_limits
+    from oracle import OracleDG
+    with threadpool_limits(1):
+        O = OracleDG(verts, tets, p, eps=eps, mu=mu, flux=flux)
+        rng = np.random.default_rng(0)
+        shp = (len(tets), 3, O.N)
+        cE, cH = rng.standard_normal(shp), rng.standard_normal(shp)
+        O.rhs(cE, cH, elems=idx[:64])  # warm caches
+        barrier.wait()
+        t0 = time.time()
+        O.rhs(cE, cH, elems=idx)
+        out.put((t0, time.time(), len(idx)))
+
+
+def _time_oracle(w, idx_list):
+    """Runs one oracle process per index set concurrently (spawned, so they
+    never touch the GPU); returns (wall seconds of the concurrent phase,
+    elements done)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(len(idx_list))
+    out = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(w.verts, w.tets, w.p, w.eps, w.mu, w.flux, idx, barrier, out))
+             for idx in idx_list]
+    for pr in procs:
+        pr.start()
+    res = [out.get() for _ in procs]
+    for pr in procs:
+        pr.join()
+        if pr.exitcode != 0:
+            raise RuntimeError(f"oracle worker failed ({pr.exitcode})")
+    return max(r[1] for r in res) - min(r[0] for r in res), sum(r[2] for r in res)
 
 
 def cpu_baseline(w, dt, sample):
-    """The FP64 oracle on a bounded sample of the same mesh (one operator
-    application = one RK stage's arithmetic on those elements)."""
-    from threadpoolctl import threadpool_info
-    from oracle import OracleDG
-    t0 = time.time()
-    O = OracleDG(w.verts, w.tets, w.p, eps=w.eps, mu=w.mu, flux=w.flux)
-    setup = time.time() - t0
+    """The FP64 oracle (numpy, as it stands) evaluating one operator
+    application (one RK stage's arithmetic) on host cores: all-core = one
+    single-threaded oracle process per core, each on its share of a bounded
+    element sample, started together; single-thread = one such process on a
+    smaller sample."""
+    ncores = min(16, len(os.sched_getaffinity(0)))
     rng = np.random.default_rng(0)
-    shp = (w.nt, 3, O.N)
-    cE, cH = rng.standard_normal(shp), rng.standard_normal(shp)
-    sample = w.nt if sample <= 0 else min(sample, w.nt)
-    idx = np.sort(rng.choice(w.nt, size=sample, replace=False))
-    O.rhs(cE, cH, elems=idx[:256])  # warm caches
-    t0 = time.time()
-    O.rhs(cE, cH, elems=idx)
-    el = time.time() - t0
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    gdof = sample * 6 * O.N / el / 1e9
-    return {"value": gdof, "unit": "GDOF/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"one operator application on {sample} of the {w.nt} elements of the same mesh "
-                       f"({el:.1f} s; oracle setup {setup:.1f} s excluded)"),
+    n_all = w.nt if sample <= 0 else min(sample, w.nt)
+    idx = np.sort(rng.choice(w.nt, size=n_all, replace=False))
+    t_all, done = _time_oracle(w, np.array_split(idx, ncores))
+    n_one = max(1, n_all // 8)
+    t_one, done1 = _time_oracle(w, [idx[:n_one]])
+    N = (w.p + 1) * (w.p + 2) * (w.p + 3) // 6
+    gdof_all = done * 6 * N / t_all / 1e9
+    gdof_one = done1 * 6 * N / t_one / 1e9
+    return {"value": gdof_all, "unit": "GDOF/s", "cores": ncores, "kind": "oracle",
+            "sample": (f"one operator application on {done} of the {w.nt} elements of the same mesh, split over "
+                       f"{ncores} single-threaded oracle processes started together ({t_all:.1f} s; oracle setup "
+                       f"excluded)"),
+            "single_thread": {"value": gdof_one, "unit": "GDOF/s", "cores": 1,
+                              "sample": f"one operator application on {done1} elements ({t_one:.1f} s)"},
             "host_cpus": os.cpu_count()}
 
 
@@ -310,7 +371,7 @@ def leapfrog_main(args):
             s = setup_solver(w, prec, dt, integrator=integ, mixed=mixed, sip_alpha=sip)
             info = s.query()
             W0 = s.energy()
-            sec = time_steps(s, args.steps, args.warmup)
+            sec, _, _ = time_steps(s, args.steps, args.warmup)
             W1 = s.energy()
             launches = (2 if integ == "leapfrog" else 4) * args.steps
             t_launch = sec / launches
@@ -368,7 +429,7 @@ def openpml_main(args):
         s.set_dipoles(*dip)
         s.bind_torch_workspace()
         info = s.query()
-        sec = time_steps(s, args.steps, args.warmup)
+        sec, _, _ = time_steps(s, args.steps, args.warmup)
         Wend = s.energy()
         stages = 4 * args.steps
         achieved = info["bytes_per_stage"] / (sec / stages) / 1e9
@@ -459,8 +520,8 @@ def main():
         s = setup_solver(w, prec, dt)
         info = s.query()
         W0 = s.energy()
-        log(f"[bench] {prec}: warmup {args.warmup}, timing {args.steps} steps")
-        sec = time_steps(s, args.steps, args.warmup)
+        log(f"[bench] {prec}: warmup >= {args.warmup} steps and {MIN_WARM_S} s, timing {REPS} x {args.steps} steps")
+        sec, reps, warm = time_steps(s, args.steps, args.warmup)
         W1 = s.energy()
         stages = 4 * args.steps
         N = info["nmodes"]
@@ -476,6 +537,7 @@ def main():
                          "kernel": "mdg::stage_kernel", "kernel_src_sha": khash},
             "flops_per_stage": info["flops_per_stage"],
             "energy_ratio": W1 / W0, "tile": info["tile_size"], "halo_per_elem": info["n_halo"] / w.nt,
+            "ms_per_step_reps": [1000.0 * t / args.steps for t in reps], "warmup_steps_run": warm,
         }
         log(f"[bench] {prec}: {gdof:.1f} GDOF/s, {1e6 * t_stage:.1f} us/stage, "
             f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM), W1/W0={W1 / W0:.6f}")
@@ -499,6 +561,9 @@ def main():
         "energy_ratio": main_r["energy_ratio"],
         "hbm_copy_GBs": copy_gbs,
         "frac_of_copy": main_r["roofline"]["achieved"] / copy_gbs,
+        "timing": f"median of {REPS} repetitions of {args.steps} steps (HIP events on the launch stream), after "
+                  f"{main_r['warmup_steps_run']} warm-up steps (at least {args.warmup} and {MIN_WARM_S} s)",
+        "ms_per_step_reps": main_r["ms_per_step_reps"],
     }
     other = [p for p in results if p != args.precision]
     for p in other:

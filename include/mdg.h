@@ -37,6 +37,11 @@
  *  - All host arrays are row-major, caller-owned and only read (or written)
  *    during the call. Device memory is owned by the caller (see
  *    mdg_bind_workspace) or, if the caller passes NULL there, by the library.
+ *  - "Synchronous" calls that write device memory (mdg_set_state,
+ *    mdg_set_sip_state, mdg_project, mdg_rhs, mdg_rhs_sip, mdg_bind_workspace
+ *    on a bound handle) first wait for all work already queued on the device,
+ *    on any stream, so they never overwrite data that earlier asynchronous
+ *    steps still read.
  *  - Every function returns an mdg_status; on error, mdg_last_error() gives a
  *    message valid until the next call on the same handle. No C++ exception
  *    crosses this boundary. A handle is not thread-safe; use one per stream.

@@ -10,6 +10,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -19,7 +20,7 @@ LIB = os.path.join(PKG, "libmdg.so")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 HIP_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 VALU ops are disabled for every HIP source of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-parameter",
@@ -39,11 +40,30 @@ def generate():
           os.path.join(CSRC, "refops_gen.txt")])
 
 
+SOURCES = ("setup.cpp", "stage_launch.hip", "adjoint_kernel.hip", "api.hip")
+# stage_kernel.hip is built once per (precision, order) instance
+INSTANCES = [(r, p) for r in ("float", "double") for p in (1, 2, 3, 4)]
+
+
 def build(verbose: bool = True) -> str:
+    """Compiles every source (and every stage-kernel instance) to an object in
+    parallel (each translation unit launches only its own kernels), then
+    links the shared library."""
     generate()
-    srcs = [os.path.join(CSRC, f) for f in ("setup.cpp", "stage_kernel.hip", "adjoint_kernel.hip", "api.hip")]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs = [os.path.join(BUILD, os.path.splitext(f)[0] + ".o") for f in SOURCES]
+    cmds = [[HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, f), "-o", o] for f, o in zip(SOURCES, objs)]
+    for r, p in INSTANCES:
+        o = os.path.join(BUILD, f"stage_kernel_{r}{p}.o")
+        objs.append(o)
+        cmds.append([HIPCC, *HIP_FLAGS, *inc, f"-DMDG_R={r}", f"-DMDG_P={p}", "-c",
+                     os.path.join(CSRC, "stage_kernel.hip"), "-o", o])
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for fut in [ex.submit(_run, c) for c in cmds]:
+            fut.result()
     tmp = LIB + ".tmp"
-    _run([HIPCC, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

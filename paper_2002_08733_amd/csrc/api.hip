@@ -58,6 +58,12 @@ void need_bound(const Solver& s) {
 
 char* dev(const Solver& s, size_t off) { return static_cast<char*>(s.ws) + off; }
 
+// The synchronous calls that write device memory (state, SIP unknown, clock,
+// operator input) upload on the NULL stream, which a non-blocking caller
+// stream (e.g. the one mdg_step_graph needs) does not order against: wait
+// for all work queued so far on the device before writing.
+void quiesce() { hip_check(hipDeviceSynchronize(), "synchronize before a host write"); }
+
 // host FP64 SoA rows -> device array of the solver's precision
 void upload(const Solver& s, const std::vector<double>& h, size_t off, hipStream_t st) {
   if (h.empty()) return;
@@ -89,6 +95,7 @@ void ensure_final(Solver& s) {
 
 void write_state(Solver& s, const double* E, const double* H, const double* P, const double* Q, size_t off,
                  size_t aoff) {
+  quiesce();
   std::vector<double> buf;
   pack_state(s, E, H, buf);
   upload(s, buf, off, nullptr);
@@ -119,6 +126,7 @@ void read_state(Solver& s, double* E, double* H, double* P, double* Q, size_t of
 // a new state starts with a zero SIP unknown
 void clear_sip(Solver& s) {
   if (!s.sip()) return;
+  quiesce();
   std::vector<double> z;
   pack_sip(s, nullptr, z);
   upload(s, z, s.L.sY, nullptr);
@@ -131,6 +139,7 @@ void no_sip(const Solver& s, const char* what) {
 // set a device clock (t0, n); synchronous
 void set_clock(Solver& s, size_t off, double t0, double n = 0.0) {
   const double c[2] = {t0, n};
+  quiesce();
   hip_check(hipMemcpy(dev(s, off), c, sizeof c, hipMemcpyHostToDevice), "clock");
 }
 
@@ -288,6 +297,7 @@ void host_rhs(Solver& s, const double* E, const double* H, const double* S, cons
               double t, double* dE, double* dH, double* dS, double* dP, double* dQ) {
   need_bound(s);
   if (!E || !H || !dE || !dH) throw Error(MDG_E_ARG, "E, H, dE, dH are required");
+  quiesce();
   const DevLayout& L = s.L;
   write_state(s, E, H, P, Q, L.Ua, L.aUa);
   if (s.sip()) {
@@ -419,6 +429,7 @@ mdg_status mdg_bind_workspace(mdg_solver* h, void* ptr, size_t bytes, void* stre
   return guarded(h, [&](Solver& s) {
     ensure_final(s);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (s.bound) quiesce();  // work queued on the old workspace
     {
       int dev_id = 0, lds_max = 0;
       hip_check(hipGetDevice(&dev_id), "hipGetDevice");
@@ -511,6 +522,7 @@ mdg_status mdg_set_sip_state(mdg_solver* h, const double* S) {
     if (!s.sip()) throw Error(MDG_E_UNSUPPORTED, "set_sip_state: the solver has no SIP unknown (sip_alpha = 0)");
     need_bound(s);
     if (!S) throw Error(MDG_E_ARG, "set_sip_state: NULL S");
+    quiesce();
     std::vector<double> buf;
     pack_sip(s, S, buf);
     upload(s, buf, s.L.sY, nullptr);

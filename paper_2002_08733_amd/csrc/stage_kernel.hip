@@ -1,1378 +1,18 @@
-// stage_kernel.hip -- fused RK4 stage of the matrix-free DG Maxwell operator
-// for gfx950 (CDNA4), plus the FP64 energy reduction.
-//
-// One launch applies the semi-discrete operator [KS Sec. III-IV] to the stage
-// input of every element and performs that stage's RK4 update in the epilogue.
-//
-// Work decomposition
-//   * Elements are ordered along a Morton curve (PML elements last) and cut
-//     into tiles of TILE consecutive elements; one workgroup per tile, two
-//     lanes per element. Lane role 0 produces the E update and reads H as its
-//     volume input; role 1 produces the H update and reads E. Both roles run
-//     the same instruction stream on different data:
-//        r_E = +s W(h) - Lift(h~) + Pen_Z([e]),   r_H = -s W(e) + Lift(e~) + Pen_Y([h])
-//     where W(v)[c] = sum_{a,d} eps_dac D_a v_d is the weak reference curl
-//     (D_a[l][m] = (d_a phi_l, phi_m), [KS eq. matrix_free_curl]; the H equation
-//     is used in its integrated-by-parts form, algebraically identical to the
-//     strong form of [KS eq. cwc] for polynomial fields), s = sign(det A).
-//   * Reference matrices are compile-time constants (generated header): every
-//     multiply by a structural zero disappears and every nonzero becomes an FMA
-//     with an inline constant. No MFMA: the operators are sparse (p = 3: 202 of
-//     1200 curl entries, 337 of 800 trace entries), and at the resulting
-//     ~2 flop/B the stage is bound by HBM, not by arithmetic.
-//   * Face coupling: every lane computes the face traces of its input field on
-//     its 4 faces, tau_k(v)[m] = sum_l T_f[m][l] (v . t^_k)[l], and stores them
-//     in LDS; faces whose neighbour lies in another tile get the neighbour's
-//     trace recomputed from global memory (halo list sorted by neighbour face so
-//     a wave mostly takes one branch). After one barrier every lane reads own
-//     and neighbour traces, forms the flux in face coefficients and lifts it
-//     with T_f^T. Both elements of a face parametrise it from the face's
-//     vertices in ascending global id, so traces combine without permutation;
-//     the tangential cross product of [KS eqs. uwc/cwc] reduces to
-//     int_F (a x n).b dS = sigma int (a.t2)(b.t1) - (a.t1)(b.t2) ds with
-//     a.t_k = a^.t^_k for covariant fields and sigma = s sigma^_f.
-//   * Upwind penalty: int_F [e]_t . v dS = sum_kl W_kl ([e].t_k)(v.t_l) with
-//     W = sqrt(det g^) g^^-1, g^_kl = t^_k^T G0^-1 t^_l (G0^-1 = A^T A/|det A|).
-//   * Mass inverse [KS Sec. III]: d_t u_l = (1/eps) G0^-1 r_l, 3x3 per mode.
-//   * PML [KS Sec. IV, eqs. p_variable, q_variable] in Cartesian, eps-scaled
-//     auxiliaries P~ = A^-T P / eps: d_t u = (1/eps) G0^-1 r - A^T(eta.c + P~),
-//     d_t P~ = -w.P~ + xi.c, c = A^-T u.
-//   * Blocks are mapped to tiles XCD-major: consecutive tiles (spatial
-//     neighbours) run on the same XCD, so halo re-reads hit its L2.
-#include <hip/hip_runtime.h>
+// stage_kernel.hip -- one (precision, order) instance of the stage kernel
+// and its companions (energy, halo publication, upwind adjoint gradient).
+// Built once per pair with -DMDG_R=<float|double> -DMDG_P=<order>, so the
+// instances compile in parallel; the device code is in stage_kernel.hpp.
+#include "stage_kernel.hpp"
 
-#include <cstdint>
-
-#include "refops_dev_gen.h"
-#include "refops_gen.h"
-#include "solver.hpp"
+#if !defined(MDG_R) || !defined(MDG_P)
+#error "build with -DMDG_R=float|double -DMDG_P=1..4"
+#endif
 
 namespace mdg {
-
-template <int P>
-using Ops = ref::Ops<P>;
-
-struct DevArgs {
-  const void* Y;      // RK base state u^n (E,H), blocked layout
-  const void* Uin;    // stage input
-  void* Uout;         // next stage input / operator output
-  void* ACC;          // RK accumulator
-  void* Yw;           // = Y (final in-place update)
-  const void* aY;     // same for the PML auxiliaries
-  const void* aUin;
-  void* aUout;
-  void* aACC;
-  void* aYw;
-  const void* sY;     // SIP surface unknown [K/64][face][k][NF][64]: RK base (leap-frog: updated in place)
-  const void* sUin;   // stage input
-  void* sUout;        // next stage input / operator output
-  void* sACC;         // RK accumulator
-  const void* geo;
-  const int32_t* nbr;
-  const int32_t* pub;        // publish codes: halo-buffer offset of each face's trace, or -1
-  const int32_t* halo_tile;  // per tile: halo block offset (reals), halo slot count
-  const void* hin;           // halo traces of the stage input
-  void* hout;                // halo traces of the stage output
-  const void* pml;
-  const void* src;            // dipole load vectors [ndip][3][N]
-  const int32_t* srcid;       // blocked [Kpad/64][64]: first dipole acting on the element, or -1
-  const int32_t* srcnext;     // [ndip]: next dipole on the same element, or -1
-  const double* srcamp;       // [ndip]: g(t) of every dipole at the stage's time
-  double* tick;               // non-null: advance this device clock (n += 1) once
-  uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes, sip_bytes;
-  int64_t pml_base;
-  int32_t tile_begin, ntiles, stage, has_src, publish;  // stage: 0..3 RK4, -1 operator, 4/5 leap-frog E/H half
-  int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
-  int32_t nh;                    // modes of h: N, or fewer with mixed orders (the rest stay zero)
-  int32_t nfh;                   // face modes of the SIP unknown: NF, or fewer with mixed orders
-  int32_t hreg;                  // reals of one field's region of the halo buffers
-  int32_t adj;                   // 1: adjoint operator (operator calls without sources)
-  double bcoef, cdt, dt;
-};
-
-// ---- raw buffer access (gfx9 buffer descriptor, bounds-checked by hardware)
-typedef __amdgpu_buffer_rsrc_t Rsrc;
-__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-// cache policy: CP_NT marks streaming data (read or written once per launch)
-// as non-temporal, so it does not push the stage input, which neighbouring
-// tiles gather for their halo faces, out of L2
-enum { CP_DEF = 0, CP_NT = 2 };
-template <typename R, int CP = CP_DEF>
-__device__ __forceinline__ R bld(Rsrc r, uint32_t vo, uint32_t so) {
-  if constexpr (sizeof(R) == 4) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, CP));
-  else return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, CP));
-}
-template <typename R, int CP = CP_DEF>
-__device__ __forceinline__ void bst(R v, Rsrc r, uint32_t vo, uint32_t so) {
-  if constexpr (sizeof(R) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, CP);
-  else {
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, CP);
-  }
-}
-__device__ __forceinline__ int32_t bldi(Rsrc r, uint32_t vo, uint32_t so) {
-  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
-}
-// byte offset of element e's block origin in a blocked array with `rows` rows
-// per element: ((e/64)*rows*64 + e%64) * size
-__device__ __forceinline__ uint32_t blk_base(uint32_t e, uint32_t rows, uint32_t size) {
-  return ((e >> 6) * rows * 64u + (e & 63u)) * size;
-}
-// byte offset of row r inside a block
-template <typename R>
-__device__ __forceinline__ constexpr uint32_t rowb(int r) { return (uint32_t)r * 64u * (uint32_t)sizeof(R); }
-
-// ---- face parametrisation constants (local face f opposite vertex f)
-// tangents t^1 = v_b - v_a, t^2 = v_c - v_a of the ascending face vertices:
-//   f=0: (-1,1,0),(-1,0,1)  f=1: (0,1,0),(0,0,1)  f=2: (1,0,0),(0,0,1)  f=3: (1,0,0),(0,1,0)
-// reference sign sigma^_f = sign((t^1 x t^2) . n^_out) = (+,-,+,-)
-template <int F, typename R>
-__device__ __forceinline__ R tan0(R x, R y, R z) {
-  if constexpr (F == 0) return y - x;
-  else if constexpr (F == 1) return y;
-  else return x;
-}
-template <int F, typename R>
-__device__ __forceinline__ R tan1(R x, R y, R z) {
-  if constexpr (F == 3) return y;
-  else if constexpr (F == 0) return z - x;
-  else return z;
-}
-template <int F>
-constexpr int ref_sign() { return (F == 0 || F == 2) ? 1 : -1; }
-
-template <int F, typename R>
-__device__ __forceinline__ void add_lift(R& ax, R& ay, R& az, R L1, R L2) {
-  if constexpr (F == 0) { ax -= L1 + L2; ay += L1; az += L2; }
-  else if constexpr (F == 1) { ay += L1; az += L2; }
-  else if constexpr (F == 2) { ax += L1; az += L2; }
-  else { ax += L1; ay += L2; }
-}
-
-// metric of face F: g^_kl = t^_k^T G t^_l for symmetric G
-template <int F, typename R>
-__device__ __forceinline__ void face_metric(R gxx, R gxy, R gxz, R gyy, R gyz, R gzz, R& g11, R& g12,
-                                            R& g22) {
-  if constexpr (F == 0) {
-    g11 = gxx - 2 * gxy + gyy;
-    g22 = gxx - 2 * gxz + gzz;
-    g12 = gxx - gxy - gxz + gyz;
-  } else if constexpr (F == 1) {
-    g11 = gyy; g22 = gzz; g12 = gyz;
-  } else if constexpr (F == 2) {
-    g11 = gxx; g22 = gzz; g12 = gxz;
-  } else {
-    g11 = gxx; g22 = gyy; g12 = gxy;
-  }
-}
-
-// ---- reference-operator constants
-// FP32: the constexpr values become instruction literals (v_fmac_f32 with an
-// inline constant). FP64: VOP3 has no literal form, so the values are read from
-// packed tables in constant memory (scalar loads, consumed in table order).
-template <typename R, int P>
-struct Cst;
-template <int P>
-struct Cst<float, P> {
-  static __device__ __forceinline__ float tr(int f, int m, int l) { return (float)Ops<P>::T[f][m][l]; }
-  static __device__ __forceinline__ float tc(int f, int m, int l) { return (float)Ops<P>::T[f][m][l]; }
-  static __device__ __forceinline__ float d(int a, int l, int m) { return (float)Ops<P>::D[a][l][m]; }
-};
-template <int P>
-__device__ __forceinline__ const double* tabTR();
-template <int P>
-__device__ __forceinline__ const double* tabTC();
-template <int P>
-__device__ __forceinline__ const double* tabD();
-#define MDG_TABS(p)                                                                  \
-  template <>                                                                        \
-  __device__ __forceinline__ const double* tabTR<p>() { return mdg_TpR_##p; }        \
-  template <>                                                                        \
-  __device__ __forceinline__ const double* tabTC<p>() { return mdg_TpC_##p; }        \
-  template <>                                                                        \
-  __device__ __forceinline__ const double* tabD<p>() { return mdg_DpV_##p; }
-MDG_TABS(1)
-MDG_TABS(2)
-MDG_TABS(3)
-MDG_TABS(4)
-#undef MDG_TABS
-template <int P>
-struct Cst<double, P> {
-  static __device__ __forceinline__ double tr(int f, int m, int l) { return tabTR<P>()[Ops<P>::TiR[f][m][l]]; }
-  static __device__ __forceinline__ double tc(int f, int m, int l) { return tabTC<P>()[Ops<P>::TiC[f][m][l]]; }
-  static __device__ __forceinline__ double d(int a, int l, int m) { return tabD<P>()[Ops<P>::DiV[a][l][m]]; }
-};
-
-// traces of a vector coefficient field on face F: t0/t1 = T_F (v . t^1/2)
-// v(c, l): coefficient l of component c (a register array or an LDS row)
-template <int P, int F, typename R, typename V>
-__device__ __forceinline__ void face_trace(const V& v, R (&t0)[Ops<P>::NF], R (&t1)[Ops<P>::NF]) {
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
-#pragma unroll
-  for (int m = 0; m < NF; ++m) {
-    R s0 = 0, s1 = 0;
-    bool first = true;
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
-      if (Ops<P>::T[F][m][l] != 0.0) {
-        const R c = Cst<R, P>::tr(F, m, l);
-        const R a = tan0<F, R>(v(0, l), v(1, l), v(2, l));
-        const R b = tan1<F, R>(v(0, l), v(1, l), v(2, l));
-        s0 = first ? c * a : fma(c, a, s0);
-        s1 = first ? c * b : fma(c, b, s1);
-        first = false;
-      }
-    }
-    t0[m] = s0;
-    t1[m] = s1;
-  }
-}
-
-// ---- work split: every (element, role) is served by four lanes, one per
-// "part" Q (wave-uniform). Part Q traces face Q and owns the modes
-// l = Q*NQ + i (i < NQ, l < N) of the output: volume rows, lift rows, mass
-// inverse, PML and epilogue.
-template <int P>
-constexpr int nq() { return (Ops<P>::N + 3) / 4; }
-
-// acc[j][i] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m]),  l = Q*NQ + i
-template <int P, int F, int Q, typename R>
-__device__ __forceinline__ void face_lift_q(const R (&A1)[Ops<P>::NF], const R (&A2)[Ops<P>::NF],
-                                            R (&acc)[3][nq<P>()]) {
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF, NQ = nq<P>();
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const int l = Q * NQ + i;
-    if (l >= N) continue;
-    R L1 = 0, L2 = 0;
-    bool first = true;
-#pragma unroll
-    for (int m = 0; m < NF; ++m) {
-      if (Ops<P>::T[F][m][l] != 0.0) {
-        const R c = Cst<R, P>::tc(F, m, l);
-        L1 = first ? c * A1[m] : fma(c, A1[m], L1);
-        L2 = first ? c * A2[m] : fma(c, A2[m], L2);
-        first = false;
-      }
-    }
-    if (!first) add_lift<F, R>(acc[0][i], acc[1][i], acc[2][i], L1, L2);
-  }
-}
-
-// acc = gs * W(v) on the modes of part Q:
-//   W[x] = D_z v_y - D_y v_z, W[y] = D_x v_z - D_z v_x, W[z] = D_y v_x - D_x v_y
-template <int P, int Q, typename R, typename V>
-__device__ __forceinline__ void volume_q(const V& v, R gs, R (&acc)[3][nq<P>()]) {
-  constexpr int N = Ops<P>::N, NQ = nq<P>();
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const int l = Q * NQ + i;
-    R ax = 0, ay = 0, az = 0;
-    if (l < N) {
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        if (Ops<P>::D[0][l][m] != 0.0) {
-          const R cx = Cst<R, P>::d(0, l, m);
-          ay = fma(cx, v(2, m), ay);
-          az = fma(-cx, v(1, m), az);
-        }
-        if (Ops<P>::D[1][l][m] != 0.0) {
-          const R cy = Cst<R, P>::d(1, l, m);
-          ax = fma(-cy, v(2, m), ax);
-          az = fma(cy, v(0, m), az);
-        }
-        if (Ops<P>::D[2][l][m] != 0.0) {
-          const R cz = Cst<R, P>::d(2, l, m);
-          ax = fma(cz, v(1, m), ax);
-          ay = fma(-cz, v(0, m), ay);
-        }
-      }
-    }
-    acc[0][i] = gs * ax;
-    acc[1][i] = gs * ay;
-    acc[2][i] = gs * az;
-  }
-}
-
-// LDS trace storage, slot-major: slot s (one face of one element) holds
-// [role][k][m] = 4 NF reals, padded to an odd stride so that consecutive lanes
-// (consecutive slots) hit distinct banks. A lane keeps one base address per
-// slot; role, k and m become immediate offsets.
-// C (compact): leap-frog halves with one field per workgroup keep only that
-// field's input traces in the in-tile slots (stride 2 NF + 1)
-template <int NF, bool C = false>
-constexpr int slot_stride() { return C ? 2 * NF + 1 : 4 * NF + 1; }
-template <int NF, bool C = false>
-__device__ __forceinline__ int lbase(int slot, int role) {
-  return slot * slot_stride<NF, C>() + (C ? 0 : role * 2 * NF);
-}
-template <int NF>
-constexpr int loff(int k, int m) { return k * NF + m; }
-// halo slots (index 4 tile + h): hrr reals per slot and field, 16-byte
-// aligned. The halo buffers hold one region per reading role (region r: the
-// traces that the role-r lanes read), each a sequence of per-tile blocks of
-// nh slots; the LDS halo area is [region 0 block][region 1 block], or only
-// the block of the active role with four lanes per element
-template <int NF, typename R>
-constexpr int hrr() { return (2 * NF * (int)sizeof(R) + 15) / 16 * 16 / (int)sizeof(R); }
-// LDS offset of field `role`'s traces in slot `slot` (in-tile or halo; nh:
-// the tile's halo slots)
-template <int NF, typename R, bool C = false>
-__device__ __forceinline__ int slot_base(int slot, int role, int tile, int nh) {
-  const int h = slot - 4 * tile;
-  return h < 0 ? lbase<NF, C>(slot, role)
-               : 4 * tile * slot_stride<NF, C>() + ((C ? 0 : role * nh) + h) * hrr<NF, R>();
-}
-// stores the NV consecutive reals v at byte offset vo (16-byte aligned) of r
-template <typename R, int NV>
-__device__ __forceinline__ void bst_run(const R (&v)[NV], Rsrc r, uint32_t vo) {
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-  constexpr int ND = NV * (int)sizeof(R) / 4;
-  uint32_t w[ND];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    if constexpr (sizeof(R) == 4) {
-      w[i] = __builtin_bit_cast(uint32_t, v[i]);
-    } else {
-      const u32x2 d = __builtin_bit_cast(u32x2, v[i]);
-      w[2 * i] = d.x;
-      w[2 * i + 1] = d.y;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i + 4 <= ND; i += 4) {
-    const u32x4 q = {w[i], w[i + 1], w[i + 2], w[i + 3]};
-    __builtin_amdgcn_raw_buffer_store_b128(q, r, vo, (uint32_t)(4 * i), 0);
-  }
-  if constexpr (ND % 4 >= 2) {
-    const u32x2 q = {w[ND / 4 * 4], w[ND / 4 * 4 + 1]};
-    __builtin_amdgcn_raw_buffer_store_b64(q, r, vo, (uint32_t)(4 * (ND / 4 * 4)), 0);
-  }
-  if constexpr (ND % 2 == 1) __builtin_amdgcn_raw_buffer_store_b32(w[ND - 1], r, vo, (uint32_t)(4 * (ND - 1)), 0);
-}
-
-// components of a field that enter the tangential trace on face F
-template <int F>
-constexpr bool face_needs(int c) {
-  return (F == 0) || (F == 1 && c != 0) || (F == 2 && c != 1) || (F == 3 && c != 2);
-}
-
-// trace of a field on face F from the LDS output staging [role][3N][tile],
-// stored to its halo-buffer slot: [input role of the field][k][m]
-template <int P, int F, typename R>
-__device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int tile, int li, Rsrc rH, int code,
-                                             int hreg) {
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
-  R w[3][N];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((sf * 3 + c) * N + l) * tile + li] : R(0);
-  R t0[NF], t1[NF];
-  face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
-  // a field's traces feed the neighbour lanes of the other role (the region
-  // of that role); the slot is 16-byte aligned, so it goes out in 16-byte stores
-  const uint32_t base = (uint32_t)(code + (1 - role) * hreg) * (uint32_t)sizeof(R);
-  R v[2 * NF];
-#pragma unroll
-  for (int m = 0; m < NF; ++m) {
-    v[m] = t0[m];
-    v[NF + m] = t1[m];
-  }
-  bst_run<R, 2 * NF>(v, rH, base);
-}
-
-// RK4 stage epilogue, one code path for every stage. The descriptors select
-// the stage: a load through a zero-length descriptor returns 0 without memory
-// traffic, a store through one is dropped.
-//   stage 0:    ACC = b k,         Uout = y + c dt k        (a = 0)
-//   stage 1,2:  ACC = a + b k,     Uout = y + c dt k
-//   stage 3:    Y   = y + dt (a + b k)                      (ACC store dropped)
-//   operator:   Uout = k                                    (y = a = 0, c dt = 1)
-//   leap-frog half (stage 4: E, 5: H): Y = y + dt k for the active field, with
-//               y taken from the staged input (the stage input is Y itself) or,
-//               with four lanes per element, loaded like the RK4 operands
-struct Epi {
-  Rsrc y_rd, a_rd, a_wr, out_wr;
-  bool final_stage;
-  double c_out;  // c_{i+1} dt, dt (final, leap-frog) or 1 (operator)
-};
-__device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* ACC, const void* Uout,
-                                        uint32_t bytes, double bcoef, double cdt, double dt, bool y_staged) {
-  Epi e;
-  const bool op = stage < 0, lf = stage >= 4;
-  e.final_stage = stage == 3;
-  e.y_rd = make_rsrc(Y, (op || (lf && y_staged)) ? 0u : bytes);
-  e.a_rd = make_rsrc(ACC, (stage >= 1 && stage <= 3) ? bytes : 0u);
-  e.a_wr = make_rsrc(ACC, (stage >= 0 && stage <= 2) ? bytes : 0u);
-  e.out_wr = make_rsrc((e.final_stage || lf) ? Y : Uout, bytes);
-  e.c_out = op ? 1.0 : ((e.final_stage || lf) ? dt : cdt);
-  (void)bcoef;
-  return e;
-}
-template <typename R>
-__device__ __forceinline__ void rk_store(const Epi& e, R k, uint32_t vo, uint32_t so, R b, R c_out, bool live) {
-  const R y = bld<R, CP_NT>(e.y_rd, vo, so);
-  const R a = bld<R, CP_NT>(e.a_rd, vo, so);
-  const R acc = fma(b, k, a);
-  if (live) {
-    bst<R, CP_NT>(acc, e.a_wr, vo, so);
-    bst<R, CP_NT>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
-  }
-}
-// same with y and a loaded earlier; returns the value written to the output
-// (the next stage input, or the new Y)
-template <typename R>
-__device__ __forceinline__ R rk_store_pre(const Epi& e, R k, R y, R a, uint32_t vo, uint32_t so, R b, R c_out,
-                                          bool live) {
-  const R acc = fma(b, k, a);
-  const R out = fma(c_out, e.final_stage ? acc : k, y);
-  if (live) {
-    bst<R, CP_NT>(acc, e.a_wr, vo, so);
-    bst<R, CP_NT>(out, e.out_wr, vo, so);
-  }
-  return out;
-}
-
-// metric of face F (runtime face index): g^_kl = t^_k^T G t^_l
-template <typename R>
-__device__ __forceinline__ void face_metric_rt(int F, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz, R& g11,
-                                               R& g12, R& g22) {
-  const R m11[4] = {gxx - 2 * gxy + gyy, gyy, gxx, gxx};
-  const R m22[4] = {gxx - 2 * gxz + gzz, gzz, gzz, gyy};
-  const R m12[4] = {gxx - gxy - gxz + gyz, gyz, gxz, gxy};
-  g11 = m11[F];
-  g22 = m22[F];
-  g12 = m12[F];
-}
-
-// flux coefficients of face F in the face basis: the lift of the face term
-// is sum_m T_F[m][l] (t^1 A1[m] + t^2 A2[m]). No reference matrix enters, so
-// the face index is a runtime (wave-uniform) value.
-template <int P, bool UPW, typename R, bool C = false>
-__device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, int tile, int li, int hn, int code, R g,
-                                               R sgn, R wz, R Z, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz,
-                                               R (&A1)[Ops<P>::NF], R (&A2)[Ops<P>::NF]) {
-  constexpr int NF = Ops<P>::NF;
-  const int so = F * tile + li;
-  // PEC faces (code < 0) read the own trace with the mirror factor:
-  // input field h+ = h- (role 0) / e+_t = -e-_t (role 1), i.e. factor g;
-  // output field: factor -g
-  const bool has = code >= 0;
-  const int sn = has ? code : so;
-  const R fin = has ? R(1) : g;
-  const R* own = lds + lbase<NF, C>(so, role);
-  const R* nbr = lds + slot_base<NF, R, C>(sn, role, tile, hn);
-  const R om = role ? R(1) - wz : wz;  // own weight of the averaged input field
-  const R rsign = (F == 0 || F == 2) ? R(1) : R(-1);  // sigma^_f = (+,-,+,-)
-  const R c = -g * rsign * sgn;
-#pragma unroll
-  for (int m = 0; m < NF; ++m) {
-    const R xm0 = own[loff<NF>(0, m)];
-    const R xm1 = own[loff<NF>(1, m)];
-    const R xp0 = fin * nbr[loff<NF>(0, m)];
-    const R xp1 = fin * nbr[loff<NF>(1, m)];
-    const R xw0 = fma(om, xm0 - xp0, xp0);
-    const R xw1 = fma(om, xm1 - xp1, xp1);
-    A1[m] = c * xw1;
-    A2[m] = -c * xw0;
-  }
-  if constexpr (UPW) {
-    const R* own_o = lds + lbase<NF, C>(so, 1 - role);
-    const R* nbr_o = lds + slot_base<NF, R, C>(sn, 1 - role, tile, hn);
-    R g11, g12, g22;
-    face_metric_rt<R>(F, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
-    const R idet = R(1) / sqrt(g11 * g22 - g12 * g12);
-    const R pen = role ? Z * (R(1) - wz) : wz / Z;  // 1/(Y-+Y+) or 1/(Z-+Z+)
-    const R W11 = pen * g22 * idet, W12 = -pen * g12 * idet, W22 = pen * g11 * idet;
-    const R fout = has ? R(1) : -g;  // jump of the lane's output field
-#pragma unroll
-    for (int m = 0; m < NF; ++m) {
-      const R ym0 = own_o[loff<NF>(0, m)];
-      const R ym1 = own_o[loff<NF>(1, m)];
-      const R j0 = fma(fout, nbr_o[loff<NF>(0, m)], -ym0);
-      const R j1 = fma(fout, nbr_o[loff<NF>(1, m)], -ym1);
-      A1[m] = fma(W11, j0, fma(W12, j1, A1[m]));
-      A2[m] = fma(W12, j0, fma(W22, j1, A2[m]));
-    }
-  }
-}
-
-// lift of all four faces onto the modes of part Q; the flux coefficients of
-// face F of this element were published in its slot F*tile + li
-template <int P, int Q, typename R, bool C = false>
-__device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int li, R (&acc)[3][nq<P>()]) {
-  constexpr int NF = Ops<P>::NF;
-#define MDG_LIFT_FACE(F)                                                   \
-  {                                                                        \
-    asm volatile("" ::: "memory");                                         \
-    const R* s_ = lds + lbase<NF, C>((F) * tile + li, role);               \
-    R A1[NF], A2[NF];                                                      \
-    _Pragma("unroll") for (int m = 0; m < NF; ++m) {                       \
-      A1[m] = s_[loff<NF>(0, m)];                                          \
-      A2[m] = s_[loff<NF>(1, m)];                                          \
-    }                                                                      \
-    face_lift_q<P, F, Q, R>(A1, A2, acc);                                  \
-  }
-  MDG_LIFT_FACE(0)
-  MDG_LIFT_FACE(1)
-  MDG_LIFT_FACE(2)
-  MDG_LIFT_FACE(3)
-#undef MDG_LIFT_FACE
-}
-
-// Occupancy: LDS (4 NF + 1 reals per element and face) admits 2 workgroups
-// per CU; with 8 lanes per element that is 16 waves (FP32, tile 64) or 8
-// waves (FP64, tile 32) per CU, so registers are capped at 128 / 256. At
-// p = 4 FP32 (32-element tiles) LDS admits 3 workgroups (12 waves), so the
-// cap is 168 registers: the tighter one only forced spills without adding a
-// wave. (FP64 at p = 4 needs more than the 256 architectural registers.)
-template <typename R, int P>
-constexpr int waves_per_eu() { return sizeof(R) == 4 ? (P >= 4 ? 3 : 4) : 2; }
-
-#define MDG_SWITCH_Q(...)                     \
-  switch (part) {                             \
-    case 0: { constexpr int Q = 0; __VA_ARGS__; } break; \
-    case 1: { constexpr int Q = 1; __VA_ARGS__; } break; \
-    case 2: { constexpr int Q = 2; __VA_ARGS__; } break; \
-    default: { constexpr int Q = 3; __VA_ARGS__; } break; \
-  }
-
-// LF: leap-frog half steps (stage 4/5), central flux only; the RK4 and
-// operator launches use LF = 0, for which every leap-frog branch folds away.
-// LF = 1 keeps eight lanes per element (both roles, one of them idle);
-// LF = 2 (64-element tiles) gives every lane to the active field: four lanes
-// per element and compact slots, so that four workgroups share a CU.
-// SIP: the symmetric interior penalty surface unknown h_s of every face
-// (central flux): part Q of the E lanes adds h_s of face Q to the averaged h
-// trace, part Q of the H lanes advances h_s of face Q from the jump of the e
-// traces (one copy per element face; both sides compute the same update).
-template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R, P>()))) void stage_kernel(
-    DevArgs a) {
-  static_assert(!(LF && UPW), "leap-frog halves need the central flux");
-  static_assert(!(SIP && UPW), "the SIP unknown comes with the central flux");
-  constexpr bool C = LF == 2;
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
-  constexpr int SS = slot_stride<NF, C>();
-  constexpr uint32_t RS = sizeof(R);
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* lds = reinterpret_cast<R*>(smem_raw);
-  // XCD-major block -> tile map (dispatch places block b on XCD b % 8)
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int tl = (b & 7) * (nb >> 3) + (b >> 3);
-  if (tl >= a.ntiles) return;  // whole block leaves together
-  const int t = a.tile_begin + tl;
-  // the step's clock advances once, from a launch that no other kernel of the
-  // step overlaps (the amplitudes of this stage were evaluated before it)
-  if (a.tick && b == 0 && threadIdx.x == 0) a.tick[1] = a.tick[1] + 1.0;
-  // 8 lanes per element (2 roles x 4 parts), or 4 (the active role's parts)
-  const int tile = blockDim.x >> (C ? 2 : 3);
-  const int tid = threadIdx.x;
-  // the lanes of one part are a multiple of 64, so the part is uniform in a wave
-  const int part = __builtin_amdgcn_readfirstlane(tid / (C ? tile : 2 * tile));
-  const int rem = tid - part * (C ? tile : 2 * tile);
-  const int role = C ? a.stage - 4 : (rem >= tile);
-  const int li = rem - (C ? 0 : role * tile);
-  const int start = a.elem_begin + tl * tile;
-  const int cnt = min(tile, a.elem_end - start);
-  // Lanes past the end of a partial tile compute on padding (arrays are padded
-  // by a full tile) so that every load is unconditional and every lane meets
-  // every barrier; their stores are suppressed.
-  const bool live = li < cnt;
-  const uint32_t el = (uint32_t)(start + li);
-  const Rsrc rU = make_rsrc(a.Uin, a.state_bytes);
-  const Rsrc rG = make_rsrc(a.geo, a.geo_bytes);
-  const uint32_t ebase = blk_base(el, 2 * R3, RS);       // element's state block
-  const uint32_t vin = ebase + (1 - role) * rowb<R>(R3);  // input field (other field)
-  const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
-  const uint32_t vgeo = blk_base(el, NGEO, RS);
-
-  // 1. input fields of the tile, each row loaded once: lane (role, part)
-  // loads rows [part RQ, part RQ + RQ) of its input field (the other field)
-  // and stages them in LDS as [field][3N][tile], in the area that holds the
-  // face traces later
-  constexpr int RQ = (R3 + 3) / 4;
-  R* stg = lds;
-  R vq[RQ];
-#pragma unroll
-  for (int i = 0; i < RQ; ++i) {
-    const int r = min(part * RQ + i, R3 - 1);
-    vq[i] = bld<R>(rU, vin, (uint32_t)r * 64u * RS);
-  }
-
-  // 2. RK operands of this part's output rows, issued now so that their
-  // latency overlaps the trace, volume and flux work (absent operands read as 0)
-  // (with four lanes per element no lane stages the output field, and the
-  // compact slots leave no room for it beside the halo slots)
-  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt, LF == 1);
-  R ypre[3][NQ], apre[3][NQ];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int l = part * NQ + q;
-      const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
-      ypre[c][q] = bld<R, CP_NT>(ef.y_rd, vout, so);
-      if constexpr (sizeof(R) == 8) apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
-    }
-
-#pragma unroll
-  for (int i = 0; i < RQ; ++i) {
-    const int r = part * RQ + i;
-    if (r < R3) stg[((C ? 0 : 1 - role) * R3 + r) * tile + li] = vq[i];
-  }
-  __syncthreads();  // B0: the tile's input fields are staged
-
-  // leap-frog half: the stage input is the state itself, so the own rows of
-  // the output field come from the staging (no second read of Y), and only
-  // the lanes of the active field store and publish. The other role's lanes
-  // run along and their results are dropped (skipping their work gains
-  // nothing: the launch is bound by the workgroup's chain of loads and
-  // barriers, and with 32-element tiles the two roles share waves). With the
-  // central flux the active field's derivative reads no trace of its own
-  // field, which is what lets the halves share one halo buffer.
-  const int lf = LF ? a.stage - 4 : -1;
-  const bool wr = live && (!LF || lf == role);
-  if (LF == 1) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
-        ypre[c][q] = stg[(role * R3 + c * N + (l < N ? l : N - 1)) * tile + li];
-      }
-  }
-
-  // 3. halo: the traces of out-of-tile neighbours were written by those
-  // neighbours in the previous stage, as an image of this tile's halo slots.
-  // Copy the block into LDS slots 4 tile.. with asynchronous LDS loads
-  // (16 bytes per lane, no registers involved); waited for before barrier 1.
-  const int hn = a.halo_tile[2 * t + 1];  // halo slots of this tile
-  {
-    typedef __attribute__((address_space(3))) unsigned char lds_byte;
-    const int hoff = a.halo_tile[2 * t];
-    // the tile's block in each region (hrr reals per slot: a multiple of 16 bytes)
-    const uint32_t rb = (uint32_t)hn * hrr<NF, R>() * RS, jump = (uint32_t)a.hreg * RS;
-    const uint32_t nbytes = C ? rb : 2u * rb;
-    const Rsrc rH = make_rsrc(a.hin, a.hbuf_bytes);
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6), nwv = blockDim.x >> 6;
-    lds_byte* dst = (lds_byte*)smem_raw + 4u * (uint32_t)tile * SS * RS;
-    for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
-      const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
-      const uint32_t src = C ? vo + (uint32_t)role * jump : (vo < rb ? vo : vo - rb + jump);
-      if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rH, dst + c * 1024u, 16, src, (uint32_t)hoff * RS, 0, 0);
-    }
-  }
-
-  // 4. trace of the input field on face `part` and the volume term of the
-  // part's modes, both reading the input field from the staging (not held in
-  // registers, which keeps the register budget at five waves per SIMD)
-  const R* vin_lds = stg + (C ? 0 : 1 - role) * R3 * tile + li;
-  auto vl = [&](int c, int l) { return vin_lds[(c * N + l) * tile]; };
-  const R g = role ? R(-1) : R(1);
-  // sign(det A); the adjoint operator negates the skew part (volume curl and
-  // the averaged face term), which both carry this factor
-  const R sgn = (a.adj ? R(-1) : R(1)) * bld<R>(rG, vgeo, rowb<R>(G_SIGN));
-  R acc[3][NQ];
-  {
-    R t0[NF], t1[NF];
-    MDG_SWITCH_Q((face_trace<P, Q, R>(vl, t0, t1)));
-    asm volatile("" ::: "memory");  // the volume term reads the staging again
-    MDG_SWITCH_Q((volume_q<P, Q, R>(vl, g * sgn, acc)));
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(acc[c][i]));
-    __syncthreads();  // B0': every lane has read the staging
-    R* d = lds + lbase<NF, C>(part * tile + li, role);
-#pragma unroll
-    for (int m = 0; m < NF; ++m) {
-      d[loff<NF>(0, m)] = t0[m];
-      d[loff<NF>(1, m)] = t1[m];
-    }
-  }
-  __builtin_amdgcn_sched_barrier(0);
-
-  // this wave's halo copies have landed in LDS
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  // 6. geometry and connectivity of face `part`, loaded while waiting at the
-  // barrier (the input field is dead here)
-  const R gxx = bld<R>(rG, vgeo, rowb<R>(G_XX)), gxy = bld<R>(rG, vgeo, rowb<R>(G_XY));
-  const R gxz = bld<R>(rG, vgeo, rowb<R>(G_XZ)), gyy = bld<R>(rG, vgeo, rowb<R>(G_YY));
-  const R gyz = bld<R>(rG, vgeo, rowb<R>(G_YZ)), gzz = bld<R>(rG, vgeo, rowb<R>(G_ZZ));
-  R Z = 1, wz = 0.5;  // central: plain average
-  if constexpr (UPW) {
-    Z = bld<R>(rG, vgeo, rowb<R>(G_Z));
-    wz = bld<R>(rG, vgeo, rowb<R>(G_WZ0 + part));
-  }
-  R sipc = 0;  // alpha_F / mu_F of face `part`
-  if constexpr (SIP) sipc = bld<R>(rG, vgeo, rowb<R>(G_SIP0 + part));
-  const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
-  const Rsrc rN = make_rsrc(a.nbr, a.nbr_bytes);
-  const int code = bldi(rN, blk_base(el, 4, 4), (uint32_t)part * 256u);
-  const Rsrc rPub = make_rsrc(a.pub, a.nbr_bytes);
-  const int pcode = bldi(rPub, blk_base(el, 4, 4), (uint32_t)part * 256u);
-
-  __syncthreads();  // B1: traces of the tile and its halo are in LDS
-  if constexpr (sizeof(R) == 4) {
-    // FP32: the accumulator rows are loaded here, still ~5 us before the
-    // epilogue, which keeps the register budget at five waves per SIMD
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
-        const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
-        apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
-      }
-  }
-
-  // 7. flux coefficients of face `part`
-  {
-    R A1[NF], A2[NF];
-    face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, hn, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz,
-                                 gzz, A1, A2);
-    if constexpr (SIP) {
-      // face `part` of this element: sig = sign((t^1 x t^2) . n_out), rows
-      // (part, k, m) of the element's surface block
-      const R sig = ((part == 0 || part == 2) ? R(1) : R(-1)) * sgn;
-      const uint32_t vs = blk_base(el, 8 * NF, RS);
-      const int srow = part * 2 * NF;
-      if (role == 0) {
-        // E: -(h_s x n, v)_F has the form of the averaged h term, so the
-        // edge-tangent components of h_s add to the averaged traces
-        const Rsrc rS = make_rsrc(a.sUin, a.sip_bytes);
-#pragma unroll
-        for (int m = 0; m < NF; ++m) {
-          const R s0 = bld<R>(rS, vs, rowb<R>(srow + m));
-          const R s1 = bld<R>(rS, vs, rowb<R>(srow + NF + m));
-          A1[m] = fma(-sig, s1, A1[m]);
-          A2[m] = fma(sig, s0, A2[m]);
-        }
-      } else {
-        // h_s: (mu/alpha) sqrt(det g) g^-1 d_t S = [-sig D_2; sig D_1] with
-        // D_k the face coefficients of (e- - e+) . t^k (e+ = 0 on PEC faces);
-        // the physical metric g is |det A| g^, whose Jacobian cancels
-        R g11, g12, g22;
-        face_metric_rt<R>(part, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
-        const R fs = sipc / sqrt(g11 * g22 - g12 * g12);
-        const bool has = code >= 0;
-        const R* own = lds + lbase<NF, C>(part * tile + li, 1);
-        const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile, hn);
-        const R hn = has ? R(1) : R(0);
-        const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip_bytes, a.bcoef, a.cdt, a.dt, false);
-        const R cs = R(es.c_out), bs = R(a.bcoef);
-#pragma unroll
-        for (int m = 0; m < NF; ++m) {
-          // with mixed orders h_s lives in the lower-order face space, whose
-          // modes are the first nfh of this basis: the others get no derivative
-          const R keep = m < a.nfh ? R(1) : R(0);
-          const R d0 = keep * fma(-hn, nbr[loff<NF>(0, m)], own[loff<NF>(0, m)]);
-          const R d1 = keep * fma(-hn, nbr[loff<NF>(1, m)], own[loff<NF>(1, m)]);
-          const R v1 = -sig * d1, v2 = sig * d0;
-          rk_store<R>(es, fs * fma(g11, v1, g12 * v2), vs, rowb<R>(srow + m), bs, cs, wr);
-          rk_store<R>(es, fs * fma(g12, v1, g22 * v2), vs, rowb<R>(srow + NF + m), bs, cs, wr);
-        }
-      }
-    }
-    __syncthreads();  // B2: every flux read of this tile is done
-    // publish the flux coefficients of face `part` in its own slot
-    R* d = lds + lbase<NF, C>(part * tile + li, role);
-#pragma unroll
-    for (int m = 0; m < NF; ++m) {
-      d[loff<NF>(0, m)] = A1[m];
-      d[loff<NF>(1, m)] = A2[m];
-    }
-  }
-  __syncthreads();  // B3
-
-  // 8. lift of the four faces onto this part's modes
-  MDG_SWITCH_Q((lift_all_q<P, Q, R, C>(lds, role, tile, li, acc)));
-
-  // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j, with the
-  // amplitudes g(t) of the stage's time evaluated just before the launch
-  if (a.has_src && role == 0) {
-    const Rsrc rS = make_rsrc(a.srcid, a.nbr_bytes / 4);
-    int d = bldi(rS, blk_base(el, 1, 4), 0);
-    if (d >= 0) {
-      const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
-      for (; d >= 0; d = a.srcnext[d]) {
-        const R amp = R(a.srcamp[d]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            const int l = part * NQ + q;
-            if (l < N) acc[c][q] = fma(-amp, src[(d * 3 + c) * N + l], acc[c][q]);
-          }
-      }
-    }
-  }
-
-  // 10. 3x3 block-diagonal mass inverse: d_t u_l = (1/eps) G0^-1 r_l
-  const R mf = role ? imu : ieps;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const R x = acc[0][q], y = acc[1][q], z = acc[2][q];
-    acc[0][q] = mf * fma(gxx, x, fma(gxy, y, gxz * z));
-    acc[1][q] = mf * fma(gxy, x, fma(gyy, y, gyz * z));
-    acc[2][q] = mf * fma(gxz, x, fma(gyz, y, gzz * z));
-  }
-
-  // mixed orders: h lives in the lower-order space, whose modes are the first
-  // nh of this basis; its other modes get no derivative (they stay zero), and
-  // the PML terms below then leave them at zero too
-  if (a.nh < N && role == 1) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (part * NQ + q >= a.nh) acc[0][q] = acc[1][q] = acc[2][q] = R(0);
-  }
-
-  const R bc = R(a.bcoef);
-  const int stage = a.stage;
-  // rows of this part: row(c, q) = c*N + part*NQ + q, skipped past N
-  // 11. PML auxiliaries
-  if constexpr (PML) {
-    const uint32_t pk = (uint32_t)((int64_t)el - a.pml_base);
-    const Rsrc rP = make_rsrc(a.pml, a.pml_bytes);
-    const uint32_t vp = blk_base(pk, NPML, RS);
-    const Rsrc raU = make_rsrc(a.aUin, a.aux_bytes);
-    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.aux_bytes, a.bcoef, a.cdt, a.dt, false);
-    const R ca = R(ea.c_out);
-    const uint32_t va = blk_base(pk, 2 * R3, RS) + role * rowb<R>(R3);
-    R AT[9], AiT[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      AT[i] = bld<R>(rP, vp, rowb<R>(PM_AT + i));
-      AiT[i] = bld<R>(rP, vp, rowb<R>(PM_AIT + i));
-    }
-    const R wx = bld<R>(rP, vp, rowb<R>(PM_OM + 0));
-    const R wy = bld<R>(rP, vp, rowb<R>(PM_OM + 1));
-    const R wzz = bld<R>(rP, vp, rowb<R>(PM_OM + 2));
-    const R ex = wy + wzz - wx, ey = wzz + wx - wy, ez = wx + wy - wzz;
-    const R xx = (wx - wy) * (wx - wzz), xy = (wy - wzz) * (wy - wx), xz = (wzz - wx) * (wzz - wy);
-    // couplings u <- -q and q <- xi c; the adjoint in the mass inner product
-    // (auxiliary weighted like its field, in Cartesian components) swaps
-    // them: u <- xi q and q <- -c (the eta and w terms are self-adjoint)
-    const R ux = a.adj ? -xx : R(1), uy = a.adj ? -xy : R(1), uz = a.adj ? -xz : R(1);
-    const R qx = a.adj ? R(-1) : xx, qy = a.adj ? R(-1) : xy, qz = a.adj ? R(-1) : xz;
-    const Rsrc raW = make_rsrc(a.aYw, LF ? a.aux_bytes : 0u);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int l = part * NQ + q;
-      if (l >= N) continue;
-      R u[3], qa[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const uint32_t so = (uint32_t)(c * N + l) * 64u * RS;
-        u[c] = bld<R>(rU, vout, so);  // own output field at the stage input
-        qa[c] = bld<R>(raU, va, so);
-      }
-      const R cx = AiT[0] * u[0] + AiT[1] * u[1] + AiT[2] * u[2];
-      const R cy = AiT[3] * u[0] + AiT[4] * u[1] + AiT[5] * u[2];
-      const R cz = AiT[6] * u[0] + AiT[7] * u[1] + AiT[8] * u[2];
-      if (LF) {
-        // leap-frog half with the damping terms by the trapezoid rule: per
-        // Cartesian component, with k the undamped derivative and h = dt/2,
-        //   x - c = dt k - h eta (x + c) - h (y + a),  y - a = h xi (x + c) - h w (y + a)
-        // for the new field x and auxiliary y, solved exactly (2x2)
-        const R h = R(0.5) * R(a.dt), dtr = R(a.dt);
-        const R kc[3] = {AiT[0] * acc[0][q] + AiT[1] * acc[1][q] + AiT[2] * acc[2][q],
-                         AiT[3] * acc[0][q] + AiT[4] * acc[1][q] + AiT[5] * acc[2][q],
-                         AiT[6] * acc[0][q] + AiT[7] * acc[1][q] + AiT[8] * acc[2][q]};
-        const R cc[3] = {cx, cy, cz}, et[3] = {ex, ey, ez}, xs[3] = {xx, xy, xz}, wv[3] = {wx, wy, wzz};
-        R xn[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const R b1 = fma(dtr, kc[c], fma(-h, fma(et[c], cc[c], qa[c]), cc[c]));
-          const R b2 = fma(h, fma(xs[c], cc[c], -wv[c] * qa[c]), qa[c]);
-          const R p1 = fma(h, et[c], R(1)), p2 = fma(h, wv[c], R(1));
-          const R idet = R(1) / fma(h * h, xs[c], p1 * p2);
-          xn[c] = (p2 * b1 - h * b2) * idet;
-          const R yn = fma(p1, b2, h * xs[c] * b1) * idet;
-          if (wr) bst<R, CP_NT>(yn, raW, va, (uint32_t)(c * N + l) * 64u * RS);
-        }
-        // the new covariant field, stored as is by the epilogue
-        acc[0][q] = AT[0] * xn[0] + AT[1] * xn[1] + AT[2] * xn[2];
-        acc[1][q] = AT[3] * xn[0] + AT[4] * xn[1] + AT[5] * xn[2];
-        acc[2][q] = AT[6] * xn[0] + AT[7] * xn[1] + AT[8] * xn[2];
-        continue;
-      }
-      const R y0 = fma(ex, cx, ux * qa[0]), y1 = fma(ey, cy, uy * qa[1]), y2 = fma(ez, cz, uz * qa[2]);
-      acc[0][q] -= AT[0] * y0 + AT[1] * y1 + AT[2] * y2;
-      acc[1][q] -= AT[3] * y0 + AT[4] * y1 + AT[5] * y2;
-      acc[2][q] -= AT[6] * y0 + AT[7] * y1 + AT[8] * y2;
-      const R k[3] = {fma(qx, cx, -wx * qa[0]), fma(qy, cy, -wy * qa[1]), fma(qz, cz, -wzz * qa[2])};
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rk_store<R>(ea, k[c], va, (uint32_t)(c * N + l) * 64u * RS, bc, ca, live);
-    }
-  }
-
-  // 12. RK4 epilogue of this part's rows of the output field; acc becomes
-  // the stored output
-  {
-    const R cf = R(ef.c_out);
-    const bool direct = PML && LF;  // the PML block computed the new field
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
-        if (l >= N) continue;
-        const uint32_t so = (uint32_t)(c * N + l) * 64u * RS;
-        if (direct) {
-          if (wr) bst<R, CP_NT>(acc[c][q], ef.out_wr, vout, so);
-        } else {
-          acc[c][q] = rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], vout, so, bc, cf, wr);
-        }
-      }
-  }
-
-  // 13. traces of the output on faces that a neighbouring tile reads in the
-  // next stage: stage the tile's output fields in LDS, then part Q traces
-  // face Q of its element into the neighbour tile's halo block
-  if (a.publish) {
-    __syncthreads();  // B4: the lifts are done with the trace area
-    R* stg = lds;     // [role][3N][tile] ([active field][3N][tile] with four lanes per element)
-    const int sf = C ? 0 : role;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
-        if (l < N) stg[((sf * 3 + c) * N + l) * tile + li] = acc[c][q];
-      }
-    __syncthreads();  // B5
-    if (wr && pcode >= 0) {
-      const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
-      MDG_SWITCH_Q((publish_face<P, Q, R>(stg, sf, role, tile, li, rHo, pcode, a.hreg)));
-    }
-  }
-}
-#undef MDG_SWITCH_Q
-
-// ---------------------------------------------------------------- energy
-// W = 1/2 sum_T sum_l eps u_l^T M u_l + mu f_l^T M f_l, M = (G0^-1)^-1 = |det A| A^-1 A^-T
-template <typename R, int N>
-__global__ __launch_bounds__(256) void energy_kernel(const R* __restrict__ Y, const R* __restrict__ geo, int64_t K,
-                                                     double* __restrict__ part, double* __restrict__ eelem) {
-  __shared__ double red[4];
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double w = 0.0;
-  if (k < K) {
-    const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
-    const double a = gk[G_XX * 64], b = gk[G_XY * 64], c = gk[G_XZ * 64];
-    const double d = gk[G_YY * 64], e = gk[G_YZ * 64], f = gk[G_ZZ * 64];
-    const double det = a * (d * f - e * e) - b * (b * f - e * c) + c * (b * e - d * c);
-    const double id = 1.0 / det;
-    const double m00 = (d * f - e * e) * id, m01 = (c * e - b * f) * id, m02 = (b * e - c * d) * id;
-    const double m11 = (a * f - c * c) * id, m12 = (b * c - a * e) * id, m22 = (a * d - b * b) * id;
-    const double eps = 1.0 / (double)gk[G_IEPS * 64], mu = 1.0 / (double)gk[G_IMU * 64];
-    const R* yk = Y + (k >> 6) * 6 * N * 64 + (k & 63);
-    double sf[2] = {0.0, 0.0};
-    for (int fld = 0; fld < 2; ++fld)
-      for (int l = 0; l < N; ++l) {
-        const double x = yk[(fld * 3 * N + 0 * N + l) * 64];
-        const double y = yk[(fld * 3 * N + 1 * N + l) * 64];
-        const double z = yk[(fld * 3 * N + 2 * N + l) * 64];
-        sf[fld] += m00 * x * x + m11 * y * y + m22 * z * z + 2.0 * (m01 * x * y + m02 * x * z + m12 * y * z);
-      }
-    w = 0.5 * (eps * sf[0] + mu * sf[1]);
-    eelem[k] = w;
-  }
-  for (int o = 32; o > 0; o >>= 1) w += __shfl_down(w, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// dipole amplitudes at the stage's time t = t0 + (n + cstage) dt of the
-// device clock: the Gaussian-modulated sinusoid
-// g(t) = sin(2 pi f0 (t - tc)) exp(-(t - tc)^2 / (2 s^2)), s = 1/(2 pi bw), in FP64
-__global__ __launch_bounds__(256) void src_amp_kernel(const double* __restrict__ clock, double cstage, double dt,
-                                                      const double* __restrict__ wave, int nd,
-                                                      double* __restrict__ amp) {
-  const int d = blockIdx.x * 256 + threadIdx.x;
-  if (d >= nd) return;
-  const double t = clock[0] + (clock[1] + cstage) * dt;
-  const double pi = 3.14159265358979323846;
-  const double tau = t - wave[3 * d + 2], sg = 1.0 / (2.0 * pi * wave[3 * d + 1]);
-  amp[d] = sin(2.0 * pi * wave[3 * d] * tau) * exp(-tau * tau / (2.0 * sg * sg));
-}
-
-__global__ __launch_bounds__(256) void energy_final(const double* __restrict__ part, int64_t n,
-                                                    double* __restrict__ out) {
-  __shared__ double red[4];
-  double w = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) w += part[i];
-  for (int o = 32; o > 0; o >>= 1) w += __shfl_down(w, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
-  __syncthreads();
-  if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// ---------------------------------------------------------------- publish
-// Halo traces of a state set from the host (the stage kernels publish those
-// of their own outputs): one lane per element and field, every face with a
-// cross-tile neighbour.
-template <int P, int F, typename R>
-__device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], int fld, Rsrc rH, int code,
-                                                    int hreg) {
-  constexpr int NF = Ops<P>::NF;
-  R t0[NF], t1[NF];
-  face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
-  const uint32_t base = (uint32_t)(code + (1 - fld) * hreg) * (uint32_t)sizeof(R);
-#pragma unroll
-  for (int m = 0; m < NF; ++m) {
-    bst<R>(t0[m], rH, base, (uint32_t)(m * sizeof(R)));
-    bst<R>(t1[m], rH, base, (uint32_t)((NF + m) * sizeof(R)));
-  }
-}
-
-template <typename R, int P>
-__global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t state_bytes, const int32_t* pub,
-                                                      uint32_t pub_bytes, void* H, uint32_t hbuf_bytes, int K,
-                                                      int hreg) {
-  constexpr int N = Ops<P>::N, R3 = 3 * N;
-  constexpr uint32_t RS = sizeof(R);
-  const int gid = blockIdx.x * 256 + threadIdx.x;
-  const int el = gid >> 1, fld = gid & 1;
-  if (el >= K) return;
-  const Rsrc rU = make_rsrc(U, state_bytes), rP = make_rsrc(pub, pub_bytes), rH = make_rsrc(H, hbuf_bytes);
-  const uint32_t vo = blk_base((uint32_t)el, 2 * R3, RS) + (uint32_t)fld * rowb<R>(R3);
-  int code[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) code[f] = bldi(rP, blk_base((uint32_t)el, 4, 4), (uint32_t)f * 256u);
-  if (code[0] < 0 && code[1] < 0 && code[2] < 0 && code[3] < 0) return;
-  R w[3][N];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int l = 0; l < N; ++l) w[c][l] = bld<R>(rU, vo, rowb<R>(c * N + l));
-  if (code[0] >= 0) publish_face_global<P, 0, R>(w, fld, rH, code[0], hreg);
-  if (code[1] >= 0) publish_face_global<P, 1, R>(w, fld, rH, code[1], hreg);
-  if (code[2] >= 0) publish_face_global<P, 2, R>(w, fld, rH, code[2], hreg);
-  if (code[3] >= 0) publish_face_global<P, 3, R>(w, fld, rH, code[3], hreg);
-}
-
-// ------------------------------------------------- adjoint, upwind flux
-// The upwind face terms depend on eps through the impedances Z = sqrt(mu/eps)
-// of the two elements of a face: the own weight of the averaged input field
-// (E rows: Z-/(Z- + Z+), H rows: Z+/(Z- + Z+)) and the penalty factor (E rows:
-// 1/(Z- + Z+), H rows: Z- Z+/(Z- + Z+)); PEC faces mirror the element (weights
-// 1/2, penalties 1/(2 Z) and Z/2). For the discrete adjoint, g_T gets
-// dZ_T/deps_T times the derivative by Z_T of (a, A x) over the faces of T: the
-// face terms of T's own equations and those of its neighbours' equations, for
-// both fields. A x is the stage derivative before the mass inverse, a the
-// adjoint stage vector, x the stage input; in the face basis (a, face term)
-// = sum_m tau_1(a)[m] A1[m] + tau_2(a)[m] A2[m] (the lift is the transposed
-// trace). Runs in FP64 on either state precision.
-
-// traces of field fld (0: E, 1: H) of element e on face F (runtime)
-template <typename R, int P>
-__device__ void traces_rt(const R* __restrict__ u, int64_t e, int fld, int F, double (&t0)[Ops<P>::NF],
-                          double (&t1)[Ops<P>::NF]) {
-  constexpr int N = Ops<P>::N;
-  const R* ue = u + (e >> 6) * 6 * N * 64 + (e & 63) + fld * 3 * N * 64;
-  auto v = [&](int c, int l) { return (double)ue[(c * N + l) * 64]; };
-  switch (F) {
-    case 0: face_trace<P, 0, double>(v, t0, t1); break;
-    case 1: face_trace<P, 1, double>(v, t0, t1); break;
-    case 2: face_trace<P, 2, double>(v, t0, t1); break;
-    default: face_trace<P, 3, double>(v, t0, t1); break;
-  }
-}
-
-// d/dZ of (a, A x) for the face terms of element e's equations on its face F
-// whose other side is (en, fn) (PEC: en = e, fn = F), given dom / dpen, the
-// derivatives of the own weight and of the penalty factor, for field role r
-template <typename R, int P>
-__device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, const R* __restrict__ geo,
-                           int64_t e, int F, int64_t en, int fn, bool has, int r, double dom, double dpen) {
-  constexpr int NF = Ops<P>::NF;
-  const double g = r ? -1.0 : 1.0;
-  const double fin = has ? 1.0 : g, fout = has ? 1.0 : -g;  // PEC mirror of the input / output field
-  const R* ge = geo + (e >> 6) * NGEO * 64 + (e & 63);
-  const double rsign = (F == 0 || F == 2) ? 1.0 : -1.0;
-  const double c = -g * rsign * (double)ge[G_SIGN * 64];
-  double g11, g12, g22;
-  face_metric_rt<double>(F, ge[G_XX * 64], ge[G_XY * 64], ge[G_XZ * 64], ge[G_YY * 64], ge[G_YZ * 64],
-                         ge[G_ZZ * 64], g11, g12, g22);
-  const double idet = 1.0 / sqrt(g11 * g22 - g12 * g12);
-  const double W11 = g22 * idet, W12 = -g12 * idet, W22 = g11 * idet;
-  double ta0[NF], ta1[NF], v0[NF], v1[NF];
-  traces_rt<R, P>(a, e, r, F, ta0, ta1);  // the adjoint of the output field
-  double s_avg = 0.0, s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
-  // averaged input field: d(A1, A2)/dom = c (xm1 - xp1, -(xm0 - xp0))
-  traces_rt<R, P>(x, e, 1 - r, F, v0, v1);
-  for (int m = 0; m < NF; ++m) s_avg += ta0[m] * v1[m] - ta1[m] * v0[m];
-  traces_rt<R, P>(x, en, 1 - r, fn, v0, v1);
-  for (int m = 0; m < NF; ++m) s_avg -= fin * (ta0[m] * v1[m] - ta1[m] * v0[m]);
-  // penalty on the jump of the output field: d(A1, A2)/dpen = W (j0, j1)
-  traces_rt<R, P>(x, en, r, fn, v0, v1);
-  for (int m = 0; m < NF; ++m) {
-    s00 += fout * ta0[m] * v0[m];
-    s01 += fout * ta0[m] * v1[m];
-    s10 += fout * ta1[m] * v0[m];
-    s11 += fout * ta1[m] * v1[m];
-  }
-  traces_rt<R, P>(x, e, r, F, v0, v1);
-  for (int m = 0; m < NF; ++m) {
-    s00 -= ta0[m] * v0[m];
-    s01 -= ta0[m] * v1[m];
-    s10 -= ta1[m] * v0[m];
-    s11 -= ta1[m] * v1[m];
-  }
-  return dom * c * s_avg + dpen * (W11 * s00 + W12 * s01 + W12 * s10 + W22 * s11);
-}
-
-template <typename R, int P>
-__global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout, const R* __restrict__ a,
-                                                      const R* __restrict__ x, const R* __restrict__ geo,
-                                                      const int32_t* __restrict__ nbrg, int64_t K) {
-  const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (k >= K) return;
-  const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
-  const double Z = gk[G_Z * 64], eps = 1.0 / (double)gk[G_IEPS * 64];
-  double sum = 0.0;
-  for (int F = 0; F < 4; ++F) {
-    const int code = nbrg[4 * k + F];
-    const bool has = code >= 0;
-    const int64_t kn = has ? code >> 2 : k;
-    const int fn = has ? (code & 3) : F;
-    const double Zn = has ? (double)geo[(kn >> 6) * NGEO * 64 + (kn & 63) + G_Z * 64] : Z;
-    const double S = Z + Zn, S2 = S * S;
-    for (int r = 0; r < 2; ++r) {
-      // own equations: weight and penalty by Z_T (= Z-)
-      double dom, dpen;
-      if (has) {
-        dom = r ? -Zn / S2 : Zn / S2;
-        dpen = r ? Zn * Zn / S2 : -1.0 / S2;
-      } else {
-        dom = 0.0;
-        dpen = r ? 0.5 : -0.5 / (Z * Z);
-      }
-      sum += upw_side<R, P>(a, x, geo, k, F, kn, fn, has, r, dom, dpen);
-      // the neighbour's equations, where T is the other side (Z_T = Z+)
-      if (has) {
-        const double dom2 = r ? Zn / S2 : -Zn / S2;
-        const double dpen2 = r ? Zn * Zn / S2 : -1.0 / S2;
-        sum += upw_side<R, P>(a, x, geo, kn, fn, k, F, true, r, dom2, dpen2);
-      }
-    }
-  }
-  gout[k] += -0.5 * Z / eps * sum;  // dZ/deps = -Z / (2 eps)
-}
-
-// ---------------------------------------------------------------- launch
-static void hip_check(hipError_t e, const char* what) {
-  if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false>
-static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
-  const int grid = (a.ntiles + 7) / 8 * 8;
-  if (lds > 64 * 1024) {
-    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-              "hipFuncSetAttribute(dynamic LDS)");
-  }
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP>), dim3(grid), dim3((LF == 2 ? 4 : 8) * tile), lds, st,
-                     a);
-  hip_check(hipGetLastError(), "stage_kernel launch");
-}
-
-// central-flux launches with or without the SIP unknown
-template <typename R, int P, bool PML, int LF>
-static void launch_c(const DevArgs& a, bool sip, int tile, size_t lds, hipStream_t st) {
-  if (sip) launch_one<R, P, false, PML, LF, true>(a, tile, lds, st);
-  else launch_one<R, P, false, PML, LF, false>(a, tile, lds, st);
-}
-
-template <typename R, int P>
-static void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
-  if (upw && sip) throw Error(MDG_E_UNSUPPORTED, "the SIP unknown needs the central flux");
-  if (a.stage >= 4) {  // leap-frog half (central flux, checked at creation)
-    if (upw) throw Error(MDG_E_UNSUPPORTED, "leap-frog needs the central flux");
-    if (tile % 64 == 0) {  // four lanes per element
-      if (pml) launch_c<R, P, true, 2>(a, sip, tile, lds, st);
-      else launch_c<R, P, false, 2>(a, sip, tile, lds, st);
-    } else {
-      if (pml) launch_c<R, P, true, 1>(a, sip, tile, lds, st);
-      else launch_c<R, P, false, 1>(a, sip, tile, lds, st);
-    }
-  } else if (upw) {
-    if (pml) launch_one<R, P, true, true, 0>(a, tile, lds, st);
-    else launch_one<R, P, true, false, 0>(a, tile, lds, st);
-  } else {
-    if (pml) launch_c<R, P, true, 0>(a, sip, tile, lds, st);
-    else launch_c<R, P, false, 0>(a, sip, tile, lds, st);
-  }
-}
-
-template <typename R>
-static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
-  switch (P) {
-    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, st); break;
-    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, st); break;
-    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, st); break;
-    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, st); break;
-    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
-  }
-}
-
-void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
-  char* base = static_cast<char*>(s.ws);
-  DevArgs a{};
-  a.Y = sp.Y;
-  a.Yw = sp.Y;
-  a.Uin = sp.Uin;
-  a.Uout = sp.Uout;
-  a.ACC = sp.ACC;
-  a.aY = sp.aY;
-  a.aYw = sp.aY;
-  a.aUin = sp.aUin;
-  a.aUout = sp.aUout;
-  a.aACC = sp.aACC;
-  a.sY = sp.sY;
-  a.sUin = sp.sUin;
-  a.sUout = sp.sUout;
-  a.sACC = sp.sACC;
-  a.geo = base + s.L.geo;
-  a.nbr = reinterpret_cast<const int32_t*>(base + s.L.nbr);
-  a.pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
-  a.halo_tile = reinterpret_cast<const int32_t*>(base + s.L.halo_tile);
-  a.hin = sp.hin;
-  a.hout = sp.hout;
-  a.publish = sp.publish && sp.hout != nullptr;
-  a.pml = base + s.L.pml;
-  a.src = base + s.L.src;
-  a.srcid = reinterpret_cast<const int32_t*>(base + s.L.srcid);
-  a.srcnext = reinterpret_cast<const int32_t*>(base + s.L.srcnext);
-  a.srcamp = reinterpret_cast<const double*>(base + s.L.srcamp);
-  a.has_src = (sp.sources && !s.dips.empty()) ? 1 : 0;
-  const size_t rs = s.real_size();
-  a.state_bytes = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
-  a.aux_bytes = (uint32_t)(size_t(6) * s.N * s.Kppad * rs);
-  a.geo_bytes = (uint32_t)(size_t(NGEO) * s.Kpad * rs);
-  a.nbr_bytes = (uint32_t)(size_t(4) * s.Kpad * 4);
-  a.pml_bytes = (uint32_t)(size_t(NPML) * s.Kppad * rs);
-  a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
-  a.sip_bytes = s.sip() ? (uint32_t)(size_t(8) * s.NF * s.Kpad * rs) : 0u;
-  if (s.sip() && !(sp.sY && sp.sUin && (sp.stage >= 3 || sp.sUout) && (sp.stage < 0 || sp.stage > 3 || sp.sACC)))
-    throw Error(MDG_E_STATE, "SIP launch without its surface buffers");
-  a.pml_base = s.K0;
-  a.nh = s.NH;
-  a.nfh = s.NFH;
-  a.hreg = (int32_t)s.hreg;
-  a.adj = sp.adj ? 1 : 0;
-  a.stage = sp.stage;
-  a.bcoef = sp.bcoef;
-  a.cdt = sp.cdt;
-  a.dt = sp.dt;
-  const bool fp32 = s.opt.precision == MDG_FP32;
-  const bool upw = s.opt.flux == MDG_UPWIND;
-  const size_t lds = (sp.stage >= 4 && s.tile % 64 == 0) ? lf_lds_bytes(s) : stage_lds_bytes(s);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (a.has_src) {
-    const int nd = (int)s.dips.size();
-    hipLaunchKernelGGL(src_amp_kernel, dim3((nd + 255) / 256), dim3(256), 0, st, sp.clock, sp.cstage, sp.dt,
-                       reinterpret_cast<const double*>(base + s.L.srcwave), nd,
-                       reinterpret_cast<double*>(base + s.L.srcamp));
-    hip_check(hipGetLastError(), "src_amp_kernel launch");
-  }
-  // non-PML tiles, then PML tiles; the last launch carries the clock tick
-  const int last = s.ntiles > s.ntiles0 ? 1 : 0;
-  for (int part = 0; part < 2; ++part) {
-    a.tick = part == last ? sp.tick : nullptr;
-    a.tile_begin = part == 0 ? 0 : (int32_t)s.ntiles0;
-    a.elem_begin = part == 0 ? 0 : (int32_t)s.K0;
-    a.elem_end = part == 0 ? (int32_t)s.K0 : (int32_t)s.K;
-    a.ntiles = part == 0 ? (int32_t)s.ntiles0 : (int32_t)(s.ntiles - s.ntiles0);
-    if (a.ntiles == 0) continue;
-    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, st);
-    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, st);
-  }
-}
-
-template <typename R>
-static void launch_energy_r(const Solver& s, const void* Y, hipStream_t st) {
-  char* base = static_cast<char*>(s.ws);
-  const int64_t nblk = (s.K + 255) / 256;
-  double* part = reinterpret_cast<double*>(base + s.L.epart);
-  double* out = reinterpret_cast<double*>(base + s.L.eout);
-  const R* geo = reinterpret_cast<const R*>(base + s.L.geo);
-  const R* y = static_cast<const R*>(Y);
-  double* ee = reinterpret_cast<double*>(base + s.L.eelem);
-  switch (s.P) {
-    case 1: hipLaunchKernelGGL((energy_kernel<R, 4>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
-    case 2: hipLaunchKernelGGL((energy_kernel<R, 10>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
-    case 3: hipLaunchKernelGGL((energy_kernel<R, 20>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
-    case 4: hipLaunchKernelGGL((energy_kernel<R, 35>), dim3(nblk), dim3(256), 0, st, y, geo, s.K, part, ee); break;
-    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
-  }
-  hip_check(hipGetLastError(), "energy_kernel launch");
-  hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, part, nblk, out);
-  hip_check(hipGetLastError(), "energy_final launch");
-}
-
-void launch_energy(const Solver& s, const void* Y, void* stream) {
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (s.opt.precision == MDG_FP32) launch_energy_r<float>(s, Y, st);
-  else launch_energy_r<double>(s, Y, st);
-}
-
-
-template <typename R>
-static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_t st) {
-  char* base = static_cast<char*>(s.ws);
-  const size_t rs = s.real_size();
-  const uint32_t sb = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
-  const uint32_t pb = (uint32_t)(size_t(4) * s.Kpad * 4);
-  const uint32_t hb = (uint32_t)(size_t(s.hbuf_reals) * rs);
-  const int32_t* pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
-  const int K = (int)s.K, hreg = (int)s.hreg;
-  const dim3 grid((unsigned)((2 * s.K + 255) / 256));
-  switch (s.P) {
-    case 1: hipLaunchKernelGGL((publish_kernel<R, 1>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
-    case 2: hipLaunchKernelGGL((publish_kernel<R, 2>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
-    case 3: hipLaunchKernelGGL((publish_kernel<R, 3>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
-    case 4: hipLaunchKernelGGL((publish_kernel<R, 4>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg); break;
-    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
-  }
-  hip_check(hipGetLastError(), "publish_kernel launch");
-}
-
-void launch_publish(const Solver& s, const void* U, void* H, void* stream) {
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (s.nhalo == 0) return;
-  if (s.opt.precision == MDG_FP32) launch_publish_r<float>(s, U, H, st);
-  else launch_publish_r<double>(s, U, H, st);
-}
-
-void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, void* stream) {
-  char* base = static_cast<char*>(s.ws);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const dim3 grid((unsigned)((s.K + 63) / 64));
-  const int32_t* nb = reinterpret_cast<const int32_t*>(base + s.L.nbrg);
-  const void* geo = base + s.L.geo;
-#define MDG_UPW(R, P)                                                                                     \
-  hipLaunchKernelGGL((grad_upw_kernel<R, P>), grid, dim3(64), 0, st, g, (const R*)a, (const R*)x,           \
-                     (const R*)geo, nb, s.K)
-  const bool fp32 = s.opt.precision == MDG_FP32;
-  switch (s.P) {
-    case 1: if (fp32) MDG_UPW(float, 1); else MDG_UPW(double, 1); break;
-    case 2: if (fp32) MDG_UPW(float, 2); else MDG_UPW(double, 2); break;
-    case 3: if (fp32) MDG_UPW(float, 3); else MDG_UPW(double, 3); break;
-    case 4: if (fp32) MDG_UPW(float, 4); else MDG_UPW(double, 4); break;
-    default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
-  }
-#undef MDG_UPW
-  hip_check(hipGetLastError(), "grad_upw_kernel launch");
-}
-
+template void launch_p<MDG_R, MDG_P>(const DevArgs&, bool, bool, bool, int, size_t, hipStream_t);
+template void launch_energy_rp<MDG_R, MDG_P>(const void*, const void*, int64_t, double*, double*, hipStream_t);
+template void launch_publish_rp<MDG_R, MDG_P>(const void*, uint32_t, const int32_t*, uint32_t, void*, uint32_t, int,
+                                               int, hipStream_t);
+template void launch_grad_upw_rp<MDG_R, MDG_P>(double*, const void*, const void*, const void*, const int32_t*,
+                                                int64_t, hipStream_t);
 }  // namespace mdg
