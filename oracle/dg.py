@@ -226,8 +226,11 @@ class OracleDG:
         """
         K, N, NH = self.K, self.N, self.NH
         idx_all = np.arange(K) if elems is None else np.asarray(elems, dtype=np.int64)
-        dE = np.zeros((len(idx_all), 3, N))
-        dH = np.zeros((len(idx_all), 3, NH))
+        # complex material values give the complex-step derivative by eps
+        # (the operator is analytic in eps and mu)
+        dtp = np.result_type(cE, cH, self.eps, self.mu)
+        dE = np.zeros((len(idx_all), 3, N), dtype=dtp)
+        dH = np.zeros((len(idx_all), 3, NH), dtype=dtp)
         Z = np.sqrt(self.mu / self.eps)
         for s in range(0, len(idx_all), chunk):
             idx = idx_all[s:s + chunk]
@@ -265,6 +268,8 @@ class OracleDG:
         # H strong: -(curl e, phi_m e_i), curl e = sum_n grad phi_n x c_n
         curl_e = np.einsum("ijl,kqjn,kln->kqi", LEVI_CIVITA, G, cE[idx], optimize=True)  # [n,Q,3]
         RH = -np.einsum("kqi,qm->kim", wJ[:, :, None] * curl_e, phh)
+        RE = RE.astype(np.result_type(RE, Z))
+        RH = RH.astype(np.result_type(RH, Z))
         # ---------------- face terms (physical face quadrature)
         s1 = self.fq[:, 0]
         s2 = self.fq[:, 1]

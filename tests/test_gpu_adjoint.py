@@ -51,36 +51,59 @@ def _tiny_omega(rng):
     return omega
 
 
-@pytest.mark.parametrize("precision,tol,pml,flux", [
-    ("fp64", 1e-10, False, "central"), ("fp32", 2e-4, False, "central"),
-    ("fp64", 1e-10, True, "central"), ("fp32", 2e-4, True, "central"),
-    # the oracle takes the upwind impedance derivative by differences of its
-    # operator (relative step 1e-5): agreement to ~1e-9 is what it can show
-    ("fp64", 1e-7, False, "upwind"), ("fp64", 1e-7, True, "upwind"), ("fp32", 2e-4, True, "upwind")])
-def test_adjoint_matches_oracle_adjoint(precision, tol, pml, flux):
+def _one_cube():
+    """One cube of 6 tets with every vertex moved (12 PEC faces, 6 interior)."""
+    verts, tets = W.kuhn_cube_mesh(1, 0.0, 1.0)
+    return verts + 0.06 * np.random.default_rng(48).standard_normal(verts.shape), tets
+
+
+# FP64 against the exact oracle adjoint (closed form for the central flux,
+# complex-step impedance derivative for the upwind flux) to 1e-12; FP32 state
+# with FP64 reductions to 2e-4
+@pytest.mark.parametrize("precision,tol,pml,flux,sip,mixed", [
+    ("fp64", 1e-12, False, "central", False, False), ("fp32", 2e-4, False, "central", False, False),
+    ("fp64", 1e-12, True, "central", False, False), ("fp32", 2e-4, True, "central", False, False),
+    ("fp64", 1e-12, False, "upwind", False, False), ("fp64", 1e-12, True, "upwind", False, False),
+    ("fp32", 2e-4, True, "upwind", False, False),
+    ("fp64", 1e-12, False, "central", True, False), ("fp64", 1e-12, True, "central", True, False),
+    ("fp32", 2e-4, True, "central", True, False), ("fp64", 1e-12, True, "central", True, True)])
+def test_adjoint_matches_oracle_adjoint(precision, tol, pml, flux, sip, mixed):
     from oracle import OracleDG
     from oracle.adjoint import adjoint_gradient
-    verts, tets = _tiny()
+    from oracle.sip import SipDG
     rng = np.random.default_rng(42)
-    eps = rng.uniform(1.0, 4.0, 48)
-    omega = _tiny_omega(rng) if pml else None
-    pos, dr = np.array([0.4, 0.45, 0.55]), np.array([0.3, 0.2, 1.0])
-    mu = np.linspace(1.0, 2.0, 48)
-    O = OracleDG(verts, tets, 1, eps=eps, mu=mu, flux=flux, omega=omega,
+    if sip:  # the SIP oracle assembles its operator column by column: one cube
+        verts, tets = _one_cube()
+        K, probes, pos = len(tets), np.array([1, 4]), np.array([0.45, 0.5, 0.55])
+        omega = None
+        if pml:
+            omega = np.zeros((K, 3))
+            sel = np.array([True, False, True, False, False, True])
+            omega[sel] = rng.uniform(1.0, 6.0, (sel.sum(), 3))
+    else:
+        verts, tets = _tiny()
+        K, probes, pos = 48, np.array([3, 17, 40]), np.array([0.4, 0.45, 0.55])
+        omega = _tiny_omega(rng) if pml else None
+    eps = rng.uniform(1.0, 4.0, K)
+    dr = np.array([0.3, 0.2, 1.0])
+    mu = np.linspace(1.0, 2.0, K)
+    pe = 2 if mixed else 1  # order of e; h at order 1
+    O = OracleDG(verts, tets, pe, eps=eps, mu=mu, flux=flux, omega=omega, ph=1,
                  dipoles=[(pos, dr, lambda t: W.dipole_waveform(t, 2.0, 1.0))])
-    cE0 = 0.3 * rng.standard_normal((48, 3, O.N))
-    cH0 = 0.3 * rng.standard_normal((48, 3, O.N))
-    dt, nsteps, probes = 0.01, 8, np.array([3, 17, 40])
-    Jo, go = adjoint_gradient(O, cE0, cH0, dt, nsteps, probes)
+    cE0 = 0.3 * rng.standard_normal((K, 3, O.N))
+    cH0 = 0.3 * rng.standard_normal((K, 3, O.NH))
+    dt, nsteps = (0.005, 6) if sip else (0.01, 8)
+    Jo, go = adjoint_gradient(O, cE0, cH0, dt, nsteps, probes, sip=SipDG(O, 1.0) if sip else None)
     dip = (pos[None], dr[None], np.array([[2.0, 1.0, 5.0 / (2 * np.pi)]]))
-    s = _solver(verts, tets, 1, eps, dt, precision, dip, omega, flux=flux, mu=mu)
+    s = _solver(verts, tets, 1, eps, dt, precision, dip, omega, flux=flux, mu=mu, mixed=mixed,
+                sip_alpha=1.0 if sip else 0.0)
     s.set_state(O.to_covariant(cE0), O.to_covariant(cH0))
     J, g = s.adjoint_probe_energy(nsteps, 3, probes)
     s.close()
     eJ = abs(J - Jo) / abs(Jo)
     eg = np.abs(g - go).max() / np.abs(go).max()
-    say(f"[adjoint vs oracle] {precision} {flux} pml={pml}: J {J:.12e} vs {Jo:.12e} ({eJ:.2e}), "
-        f"grad max rel {eg:.2e}")
+    say(f"[adjoint vs oracle] {precision} {flux} pml={pml} sip={sip} mixed={mixed}: J {J:.12e} vs {Jo:.12e} "
+        f"({eJ:.2e}), grad max rel {eg:.2e}")
     assert eJ < tol and eg < tol
 
 
