@@ -66,7 +66,7 @@ enum {
   MDG_E_HIP = -3,         /* HIP runtime error (message has the HIP error) */
   MDG_E_OOM = -4,         /* workspace too small / allocation failed */
   MDG_E_STATE = -5,       /* call order violated (e.g. step before set_mesh) */
-  MDG_E_UNSTABLE = -6,    /* energy became non-finite */
+  MDG_E_UNSTABLE = -6,    /* energy became non-finite, or grew (mdg_options.monitor) */
   MDG_E_UNSUPPORTED = -7  /* option not compiled in (e.g. order > 4) */
 };
 
@@ -89,6 +89,14 @@ typedef struct mdg_options {
                          with alpha_F = sip_alpha (p+1)(p+3)/3 |F| / min(|T|, |T'|), p the
                          order of e;
                          0: none. Central flux only (see mdg_set_sip_state) */
+  int32_t monitor;    /* > 0: mdg_step evaluates the FP64 energy of the state every `monitor`
+                         steps (and at its start) and returns MDG_E_UNSTABLE when it is not
+                         finite or, with RK4 on a mesh without sources, PML elements or the
+                         SIP unknown, when it grows by more than a relative 1e-10 (FP64) /
+                         1e-5 (FP32) from one check to the next. The semi-discrete energy is conserved by the central flux
+                         and decays with the upwind flux [KS Sec. III]; RK4 is strongly stable
+                         over two steps, not one, so `monitor` must be >= 2 (MDG_E_ARG). With a
+                         monitor mdg_step synchronises its stream before returning. 0: off */
 } mdg_options;
 
 typedef struct mdg_info {

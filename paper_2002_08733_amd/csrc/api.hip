@@ -5,6 +5,7 @@
 // allocated here on demand; all device work is enqueued on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -364,6 +365,7 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
     return MDG_E_UNSUPPORTED;
   }
   if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
+  if (o->monitor < 0 || o->monitor == 1) { g_create_error = "monitor must be 0 or >= 2"; return MDG_E_ARG; }
   mdg_solver* h = new (std::nothrow) mdg_solver();
   if (!h) return MDG_E_OOM;
   h->s.opt = *o;
@@ -572,8 +574,36 @@ mdg_status mdg_step(mdg_solver* h, int64_t nsteps, void* stream) {
     if (nsteps < 0) throw Error(MDG_E_ARG, "nsteps < 0");
     if (nsteps == 0) return;
     publish_if_needed(s, stream);
-    enqueue_steps(s, nsteps, stream);
+    const int64_t k = s.opt.monitor;
+    if (k <= 0) {
+      enqueue_steps(s, nsteps, stream);
+      s.nstep += nsteps;
+      return;
+    }
+    // energy monitor: the energy at the start, then after every k steps (and
+    // at the end); growth is a failure only where this energy must not grow:
+    // RK4 without sources, PML elements or the SIP unknown (whose face energy
+    // the field energy exchanges with)
+    const bool growth = s.dips.empty() && s.Kp == 0 && !s.sip() && s.opt.integrator == MDG_RK4;
+    const double tol = s.opt.precision == MDG_FP32 ? 1e-5 : 1e-10;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    launch_energy(s, dev(s, s.L.Y), stream);
+    launch_monitor(s, true, growth, tol, stream);
+    for (int64_t done = 0; done < nsteps;) {
+      const int64_t n = std::min<int64_t>(k, nsteps - done);
+      enqueue_steps(s, n, stream);
+      done += n;
+      launch_energy(s, dev(s, s.L.Y), stream);
+      launch_monitor(s, false, growth, tol, stream);
+    }
     s.nstep += nsteps;
+    double mon[4];
+    hip_check(hipStreamSynchronize(st), "sync");
+    hip_check(hipMemcpy(mon, dev(s, s.L.mon), sizeof mon, hipMemcpyDeviceToHost), "monitor");
+    if (mon[1] == 2.0) throw Error(MDG_E_UNSTABLE, "energy is not finite");
+    if (mon[1] == 1.0)
+      throw Error(MDG_E_UNSTABLE, "energy grew between two checks (from " + std::to_string(mon[2]) + " to " +
+                                      std::to_string(mon[3]) + " over the call)");
   });
 }
 

@@ -523,6 +523,7 @@ void finalize(Solver& s) {
   const size_t nblk = (s.K + 255) / 256;
   L.epart = off; off = align256(off + nblk * 8);
   L.eout = off; off = align256(off + 8);
+  L.mon = off; off = align256(off + 4 * 8);
   L.total = off;
   if (field >= (size_t(1) << 32) || sfield >= (size_t(1) << 32) || size_t(NGEO) * s.Kpad * rs >= (size_t(1) << 32))
     throw Error(MDG_E_UNSUPPORTED, "mesh too large: a state array exceeds 4 GiB");

@@ -65,6 +65,7 @@ struct DevLayout {
   size_t eelem;                         // per-element energies (FP64)
   size_t H0, H1;  // halo trace buffers: stage inputs' traces on cross-tile faces (ping-pong)
   size_t epart, eout;
+  size_t mon;  // energy monitor of mdg_step: last energy, flag, first/last energies (FP64)
   size_t total;
 };
 
@@ -190,6 +191,10 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream);
 // halo traces of state U (blocked layout) into the halo buffer H
 void launch_publish(const Solver& s, const void* U, void* H, void* stream);
 void launch_energy(const Solver& s, const void* Y, void* stream);
+// energy monitor: after launch_energy, compare the energy with the last one
+// recorded in mon (init: only record it); sets mon[1] to 1 on growth beyond
+// the relative tolerance tol (if growth checks apply), 2 on a non-finite value
+void launch_monitor(const Solver& s, bool init, bool growth, double tol, void* stream);
 
 // ---- adjoint_kernel.hip (state vectors in the blocked layout, E and H)
 // z = a x + b y + c w over a state vector (kind 0), a PML auxiliary vector

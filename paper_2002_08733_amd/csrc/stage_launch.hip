@@ -148,6 +148,30 @@ void launch_energy(const Solver& s, const void* Y, void* stream) {
   else launch_energy_r<double>(s, Y, st);
 }
 
+// mon = [last energy, flag (0 ok, 1 growth, 2 not finite), first energy, latest energy]
+__global__ void monitor_kernel(const double* __restrict__ W, double* __restrict__ mon, int init, int growth,
+                               double tol) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double w = W[0];
+  if (init) {
+    mon[1] = 0.0;
+    mon[2] = w;
+  } else if (growth && w > mon[0] * (1.0 + tol) && mon[1] == 0.0) {
+    mon[1] = 1.0;
+  }
+  if (!(w - w == 0.0)) mon[1] = 2.0;  // NaN or infinite
+  mon[0] = w;
+  mon[3] = w;
+}
+
+void launch_monitor(const Solver& s, bool init, bool growth, double tol, void* stream) {
+  char* base = static_cast<char*>(s.ws);
+  hipLaunchKernelGGL(monitor_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                     reinterpret_cast<const double*>(base + s.L.eout), reinterpret_cast<double*>(base + s.L.mon),
+                     init ? 1 : 0, growth ? 1 : 0, tol);
+  hip_check(hipGetLastError(), "monitor_kernel launch");
+}
+
 template <typename R>
 static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_t st) {
   char* base = static_cast<char*>(s.ws);

@@ -363,3 +363,12 @@ def test_empty_and_oversized_meshes(lib):
     s.set_mesh(v, t)
     assert s.workspace_size() > 4 * 6 * 20 * 4 * len(t)
     s.close()
+
+
+def test_monitor_option_is_checked(lib):
+    """mdg_options.monitor: 0 or >= 2 (RK4 is strongly stable over two steps)."""
+    for bad in (1, -3):
+        with pytest.raises(lib.MdgError) as e:
+            lib.Solver(2, monitor=bad)
+        assert e.value.status == lib.MDG_E_ARG
+    lib.Solver(2, monitor=2).close()
