@@ -282,6 +282,19 @@ mdg_status mdg_rhs(mdg_solver* s, const double* E, const double* H, const double
 mdg_status mdg_probe_energy(mdg_solver* s, int64_t nsteps, int32_t nprobe, const int64_t* probes, double* J,
                             void* stream);
 
+/* Same as mdg_probe_energy, allocating no device memory, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The accumulator and the probe list live in
+ * a library-wide device array of 256 + 8 MDG_NOALLOC_MAX_PROBES bytes, one copy
+ * per GPU, held until the process ends and set up on the first call on each
+ * device. nprobe > MDG_NOALLOC_MAX_PROBES gives MDG_E_ARG. The accumulator is
+ * cleared at the start of every call; calls that overlap on one GPU (handles
+ * driven from several host threads or streams at once) race on that array
+ * and must be serialised by the caller. Synchronous. */
+#define MDG_NOALLOC_MAX_PROBES 4096
+mdg_status mdg_probe_energy_noalloc(mdg_solver* s, int64_t nsteps, int32_t nprobe, const int64_t* probes,
+                                    double* J, void* stream);
+
 /* Probe energy and its gradient with respect to every element's permittivity
  * (the material of [KS Sec. I]), by the discrete adjoint of the RK4 steps.
  * From the current state, advances nsteps steps (the solver ends in the

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -335,6 +336,42 @@ void host_rhs(Solver& s, const double* E, const double* H, const double* S, cons
     download(s, L.sUb, size_t(8) * s.NF * s.Kpad, buf);
     unpack_sip(s, buf, dS);
   }
+}
+
+}  // namespace
+
+// ------------------------------------------------ allocation-free probe energy
+// For callers that cannot allocate device memory: the accumulator (bytes
+// 0..7) and the probe list (from byte 256, int64) of mdg_probe_energy_noalloc
+// live in this array, one copy per GPU, held until the process ends. In host
+// code `scratch` names a host-side stand-in: kernels and copies get the
+// device address from hipGetSymbolAddress, kept per device.
+static __device__ __align__(256) unsigned char scratch[256 + 8 * MDG_NOALLOC_MAX_PROBES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+unsigned char* scratch_ptr() {
+  int d = 0;
+  hip_check(hipGetDevice(&d), "hipGetDevice");
+  if (d < 0 || d >= MAX_DEVICES) throw Error(MDG_E_HIP, "device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (!g_scratch_ptr[d]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) throw Error(MDG_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[d] = p;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[d]);
+}
+
+// clears the accumulator with a kernel (no memset node if the caller captures)
+__global__ void zero_one(double* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0.0;
 }
 
 }  // namespace
@@ -681,6 +718,38 @@ mdg_status mdg_probe_energy(mdg_solver* h, int64_t nsteps, int32_t nprobe, const
     int64_t* pd = static_cast<int64_t*>(B.get(size_t(nprobe) * 8));
     hip_check(hipMemcpyAsync(pd, pin.data(), pin.size() * 8, hipMemcpyHostToDevice, st), "probes");
     hip_check(hipMemsetAsync(Jd, 0, 8, st), "J");
+    publish_if_needed(s, stream);
+    for (int64_t n = 0; n < nsteps; ++n) {
+      enqueue_steps(s, 1, stream);
+      launch_probe_energy(s, dev(s, s.L.Y), pd, nprobe, s.dt, Jd, stream);
+    }
+    hip_check(hipStreamSynchronize(st), "sync");
+    s.nstep += nsteps;
+    hip_check(hipMemcpy(J, Jd, 8, hipMemcpyDeviceToHost), "J");
+  });
+}
+
+mdg_status mdg_probe_energy_noalloc(mdg_solver* h, int64_t nsteps, int32_t nprobe, const int64_t* probes, double* J,
+                                    void* stream) {
+  return guarded(h, [&](Solver& s) {
+    need_bound(s);
+    if (nsteps < 0) throw Error(MDG_E_ARG, "probe energy: nsteps >= 0");
+    if (nprobe < 1 || !probes || !J) throw Error(MDG_E_ARG, "probe energy: probes and J required");
+    if (nprobe > MDG_NOALLOC_MAX_PROBES)
+      throw Error(MDG_E_ARG, "probe_energy_noalloc: nprobe > MDG_NOALLOC_MAX_PROBES (" +
+                                 std::to_string(MDG_NOALLOC_MAX_PROBES) + ")");
+    int64_t pin[MDG_NOALLOC_MAX_PROBES];
+    for (int i = 0; i < nprobe; ++i) {
+      if (probes[i] < 0 || probes[i] >= s.nt) throw Error(MDG_E_ARG, "probe energy: element out of range");
+      pin[i] = s.iperm[probes[i]];
+    }
+    unsigned char* base = scratch_ptr();
+    double* Jd = reinterpret_cast<double*>(base);
+    int64_t* pd = reinterpret_cast<int64_t*>(base + 256);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(hipMemcpyAsync(pd, pin, size_t(nprobe) * 8, hipMemcpyHostToDevice, st), "probes");
+    hipLaunchKernelGGL(zero_one, dim3(1), dim3(64), 0, st, Jd);
+    hip_check(hipGetLastError(), "zero_one launch");
     publish_if_needed(s, stream);
     for (int64_t n = 0; n < nsteps; ++n) {
       enqueue_steps(s, 1, stream);

@@ -83,6 +83,7 @@ SIGNATURES = {
     "mdg_energy_instances": (_S, [_VP, _D]),
     "mdg_adjoint_probe_energy": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _I64, _D, _D, _VP]),
     "mdg_probe_energy": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, _I64, _D, _VP]),
+    "mdg_probe_energy_noalloc": (_S, [_VP, ctypes.c_int64, ctypes.c_int32, _I64, _D, _VP]),
     "mdg_query": (_S, [_VP, ctypes.POINTER(mdg_info)]),
 }
 
@@ -304,6 +305,14 @@ class Solver:
         J = ctypes.c_double()
         self._chk(self.lib.mdg_probe_energy(self.h, int(nsteps), len(pr), pr.ctypes.data_as(_I64),
                                             ctypes.byref(J), stream))
+        return J.value
+
+    def probe_energy_noalloc(self, nsteps, probes, stream=None):
+        """probe_energy through the entry point that allocates no device memory."""
+        pr = np.ascontiguousarray(probes, dtype=np.int64)
+        J = ctypes.c_double()
+        self._chk(self.lib.mdg_probe_energy_noalloc(self.h, int(nsteps), len(pr), pr.ctypes.data_as(_I64),
+                                                    ctypes.byref(J), stream))
         return J.value
 
     def adjoint_probe_energy(self, nsteps, every, probes, stream=None):
