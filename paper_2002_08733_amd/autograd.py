@@ -33,30 +33,56 @@ class ProbeEnergyProblem:
         self.probes = np.asarray(probes, dtype=np.int64)
         self.precision = precision
 
-    def run(self, eps):
-        s = Solver(self.order, self.precision, self.flux, dt=self.dt, mixed=self.mixed, sip_alpha=self.sip_alpha)
-        try:
+    def _solver(self, eps):
+        """The problem's solver with permittivity eps and the initial state:
+        built once (mesh setup, device workspace), re-bound for a new eps."""
+        if getattr(self, "_s", None) is None:
+            s = Solver(self.order, self.precision, self.flux, dt=self.dt, mixed=self.mixed,
+                       sip_alpha=self.sip_alpha)
             s.set_mesh(self.verts, self.tets)
             s.set_material(eps, self.mu)
             if self.omega is not None:
                 s.set_pml(self.omega)
             if self.dipoles is not None:
                 s.set_dipoles(*self.dipoles)
-            s.bind_torch_workspace()
-            s.set_state(self.E0, self.H0)
-            return s.adjoint_probe_energy(self.nsteps, self.every, self.probes)
-        finally:
-            s.close()
+            self._ws = s.bind_torch_workspace()
+            self._s = s
+        else:
+            s = self._s
+            s.set_material(eps, self.mu)
+            s.bind_workspace(self._ws, torch.cuda.current_stream(self._ws.device).cuda_stream)
+        s.set_state(self.E0, self.H0)
+        return s
+
+    def run(self, eps):
+        """(J, dJ/deps) by the library's checkpointed discrete adjoint."""
+        return self._solver(eps).adjoint_probe_energy(self.nsteps, self.every, self.probes)
+
+    def objective(self, eps):
+        """J alone (the forward steps only)."""
+        return self._solver(eps).probe_energy(self.nsteps, self.probes)
+
+    def close(self):
+        if getattr(self, "_s", None) is not None:
+            self._s.close()
+            self._s = None
+            self._ws = None
 
     def __call__(self, eps: torch.Tensor) -> torch.Tensor:
         return ProbeEnergy.apply(eps, self)
 
 
 class ProbeEnergy(torch.autograd.Function):
+    """J(eps); the adjoint sweep runs only when a gradient is requested."""
+
     @staticmethod
     def forward(ctx, eps, problem):
-        J, g = problem.run(eps.detach().cpu().double().numpy())
-        ctx.save_for_backward(torch.as_tensor(g, dtype=eps.dtype, device=eps.device))
+        e = eps.detach().cpu().double().numpy()
+        if ctx.needs_input_grad[0]:
+            J, g = problem.run(e)
+            ctx.save_for_backward(torch.as_tensor(g, dtype=eps.dtype, device=eps.device))
+        else:
+            J = problem.objective(e)
         return eps.new_tensor(J)
 
     @staticmethod

@@ -264,6 +264,10 @@ def test_autograd_function(case):
     say(f"[autograd] {case}: J={J.item():.10e}")
     assert J.item() == Jd
     assert np.array_equal(gt.numpy(), 3.0 * gd)
+    # without a gradient request only the forward steps run: the same J
+    with torch.no_grad():
+        assert prob(eps).item() == Jd
+    assert prob(torch.tensor(w.eps, dtype=torch.float64)).item() == Jd
     # the same objective through the library directly, finite differences on one element
     T = 222
     h = 1e-6 * w.eps[T]
@@ -271,4 +275,5 @@ def test_autograd_function(case):
     e1[T] += h
     e2[T] -= h
     fd = (prob.run(e1)[0] - prob.run(e2)[0]) / (2 * h)
+    prob.close()
     assert abs(gd[T] - fd) <= 1e-5 * abs(fd) + 1e-7 * np.abs(gd).max()
