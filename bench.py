@@ -55,12 +55,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def setup_solver(w, precision, dt, q=4, integrator="rk4", mixed=False, sip_alpha=0.0):
+def setup_solver(w, precision, dt, q=4, integrator="rk4", mixed=False, sip_alpha=0.0, mfma=False):
     import torch
     from paper_2002_08733_amd import Solver
     # mixed: e at the workload's order, h one order lower
     s = Solver(w.p - (1 if mixed else 0), precision, w.flux, dt=dt, integrator=integrator, mixed=mixed,
-               sip_alpha=sip_alpha)
+               sip_alpha=sip_alpha, mfma=mfma)
     s.set_mesh(w.verts, w.tets)
     s.set_material(w.eps, w.mu)
     s.bind_torch_workspace()
@@ -463,6 +463,7 @@ def main():
     ap.add_argument("--n", type=int, default=32, help="cubes per axis (32 = headline workload)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-mfma", action="store_true", help="skip the FP32 row with the MFMA volume term")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="elements in the oracle timing sample (0 = the whole mesh)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -515,9 +516,11 @@ def main():
     khash = kernel_source_hash()
     results = {}
     precs = [args.precision] + ([] if args.skip_fp64 else [p for p in ("fp32", "fp64") if p != args.precision])
+    if not args.skip_mfma:
+        precs.append("fp32_mfma")  # the volume term as BF16x3 MFMA products
     for prec in precs:
         log(f"[bench] setup {prec} n={args.n} K={w.nt}")
-        s = setup_solver(w, prec, dt)
+        s = setup_solver(w, prec.split("_")[0], dt, mfma=prec.endswith("mfma"))
         info = s.query()
         W0 = s.energy()
         log(f"[bench] {prec}: warmup >= {args.warmup} steps and {MIN_WARM_S} s, timing {REPS} x {args.steps} steps")
@@ -528,7 +531,7 @@ def main():
         gdof = w.nt * 6 * N * stages / sec / 1e9
         t_stage = sec / stages
         achieved = info["bytes_per_stage"] / t_stage / 1e9
-        tr = traffic_for(khash, prec)
+        tr = traffic_for(khash, prec) if not prec.endswith("mfma") else None
         results[prec] = {
             "value": gdof, "ms_per_step": 1000.0 * sec / args.steps, "us_per_stage": 1e6 * t_stage,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -97,6 +97,12 @@ typedef struct mdg_options {
                          and decays with the upwind flux [KS Sec. III]; RK4 is strongly stable
                          over two steps, not one, so `monitor` must be >= 2 (MDG_E_ARG). With a
                          monitor mdg_step synchronises its stream before returning. 0: off */
+  int32_t mfma;       /* 1: the volume term (the reference-curl contraction of [KS Sec. III,
+                         eq. matrix_free_curl]) on the matrix cores, as BF16x3 split products
+                         (v_mfma_f32_16x16x32_bf16, each operand split exactly into three
+                         bfloat16 parts, six products accumulated in FP32: FP32 accuracy).
+                         Needs MDG_FP32, MDG_RK4, order <= 3 and 64-element tiles
+                         (MDG_E_UNSUPPORTED otherwise). 0: sparse VALU contraction (default) */
 } mdg_options;
 
 typedef struct mdg_info {

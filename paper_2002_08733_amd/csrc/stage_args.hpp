@@ -50,7 +50,7 @@ struct DevArgs {
 };
 
 template <typename R, int P>
-void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st);
+void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, hipStream_t st);
 template <typename R, int P>
 void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, hipStream_t st);
 template <typename R, int P>

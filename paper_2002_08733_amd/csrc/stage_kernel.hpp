@@ -492,6 +492,107 @@ __device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int
 #undef MDG_LIFT_FACE
 }
 
+// ---- BF16x3 MFMA form of the volume term (FP32 state, 64-element tiles)
+// The weak reference curl W of a tile's input field is one product
+// W[3N x 64] = Dbig[3N x 3N] V[3N x 64] over the tile's elements [KS Sec. III,
+// eq. matrix_free_curl]. The wave of part Q computes the rows of its output
+// modes (rho = c NQ + i, one 16-row M-tile) for the 64 elements (four 16-column
+// N-tiles) with v_mfma_f32_16x16x32_bf16 over K = 3N input rows in steps of 32.
+// Both operands are split exactly into bfloat16 parts (x = hi + mid + lo; the
+// constant side at build time), and the six products down to order 2^-16 are
+// accumulated in FP32, smallest first, which keeps FP32 accuracy. Operand
+// layouts (lane l): A row l % 16, K entries 8 (l / 16) .. +7; B column l % 16,
+// the same K entries; D column l % 16, rows 4 (l / 16) .. +3. A 4 x 4 block
+// transpose across the 16-lane rows (two permlane32 and two permlane16 swaps
+// per accumulator register) hands every lane the 16 rows of its own element.
+typedef __bf16 mdg_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float mdg_f32x4 __attribute__((ext_vector_type(4)));
+template <int P>
+__device__ __forceinline__ const uint4* mfa_table();
+template <>
+__device__ __forceinline__ const uint4* mfa_table<1>() { return reinterpret_cast<const uint4*>(mdg_mfA_1); }
+template <>
+__device__ __forceinline__ const uint4* mfa_table<2>() { return reinterpret_cast<const uint4*>(mdg_mfA_2); }
+template <>
+__device__ __forceinline__ const uint4* mfa_table<3>() { return reinterpret_cast<const uint4*>(mdg_mfA_3); }
+
+// hi + mid + lo = x exactly (each part rounded to nearest even in turn)
+__device__ __forceinline__ void split_bf16x3(const float (&x)[8], mdg_bf16x8& hi, mdg_bf16x8& mid, mdg_bf16x8& lo) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const __bf16 h = (__bf16)x[t];
+    const float r1 = x[t] - (float)h;
+    const __bf16 m = (__bf16)r1;
+    const float r2 = r1 - (float)m;
+    hi[t] = h;
+    mid[t] = m;
+    lo[t] = (__bf16)r2;
+  }
+}
+
+// acc = gs W(v) on the modes of part `part`; stg_in: the tile's staged input
+// field [3N][64] (LDS)
+template <int P>
+__device__ __forceinline__ void volume_mfma(const float* stg_in, int part, float gs, float (&acc)[3][nq<P>()]) {
+  constexpr int N = Ops<P>::N, NQ = nq<P>(), R3 = 3 * N, KS = (R3 + 31) / 32;
+  static_assert(3 * NQ <= 16, "one M-tile per part (orders up to 3)");
+  const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+  const uint4* tab = mfa_table<P>();
+  mdg_f32x4 Cacc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Cacc[j] = mdg_f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    mdg_bf16x8 A[3];
+#pragma unroll
+    for (int sp = 0; sp < 3; ++sp)
+      A[sp] = __builtin_bit_cast(mdg_bf16x8, tab[((part * KS + ks) * 3 + sp) * 64 + lane]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float x[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = 32 * ks + 8 * grp + t;
+        const float v = stg_in[(k < R3 ? k : R3 - 1) * 64 + 16 * j + col];
+        x[t] = k < R3 ? v : 0.f;
+      }
+      mdg_bf16x8 bh, bm, bl;
+      split_bf16x3(x, bh, bm, bl);
+      mdg_f32x4 c = Cacc[j];
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], bh, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], bm, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], bl, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], bh, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], bm, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], bh, c, 0, 0, 0);
+      Cacc[j] = c;
+    }
+  }
+  // lane d = 16 j + r gets rows 4 k + i of element d from lane 16 k + r of N-tile j
+  float rows[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    // the elements go through plain floats: a bit cast applied to a vector
+    // element expression reads element 0 with this toolchain
+    const float f0 = Cacc[0][i], f1 = Cacc[1][i], f2 = Cacc[2][i], f3 = Cacc[3][i];
+    const unsigned u0 = __float_as_uint(f0), u1 = __float_as_uint(f1), u2 = __float_as_uint(f2),
+                   u3 = __float_as_uint(f3);
+    const auto s02 = __builtin_amdgcn_permlane32_swap(u0, u2, false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(u1, u3, false, false);
+    const auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+    const auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+    const unsigned y0 = s01[0], y1 = s01[1], y2 = s23[0], y3 = s23[1];
+    rows[i] = __uint_as_float(y0);
+    rows[4 + i] = __uint_as_float(y1);
+    rows[8 + i] = __uint_as_float(y2);
+    rows[12 + i] = __uint_as_float(y3);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) acc[c][i] = gs * rows[c * NQ + i];
+}
+
 // Occupancy: LDS (4 NF + 1 reals per element and face) admits 2 workgroups
 // per CU; with 8 lanes per element that is 16 waves (FP32, tile 64) or 8
 // waves (FP64, tile 32) per CU, so registers are capped at 128 / 256. At
@@ -518,11 +619,14 @@ constexpr int waves_per_eu() { return sizeof(R) == 4 ? (P >= 4 ? 3 : 4) : 2; }
 // (central flux): part Q of the E lanes adds h_s of face Q to the averaged h
 // trace, part Q of the H lanes advances h_s of face Q from the jump of the e
 // traces (one copy per element face; both sides compute the same update).
-template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false>
+// MF: the volume term by BF16x3 MFMA products (FP32, RK4 and operator calls,
+// 64-element tiles) instead of the sparse VALU contraction.
+template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false, bool MF = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R, P>()))) void stage_kernel(
     DevArgs a) {
   static_assert(!(LF && UPW), "leap-frog halves need the central flux");
   static_assert(!(SIP && UPW), "the SIP unknown comes with the central flux");
+  static_assert(!MF || (sizeof(R) == 4 && LF == 0 && P <= 3), "MFMA volume: FP32, RK4, orders 1-3");
   constexpr bool C = LF == 2;
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
   constexpr int SS = slot_stride<NF, C>();
@@ -648,9 +752,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   R acc[3][NQ];
   {
     R t0[NF], t1[NF];
-    MDG_SWITCH_Q((face_trace<P, Q, R>(vl, t0, t1)));
-    asm volatile("" ::: "memory");  // the volume term reads the staging again
-    MDG_SWITCH_Q((volume_q<P, Q, R>(vl, g * sgn, acc)));
+    if constexpr (MF) {
+      volume_mfma<P>(stg + (1 - role) * R3 * tile, part, g * sgn, acc);
+      asm volatile("" ::: "memory");
+      MDG_SWITCH_Q((face_trace<P, Q, R>(vl, t0, t1)));
+    } else {
+      MDG_SWITCH_Q((face_trace<P, Q, R>(vl, t0, t1)));
+      asm volatile("" ::: "memory");  // the volume term reads the staging again
+      MDG_SWITCH_Q((volume_q<P, Q, R>(vl, g * sgn, acc)));
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -1116,17 +1226,37 @@ static inline void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false>
+template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false, bool MF = false>
 static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
   const int grid = (a.ntiles + 7) / 8 * 8;
   if (lds > 64 * 1024) {
-    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP>),
+    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP, MF>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
               "hipFuncSetAttribute(dynamic LDS)");
   }
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP>), dim3(grid), dim3((LF == 2 ? 4 : 8) * tile), lds, st,
-                     a);
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP, MF>), dim3(grid), dim3((LF == 2 ? 4 : 8) * tile), lds,
+                     st, a);
   hip_check(hipGetLastError(), "stage_kernel launch");
+}
+
+// RK4 stage or operator call with the MFMA volume term (FP32, orders 1-3, 64-element tiles)
+template <typename R, int P>
+static void launch_mfma(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
+  if constexpr (sizeof(R) == 4 && P <= 3) {
+    if (tile != 64) throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term needs 64-element tiles");
+    if (upw) {
+      if (pml) launch_one<R, P, true, true, 0, false, true>(a, tile, lds, st);
+      else launch_one<R, P, true, false, 0, false, true>(a, tile, lds, st);
+    } else if (sip) {
+      if (pml) launch_one<R, P, false, true, 0, true, true>(a, tile, lds, st);
+      else launch_one<R, P, false, false, 0, true, true>(a, tile, lds, st);
+    } else {
+      if (pml) launch_one<R, P, false, true, 0, false, true>(a, tile, lds, st);
+      else launch_one<R, P, false, false, 0, false, true>(a, tile, lds, st);
+    }
+  } else {
+    throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term is built for FP32 and orders 1-3");
+  }
 }
 
 // central-flux launches with or without the SIP unknown
@@ -1137,8 +1267,13 @@ static void launch_c(const DevArgs& a, bool sip, int tile, size_t lds, hipStream
 }
 
 template <typename R, int P>
-void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
+void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, hipStream_t st) {
   if (upw && sip) throw Error(MDG_E_UNSUPPORTED, "the SIP unknown needs the central flux");
+  if (mfma) {
+    if (a.stage >= 4) throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term runs with RK4");
+    launch_mfma<R, P>(a, upw, sip, pml, tile, lds, st);
+    return;
+  }
   if (a.stage >= 4) {  // leap-frog half (central flux, checked at creation)
     if (upw) throw Error(MDG_E_UNSUPPORTED, "leap-frog needs the central flux");
     if (tile % 64 == 0) {  // four lanes per element

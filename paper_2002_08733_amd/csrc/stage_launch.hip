@@ -40,12 +40,13 @@ __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ p
 }
 
 template <typename R>
-static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
+static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma,
+                     hipStream_t st) {
   switch (P) {
-    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, st); break;
-    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, st); break;
-    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, st); break;
-    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, st); break;
+    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, mfma, st); break;
+    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, mfma, st); break;
+    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, mfma, st); break;
+    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, mfma, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
 }
@@ -119,8 +120,8 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
     a.elem_end = part == 0 ? (int32_t)s.K0 : (int32_t)s.K;
     a.ntiles = part == 0 ? (int32_t)s.ntiles0 : (int32_t)(s.ntiles - s.ntiles0);
     if (a.ntiles == 0) continue;
-    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, st);
-    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, st);
+    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, st);
+    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, st);
   }
 }
 

@@ -372,3 +372,16 @@ def test_monitor_option_is_checked(lib):
             lib.Solver(2, monitor=bad)
         assert e.value.status == lib.MDG_E_ARG
     lib.Solver(2, monitor=2).close()
+
+
+def test_mfma_option_is_checked(lib):
+    """mdg_options.mfma: FP32, RK4, order <= 3 and 64-element tiles only."""
+    lib.Solver(3, "fp32", mfma=True).close()
+    for kw in (dict(precision="fp64"), dict(precision="fp32", integrator="leapfrog"),
+               dict(precision="fp32", tile=32)):
+        with pytest.raises(lib.MdgError) as e:
+            lib.Solver(3, mfma=True, **kw)
+        assert e.value.status == lib.MDG_E_UNSUPPORTED
+    with pytest.raises(lib.MdgError) as e:
+        lib.Solver(4, "fp32", mfma=True)
+    assert e.value.status == lib.MDG_E_UNSUPPORTED
