@@ -103,7 +103,16 @@ typedef struct mdg_options {
                          bfloat16 parts, six products accumulated in FP32: FP32 accuracy).
                          Needs MDG_FP32, MDG_RK4, order <= 3 and 64-element tiles
                          (MDG_E_UNSUPPORTED otherwise). 0: sparse VALU contraction (default) */
+  int32_t launch;     /* stage-kernel grid: MDG_LAUNCH_PERSISTENT, only the workgroups the GPU
+                         holds at once, each looping over its tiles and requesting the next
+                         tile's input field and halo traces before publishing the current
+                         tile's traces (FP32, orders 1-3; one workgroup per tile otherwise);
+                         MDG_LAUNCH_PER_TILE, one workgroup per tile, which the hardware
+                         dispatches as others finish; MDG_LAUNCH_AUTO (0) = per tile. Results
+                         are identical bit for bit */
 } mdg_options;
+
+enum { MDG_LAUNCH_AUTO = 0, MDG_LAUNCH_PERSISTENT = 1, MDG_LAUNCH_PER_TILE = 2 };
 
 typedef struct mdg_info {
   int32_t order, nmodes, nfacemodes, precision, flux, tile_size;

@@ -404,6 +404,10 @@ mdg_status mdg_create(const mdg_options* o, mdg_solver** out) {
   if (!(o->dt >= 0) || (o->dt == 0 && !(o->cfl > 0))) { g_create_error = "need dt > 0 or cfl > 0"; return MDG_E_ARG; }
   if (o->monitor < 0 || o->monitor == 1) { g_create_error = "monitor must be 0 or >= 2"; return MDG_E_ARG; }
   if (o->mfma != 0 && o->mfma != 1) { g_create_error = "mfma must be 0 or 1"; return MDG_E_ARG; }
+  if (o->launch < MDG_LAUNCH_AUTO || o->launch > MDG_LAUNCH_PER_TILE) {
+    g_create_error = "launch must be MDG_LAUNCH_AUTO, MDG_LAUNCH_PERSISTENT or MDG_LAUNCH_PER_TILE";
+    return MDG_E_ARG;
+  }
   if (o->mfma && (o->precision != MDG_FP32 || o->integrator != MDG_RK4 || o->order + o->mixed > 3 ||
                   (o->tile != 0 && o->tile != 64))) {
     g_create_error = "the MFMA volume term needs FP32, RK4, order <= 3 and 64-element tiles";

@@ -223,19 +223,36 @@ void setup_dipoles(Solver& s, int n, const int32_t* inst, const double* pos, con
   s.bound = false;
 }
 
-size_t stage_lds_bytes(const Solver& s) {
-  // trace slots of the tile's faces and of its halo, plus 16 bytes of slack
-  // for the 16-byte granules of the halo copy
-  const size_t rs = s.real_size();
-  return ((4ull * s.NF + 1) * 4ull * s.tile + 2ull * halo_role_reals(s.NF, (int)rs) * s.hmax) * rs + 16;
+LdsLayout stage_lds_layout(const Solver& s, bool compact) {
+  // reals: in-tile trace slots [0, T) (the publication stages the output in
+  // [0, ST)), the staged input [SB, SB + ST), the halo slots from HB; plus 16
+  // bytes of slack for the 16-byte granules of the halo copy
+  const int rs = (int)s.real_size();
+  const size_t ss = compact ? 2ull * s.NF + 1 : 4ull * s.NF + 1;
+  const size_t T = 4ull * s.tile * ss;
+  const size_t ST = (compact ? 1ull : 2ull) * 3ull * s.N * s.tile;
+  const size_t H = (compact ? 1ull : 2ull) * (size_t)halo_role_reals(s.NF, rs) * (size_t)s.hmax;
+  LdsLayout shared{0, (int32_t)std::max(T, ST), 0, 0}, beside{(int32_t)ST, (int32_t)std::max(T, 2 * ST), 0, 0};
+  shared.bytes = (size_t(shared.halo_base) + H) * rs + 16;
+  beside.bytes = (size_t(beside.halo_base) + H) * rs + 16;
+  // the publication stages the output beside the trace slots (the input and
+  // halo areas are dead by then) when that fits the same allocation
+  for (LdsLayout* l : {&shared, &beside})
+    if ((T + ST) * rs + 16 <= l->bytes) l->out_base = (int32_t)T;
+  // workgroups per CU: by LDS, and by the register budget the kernel is
+  // compiled for (waves per SIMD: FP32 4, or 3 at order 4; FP64 2)
+  const int wpe = s.opt.precision == MDG_FP32 ? (s.P >= 4 ? 3 : 4) : 2;
+  const int wg_waves = std::max(1, (compact ? 4 : 8) * s.tile / 64);
+  const size_t by_regs = (size_t)std::max(1, 4 * wpe / wg_waves);
+  auto per_cu = [&](size_t b) { return std::min(LDS_MAX_BYTES / b, by_regs); };
+  // the input beside the output staging lets a workgroup copy its next
+  // tile's input while publishing; take it unless it costs occupancy
+  return per_cu(beside.bytes) >= per_cu(shared.bytes) ? beside : shared;
 }
 
-size_t lf_lds_bytes(const Solver& s) {
-  // compact in-tile slots and the halo block of the active role only
-  const size_t rs = s.real_size();
-  const size_t slots = (2ull * s.NF + 1) * 4ull * s.tile + 1ull * halo_role_reals(s.NF, (int)rs) * s.hmax;
-  return std::max<size_t>(slots, 3ull * s.N * s.tile) * rs + 16;
-}
+size_t stage_lds_bytes(const Solver& s) { return stage_lds_layout(s, false).bytes; }
+
+size_t lf_lds_bytes(const Solver& s) { return stage_lds_layout(s, true).bytes; }
 
 int tile_size_for(int P, bool fp32) {
   // elements per workgroup (eight lanes each: 2 fields x 4 parts, so 2*tile
@@ -393,7 +410,7 @@ void finalize(Solver& s) {
     const size_t lds = stage_lds_bytes(s);
     // the default choice keeps two workgroups per CU; a forced tile only has
     // to fit the LDS of one workgroup
-    if (lds <= 64 * 1024 || (forced && lds <= LDS_MAX_BYTES)) break;
+    if (lds <= LDS_MAX_BYTES / 2 || (forced && lds <= LDS_MAX_BYTES)) break;
     if (lf && tile == 64 && lf_lds_bytes(s) <= LDS_MAX_BYTES / 2 && lds <= LDS_MAX_BYTES) break;
     if (tile <= 32) {
       // up to 160 KiB per workgroup on gfx950 (checked against the device at bind time)
@@ -401,8 +418,6 @@ void finalize(Solver& s) {
       throw Error(MDG_E_UNSUPPORTED, "face-trace exchange does not fit in the LDS of one workgroup");
     }
   }
-  // the output staging of the trace publication reuses the trace area
-  if (size_t(6) * s.N * s.tile * rs > stage_lds_bytes(s)) throw Error(MDG_E_UNSUPPORTED, "LDS staging too small");
   if (s.K >= (int64_t(1) << 29)) throw Error(MDG_E_ARG, "mesh too large");
   if (size_t(s.hbuf_reals) * rs >= (size_t(1) << 32)) throw Error(MDG_E_UNSUPPORTED, "mesh too large: halo buffer exceeds 4 GiB");
 

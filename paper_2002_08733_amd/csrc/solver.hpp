@@ -136,6 +136,16 @@ int tile_size_for(int P, bool fp32);
 // buffer holds one region per reading role; a tile's block in each region
 // has one slot per halo face. In-tile slots keep the odd stride 4 NF + 1.
 inline int halo_role_reals(int NF, int rs) { return (2 * NF * rs + 15) / 16 * 16 / rs; }
+// LDS of one stage-kernel workgroup: offsets (reals) of the staged input
+// field(s) and of the halo slots, and the bytes. compact: leap-frog halves
+// with four lanes per element (64-element tiles: the input field staged,
+// compact in-tile slots, the halo block of the active role only)
+struct LdsLayout {
+  int32_t stg_base, halo_base;
+  size_t bytes;
+  int32_t out_base;  // output staging of the publication beside the trace slots, or 0
+};
+LdsLayout stage_lds_layout(const Solver& s, bool compact);
 // dynamic LDS of one stage-kernel workgroup: the face-trace exchange
 size_t stage_lds_bytes(const Solver& s);
 // leap-frog halves with four lanes per element (64-element tiles): the input

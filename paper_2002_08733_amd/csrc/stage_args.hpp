@@ -46,11 +46,15 @@ struct DevArgs {
   int32_t nfh;                   // face modes of the SIP unknown: NF, or fewer with mixed orders
   int32_t hreg;                  // reals of one field's region of the halo buffers
   int32_t adj;                   // 1: adjoint operator (operator calls without sources)
+  int32_t stg_base, halo_base;   // LDS offsets (reals) of the staged input and of the halo slots
+  int32_t out_base;              // LDS offset (reals) of the output staging of the publication (0: the trace area)
+  int32_t tile;                  // elements per workgroup (block: 8 lanes per element, 4 for compact leap-frog halves)
   double bcoef, cdt, dt;
 };
 
 template <typename R, int P>
-void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, hipStream_t st);
+void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, bool persist,
+              hipStream_t st);
 template <typename R, int P>
 void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, hipStream_t st);
 template <typename R, int P>

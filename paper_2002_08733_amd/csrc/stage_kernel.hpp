@@ -47,6 +47,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "refops_dev_gen.h"
@@ -82,6 +83,12 @@ __device__ __forceinline__ void bst(R v, Rsrc r, uint32_t vo, uint32_t so) {
 }
 __device__ __forceinline__ int32_t bldi(Rsrc r, uint32_t vo, uint32_t so) {
   return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+}
+// wave-uniform read of a table that no kernel of the launch writes, through
+// the scalar cache (a plain load after stores in the same loop would be a
+// vector load, and waiting for it would wait for every copy in flight)
+__device__ __forceinline__ int32_t uniform_ld(const int32_t* p, int i) {
+  return ((const __attribute__((address_space(4))) int32_t*)p)[i];
 }
 // byte offset of element e's block origin in a blocked array with `rows` rows
 // per element: ((e/64)*rows*64 + e%64) * size
@@ -286,12 +293,11 @@ constexpr int loff(int k, int m) { return k * NF + m; }
 template <int NF, typename R>
 constexpr int hrr() { return (2 * NF * (int)sizeof(R) + 15) / 16 * 16 / (int)sizeof(R); }
 // LDS offset of field `role`'s traces in slot `slot` (in-tile or halo; nh:
-// the tile's halo slots)
+// the tile's halo slots, hb: LDS offset of the halo area)
 template <int NF, typename R, bool C = false>
-__device__ __forceinline__ int slot_base(int slot, int role, int tile, int nh) {
+__device__ __forceinline__ int slot_base(int slot, int role, int tile, int nh, int hb) {
   const int h = slot - 4 * tile;
-  return h < 0 ? lbase<NF, C>(slot, role)
-               : 4 * tile * slot_stride<NF, C>() + ((C ? 0 : role * nh) + h) * hrr<NF, R>();
+  return h < 0 ? lbase<NF, C>(slot, role) : hb + ((C ? 0 : role * nh) + h) * hrr<NF, R>();
 }
 // stores the NV consecutive reals v at byte offset vo (16-byte aligned) of r
 template <typename R, int NV>
@@ -421,7 +427,7 @@ __device__ __forceinline__ void face_metric_rt(int F, R gxx, R gxy, R gxz, R gyy
 // is sum_m T_F[m][l] (t^1 A1[m] + t^2 A2[m]). No reference matrix enters, so
 // the face index is a runtime (wave-uniform) value.
 template <int P, bool UPW, typename R, bool C = false>
-__device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, int tile, int li, int hn, int code, R g,
+__device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, int tile, int li, int hn, int hb, int code, R g,
                                                R sgn, R wz, R Z, R gxx, R gxy, R gxz, R gyy, R gyz, R gzz,
                                                R (&A1)[Ops<P>::NF], R (&A2)[Ops<P>::NF]) {
   constexpr int NF = Ops<P>::NF;
@@ -433,7 +439,7 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   const int sn = has ? code : so;
   const R fin = has ? R(1) : g;
   const R* own = lds + lbase<NF, C>(so, role);
-  const R* nbr = lds + slot_base<NF, R, C>(sn, role, tile, hn);
+  const R* nbr = lds + slot_base<NF, R, C>(sn, role, tile, hn, hb);
   const R om = role ? R(1) - wz : wz;  // own weight of the averaged input field
   const R rsign = (F == 0 || F == 2) ? R(1) : R(-1);  // sigma^_f = (+,-,+,-)
   const R c = -g * rsign * sgn;
@@ -450,7 +456,7 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   }
   if constexpr (UPW) {
     const R* own_o = lds + lbase<NF, C>(so, 1 - role);
-    const R* nbr_o = lds + slot_base<NF, R, C>(sn, 1 - role, tile, hn);
+    const R* nbr_o = lds + slot_base<NF, R, C>(sn, 1 - role, tile, hn, hb);
     R g11, g12, g22;
     face_metric_rt<R>(F, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
     const R idet = R(1) / sqrt(g11 * g22 - g12 * g12);
@@ -601,6 +607,9 @@ __device__ __forceinline__ void volume_mfma(const float* stg_in, int part, float
 // wave. (FP64 at p = 4 needs more than the 256 architectural registers.)
 template <typename R, int P>
 constexpr int waves_per_eu() { return sizeof(R) == 4 ? (P >= 4 ? 3 : 4) : 2; }
+// instances whose workgroups may take several tiles (see stage_kernel)
+template <typename R, int P>
+constexpr bool persistent_kernel() { return sizeof(R) == 4 && P <= 3; }
 
 #define MDG_SWITCH_Q(...)                     \
   switch (part) {                             \
@@ -629,26 +638,159 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   static_assert(!MF || (sizeof(R) == 4 && LF == 0 && P <= 3), "MFMA volume: FP32, RK4, orders 1-3");
   constexpr bool C = LF == 2;
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
+  // several tiles per workgroup (FP32, orders 1-3): in a loop the compiler
+  // keeps loop-invariant values in registers, which the FP64 constant tables
+  // and the order-4 register budget cannot afford
+  constexpr bool PERSIST = persistent_kernel<R, P>();
   constexpr int SS = slot_stride<NF, C>();
   constexpr uint32_t RS = sizeof(R);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
-  // XCD-major block -> tile map (dispatch places block b on XCD b % 8)
+  // Tiles -> workgroups, XCD-major (dispatch places block b on XCD b % 8): the
+  // workgroups of XCD x take the contiguous tile range [x T8, (x+1) T8),
+  // T8 = ceil(ntiles / 8), so spatially adjacent tiles share that XCD's L2.
+  // Workgroup j of an XCD (nx per XCD) takes tiles j, j + nx, j + 2 nx, ... of
+  // the range: one tile each when the grid covers every tile, several when
+  // the grid holds only the resident workgroups (persistent launch).
   const int nb = gridDim.x, b = blockIdx.x;
-  const int tl = (b & 7) * (nb >> 3) + (b >> 3);
-  if (tl >= a.ntiles) return;  // whole block leaves together
-  const int t = a.tile_begin + tl;
+  const int nx = nb >> 3, T8 = (a.ntiles + 7) >> 3;
+  const int tend = min((b & 7) * T8 + T8, a.ntiles);
+  int tl = (b & 7) * T8 + (b >> 3);
+  if (tl >= tend) return;  // whole block leaves together
   // the step's clock advances once, from a launch that no other kernel of the
   // step overlaps (the amplitudes of this stage were evaluated before it)
   if (a.tick && b == 0 && threadIdx.x == 0) a.tick[1] = a.tick[1] + 1.0;
   // 8 lanes per element (2 roles x 4 parts), or 4 (the active role's parts)
-  const int tile = blockDim.x >> (C ? 2 : 3);
-  const int tid = threadIdx.x;
-  // the lanes of one part are a multiple of 64, so the part is uniform in a wave
-  const int part = __builtin_amdgcn_readfirstlane(tid / (C ? tile : 2 * tile));
-  const int rem = tid - part * (C ? tile : 2 * tile);
-  const int role = C ? a.stage - 4 : (rem >= tile);
-  const int li = rem - (C ? 0 : role * tile);
+  // (the tile comes from the arguments: blockDim is read with a vector load,
+  // whose wait would also wait for every copy in flight)
+  const int tile = a.tile;
+  const uint32_t nwv = (uint32_t)((C ? 4 : 8) * tile) >> 6;  // waves of the workgroup
+  // LDS layout (reals): the in-tile trace slots [0, 4 tile SS), in which the
+  // publication stages the tile's output fields [0, ST); the tile's input
+  // field(s) [SB, SB + ST) as [field][3N][tile]; the halo slots from HB on.
+  // ST = (C ? 1 : 2) 3N tile. With SB >= ST (when LDS allows it at the same
+  // occupancy) a tile's input is copied in while the previous tile of the
+  // workgroup publishes; with SB = 0 it shares the trace area and is copied
+  // at the start of the tile.
+  const int ST = (C ? 1 : 2) * R3 * tile;
+  const int SB = a.stg_base, HB = a.halo_base;
+  const bool early = SB >= ST;
+  // the launch arguments, read through the kernel-argument segment
+  typedef __attribute__((address_space(4))) const DevArgs KArgs;
+  typedef __attribute__((address_space(3))) unsigned char lds_byte;
+  // lane -> (part, role, element of the tile); the lanes of one part are a
+  // multiple of 64, so the part is uniform in a wave
+  struct Lane {
+    int part, role, li;
+  };
+  auto lane_of = [&](KArgs& A, int tid) {
+    Lane L;
+    L.part = __builtin_amdgcn_readfirstlane(tid / (C ? tile : 2 * tile));
+    // four parts: with it the compiler drops the mode-range branches where
+    // 4 NQ = N (orders 1 and 3), which would split the epilogue into blocks
+    // whose merged wait counts drain every memory operation in flight
+    __builtin_assume(L.part >= 0 && L.part < 4);
+    const int rem = tid - L.part * (C ? tile : 2 * tile);
+    L.role = C ? A.stage - 4 : (rem >= tile);
+    L.li = rem - (C ? 0 : L.role * tile);
+    return L;
+  };
+
+  // 1. the input field(s) of a tile (role r lanes read field 1 - r) into
+  // [SB, SB + ST) with asynchronous LDS loads, 16 bytes per lane and 1 KiB per
+  // wave instruction: a row of the tile is tile RS bytes of one 64-element
+  // block row, and the staged rows are consecutive rows of the state block
+  auto input_copy = [&](KArgs& A, int tid, int tix) {
+    const int fst = C ? 1 - (A.stage - 4) : 0;  // first staged field
+    const uint32_t e0 = (uint32_t)(A.elem_begin + tix * tile);
+    const uint32_t rsh = __builtin_ctz((uint32_t)tile * RS);  // log2 of the row bytes
+    const uint32_t nbytes = (uint32_t)ST * RS;
+    const Rsrc rU = make_rsrc(A.Uin, A.state_bytes);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    lds_byte* dst = (lds_byte*)smem_raw + (uint32_t)SB * RS;
+    if (e0 % (uint32_t)tile == 0) {
+      // the tile lies in one 64-element block: 16 bytes per lane
+      const uint32_t base = blk_base(e0, 2 * R3, RS) + (uint32_t)fst * rowb<R>(R3);
+      for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
+        const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
+        const uint32_t src = base + (vo >> rsh) * rowb<R>(1) + (vo & ((1u << rsh) - 1u));
+        if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 1024u, 16, src, 0, 0, 0);
+      }
+    } else {
+      // a tile of the damped partition that straddles two blocks: 4 bytes
+      // per lane, each addressed through its own element
+      for (uint32_t c = wv; c * 256u < nbytes; c += nwv) {
+        const uint32_t vo = c * 256u + (uint32_t)(tid & 63) * 4u;
+        const uint32_t row = vo >> rsh, w = vo & ((1u << rsh) - 1u);
+        const uint32_t src = blk_base(e0 + w / RS, 2 * R3, RS) + (uint32_t)(fst * R3 + row) * rowb<R>(1) + w % RS;
+        if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, 0);
+      }
+    }
+  };
+  // 3. halo: the traces of out-of-tile neighbours were written by those
+  // neighbours in the previous stage, as an image of the tile's halo slots;
+  // the block is copied into the halo area the same way
+  auto halo_copy = [&](KArgs& A, int tid, int tg) {
+    const int role = lane_of(A, tid).role;
+    const int hoff = uniform_ld(A.halo_tile, 2 * tg), hcount = uniform_ld(A.halo_tile, 2 * tg + 1);
+    // the tile's block in each region (hrr reals per slot: a multiple of 16 bytes)
+    const uint32_t rb = (uint32_t)hcount * hrr<NF, R>() * RS, jump = (uint32_t)A.hreg * RS;
+    const uint32_t nbytes = C ? rb : 2u * rb;
+    const Rsrc rH = make_rsrc(A.hin, A.hbuf_bytes);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    lds_byte* dst = (lds_byte*)smem_raw + (uint32_t)HB * RS;
+    for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
+      const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
+      const uint32_t src = C ? vo + (uint32_t)role * jump : (vo < rb ? vo : vo - rb + jump);
+      if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rH, dst + c * 1024u, 16, src, (uint32_t)hoff * RS, 0, 0);
+    }
+  };
+  // 2. RK operands of the part's output rows (absent operands read as 0),
+  // requested with the tile's copies so that their latency overlaps the
+  // trace, volume and flux work. FP32 loads the accumulator after barrier 1,
+  // which keeps the register budget at four waves per SIMD.
+  R ypre[3][NQ], apre[3][NQ];
+  auto load_operands = [&](KArgs& A, int tid, int tix) {
+    const Lane L = lane_of(A, tid);
+    const uint32_t e = (uint32_t)(A.elem_begin + tix * tile + L.li);
+    const uint32_t vo = blk_base(e, 2 * R3, RS) + L.role * rowb<R>(R3);
+    const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.state_bytes, A.bcoef, A.cdt, A.dt, LF == 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int l = L.part * NQ + q;
+        const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
+        ypre[c][q] = bld<R, CP_NT>(ef.y_rd, vo, so);
+        if constexpr (sizeof(R) == 8) apre[c][q] = bld<R, CP_NT>(ef.a_rd, vo, so);
+      }
+  };
+  // everything a tile needs from memory before its first barrier; the
+  // copies go first, so that a barrier waits for them but not for the
+  // operand loads behind them
+  auto prefetch = [&](KArgs& A, int tid, int tix, bool with_input) {
+    if (with_input) input_copy(A, tid, tix);
+    halo_copy(A, tid, A.tile_begin + tix);
+    __builtin_amdgcn_sched_barrier(0);
+    load_operands(A, tid, tix);
+  };
+  prefetch(*(KArgs*)__builtin_amdgcn_kernarg_segment_ptr(), (int)threadIdx.x, tl, true);
+
+  for (;;) {
+  // the launch arguments and the lane's indices are re-derived for every
+  // tile, opaque to the compiler, so that nothing computed from them (buffer
+  // descriptors, LDS and memory offsets) is held in registers across tiles
+  KArgs* ap = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+  int tid = threadIdx.x;
+  asm volatile("" : "+s"(ap), "+v"(tid));
+  KArgs& a = *ap;
+  const Lane lane = lane_of(a, tid);
+  const int part = lane.part, role = lane.role, li = lane.li;
+  const Rsrc rU = make_rsrc(a.Uin, a.state_bytes);
+  const Rsrc rG = make_rsrc(a.geo, a.geo_bytes);
+  const int t = a.tile_begin + tl;
+  const int tnext = tl + nx;
+  const bool more = PERSIST && tnext < tend;
   const int start = a.elem_begin + tl * tile;
   const int cnt = min(tile, a.elem_end - start);
   // Lanes past the end of a partial tile compute on padding (arrays are padded
@@ -656,48 +798,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // every barrier; their stores are suppressed.
   const bool live = li < cnt;
   const uint32_t el = (uint32_t)(start + li);
-  const Rsrc rU = make_rsrc(a.Uin, a.state_bytes);
-  const Rsrc rG = make_rsrc(a.geo, a.geo_bytes);
   const uint32_t ebase = blk_base(el, 2 * R3, RS);       // element's state block
-  const uint32_t vin = ebase + (1 - role) * rowb<R>(R3);  // input field (other field)
   const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
   const uint32_t vgeo = blk_base(el, NGEO, RS);
-
-  // 1. input fields of the tile, each row loaded once: lane (role, part)
-  // loads rows [part RQ, part RQ + RQ) of its input field (the other field)
-  // and stages them in LDS as [field][3N][tile], in the area that holds the
-  // face traces later
-  constexpr int RQ = (R3 + 3) / 4;
-  R* stg = lds;
-  R vq[RQ];
-#pragma unroll
-  for (int i = 0; i < RQ; ++i) {
-    const int r = min(part * RQ + i, R3 - 1);
-    vq[i] = bld<R>(rU, vin, (uint32_t)r * 64u * RS);
-  }
-
-  // 2. RK operands of this part's output rows, issued now so that their
-  // latency overlaps the trace, volume and flux work (absent operands read as 0)
-  // (with four lanes per element no lane stages the output field, and the
-  // compact slots leave no room for it beside the halo slots)
   const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt, LF == 1);
-  R ypre[3][NQ], apre[3][NQ];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int l = part * NQ + q;
-      const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
-      ypre[c][q] = bld<R, CP_NT>(ef.y_rd, vout, so);
-      if constexpr (sizeof(R) == 8) apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
-    }
-
-#pragma unroll
-  for (int i = 0; i < RQ; ++i) {
-    const int r = part * RQ + i;
-    if (r < R3) stg[((C ? 0 : 1 - role) * R3 + r) * tile + li] = vq[i];
-  }
-  __syncthreads();  // B0: the tile's input fields are staged
+  const int hn = uniform_ld(a.halo_tile, 2 * t + 1);  // halo slots of this tile
+  const int hb = HB;
+  __syncthreads();  // B0: the tile's input field(s) and halo block are in LDS
+  const R* stg = lds + SB;
 
   // leap-frog half: the stage input is the state itself, so the own rows of
   // the output field come from the staging (no second read of Y), and only
@@ -717,27 +825,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const int l = part * NQ + q;
         ypre[c][q] = stg[(role * R3 + c * N + (l < N ? l : N - 1)) * tile + li];
       }
-  }
-
-  // 3. halo: the traces of out-of-tile neighbours were written by those
-  // neighbours in the previous stage, as an image of this tile's halo slots.
-  // Copy the block into LDS slots 4 tile.. with asynchronous LDS loads
-  // (16 bytes per lane, no registers involved); waited for before barrier 1.
-  const int hn = a.halo_tile[2 * t + 1];  // halo slots of this tile
-  {
-    typedef __attribute__((address_space(3))) unsigned char lds_byte;
-    const int hoff = a.halo_tile[2 * t];
-    // the tile's block in each region (hrr reals per slot: a multiple of 16 bytes)
-    const uint32_t rb = (uint32_t)hn * hrr<NF, R>() * RS, jump = (uint32_t)a.hreg * RS;
-    const uint32_t nbytes = C ? rb : 2u * rb;
-    const Rsrc rH = make_rsrc(a.hin, a.hbuf_bytes);
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6), nwv = blockDim.x >> 6;
-    lds_byte* dst = (lds_byte*)smem_raw + 4u * (uint32_t)tile * SS * RS;
-    for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
-      const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
-      const uint32_t src = C ? vo + (uint32_t)role * jump : (vo < rb ? vo : vo - rb + jump);
-      if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rH, dst + c * 1024u, 16, src, (uint32_t)hoff * RS, 0, 0);
-    }
   }
 
   // 4. trace of the input field on face `part` and the volume term of the
@@ -775,8 +862,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   }
   __builtin_amdgcn_sched_barrier(0);
 
-  // this wave's halo copies have landed in LDS
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   // 6. geometry and connectivity of face `part`, loaded while waiting at the
   // barrier (the input field is dead here)
   const R gxx = bld<R>(rG, vgeo, rowb<R>(G_XX)), gxy = bld<R>(rG, vgeo, rowb<R>(G_XY));
@@ -812,7 +897,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // 7. flux coefficients of face `part`
   {
     R A1[NF], A2[NF];
-    face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, hn, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz,
+    face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, hn, hb, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz,
                                  gzz, A1, A2);
     if constexpr (SIP) {
       // face `part` of this element: sig = sign((t^1 x t^2) . n_out), rows
@@ -840,7 +925,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const R fs = sipc / sqrt(g11 * g22 - g12 * g12);
         const bool has = code >= 0;
         const R* own = lds + lbase<NF, C>(part * tile + li, 1);
-        const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile, hn);
+        const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile, hn, hb);
         const R hn = has ? R(1) : R(0);
         const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip_bytes, a.bcoef, a.cdt, a.dt, false);
         const R cs = R(es.c_out), bs = R(a.bcoef);
@@ -1012,24 +1097,39 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 
   // 13. traces of the output on faces that a neighbouring tile reads in the
   // next stage: stage the tile's output fields in LDS, then part Q traces
-  // face Q of its element into the neighbour tile's halo block
+  // face Q of its element into the neighbour tile's halo block. The next
+  // tile's copies and operands are requested after the last barrier before
+  // the final LDS reads of this tile.
+  // the output is staged at OB: beside the trace slots when LDS has room
+  // (one tile per workgroup), else in the trace area once the lifts are done
+  const int OB = a.out_base;
+  if (OB == 0) __syncthreads();  // B4: the lifts are done with the trace area
+  const int sf = C ? 0 : role;
   if (a.publish) {
-    __syncthreads();  // B4: the lifts are done with the trace area
-    R* stg = lds;     // [role][3N][tile] ([active field][3N][tile] with four lanes per element)
-    const int sf = C ? 0 : role;
+    R* sto = lds + OB;  // [role][3N][tile] ([active field][3N][tile] with four lanes per element)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int l = part * NQ + q;
-        if (l < N) stg[((sf * 3 + c) * N + l) * tile + li] = acc[c][q];
+        if (l < N) sto[((sf * 3 + c) * N + l) * tile + li] = acc[c][q];
       }
     __syncthreads();  // B5
-    if (wr && pcode >= 0) {
-      const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
-      MDG_SWITCH_Q((publish_face<P, Q, R>(stg, sf, role, tile, li, rHo, pcode, a.hreg)));
-    }
   }
+  if (more) prefetch(a, tid, tnext, early);
+  if (a.publish && wr && pcode >= 0) {
+    const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
+    MDG_SWITCH_Q((publish_face<P, Q, R>(lds + OB, sf, role, tile, li, rHo, pcode, a.hreg)));
+  }
+  if (!more) break;
+  tl = tnext;
+  // without room for the next tile's input beside the output staging it is
+  // copied now, once every lane has read the staging (B6)
+  if (!early) {
+    __syncthreads();  // B6
+    input_copy(a, tid, tl);
+  }
+  }  // tile loop
 }
 #undef MDG_SWITCH_Q
 
@@ -1226,33 +1326,60 @@ static inline void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// resident workgroups of a kernel on the current device (its occupancy times
+// the CU count), looked up once per kernel and device
+static int resident_workgroups(const void* kern, int block, size_t lds, int* cache) {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 16) dev = 15;
+  if (cache[dev] > 0) return cache[dev];
+  int per_cu = 0, ncu = 0;
+  hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds),
+            "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+  hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  cache[dev] = std::max(1, per_cu) * std::max(1, ncu);
+  return cache[dev];
+}
+
+// persist: a grid of the resident workgroups only (rounded down to whole
+// XCDs), each looping over its share of the tiles; otherwise one workgroup
+// per tile
 template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false, bool MF = false>
-static void launch_one(const DevArgs& a, int tile, size_t lds, hipStream_t st) {
-  const int grid = (a.ntiles + 7) / 8 * 8;
-  if (lds > 64 * 1024) {
-    hip_check(hipFuncSetAttribute(reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP, MF>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+static void launch_one(const DevArgs& a, int tile, size_t lds, bool persist, hipStream_t st) {
+  const void* kern = reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP, MF>);
+  const int block = (LF == 2 ? 4 : 8) * tile;
+  if (lds > 64 * 1024)
+    hip_check(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
               "hipFuncSetAttribute(dynamic LDS)");
+  int grid = (a.ntiles + 7) / 8 * 8;
+  DevArgs b = a;
+  if (persist && persistent_kernel<R, P>()) {
+    static int cache[16] = {0};
+    const int res = resident_workgroups(kern, block, lds, cache);
+    grid = std::min(grid, std::max(8, res / 8 * 8));
+    // the next tile's copies land beside the trace slots while this tile
+    // publishes, so the output is staged in the trace area
+    b.out_base = 0;
   }
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP, MF>), dim3(grid), dim3((LF == 2 ? 4 : 8) * tile), lds,
-                     st, a);
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP, MF>), dim3(grid), dim3(block), lds, st, b);
   hip_check(hipGetLastError(), "stage_kernel launch");
 }
 
 // RK4 stage or operator call with the MFMA volume term (FP32, orders 1-3, 64-element tiles)
 template <typename R, int P>
-static void launch_mfma(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, hipStream_t st) {
+static void launch_mfma(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool ps,
+                        hipStream_t st) {
   if constexpr (sizeof(R) == 4 && P <= 3) {
     if (tile != 64) throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term needs 64-element tiles");
     if (upw) {
-      if (pml) launch_one<R, P, true, true, 0, false, true>(a, tile, lds, st);
-      else launch_one<R, P, true, false, 0, false, true>(a, tile, lds, st);
+      if (pml) launch_one<R, P, true, true, 0, false, true>(a, tile, lds, ps, st);
+      else launch_one<R, P, true, false, 0, false, true>(a, tile, lds, ps, st);
     } else if (sip) {
-      if (pml) launch_one<R, P, false, true, 0, true, true>(a, tile, lds, st);
-      else launch_one<R, P, false, false, 0, true, true>(a, tile, lds, st);
+      if (pml) launch_one<R, P, false, true, 0, true, true>(a, tile, lds, ps, st);
+      else launch_one<R, P, false, false, 0, true, true>(a, tile, lds, ps, st);
     } else {
-      if (pml) launch_one<R, P, false, true, 0, false, true>(a, tile, lds, st);
-      else launch_one<R, P, false, false, 0, false, true>(a, tile, lds, st);
+      if (pml) launch_one<R, P, false, true, 0, false, true>(a, tile, lds, ps, st);
+      else launch_one<R, P, false, false, 0, false, true>(a, tile, lds, ps, st);
     }
   } else {
     throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term is built for FP32 and orders 1-3");
@@ -1261,34 +1388,35 @@ static void launch_mfma(const DevArgs& a, bool upw, bool sip, bool pml, int tile
 
 // central-flux launches with or without the SIP unknown
 template <typename R, int P, bool PML, int LF>
-static void launch_c(const DevArgs& a, bool sip, int tile, size_t lds, hipStream_t st) {
-  if (sip) launch_one<R, P, false, PML, LF, true>(a, tile, lds, st);
-  else launch_one<R, P, false, PML, LF, false>(a, tile, lds, st);
+static void launch_c(const DevArgs& a, bool sip, int tile, size_t lds, bool ps, hipStream_t st) {
+  if (sip) launch_one<R, P, false, PML, LF, true>(a, tile, lds, ps, st);
+  else launch_one<R, P, false, PML, LF, false>(a, tile, lds, ps, st);
 }
 
 template <typename R, int P>
-void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, hipStream_t st) {
+void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, bool ps,
+              hipStream_t st) {
   if (upw && sip) throw Error(MDG_E_UNSUPPORTED, "the SIP unknown needs the central flux");
   if (mfma) {
     if (a.stage >= 4) throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term runs with RK4");
-    launch_mfma<R, P>(a, upw, sip, pml, tile, lds, st);
+    launch_mfma<R, P>(a, upw, sip, pml, tile, lds, ps, st);
     return;
   }
   if (a.stage >= 4) {  // leap-frog half (central flux, checked at creation)
     if (upw) throw Error(MDG_E_UNSUPPORTED, "leap-frog needs the central flux");
     if (tile % 64 == 0) {  // four lanes per element
-      if (pml) launch_c<R, P, true, 2>(a, sip, tile, lds, st);
-      else launch_c<R, P, false, 2>(a, sip, tile, lds, st);
+      if (pml) launch_c<R, P, true, 2>(a, sip, tile, lds, ps, st);
+      else launch_c<R, P, false, 2>(a, sip, tile, lds, ps, st);
     } else {
-      if (pml) launch_c<R, P, true, 1>(a, sip, tile, lds, st);
-      else launch_c<R, P, false, 1>(a, sip, tile, lds, st);
+      if (pml) launch_c<R, P, true, 1>(a, sip, tile, lds, ps, st);
+      else launch_c<R, P, false, 1>(a, sip, tile, lds, ps, st);
     }
   } else if (upw) {
-    if (pml) launch_one<R, P, true, true, 0>(a, tile, lds, st);
-    else launch_one<R, P, true, false, 0>(a, tile, lds, st);
+    if (pml) launch_one<R, P, true, true, 0>(a, tile, lds, ps, st);
+    else launch_one<R, P, true, false, 0>(a, tile, lds, ps, st);
   } else {
-    if (pml) launch_c<R, P, true, 0>(a, sip, tile, lds, st);
-    else launch_c<R, P, false, 0>(a, sip, tile, lds, st);
+    if (pml) launch_c<R, P, true, 0>(a, sip, tile, lds, ps, st);
+    else launch_c<R, P, false, 0>(a, sip, tile, lds, ps, st);
   }
 }
 

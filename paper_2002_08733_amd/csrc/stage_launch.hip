@@ -41,12 +41,12 @@ __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ p
 
 template <typename R>
 static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma,
-                     hipStream_t st) {
+                     bool ps, hipStream_t st) {
   switch (P) {
-    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, mfma, st); break;
-    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, mfma, st); break;
-    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, mfma, st); break;
-    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, mfma, st); break;
+    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
+    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
+    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
+    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
 }
@@ -102,7 +102,12 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.dt = sp.dt;
   const bool fp32 = s.opt.precision == MDG_FP32;
   const bool upw = s.opt.flux == MDG_UPWIND;
-  const size_t lds = (sp.stage >= 4 && s.tile % 64 == 0) ? lf_lds_bytes(s) : stage_lds_bytes(s);
+  const LdsLayout ll = stage_lds_layout(s, sp.stage >= 4 && s.tile % 64 == 0);
+  const size_t lds = ll.bytes;
+  a.stg_base = ll.stg_base;
+  a.halo_base = ll.halo_base;
+  a.out_base = ll.out_base;
+  a.tile = s.tile;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (a.has_src) {
     const int nd = (int)s.dips.size();
@@ -120,8 +125,9 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
     a.elem_end = part == 0 ? (int32_t)s.K0 : (int32_t)s.K;
     a.ntiles = part == 0 ? (int32_t)s.ntiles0 : (int32_t)(s.ntiles - s.ntiles0);
     if (a.ntiles == 0) continue;
-    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, st);
-    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, st);
+    const bool ps = s.opt.launch == MDG_LAUNCH_PERSISTENT;
+    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, ps, st);
+    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, ps, st);
   }
 }
 

@@ -32,11 +32,14 @@ class MdgError(RuntimeError):
         self.status = status
 
 
+_LAUNCH = {"auto": 0, "persistent": 1, "per_tile": 2}
+
+
 class mdg_options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("flux", ctypes.c_int32),
                 ("integrator", ctypes.c_int32), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("tile", ctypes.c_int32), ("mixed", ctypes.c_int32), ("sip_alpha", ctypes.c_double),
-                ("monitor", ctypes.c_int32), ("mfma", ctypes.c_int32)]
+                ("monitor", ctypes.c_int32), ("mfma", ctypes.c_int32), ("launch", ctypes.c_int32)]
 
 
 class mdg_info(ctypes.Structure):
@@ -130,12 +133,13 @@ class Solver:
     """One libmdg handle. Methods mirror the C entry points one to one."""
 
     def __init__(self, order, precision="fp64", flux="central", dt=0.0, cfl=0.3, tile=0, integrator="rk4",
-                 mixed=False, sip_alpha=0.0, monitor=0, mfma=False):
+                 mixed=False, sip_alpha=0.0, monitor=0, mfma=False, launch="auto"):
         """order: polynomial order of h (and of e, unless mixed: then e is one
         order higher, the paper's pairing). sip_alpha > 0 adds the SIP
         surface unknown (central flux). monitor >= 2: step() checks the
         energy every `monitor` steps (see mdg_options.monitor). mfma: the
-        volume term as BF16x3 MFMA products (FP32, RK4, order <= 3)."""
+        volume term as BF16x3 MFMA products (FP32, RK4, order <= 3). launch:
+        "auto", "persistent" or "per_tile" (see mdg_options.launch)."""
         self.lib = load_library()
         if integrator not in ("rk4", "leapfrog"):
             raise ValueError("integrator must be 'rk4' or 'leapfrog'")
@@ -143,7 +147,7 @@ class Solver:
                         flux=MDG_UPWIND if flux == "upwind" else MDG_CENTRAL,
                         integrator=MDG_RK4 if integrator == "rk4" else MDG_LEAPFROG, dt=float(dt), cfl=float(cfl),
                         tile=int(tile), mixed=1 if mixed else 0, sip_alpha=float(sip_alpha), monitor=int(monitor),
-                        mfma=1 if mfma else 0)
+                        mfma=1 if mfma else 0, launch=_LAUNCH[launch])
         h = _VP()
         st = self.lib.mdg_create(ctypes.byref(o), ctypes.byref(h))
         if st != MDG_OK:
