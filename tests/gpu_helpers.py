@@ -69,3 +69,52 @@ def rel_energy_err(O, aE, aH, bE, bH, aP=None, aQ=None, bP=None, bQ=None, elemen
     if elementwise:
         err = max(err, np.sqrt(d2.max() / b2.max()))
     return err
+
+
+def element_energy(verts, tets, eps, mu, E, H, P=None, Q=None, chunk=1 << 18):
+    """Per-element energy 1/2 (eps u.M u + mu f.M f [+ p.M p / eps + q.M q / mu])
+    of covariant coefficients [nt][3][N] in the canonical element frame
+    (vertices in ascending id order, A = [v1-v0, v2-v0, v3-v0]), with
+    M = |det A| A^-1 A^-T: the L2 norm of the Cartesian field A^-T u. Written
+    from the mesh alone, independent of the library's energy reduction."""
+    out = np.empty(len(tets))
+    for s in range(0, len(tets), chunk):
+        sl = slice(s, s + chunk)
+        X = verts[np.sort(tets[sl], axis=1)]
+        A = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+        Ai = np.linalg.inv(A)
+        M = np.abs(np.linalg.det(A))[:, None, None] * (Ai @ np.transpose(Ai, (0, 2, 1)))
+
+        def q(U):
+            return np.einsum("kim,kij,kjm->k", U[sl], M, U[sl])
+
+        w = eps[sl] * q(E) + mu[sl] * q(H)
+        if P is not None:
+            w += q(P) / eps[sl] + q(Q) / mu[sl]
+        out[sl] = 0.5 * w
+    return out
+
+
+def rel_state_err(verts, tets, eps, mu, a, b):
+    """Relative energy-norm difference of covariant states a, b (tuples E, H
+    [, P, Q]): the larger of sqrt(sum_T W_T(a - b) / sum_T W_T(b)) and the
+    per-element sqrt(max_T W_T(a - b) / max_T W_T(b)), so that one bad element
+    cannot hide in the global sum."""
+    d = element_energy(verts, tets, eps, mu, *[x - y for x, y in zip(a, b)])
+    r = element_energy(verts, tets, eps, mu, *b)
+    return float(max(np.sqrt(d.sum() / r.sum()), np.sqrt(d.max() / r.max())))
+
+
+def element_bilinear(verts, tets, eps, mu, a, b, chunk=1 << 18):
+    """Per-element eps a_E.M b_E + mu a_H.M b_H of covariant coefficient
+    pairs a = (E, H), b = (E, H) (canonical frame, M as in element_energy)."""
+    out = np.empty(len(tets))
+    for s in range(0, len(tets), chunk):
+        sl = slice(s, s + chunk)
+        X = verts[np.sort(tets[sl], axis=1)]
+        A = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+        Ai = np.linalg.inv(A)
+        M = np.abs(np.linalg.det(A))[:, None, None] * (Ai @ np.transpose(Ai, (0, 2, 1)))
+        out[sl] = (eps[sl] * np.einsum("kim,kij,kjm->k", a[0][sl], M, b[0][sl])
+                   + mu[sl] * np.einsum("kim,kij,kjm->k", a[1][sl], M, b[1][sl]))
+    return out
