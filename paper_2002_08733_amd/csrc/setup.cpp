@@ -540,8 +540,6 @@ void finalize(Solver& s) {
   L.eout = off; off = align256(off + 8);
   L.mon = off; off = align256(off + 4 * 8);
   L.total = off;
-  if (field >= (size_t(1) << 32) || sfield >= (size_t(1) << 32) || size_t(NGEO) * s.Kpad * rs >= (size_t(1) << 32))
-    throw Error(MDG_E_UNSUPPORTED, "mesh too large: a state array exceeds 4 GiB");
   s.finalized = true;
 }
 

@@ -38,7 +38,12 @@ struct DevArgs {
   const int32_t* srcnext;     // [ndip]: next dipole on the same element, or -1
   const double* srcamp;       // [ndip]: g(t) of every dipole at the stage's time
   double* tick;               // non-null: advance this device clock (n += 1) once
-  uint32_t state_bytes, aux_bytes, geo_bytes, nbr_bytes, pml_bytes, hbuf_bytes, sip_bytes;
+  // array sizes: the element arrays (whole 64-element blocks) are addressed
+  // through per-tile windows and given in blocks (any size): nblk for the
+  // arrays over all elements, pnblk for those over the damped ones; the halo
+  // buffers through 32-bit offsets (under 4 GiB)
+  uint32_t nblk, pnblk, hbuf_bytes;
+  int32_t sip;  // the SIP surface arrays exist
   int64_t pml_base;
   int32_t tile_begin, ntiles, stage, has_src, publish;  // stage: 0..3 RK4, -1 operator, 4/5 leap-frog E/H half
   int32_t elem_begin, elem_end;  // element range of this launch (tiles of `tile` elements from elem_begin)
@@ -58,8 +63,8 @@ void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t l
 template <typename R, int P>
 void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, hipStream_t st);
 template <typename R, int P>
-void launch_publish_rp(const void* U, uint32_t sb, const int32_t* pub, uint32_t pb, void* H, uint32_t hb, int K,
-                       int hreg, hipStream_t st);
+void launch_publish_rp(const void* U, uint32_t nblk, const int32_t* pub, void* H, uint32_t hb, int K, int hreg,
+                       hipStream_t st);
 template <typename R, int P>
 void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* geo, const int32_t* nbrg, int64_t K,
                         hipStream_t st);

@@ -95,6 +95,31 @@ __device__ __forceinline__ int32_t uniform_ld(const int32_t* p, int i) {
 __device__ __forceinline__ uint32_t blk_base(uint32_t e, uint32_t rows, uint32_t size) {
   return ((e >> 6) * rows * 64u + (e & 63u)) * size;
 }
+// Windows: a workgroup touches only the (at most two) 64-element blocks of
+// its tile, so a per-element array is addressed through a descriptor based
+// at the tile's first block (64-bit address arithmetic once per tile) with
+// 32-bit offsets relative to it, and no array is limited to 4 GiB. `on`
+// false gives a zero-length descriptor (loads return 0, stores are dropped).
+// nblk: the array's blocks (every element array holds whole blocks). The
+// range is computed in 32-bit arithmetic: a 64-bit comparison would be done
+// in vector registers, and a descriptor there turns every access through it
+// into a loop over the lanes' values.
+__device__ __forceinline__ Rsrc win_rsrc(const void* p, uint32_t nblk, uint32_t b0, uint32_t block_bytes,
+                                         bool on = true) {
+  // the saturating subtraction and the fused 64-bit multiply-add have only
+  // vector forms: both results are taken back to scalar registers
+  const uint32_t left = b0 < nblk ? nblk - b0 : 0u;
+  const uint32_t len = __builtin_amdgcn_readfirstlane((left < 2u ? left : 2u) * block_bytes);
+  const uint64_t addr = reinterpret_cast<uint64_t>(p) + (uint64_t)b0 * block_bytes;
+  // (readfirstlane returns a signed int: zero-extend each half)
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)addr);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+  return make_rsrc(reinterpret_cast<const void*>(hi << 32 | lo), on ? len : 0u);
+}
+// element e's block origin relative to block b0 of its window
+__device__ __forceinline__ uint32_t blk_rel(uint32_t e, uint32_t b0, uint32_t rows, uint32_t size) {
+  return (((e >> 6) - b0) * rows * 64u + (e & 63u)) * size;
+}
 // byte offset of row r inside a block
 template <typename R>
 __device__ __forceinline__ constexpr uint32_t rowb(int r) { return (uint32_t)r * 64u * (uint32_t)sizeof(R); }
@@ -375,14 +400,15 @@ struct Epi {
   double c_out;  // c_{i+1} dt, dt (final, leap-frog) or 1 (operator)
 };
 __device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* ACC, const void* Uout,
-                                        uint32_t bytes, double bcoef, double cdt, double dt, bool y_staged) {
+                                        uint32_t nblk, uint32_t b0, uint32_t block_bytes, double bcoef,
+                                        double cdt, double dt, bool y_staged) {
   Epi e;
   const bool op = stage < 0, lf = stage >= 4;
   e.final_stage = stage == 3;
-  e.y_rd = make_rsrc(Y, (op || (lf && y_staged)) ? 0u : bytes);
-  e.a_rd = make_rsrc(ACC, (stage >= 1 && stage <= 3) ? bytes : 0u);
-  e.a_wr = make_rsrc(ACC, (stage >= 0 && stage <= 2) ? bytes : 0u);
-  e.out_wr = make_rsrc((e.final_stage || lf) ? Y : Uout, bytes);
+  e.y_rd = win_rsrc(Y, nblk, b0, block_bytes, !(op || (lf && y_staged)));
+  e.a_rd = win_rsrc(ACC, nblk, b0, block_bytes, stage >= 1 && stage <= 3);
+  e.a_wr = win_rsrc(ACC, nblk, b0, block_bytes, stage >= 0 && stage <= 2);
+  e.out_wr = win_rsrc((e.final_stage || lf) ? Y : Uout, nblk, b0, block_bytes);
   e.c_out = op ? 1.0 : ((e.final_stage || lf) ? dt : cdt);
   (void)bcoef;
   return e;
@@ -644,6 +670,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   constexpr bool PERSIST = persistent_kernel<R, P>();
   constexpr int SS = slot_stride<NF, C>();
   constexpr uint32_t RS = sizeof(R);
+  constexpr uint32_t SBLK = 2u * R3 * 64u * RS;  // bytes of one 64-element block of a state array
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
   // Tiles -> workgroups, XCD-major (dispatch places block b on XCD b % 8): the
@@ -702,15 +729,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // block row, and the staged rows are consecutive rows of the state block
   auto input_copy = [&](KArgs& A, int tid, int tix) {
     const int fst = C ? 1 - (A.stage - 4) : 0;  // first staged field
-    const uint32_t e0 = (uint32_t)(A.elem_begin + tix * tile);
+    const uint32_t e0 = (uint32_t)(A.elem_begin + tix * tile), b0 = e0 >> 6;
     const uint32_t rsh = __builtin_ctz((uint32_t)tile * RS);  // log2 of the row bytes
     const uint32_t nbytes = (uint32_t)ST * RS;
-    const Rsrc rU = make_rsrc(A.Uin, A.state_bytes);
+    const Rsrc rU = win_rsrc(A.Uin, A.nblk, b0, SBLK);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     lds_byte* dst = (lds_byte*)smem_raw + (uint32_t)SB * RS;
     if (e0 % (uint32_t)tile == 0) {
       // the tile lies in one 64-element block: 16 bytes per lane
-      const uint32_t base = blk_base(e0, 2 * R3, RS) + (uint32_t)fst * rowb<R>(R3);
+      const uint32_t base = blk_rel(e0, b0, 2 * R3, RS) + (uint32_t)fst * rowb<R>(R3);
       for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
         const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
         const uint32_t src = base + (vo >> rsh) * rowb<R>(1) + (vo & ((1u << rsh) - 1u));
@@ -722,7 +749,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       for (uint32_t c = wv; c * 256u < nbytes; c += nwv) {
         const uint32_t vo = c * 256u + (uint32_t)(tid & 63) * 4u;
         const uint32_t row = vo >> rsh, w = vo & ((1u << rsh) - 1u);
-        const uint32_t src = blk_base(e0 + w / RS, 2 * R3, RS) + (uint32_t)(fst * R3 + row) * rowb<R>(1) + w % RS;
+        const uint32_t src = blk_rel(e0 + w / RS, b0, 2 * R3, RS) + (uint32_t)(fst * R3 + row) * rowb<R>(1) + w % RS;
         if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, 0);
       }
     }
@@ -752,9 +779,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   R ypre[3][NQ], apre[3][NQ];
   auto load_operands = [&](KArgs& A, int tid, int tix) {
     const Lane L = lane_of(A, tid);
+    const uint32_t b0 = (uint32_t)(A.elem_begin + tix * tile) >> 6;
     const uint32_t e = (uint32_t)(A.elem_begin + tix * tile + L.li);
-    const uint32_t vo = blk_base(e, 2 * R3, RS) + L.role * rowb<R>(R3);
-    const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.state_bytes, A.bcoef, A.cdt, A.dt, LF == 1);
+    const uint32_t vo = blk_rel(e, b0, 2 * R3, RS) + L.role * rowb<R>(R3);
+    const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.nblk, b0, SBLK, A.bcoef, A.cdt, A.dt, LF == 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -786,8 +814,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   KArgs& a = *ap;
   const Lane lane = lane_of(a, tid);
   const int part = lane.part, role = lane.role, li = lane.li;
-  const Rsrc rU = make_rsrc(a.Uin, a.state_bytes);
-  const Rsrc rG = make_rsrc(a.geo, a.geo_bytes);
   const int t = a.tile_begin + tl;
   const int tnext = tl + nx;
   const bool more = PERSIST && tnext < tend;
@@ -798,10 +824,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // every barrier; their stores are suppressed.
   const bool live = li < cnt;
   const uint32_t el = (uint32_t)(start + li);
-  const uint32_t ebase = blk_base(el, 2 * R3, RS);       // element's state block
+  const uint32_t b0 = (uint32_t)start >> 6;  // first block of the tile (windows of the element arrays)
+  const Rsrc rU = win_rsrc(a.Uin, a.nblk, b0, SBLK);
+  const Rsrc rG = win_rsrc(a.geo, a.nblk, b0, NGEO * 64u * RS);
+  const uint32_t ebase = blk_rel(el, b0, 2 * R3, RS);   // element's state block
   const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
-  const uint32_t vgeo = blk_base(el, NGEO, RS);
-  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.state_bytes, a.bcoef, a.cdt, a.dt, LF == 1);
+  const uint32_t vgeo = blk_rel(el, b0, NGEO, RS);
+  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.nblk, b0, SBLK, a.bcoef, a.cdt, a.dt, LF == 1);
   const int hn = uniform_ld(a.halo_tile, 2 * t + 1);  // halo slots of this tile
   const int hb = HB;
   __syncthreads();  // B0: the tile's input field(s) and halo block are in LDS
@@ -875,10 +904,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   R sipc = 0;  // alpha_F / mu_F of face `part`
   if constexpr (SIP) sipc = bld<R>(rG, vgeo, rowb<R>(G_SIP0 + part));
   const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
-  const Rsrc rN = make_rsrc(a.nbr, a.nbr_bytes);
-  const int code = bldi(rN, blk_base(el, 4, 4), (uint32_t)part * 256u);
-  const Rsrc rPub = make_rsrc(a.pub, a.nbr_bytes);
-  const int pcode = bldi(rPub, blk_base(el, 4, 4), (uint32_t)part * 256u);
+  const Rsrc rN = win_rsrc(a.nbr, a.nblk, b0, 4u * 64u * 4u);
+  const int code = bldi(rN, blk_rel(el, b0, 4, 4), (uint32_t)part * 256u);
+  const Rsrc rPub = win_rsrc(a.pub, a.nblk, b0, 4u * 64u * 4u);
+  const int pcode = bldi(rPub, blk_rel(el, b0, 4, 4), (uint32_t)part * 256u);
 
   __syncthreads();  // B1: traces of the tile and its halo are in LDS
   if constexpr (sizeof(R) == 4) {
@@ -903,12 +932,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       // face `part` of this element: sig = sign((t^1 x t^2) . n_out), rows
       // (part, k, m) of the element's surface block
       const R sig = ((part == 0 || part == 2) ? R(1) : R(-1)) * sgn;
-      const uint32_t vs = blk_base(el, 8 * NF, RS);
+      const uint32_t vs = blk_rel(el, b0, 8 * NF, RS);
       const int srow = part * 2 * NF;
       if (role == 0) {
         // E: -(h_s x n, v)_F has the form of the averaged h term, so the
         // edge-tangent components of h_s add to the averaged traces
-        const Rsrc rS = make_rsrc(a.sUin, a.sip_bytes);
+        const Rsrc rS = win_rsrc(a.sUin, a.nblk, b0, 8u * NF * 64u * RS, a.sip != 0);
 #pragma unroll
         for (int m = 0; m < NF; ++m) {
           const R s0 = bld<R>(rS, vs, rowb<R>(srow + m));
@@ -927,7 +956,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const R* own = lds + lbase<NF, C>(part * tile + li, 1);
         const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile, hn, hb);
         const R hn = has ? R(1) : R(0);
-        const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip_bytes, a.bcoef, a.cdt, a.dt, false);
+        const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip ? a.nblk : 0u, b0, 8u * NF * 64u * RS, a.bcoef,
+                                a.cdt, a.dt, false);
         const R cs = R(es.c_out), bs = R(a.bcoef);
 #pragma unroll
         for (int m = 0; m < NF; ++m) {
@@ -959,8 +989,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j, with the
   // amplitudes g(t) of the stage's time evaluated just before the launch
   if (a.has_src && role == 0) {
-    const Rsrc rS = make_rsrc(a.srcid, a.nbr_bytes / 4);
-    int d = bldi(rS, blk_base(el, 1, 4), 0);
+    const Rsrc rS = win_rsrc(a.srcid, a.nblk, b0, 64u * 4u);
+    int d = bldi(rS, blk_rel(el, b0, 1, 4), 0);
     if (d >= 0) {
       const R* __restrict__ src = reinterpret_cast<const R*>(a.src);
       for (; d >= 0; d = a.srcnext[d]) {
@@ -1000,13 +1030,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // rows of this part: row(c, q) = c*N + part*NQ + q, skipped past N
   // 11. PML auxiliaries
   if constexpr (PML) {
+    // damped elements are numbered from pml_base in the auxiliary arrays,
+    // where the partition's tiles start at multiples of the tile
     const uint32_t pk = (uint32_t)((int64_t)el - a.pml_base);
-    const Rsrc rP = make_rsrc(a.pml, a.pml_bytes);
-    const uint32_t vp = blk_base(pk, NPML, RS);
-    const Rsrc raU = make_rsrc(a.aUin, a.aux_bytes);
-    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.aux_bytes, a.bcoef, a.cdt, a.dt, false);
+    const uint32_t pb0 = (uint32_t)((int64_t)start - a.pml_base) >> 6;
+    const Rsrc rP = win_rsrc(a.pml, a.pnblk, pb0, NPML * 64u * RS);
+    const uint32_t vp = blk_rel(pk, pb0, NPML, RS);
+    const Rsrc raU = win_rsrc(a.aUin, a.pnblk, pb0, SBLK);
+    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.pnblk, pb0, SBLK, a.bcoef, a.cdt, a.dt, false);
     const R ca = R(ea.c_out);
-    const uint32_t va = blk_base(pk, 2 * R3, RS) + role * rowb<R>(R3);
+    const uint32_t va = blk_rel(pk, pb0, 2 * R3, RS) + role * rowb<R>(R3);
     R AT[9], AiT[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -1023,7 +1056,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     // them: u <- xi q and q <- -c (the eta and w terms are self-adjoint)
     const R ux = a.adj ? -xx : R(1), uy = a.adj ? -xy : R(1), uz = a.adj ? -xz : R(1);
     const R qx = a.adj ? R(-1) : xx, qy = a.adj ? R(-1) : xy, qz = a.adj ? R(-1) : xz;
-    const Rsrc raW = make_rsrc(a.aYw, LF ? a.aux_bytes : 0u);
+    const Rsrc raW = win_rsrc(a.aYw, a.pnblk, pb0, SBLK, LF != 0);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int l = part * NQ + q;
@@ -1187,19 +1220,22 @@ __device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], 
 }
 
 template <typename R, int P>
-__global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t state_bytes, const int32_t* pub,
-                                                      uint32_t pub_bytes, void* H, uint32_t hbuf_bytes, int K,
+__global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nblk, const int32_t* pub,
+                                                      void* H, uint32_t hbuf_bytes, int K,
                                                       int hreg) {
   constexpr int N = Ops<P>::N, R3 = 3 * N;
   constexpr uint32_t RS = sizeof(R);
   const int gid = blockIdx.x * 256 + threadIdx.x;
   const int el = gid >> 1, fld = gid & 1;
   if (el >= K) return;
-  const Rsrc rU = make_rsrc(U, state_bytes), rP = make_rsrc(pub, pub_bytes), rH = make_rsrc(H, hbuf_bytes);
-  const uint32_t vo = blk_base((uint32_t)el, 2 * R3, RS) + (uint32_t)fld * rowb<R>(R3);
+  // the 32 elements of a wave lie in one 64-element block: windows at it
+  const uint32_t b0 = (uint32_t)((blockIdx.x * 256 + (threadIdx.x & ~63u)) >> 1) >> 6;
+  const Rsrc rU = win_rsrc(U, nblk, b0, 2u * R3 * 64u * RS), rP = win_rsrc(pub, nblk, b0, 4u * 64u * 4u);
+  const Rsrc rH = make_rsrc(H, hbuf_bytes);
+  const uint32_t vo = blk_rel((uint32_t)el, b0, 2 * R3, RS) + (uint32_t)fld * rowb<R>(R3);
   int code[4];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) code[f] = bldi(rP, blk_base((uint32_t)el, 4, 4), (uint32_t)f * 256u);
+  for (int f = 0; f < 4; ++f) code[f] = bldi(rP, blk_rel((uint32_t)el, b0, 4, 4), (uint32_t)f * 256u);
   if (code[0] < 0 && code[1] < 0 && code[2] < 0 && code[3] < 0) return;
   R w[3][N];
 #pragma unroll
@@ -1429,10 +1465,10 @@ void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, d
 }
 
 template <typename R, int P>
-void launch_publish_rp(const void* U, uint32_t sb, const int32_t* pub, uint32_t pb, void* H, uint32_t hb, int K,
-                       int hreg, hipStream_t st) {
+void launch_publish_rp(const void* U, uint32_t nblk, const int32_t* pub, void* H, uint32_t hb, int K, int hreg,
+                       hipStream_t st) {
   const dim3 grid((unsigned)((2 * (int64_t)K + 255) / 256));
-  hipLaunchKernelGGL((publish_kernel<R, P>), grid, dim3(256), 0, st, U, sb, pub, pb, H, hb, K, hreg);
+  hipLaunchKernelGGL((publish_kernel<R, P>), grid, dim3(256), 0, st, U, nblk, pub, H, hb, K, hreg);
   hip_check(hipGetLastError(), "publish_kernel launch");
 }
 

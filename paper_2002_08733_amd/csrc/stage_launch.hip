@@ -82,13 +82,10 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.srcamp = reinterpret_cast<const double*>(base + s.L.srcamp);
   a.has_src = (sp.sources && !s.dips.empty()) ? 1 : 0;
   const size_t rs = s.real_size();
-  a.state_bytes = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
-  a.aux_bytes = (uint32_t)(size_t(6) * s.N * s.Kppad * rs);
-  a.geo_bytes = (uint32_t)(size_t(NGEO) * s.Kpad * rs);
-  a.nbr_bytes = (uint32_t)(size_t(4) * s.Kpad * 4);
-  a.pml_bytes = (uint32_t)(size_t(NPML) * s.Kppad * rs);
+  a.nblk = (uint32_t)(s.Kpad / 64);
+  a.pnblk = (uint32_t)(s.Kppad / 64);
   a.hbuf_bytes = (uint32_t)(size_t(s.hbuf_reals) * rs);
-  a.sip_bytes = s.sip() ? (uint32_t)(size_t(8) * s.NF * s.Kpad * rs) : 0u;
+  a.sip = s.sip() ? 1 : 0;
   if (s.sip() && !(sp.sY && sp.sUin && (sp.stage >= 3 || sp.sUout) && (sp.stage < 0 || sp.stage > 3 || sp.sACC)))
     throw Error(MDG_E_STATE, "SIP launch without its surface buffers");
   a.pml_base = s.K0;
@@ -183,16 +180,15 @@ template <typename R>
 static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_t st) {
   char* base = static_cast<char*>(s.ws);
   const size_t rs = s.real_size();
-  const uint32_t sb = (uint32_t)(size_t(6) * s.N * s.Kpad * rs);
-  const uint32_t pb = (uint32_t)(size_t(4) * s.Kpad * 4);
+  const uint32_t nblk = (uint32_t)(s.Kpad / 64);
   const uint32_t hb = (uint32_t)(size_t(s.hbuf_reals) * rs);
   const int32_t* pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
   const int K = (int)s.K, hreg = (int)s.hreg;
   switch (s.P) {
-    case 1: launch_publish_rp<R, 1>(U, sb, pub, pb, H, hb, K, hreg, st); break;
-    case 2: launch_publish_rp<R, 2>(U, sb, pub, pb, H, hb, K, hreg, st); break;
-    case 3: launch_publish_rp<R, 3>(U, sb, pub, pb, H, hb, K, hreg, st); break;
-    case 4: launch_publish_rp<R, 4>(U, sb, pub, pb, H, hb, K, hreg, st); break;
+    case 1: launch_publish_rp<R, 1>(U, nblk, pub, H, hb, K, hreg, st); break;
+    case 2: launch_publish_rp<R, 2>(U, nblk, pub, H, hb, K, hreg, st); break;
+    case 3: launch_publish_rp<R, 3>(U, nblk, pub, H, hb, K, hreg, st); break;
+    case 4: launch_publish_rp<R, 4>(U, nblk, pub, H, hb, K, hreg, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
 }

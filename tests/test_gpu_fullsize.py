@@ -8,6 +8,9 @@
 * FP32 state after 1000 RK4 steps of the benchmark workload against the FP64
   state of the library: 1e-5 relative in the energy norm (north-star bound;
   the FP64 path itself is oracle-checked in test_gpu_parity.py).
+* A mesh whose FP64 state arrays exceed 4 GiB (order 4, 4,374,000 tets,
+  7.3 GB per state array): the central scheme's energy identity over every
+  element and sampled parity against the oracle.
 * Tile-size independence: interior faces resolved in LDS and faces resolved
   through the published halo traces must give the same numbers.
 * A mesh made only of PML elements (no non-PML launch), and resetting the
@@ -18,7 +21,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_helpers import make_pair, say, unit_jittered
+from tests.gpu_helpers import element_bilinear, make_pair, rel_state_err, say, unit_jittered
 
 pytestmark = pytest.mark.gpu
 
@@ -116,8 +119,11 @@ def test_fullsize_fp32_vs_fp64_1000_steps():
     Wd = s64.energy()
     s64.close()
     err = float(np.sqrt(Wd / W64))
-    say(f"  FP32 vs FP64 rel energy-norm difference {err:.3e} (W = {W64:.6e})")
+    # and from the mesh in numpy, globally and per element
+    err_el = rel_state_err(w.verts, w.tets, w.eps, w.mu, (E32, H32), (E64, H64))
+    say(f"  FP32 vs FP64 rel energy-norm difference {err:.3e} (W = {W64:.6e}); global/per element {err_el:.3e}")
     assert np.isfinite(err) and err < 1e-5
+    assert err_el < 1e-5
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_tile_size_independence(precision):
@@ -193,3 +199,44 @@ def test_state_reset_and_rhs_between_steps():
     b.close()
     say(f"[reset] K={w.nt}: max |a-b| = {max(np.abs(Ea - Eb).max(), np.abs(Ha - Hb).max()):.3e}")
     assert np.array_equal(Ea, Eb) and np.array_equal(Ha, Hb)
+
+
+def test_state_array_beyond_4gib():
+    """FP64 at order 4 on 90^3 jittered Kuhn cubes (4,374,000 tets): a state
+    array holds 6 x 35 x 8 bytes per element, 7.3 GB, so 41% of the elements
+    lie beyond the first 4 GiB of every array. One operator application over
+    the whole mesh (central flux, random state, eps and mu): (i) the
+    semi-discrete energy identity of the central scheme [KS Sec. III],
+    sum_T (eps u.M du + mu f.M df) = 0, checked over all elements against
+    sum_T |...|; (ii) parity with the FP64 oracle on 1024 random elements."""
+    from oracle import OracleDG
+    from paper_2002_08733_amd import Solver
+    n, p = 90, 4
+    verts, tets = W.kuhn_cube_mesh(n, 0.0, 1.0)
+    rng = np.random.default_rng(41)
+    verts = W.jitter_interior(verts, 0.0, 1.0, 1.0 / n, 0.1, rng)
+    K = len(tets)
+    eps = rng.uniform(1.0, 4.0, K)
+    mu = rng.uniform(1.0, 2.0, K)
+    s = Solver(p, "fp64", "central", dt=1e-4)
+    s.set_mesh(verts, tets)
+    s.set_material(eps, mu)
+    N = s.nmodes
+    say(f"[4 GiB] K={K} p={p} fp64 central: state array {6 * N * 8 * K / 1e9:.2f} GB, "
+        f"workspace {s.workspace_size() / 1e9:.1f} GB")
+    assert 6 * N * 8 * K > 4 << 30
+    s.bind_torch_workspace()
+    shp = (K, 3, N)
+    uE, uH = rng.standard_normal(shp), rng.standard_normal(shp)
+    dE, dH = s.rhs(uE, uH, t=0.0)
+    s.close()
+    b = element_bilinear(verts, tets, eps, mu, (uE, uH), (dE, dH))
+    rel = abs(b.sum()) / np.abs(b).sum()
+    say(f"  energy identity over all elements: |sum| / sum|.| = {rel:.3e}")
+    assert rel < 1e-11
+    O = OracleDG(verts, tets, p, eps=eps, mu=mu, flux="central")
+    idx = np.sort(rng.choice(K, size=1024, replace=False))
+    oE, oH, _, _ = O.rhs(O.to_cartesian(uE), O.to_cartesian(uH), elems=idx)
+    err = _sampled_err(O, idx, dE, dH, oE, oH)
+    say(f"  sampled rel err vs oracle {err:.3e}")
+    assert err < 1e-12

@@ -341,10 +341,10 @@ def test_sip_option_and_host_side_errors(lib):
 
 def test_empty_and_oversized_meshes(lib):
     """Edge cases of the decomposition: an empty mesh is refused, and a mesh
-    whose state array would pass 4 GiB (the stage kernel addresses each array
-    with 32-bit buffer offsets) is refused when the setup is finalised, before
-    any device memory is requested: FP64 at order 4 holds 6 x 35 x 8 bytes per
-    element, so 2,633,856 tets (76^3 cubes) need 4.4 GB for one state array."""
+    whose state array passes 4 GiB is accepted (the stage kernel addresses
+    every element array through per-tile windows): FP64 at order 4 holds
+    6 x 35 x 8 bytes per element, so 2,633,856 tets (76^3 cubes) need 4.4 GB
+    for one state array."""
     s = lib.Solver(2, dt=1e-3)
     v, t = W.kuhn_cube_mesh(1, 0.0, 1.0)
     with pytest.raises(lib.MdgError) as e:
@@ -354,9 +354,7 @@ def test_empty_and_oversized_meshes(lib):
     v, t = W.kuhn_cube_mesh(76, 0.0, 1.0)
     s = lib.Solver(4, "fp64", dt=1e-3)
     s.set_mesh(v, t)
-    with pytest.raises(lib.MdgError) as e:
-        s.workspace_size()
-    assert e.value.status == lib.MDG_E_UNSUPPORTED and "4 GiB" in str(e.value)
+    assert s.workspace_size() > 4 * (4 << 30)
     s.close()
     # the same mesh in FP32 at order 3 (2.1 GB per state array) is accepted
     s = lib.Solver(3, "fp32", dt=1e-3)
