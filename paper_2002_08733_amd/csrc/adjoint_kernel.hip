@@ -1,7 +1,7 @@
 // adjoint_kernel.hip -- device kernels of the discrete adjoint of the RK4
-// trajectory (probe-energy objective, gradient w.r.t. per-element eps):
-// state-vector combinations, the probe energy and its derivative, and the
-// per-element gradient accumulation. The operator applications themselves are
+// trajectory (probe-energy objective, gradient w.r.t. per-element eps): the
+// probe energy and its derivative, and the per-element gradient
+// accumulation. The forward stage values and the adjoint steps themselves are
 // stage-kernel launches (stage_kernel.hip).
 //
 // All state vectors use the blocked layout of the stage kernel:
@@ -15,20 +15,6 @@
 #include "solver.hpp"
 
 namespace mdg {
-
-// z = a x + b y + c w (x, y, w may be null: then their coefficient is unused)
-template <typename R>
-__global__ __launch_bounds__(256) void comb3_kernel(R* __restrict__ z, double a, const R* __restrict__ x, double b,
-                                                    const R* __restrict__ y, double c, const R* __restrict__ w,
-                                                    int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double v = 0.0;
-  if (x) v += a * (double)x[i];
-  if (y) v += b * (double)y[i];
-  if (w) v += c * (double)w[i];
-  z[i] = (R)v;
-}
 
 // M0 of element k from its geometry record
 template <typename R>
@@ -106,7 +92,7 @@ template <typename R, int N>
 __global__ __launch_bounds__(256) void grad_pml_kernel(double* __restrict__ g, const R* __restrict__ a,
                                                        const R* __restrict__ x, const R* __restrict__ xa,
                                                        const R* __restrict__ geo, const R* __restrict__ pml,
-                                                       int64_t K0, int64_t Kp) {
+                                                       int64_t K0, int64_t Kp, double scale) {
   const int64_t pk = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (pk >= Kp) return;
   const int64_t k = K0 + pk;
@@ -135,38 +121,24 @@ __global__ __launch_bounds__(256) void grad_pml_kernel(double* __restrict__ g, c
     s += v[0] * (m[0] * z[0] + m[1] * z[1] + m[2] * z[2]) + v[1] * (m[1] * z[0] + m[3] * z[1] + m[4] * z[2]) +
          v[2] * (m[2] * z[0] + m[4] * z[1] + m[5] * z[2]);
   }
-  g[k] -= s;
+  g[k] -= scale * s;
 }
 
 // g_T -= (a, K)_{M0, E, T} for every element
 template <typename R, int N>
 __global__ __launch_bounds__(256) void grad_acc_kernel(double* __restrict__ g, const R* __restrict__ a,
-                                                       const R* __restrict__ K, const R* __restrict__ geo, int64_t nk) {
+                                                       const R* __restrict__ K, const R* __restrict__ geo, int64_t nk,
+                                                       double scale) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= nk) return;
   double m[6];
   mass0(geo, k, m);
-  g[k] -= e_dot<R, N>(a, K, m, k);
+  g[k] -= scale * e_dot<R, N>(a, K, m, k);
 }
 
 // ---------------------------------------------------------------- launch
 static void check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
-                  const void* w, void* stream, int kind) {
-  const int64_t n = kind == 2 ? int64_t(8) * s.NF * s.Kpad : int64_t(6) * s.N * (kind == 1 ? s.Kppad : s.Kpad);
-  if (n == 0) return;
-  const dim3 grid((unsigned)((n + 255) / 256));
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (s.opt.precision == MDG_FP32)
-    hipLaunchKernelGGL(comb3_kernel<float>, grid, dim3(256), 0, st, (float*)z, a, (const float*)x, b,
-                       (const float*)y, c, (const float*)w, n);
-  else
-    hipLaunchKernelGGL(comb3_kernel<double>, grid, dim3(256), 0, st, (double*)z, a, (const double*)x, b,
-                       (const double*)y, c, (const double*)w, n);
-  check(hipGetLastError(), "comb3_kernel launch");
 }
 
 #define MDG_BY_ORDER(R, KERNEL, ...)                                                  \
@@ -207,20 +179,21 @@ void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* p
   check(hipGetLastError(), "probe_add_kernel launch");
 }
 
-void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, void* stream) {
+void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, double scale, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void* geo = static_cast<char*>(s.ws) + s.L.geo;
   const dim3 grid((unsigned)((s.K + 255) / 256));
   if (s.opt.precision == MDG_FP32) {
     MDG_BY_ORDER(float, grad_acc_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)K,
-                 (const float*)geo, s.K)
+                 (const float*)geo, s.K, scale)
   } else {
     MDG_BY_ORDER(double, grad_acc_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)K,
-                 (const double*)geo, s.K)
+                 (const double*)geo, s.K, scale)
   }
   check(hipGetLastError(), "grad_acc_kernel launch");
 }
-void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, void* stream) {
+void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, double scale,
+                     void* stream) {
   if (s.Kp == 0) return;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void* geo = static_cast<char*>(s.ws) + s.L.geo;
@@ -228,10 +201,10 @@ void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, c
   const dim3 grid((unsigned)((s.Kp + 255) / 256));
   if (s.opt.precision == MDG_FP32) {
     MDG_BY_ORDER(float, grad_pml_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)x,
-                 (const float*)xa, (const float*)geo, (const float*)pml, s.K0, s.Kp)
+                 (const float*)xa, (const float*)geo, (const float*)pml, s.K0, s.Kp, scale)
   } else {
     MDG_BY_ORDER(double, grad_pml_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)x,
-                 (const double*)xa, (const double*)geo, (const double*)pml, s.K0, s.Kp)
+                 (const double*)xa, (const double*)geo, (const double*)pml, s.K0, s.Kp, scale)
   }
   check(hipGetLastError(), "grad_pml_kernel launch");
 }

@@ -160,41 +160,6 @@ struct DevBufs {
   }
 };
 
-// Kout = L U (operator without the RK update), or with adj the adjoint
-// operator in the mass inner product, at the time t0 + cstage dt of the
-// mdg_rhs clock; PML auxiliaries are read from aU and written to aK (the
-// stage scratch pair when null); the input's halo traces are published into
-// H1 first
-void apply_operator(Solver& s, const void* U, void* Kout, double cstage, bool sources, void* stream,
-                    const void* aU = nullptr, void* aK = nullptr, bool adj = false, const void* sU = nullptr,
-                    void* sK = nullptr) {
-  const DevLayout& L = s.L;
-  launch_publish(s, U, dev(s, L.H1), stream);
-  StageParams sp{};
-  sp.stage = -1;
-  sp.dt = s.dt;
-  sp.cstage = cstage;
-  sp.clock = reinterpret_cast<const double*>(dev(s, L.rhs_clock));
-  sp.sources = sources;
-  sp.adj = adj;
-  sp.Y = dev(s, L.Y);
-  sp.Uin = U;
-  sp.Uout = Kout;
-  sp.ACC = dev(s, L.ACC);
-  sp.aY = dev(s, L.aY);
-  sp.aUin = aU ? aU : dev(s, L.aUa);
-  sp.aUout = aK ? aK : dev(s, L.aUb);
-  sp.aACC = dev(s, L.aACC);
-  sp.sY = dev(s, L.sY);
-  sp.sUin = sU ? sU : dev(s, L.sUa);
-  sp.sUout = sK ? sK : dev(s, L.sUb);
-  sp.sACC = dev(s, L.sACC);
-  sp.hin = dev(s, L.H1);
-  sp.hout = nullptr;
-  sp.publish = false;
-  launch_stage(s, sp, stream);
-}
-
 void drop_graph(Solver& s) {
   if (s.graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(s.graph_exec));
   if (s.graph) (void)hipGraphDestroy(static_cast<hipGraph_t>(s.graph));
@@ -237,6 +202,69 @@ void enqueue_leapfrog_steps(Solver& s, int64_t nsteps, void* stream) {
   }
 }
 
+// the arrays of one RK4 stepping: base Y, stage inputs Ua/Ub, accumulator
+// ACC, for the fields (E, H), the PML auxiliaries and the SIP unknown
+struct RKBufs {
+  void *Y, *Ua, *Ub, *ACC;
+  void *aY, *aUa, *aUb, *aACC;
+  void *sY, *sUa, *sUb, *sACC;
+};
+
+RKBufs solver_bufs(const Solver& s) {
+  const DevLayout& L = s.L;
+  return RKBufs{dev(s, L.Y),  dev(s, L.Ua),  dev(s, L.Ub),  dev(s, L.ACC), dev(s, L.aY),  dev(s, L.aUa),
+                dev(s, L.aUb), dev(s, L.aACC), dev(s, L.sY), dev(s, L.sUa), dev(s, L.sUb), dev(s, L.sACC)};
+}
+
+static const double RK_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+static const double RK_C[4] = {0.0, 0.5, 0.5, 1.0};
+
+// one classic RK4 step of the arrays b, one stage launch each (two with PML
+// elements): stage inputs Y -> Ua -> Ub -> Ua, the final update in place
+// into Y. The halo traces of Y must be in H0 (they are again after the step).
+// adj: the adjoint operator in the mass inner product (no sources); tick:
+// clock advanced by the last launch, or null. before(i, in): called before
+// stage i is enqueued, with the arrays of its input (Y, Ua or Ub).
+template <typename F>
+void enqueue_rk4_step(Solver& s, const RKBufs& b, const double* clock, bool sources, bool adj, double* tick,
+                      void* stream, F&& before) {
+  const DevLayout& L = s.L;
+  for (int i = 0; i < 4; ++i) {
+    StageParams sp{};
+    sp.stage = i;
+    sp.bcoef = RK_B[i];
+    sp.cdt = i < 3 ? RK_C[i + 1] * s.dt : 0.0;
+    sp.dt = s.dt;
+    sp.cstage = RK_C[i];
+    sp.clock = clock;
+    sp.sources = sources;
+    sp.adj = adj;
+    const int in = i == 0 ? 0 : (i == 2 ? 2 : 1);  // Y, Ua, Ub
+    void* const U[3] = {b.Y, b.Ua, b.Ub};
+    void* const aU[3] = {b.aY, b.aUa, b.aUb};
+    void* const sU[3] = {b.sY, b.sUa, b.sUb};
+    before(i, U[in], aU[in], sU[in]);
+    sp.Y = b.Y;
+    sp.Uin = U[in];
+    sp.Uout = i == 1 ? b.Ub : b.Ua;
+    sp.ACC = b.ACC;
+    sp.aY = b.aY;
+    sp.aUin = aU[in];
+    sp.aUout = i == 1 ? b.aUb : b.aUa;
+    sp.aACC = b.aACC;
+    sp.sY = b.sY;
+    sp.sUin = sU[in];
+    sp.sUout = i == 1 ? b.sUb : b.sUa;
+    sp.sACC = b.sACC;
+    // halo traces of the stage input in, of the stage output out
+    sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
+    sp.hout = dev(s, (i & 1) ? L.H0 : L.H1);
+    sp.publish = true;
+    if (i == 3) sp.tick = tick;
+    launch_stage(s, sp, stream);
+  }
+}
+
 // enqueue n steps: RK4 (4 or 8 stage launches each; the last advances the
 // clock) or leap-frog
 void enqueue_steps(Solver& s, int64_t nsteps, void* stream) {
@@ -244,46 +272,10 @@ void enqueue_steps(Solver& s, int64_t nsteps, void* stream) {
     enqueue_leapfrog_steps(s, nsteps, stream);
     return;
   }
-  static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-  static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
-  const DevLayout& L = s.L;
-  for (int64_t n = 0; n < nsteps; ++n) {
-    for (int i = 0; i < 4; ++i) {
-      StageParams sp{};
-      sp.stage = i;
-      sp.bcoef = bw[i];
-      sp.cdt = i < 3 ? cn[i + 1] * s.dt : 0.0;
-      sp.dt = s.dt;
-      sp.cstage = cn[i];
-      sp.clock = reinterpret_cast<const double*>(dev(s, L.clock));
-      // stage inputs: Y -> Ua -> Ub -> Ua, final update in place into Y
-      const size_t in = i == 0 ? L.Y : (i == 2 ? L.Ub : L.Ua);
-      const size_t outb = i == 1 ? L.Ub : L.Ua;
-      const size_t ain = i == 0 ? L.aY : (i == 2 ? L.aUb : L.aUa);
-      const size_t aout = i == 1 ? L.aUb : L.aUa;
-      const size_t sin = i == 0 ? L.sY : (i == 2 ? L.sUb : L.sUa);
-      const size_t sout = i == 1 ? L.sUb : L.sUa;
-      sp.Y = dev(s, L.Y);
-      sp.Uin = dev(s, in);
-      sp.Uout = dev(s, outb);
-      sp.ACC = dev(s, L.ACC);
-      sp.aY = dev(s, L.aY);
-      sp.aUin = dev(s, ain);
-      sp.aUout = dev(s, aout);
-      sp.aACC = dev(s, L.aACC);
-      sp.sY = dev(s, L.sY);
-      sp.sUin = dev(s, sin);
-      sp.sUout = dev(s, sout);
-      sp.sACC = dev(s, L.sACC);
-      // halo traces of the stage input in, of the stage output out; after
-      // the last stage H0 again holds the traces of Y
-      sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
-      sp.hout = dev(s, (i & 1) ? L.H0 : L.H1);
-      sp.publish = true;
-      if (i == 3) sp.tick = reinterpret_cast<double*>(dev(s, L.clock));
-      launch_stage(s, sp, stream);
-    }
-  }
+  const RKBufs b = solver_bufs(s);
+  double* clock = reinterpret_cast<double*>(dev(s, s.L.clock));
+  for (int64_t n = 0; n < nsteps; ++n)
+    enqueue_rk4_step(s, b, clock, true, false, clock, stream, [](int, const void*, const void*, const void*) {});
 }
 
 void publish_if_needed(Solver& s, void* stream) {
@@ -808,28 +800,17 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
       if (pml) hip_check(hipMemcpyAsync(d.q, x.q, SA, hipMemcpyDeviceToDevice, st), "adjoint copy");
       if (sip) hip_check(hipMemcpyAsync(d.s, x.s, SS, hipMemcpyDeviceToDevice, st), "adjoint copy");
     };
-    // z = a x + b y + c w
-    auto comb = [&](SV z, double a, SV x, double b = 0.0, const SV* y = nullptr, double c = 0.0,
-                    const SV* w = nullptr) {
-      launch_comb3(s, z.u, a, x.u, b, y ? y->u : nullptr, c, w ? w->u : nullptr, stream);
-      if (pml) launch_comb3(s, z.q, a, x.q, b, y ? y->q : nullptr, c, w ? w->q : nullptr, stream, 1);
-      if (sip) launch_comb3(s, z.s, a, x.s, b, y ? y->s : nullptr, c, w ? w->s : nullptr, stream, 2);
-    };
-    // with SIP, the adjoint flag negates its couplings too (the block system
-    // is skew in the mass inner product that weights h_s with M_{mu/alpha}),
-    // and eps enters them only through the E mass inverse, so the gradient
-    // terms below need nothing more
-    auto op = [&](SV in, SV out, double cstage, bool sources, bool adj) {
-      apply_operator(s, in.u, out.u, cstage, sources, stream, in.q, out.q, adj, in.s, out.s);
-    };
     const int64_t k = std::min<int64_t>(every, nsteps);
     const int64_t nseg = (nsteps + k - 1) / k;
     std::vector<SV> ck(nseg), seg(k);
     for (auto& q : ck) q = alloc();
     for (auto& q : seg) q = alloc();
-    SV K4s[4];
-    for (auto& q : K4s) q = alloc();
-    const SV X = alloc(), nu = alloc(), a = alloc(), m = alloc(), msum = alloc(), uend = alloc();
+    // forward stage values of one step: X_1 = x (the step's state), X_2..X_4
+    // and K_1..K_4; the adjoint stepping arrays (nu is its base state)
+    SV Xv[4], Kv[4];
+    for (int i = 1; i < 4; ++i) Xv[i] = alloc();
+    for (auto& q : Kv) q = alloc();
+    const SV nu = alloc(), aUa = alloc(), aUb = alloc(), aAcc = alloc(), uend = alloc();
     SV state;
     state.u = dev(s, s.L.Y);
     state.q = pml ? dev(s, s.L.aY) : nullptr;
@@ -842,6 +823,17 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     hip_check(hipMemsetAsync(Jd, 0, 8, st), "J");
     const double dt = s.dt;
     const int64_t nbase = s.nstep;
+    // the time of every step on the device, (t0, n): stage times t0 + (n + c) dt
+    double* clk = static_cast<double*>(B.get(size_t(16) * nsteps));
+    {
+      std::vector<double> c(size_t(2) * nsteps);
+      for (int64_t n = 0; n < nsteps; ++n) {
+        c[2 * n] = s.t0;
+        c[2 * n + 1] = double(nbase + n);
+      }
+      hip_check(hipMemcpyAsync(clk, c.data(), c.size() * 8, hipMemcpyHostToDevice, st), "clocks");
+      hip_check(hipStreamSynchronize(st), "sync");
+    }
     // forward: J and checkpoints u^{j k}
     publish_if_needed(s, stream);
     for (int64_t n = 0; n < nsteps; ++n) {
@@ -851,22 +843,53 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     }
     copy(uend, state);
     // reverse sweep in nu = M^-1 lambda (M: the mass, auxiliaries weighted
-    // like their field): every adjoint stage is one adjoint operator call
-    // m_i = L* a_i, L* = M^-1 L^T M, which the stage kernel evaluates
-    // directly (skew part negated, PML couplings transposed)
+    // like their field). With a_i the adjoint stage vectors of the RK4 step
+    // and m_i = L* a_i, L* = M^-1 L^T M, the scaled vectors a_i / (b_i dt) are
+    // the stage inputs of one classic RK4 step of L* (with its stages in
+    // reverse order: a_4 / (b_4 dt) = nu, a_3 / (b_3 dt) = nu + dt/2 m_4 / (b_4 dt),
+    // ...), and the update nu + sum_i m_i is that step's result: the adjoint of
+    // a step is one fused RK4 step of the adjoint operator, which the stage
+    // kernel evaluates directly (skew part negated, PML couplings transposed)
     hip_check(hipMemsetAsync(nu.u, 0, SB, st), "nu");
     if (pml) hip_check(hipMemsetAsync(nu.q, 0, SA, st), "nu");
     if (sip) hip_check(hipMemsetAsync(nu.s, 0, SS, st), "nu");
     launch_probe_add(s, nu.u, uend.u, pd, nprobe, dt, stream);
-    // g -= (a_i, K_i)_M0 over the E rows, K_i without its damping part on
-    // PML elements (only the rest scales with 1/eps); X_i is the stage input
-    // with the upwind flux the face impedances depend on eps too: g += (a_i, dA/deps X_i)
-    auto grad = [&](SV ai, SV Ki, SV Xi) {
-      launch_grad_acc(s, g, ai.u, Ki.u, stream);
-      if (pml) launch_grad_pml(s, g, ai.u, Xi.u, Xi.q, stream);
-      if (upw) launch_grad_upw(s, g, ai.u, Xi.u, stream);
+    const DevLayout& L = s.L;
+    // forward stage values of the step from x at clock ck: stage i < 3 is one
+    // launch with the first stage's epilogue and b = 1 (ACC <- K_i, the
+    // output <- X_{i+1} = x + c_{i+1} dt K_i, its halo traces published), K_4
+    // one operator launch
+    auto stage_values = [&](SV x, const double* ckl) {
+      launch_publish(s, x.u, dev(s, L.H0), stream);
+      for (int i = 0; i < 4; ++i) {
+        const SV in = i == 0 ? x : Xv[i];
+        StageParams sp{};
+        sp.stage = i < 3 ? 0 : -1;
+        sp.bcoef = 1.0;
+        sp.cdt = i < 3 ? RK_C[i + 1] * dt : 0.0;
+        sp.dt = dt;
+        sp.cstage = RK_C[i];
+        sp.clock = ckl;
+        sp.sources = true;
+        sp.Y = x.u;
+        sp.Uin = in.u;
+        sp.Uout = i < 3 ? Xv[i + 1].u : Kv[3].u;
+        sp.ACC = Kv[i].u;
+        sp.aY = x.q;
+        sp.aUin = in.q;
+        sp.aUout = i < 3 ? Xv[i + 1].q : Kv[3].q;
+        sp.aACC = Kv[i].q;
+        sp.sY = x.s;
+        sp.sUin = in.s;
+        sp.sUout = i < 3 ? Xv[i + 1].s : Kv[3].s;
+        sp.sACC = Kv[i].s;
+        sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
+        sp.hout = i < 3 ? dev(s, (i & 1) ? L.H0 : L.H1) : nullptr;
+        sp.publish = i < 3;
+        launch_stage(s, sp, stream);
+      }
     };
-    static const double cn[4] = {0.0, 0.5, 0.5, 1.0};
+    const RKBufs ab{nu.u, aUa.u, aUb.u, aAcc.u, nu.q, aUa.q, aUb.q, aAcc.q, nu.s, aUa.s, aUb.s, aAcc.s};
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
       const int64_t n0 = sgi * k, n1 = std::min(nsteps, n0 + k);
       // recompute u^{n0 .. n1-1} from the checkpoint with the stepping path
@@ -882,36 +905,22 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
       }
       for (int64_t n = n1 - 1; n >= n0; --n) {
         const SV x = seg[n - n0];
-        hip_check(hipStreamSynchronize(st), "sync");
-        set_clock(s, s.L.rhs_clock, s.t0, double(nbase + n));
-        // forward stage derivatives K_i = F(X_i) at this step
-        op(x, K4s[0], cn[0], true, false);
-        comb(X, 1.0, x, 0.5 * dt, &K4s[0]);
-        op(X, K4s[1], cn[1], true, false);
-        comb(X, 1.0, x, 0.5 * dt, &K4s[1]);
-        op(X, K4s[2], cn[2], true, false);
-        comb(X, 1.0, x, dt, &K4s[2]);
-        op(X, K4s[3], cn[3], true, false);
-        // adjoint stages (X holds X_4 here; the others are rebuilt for the
-        // PML and upwind parts of the gradient)
-        comb(a, dt / 6.0, nu);  // a4
-        grad(a, K4s[3], X);
-        op(a, m, 0.0, false, true);  // m4
-        comb(msum, 1.0, m);
-        comb(a, dt / 3.0, nu, dt, &m);  // a3
-        if (pml || upw) comb(X, 1.0, x, 0.5 * dt, &K4s[1]);
-        grad(a, K4s[2], X);
-        op(a, m, 0.0, false, true);  // m3
-        comb(msum, 1.0, msum, 1.0, &m);
-        comb(a, dt / 3.0, nu, 0.5 * dt, &m);  // a2
-        if (pml || upw) comb(X, 1.0, x, 0.5 * dt, &K4s[0]);
-        grad(a, K4s[1], X);
-        op(a, m, 0.0, false, true);  // m2
-        comb(msum, 1.0, msum, 1.0, &m);
-        comb(a, dt / 6.0, nu, 0.5 * dt, &m);  // a1
-        grad(a, K4s[0], x);
-        op(a, m, 0.0, false, true);  // m1
-        comb(nu, 1.0, nu, 1.0, &msum, 1.0, &m);
+        stage_values(x, clk + 2 * n);
+        // the adjoint step; before its stage i (input a_{4-i} / (b_{4-i} dt))
+        // the gradient takes g -= (a, K_curl)_M0 over the E rows with the
+        // forward stage 4-i (only the curl part of K scales with 1/eps; PML
+        // elements add the damping part back) and, with the upwind flux,
+        // g += (a, dA/deps X) for the face impedances
+        launch_publish(s, nu.u, dev(s, L.H0), stream);
+        enqueue_rk4_step(s, ab, clk + 2 * n, false, true, nullptr, stream,
+                         [&](int i, const void* in, const void*, const void*) {
+                           const int f = 3 - i;  // forward stage
+                           const double sc = RK_B[f] * dt;
+                           launch_grad_acc(s, g, in, Kv[f].u, sc, stream);
+                           const SV Xf = f == 0 ? x : Xv[f];
+                           if (pml) launch_grad_pml(s, g, in, Xf.u, Xf.q, sc, stream);
+                           if (upw) launch_grad_upw(s, g, in, Xf.u, sc, stream);
+                         });
         if (n >= 1) launch_probe_add(s, nu.u, x.u, pd, nprobe, dt, stream);
       }
     }

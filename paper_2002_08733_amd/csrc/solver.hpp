@@ -207,19 +207,17 @@ void launch_energy(const Solver& s, const void* Y, void* stream);
 void launch_monitor(const Solver& s, bool init, bool growth, double tol, void* stream);
 
 // ---- adjoint_kernel.hip (state vectors in the blocked layout, E and H)
-// z = a x + b y + c w over a state vector (kind 0), a PML auxiliary vector
-// (kind 1) or the SIP unknown (kind 2)
-void launch_comb3(const Solver& s, void* z, double a, const void* x, double b, const void* y, double c,
-                  const void* w, void* stream, int kind = 0);
 void launch_probe_energy(const Solver& s, const void* u, const int64_t* probes, int np, double dt, double* J,
                          void* stream);  // J += dt sum_probes (e, e)_M0
 void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* probes, int np, double dt,
                       void* stream);  // nu_E += 2 dt / eps u_E on probes
-void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, void* stream);  // g -= (a, K)_M0,E
-// PML elements: g -= (a, A^T (eta A^-T x_E + xa_E))_M0,E for stage input (x, xa)
-void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, void* stream);
-// upwind flux: g += (a, dA/deps x), the impedance dependence of the face terms
-// (stage_kernel.hip, where the face operators live)
-void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, void* stream);
+// g -= scale (a, K)_M0,E
+void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, double scale, void* stream);
+// PML elements: g -= scale (a, A^T (eta A^-T x_E + xa_E))_M0,E for stage input (x, xa)
+void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, double scale,
+                     void* stream);
+// upwind flux: g += scale (a, dA/deps x), the impedance dependence of the face
+// terms (stage_kernel.hip, where the face operators live)
+void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, double scale, void* stream);
 
 }  // namespace mdg

@@ -67,7 +67,7 @@ void launch_publish_rp(const void* U, uint32_t nblk, const int32_t* pub, void* H
                        hipStream_t st);
 template <typename R, int P>
 void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* geo, const int32_t* nbrg, int64_t K,
-                        hipStream_t st);
+                        double scale, hipStream_t st);
 
 // every (precision, order) pair the library is built for
 #define MDG_FOR_EACH_RP(X) X(float, 1) X(float, 2) X(float, 3) X(float, 4) X(double, 1) X(double, 2) X(double, 3) X(double, 4)

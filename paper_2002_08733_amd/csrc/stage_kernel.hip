@@ -14,5 +14,5 @@ template void launch_energy_rp<MDG_R, MDG_P>(const void*, const void*, int64_t, 
 template void launch_publish_rp<MDG_R, MDG_P>(const void*, uint32_t, const int32_t*, void*, uint32_t, int, int,
                                                hipStream_t);
 template void launch_grad_upw_rp<MDG_R, MDG_P>(double*, const void*, const void*, const void*, const int32_t*,
-                                                int64_t, hipStream_t);
+                                                int64_t, double, hipStream_t);
 }  // namespace mdg

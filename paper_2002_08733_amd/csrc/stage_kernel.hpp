@@ -1322,7 +1322,7 @@ __device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, con
 template <typename R, int P>
 __global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout, const R* __restrict__ a,
                                                       const R* __restrict__ x, const R* __restrict__ geo,
-                                                      const int32_t* __restrict__ nbrg, int64_t K) {
+                                                      const int32_t* __restrict__ nbrg, int64_t K, double scale) {
   const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (k >= K) return;
   const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
@@ -1354,7 +1354,7 @@ __global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout,
       }
     }
   }
-  gout[k] += -0.5 * Z / eps * sum;  // dZ/deps = -Z / (2 eps)
+  gout[k] += scale * (-0.5 * Z / eps * sum);  // dZ/deps = -Z / (2 eps)
 }
 
 // ---------------------------------------------------------------- launch
@@ -1474,10 +1474,10 @@ void launch_publish_rp(const void* U, uint32_t nblk, const int32_t* pub, void* H
 
 template <typename R, int P>
 void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* geo, const int32_t* nbrg, int64_t K,
-                        hipStream_t st) {
+                        double scale, hipStream_t st) {
   const dim3 grid((unsigned)((K + 63) / 64));
   hipLaunchKernelGGL((grad_upw_kernel<R, P>), grid, dim3(64), 0, st, g, static_cast<const R*>(a),
-                     static_cast<const R*>(x), static_cast<const R*>(geo), nbrg, K);
+                     static_cast<const R*>(x), static_cast<const R*>(geo), nbrg, K, scale);
   hip_check(hipGetLastError(), "grad_upw_kernel launch");
 }
 

@@ -200,12 +200,12 @@ void launch_publish(const Solver& s, const void* U, void* H, void* stream) {
   else launch_publish_r<double>(s, U, H, st);
 }
 
-void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, void* stream) {
+void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, double scale, void* stream) {
   char* base = static_cast<char*>(s.ws);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int32_t* nb = reinterpret_cast<const int32_t*>(base + s.L.nbrg);
   const void* geo = base + s.L.geo;
-#define MDG_UPW(R, P) launch_grad_upw_rp<R, P>(g, a, x, geo, nb, s.K, st)
+#define MDG_UPW(R, P) launch_grad_upw_rp<R, P>(g, a, x, geo, nb, s.K, scale, st)
   const bool fp32 = s.opt.precision == MDG_FP32;
   switch (s.P) {
     case 1: if (fp32) MDG_UPW(float, 1); else MDG_UPW(double, 1); break;
