@@ -35,9 +35,9 @@ __device__ __forceinline__ void mass0(const R* __restrict__ geo, int64_t k, doub
 // (u, v)_{M0, E, T} = sum_l u_l^T M0_T v_l over the E rows of element k
 template <typename R, int N>
 __device__ __forceinline__ double e_dot(const R* __restrict__ u, const R* __restrict__ v, const double (&m)[6],
-                                        int64_t k) {
-  const R* uk = u + (k >> 6) * 6 * N * 64 + (k & 63);
-  const R* vk = v + (k >> 6) * 6 * N * 64 + (k & 63);
+                                        int64_t k, int64_t rb) {
+  const R* uk = u + (k >> 6) * rb * 64 + (k & 63);
+  const R* vk = v + (k >> 6) * rb * 64 + (k & 63);
   double s = 0.0;
   for (int l = 0; l < N; ++l) {
     const double ux = uk[(0 * N + l) * 64], uy = uk[(1 * N + l) * 64], uz = uk[(2 * N + l) * 64];
@@ -52,13 +52,13 @@ __device__ __forceinline__ double e_dot(const R* __restrict__ u, const R* __rest
 template <typename R, int N>
 __global__ __launch_bounds__(256) void probe_energy_kernel(const R* __restrict__ u, const R* __restrict__ geo,
                                                            const int64_t* __restrict__ probes, int np, double dt,
-                                                           double* __restrict__ J) {
+                                                           double* __restrict__ J, int64_t rb) {
   __shared__ double red[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += 256) {
     double m[6];
     mass0(geo, probes[i], m);
-    s += e_dot<R, N>(u, u, m, probes[i]);
+    s += e_dot<R, N>(u, u, m, probes[i], rb);
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -74,13 +74,13 @@ __global__ __launch_bounds__(256) void probe_energy_kernel(const R* __restrict__
 template <typename R, int N>
 __global__ __launch_bounds__(256) void probe_add_kernel(R* __restrict__ nu, const R* __restrict__ u,
                                                         const R* __restrict__ geo, const int64_t* __restrict__ probes,
-                                                        int np, double dt) {
+                                                        int np, double dt, int64_t rb) {
   const int i = blockIdx.x;
   if (i >= np) return;
   const int64_t k = probes[i];
   const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
   const double f = 2.0 * dt * (double)gk[G_IEPS * 64];
-  const int64_t base = (k >> 6) * 6 * N * 64 + (k & 63);
+  const int64_t base = (k >> 6) * rb * 64 + (k & 63);
   for (int r = threadIdx.x; r < 3 * N; r += 256) nu[base + r * 64] = (R)((double)nu[base + r * 64] + f * (double)u[base + r * 64]);
 }
 
@@ -92,7 +92,7 @@ template <typename R, int N>
 __global__ __launch_bounds__(256) void grad_pml_kernel(double* __restrict__ g, const R* __restrict__ a,
                                                        const R* __restrict__ x, const R* __restrict__ xa,
                                                        const R* __restrict__ geo, const R* __restrict__ pml,
-                                                       int64_t K0, int64_t Kp, double scale) {
+                                                       int64_t K0, int64_t Kp, double scale, int64_t rb) {
   const int64_t pk = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (pk >= Kp) return;
   const int64_t k = K0 + pk;
@@ -106,9 +106,9 @@ __global__ __launch_bounds__(256) void grad_pml_kernel(double* __restrict__ g, c
   }
   const double wx = pr[(PM_OM + 0) * 64], wy = pr[(PM_OM + 1) * 64], wz = pr[(PM_OM + 2) * 64];
   const double eta[3] = {wy + wz - wx, wz + wx - wy, wx + wy - wz};
-  const R* xk = x + (k >> 6) * 6 * N * 64 + (k & 63);
-  const R* qk = xa + (pk >> 6) * 6 * N * 64 + (pk & 63);
-  const R* ak = a + (k >> 6) * 6 * N * 64 + (k & 63);
+  const R* xk = x + (k >> 6) * rb * 64 + (k & 63);
+  const R* qk = xa + (pk >> 6) * rb * 64 + (pk & 63);
+  const R* ak = a + (k >> 6) * rb * 64 + (k & 63);
   double s = 0.0;
   for (int l = 0; l < N; ++l) {
     double u[3], y[3], z[3], v[3];
@@ -128,12 +128,12 @@ __global__ __launch_bounds__(256) void grad_pml_kernel(double* __restrict__ g, c
 template <typename R, int N>
 __global__ __launch_bounds__(256) void grad_acc_kernel(double* __restrict__ g, const R* __restrict__ a,
                                                        const R* __restrict__ K, const R* __restrict__ geo, int64_t nk,
-                                                       double scale) {
+                                                       double scale, int64_t rb) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= nk) return;
   double m[6];
   mass0(geo, k, m);
-  g[k] -= scale * e_dot<R, N>(a, K, m, k);
+  g[k] -= scale * e_dot<R, N>(a, K, m, k, rb);
 }
 
 // ---------------------------------------------------------------- launch
@@ -154,12 +154,13 @@ void launch_probe_energy(const Solver& s, const void* u, const int64_t* probes, 
                          void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void* geo = static_cast<char*>(s.ws) + s.L.geo;
+  const int64_t rb = state_rows(s);
   if (s.opt.precision == MDG_FP32) {
     MDG_BY_ORDER(float, probe_energy_kernel, dim3(1), dim3(256), 0, st, (const float*)u, (const float*)geo, probes,
-                 np, dt, J)
+                 np, dt, J, rb)
   } else {
     MDG_BY_ORDER(double, probe_energy_kernel, dim3(1), dim3(256), 0, st, (const double*)u, (const double*)geo,
-                 probes, np, dt, J)
+                 probes, np, dt, J, rb)
   }
   check(hipGetLastError(), "probe_energy_kernel launch");
 }
@@ -169,12 +170,13 @@ void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* p
   if (np == 0) return;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void* geo = static_cast<char*>(s.ws) + s.L.geo;
+  const int64_t rb = state_rows(s);
   if (s.opt.precision == MDG_FP32) {
     MDG_BY_ORDER(float, probe_add_kernel, dim3(np), dim3(256), 0, st, (float*)nu, (const float*)u, (const float*)geo,
-                 probes, np, dt)
+                 probes, np, dt, rb)
   } else {
     MDG_BY_ORDER(double, probe_add_kernel, dim3(np), dim3(256), 0, st, (double*)nu, (const double*)u,
-                 (const double*)geo, probes, np, dt)
+                 (const double*)geo, probes, np, dt, rb)
   }
   check(hipGetLastError(), "probe_add_kernel launch");
 }
@@ -183,12 +185,13 @@ void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, d
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void* geo = static_cast<char*>(s.ws) + s.L.geo;
   const dim3 grid((unsigned)((s.K + 255) / 256));
+  const int64_t rb = state_rows(s);
   if (s.opt.precision == MDG_FP32) {
     MDG_BY_ORDER(float, grad_acc_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)K,
-                 (const float*)geo, s.K, scale)
+                 (const float*)geo, s.K, scale, rb)
   } else {
     MDG_BY_ORDER(double, grad_acc_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)K,
-                 (const double*)geo, s.K, scale)
+                 (const double*)geo, s.K, scale, rb)
   }
   check(hipGetLastError(), "grad_acc_kernel launch");
 }
@@ -199,12 +202,13 @@ void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, c
   const void* geo = static_cast<char*>(s.ws) + s.L.geo;
   const void* pml = static_cast<char*>(s.ws) + s.L.pml;
   const dim3 grid((unsigned)((s.Kp + 255) / 256));
+  const int64_t rb = state_rows(s);
   if (s.opt.precision == MDG_FP32) {
     MDG_BY_ORDER(float, grad_pml_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)x,
-                 (const float*)xa, (const float*)geo, (const float*)pml, s.K0, s.Kp, scale)
+                 (const float*)xa, (const float*)geo, (const float*)pml, s.K0, s.Kp, scale, rb)
   } else {
     MDG_BY_ORDER(double, grad_pml_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)x,
-                 (const double*)xa, (const double*)geo, (const double*)pml, s.K0, s.Kp, scale)
+                 (const double*)xa, (const double*)geo, (const double*)pml, s.K0, s.Kp, scale, rb)
   }
   check(hipGetLastError(), "grad_pml_kernel launch");
 }

@@ -111,12 +111,12 @@ void read_state(Solver& s, double* E, double* H, double* P, double* Q, size_t of
   hip_check(hipDeviceSynchronize(), "synchronize");
   std::vector<double> buf;
   if (E || H) {
-    download(s, off, size_t(6) * s.N * s.Kpad, buf);
+    download(s, off, size_t(state_rows(s)) * s.Kpad, buf);
     unpack_state(s, buf, E, H);
   }
   if (P || Q) {
     if (s.Kp > 0) {
-      download(s, aoff, size_t(6) * s.N * s.Kppad, buf);
+      download(s, aoff, size_t(state_rows(s)) * s.Kppad, buf);
       unpack_aux(s, buf, P, Q);
     } else {
       if (P) std::memset(P, 0, size_t(s.nt) * 3 * s.N * sizeof(double));
@@ -778,8 +778,8 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     // a state vector: fields (blocked layout), with PML elements the
     // auxiliaries of the PML elements, with SIP the surface unknown
     const bool pml = s.Kp > 0, upw = s.opt.flux == MDG_UPWIND, sip = s.sip();
-    const size_t SB = size_t(6) * s.N * s.Kpad * s.real_size();
-    const size_t SA = pml ? size_t(6) * s.N * s.Kppad * s.real_size() : 0;
+    const size_t SB = size_t(state_rows(s)) * s.Kpad * s.real_size();
+    const size_t SA = pml ? size_t(state_rows(s)) * s.Kppad * s.real_size() : 0;
     const size_t SS = sip ? size_t(8) * s.NF * s.Kpad * s.real_size() : 0;
     struct SV {
       void* u = nullptr;

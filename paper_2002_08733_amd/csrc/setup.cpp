@@ -503,8 +503,8 @@ void finalize(Solver& s) {
   // device layout
   DevLayout& L = s.L;
   size_t off = 0;
-  const size_t field = size_t(6) * s.N * s.Kpad * rs;
-  const size_t afield = s.Kp > 0 ? size_t(6) * s.N * s.Kppad * rs : 0;
+  const size_t field = size_t(state_rows(s)) * s.Kpad * rs;
+  const size_t afield = s.Kp > 0 ? size_t(state_rows(s)) * s.Kppad * rs : 0;
   L.Y = off; off = align256(off + field);
   L.Ua = off; off = align256(off + field);
   L.Ub = off; off = align256(off + field);
@@ -612,31 +612,30 @@ void project_fields(const Solver& s, int q, const double* vals, int N, std::vect
   }
 }
 
-// host arrays: E [nt][3][N], H [nt][3][NH]; device rows c*N + l per field,
-// the rows l >= NH of h zero
+// host arrays: E [nt][3][N], H [nt][3][NH]; device rows state_row
 void pack_state(const Solver& s, const double* E, const double* H, std::vector<double>& out) {
-  const int N = s.N, NH = s.NH, R3 = 3 * N;
-  out.assign(size_t(6) * N * s.Kpad, 0.0);
+  const int N = s.N, NH = s.NH, RB = state_rows(s);
+  out.assign(size_t(RB) * s.Kpad, 0.0);
   for (int64_t k = 0; k < s.K; ++k) {
     const int64_t u = s.perm[k];
     for (int c = 0; c < 3; ++c) {
       if (E)
-        for (int l = 0; l < N; ++l) out[blk_index(k, c * N + l, 2 * R3)] = E[(u * 3 + c) * N + l];
+        for (int l = 0; l < N; ++l) out[blk_index(k, state_row(s, 0, c, l), RB)] = E[(u * 3 + c) * N + l];
       if (H)
-        for (int l = 0; l < NH; ++l) out[blk_index(k, R3 + c * N + l, 2 * R3)] = H[(u * 3 + c) * NH + l];
+        for (int l = 0; l < NH; ++l) out[blk_index(k, state_row(s, 1, c, l), RB)] = H[(u * 3 + c) * NH + l];
     }
   }
 }
 
 void unpack_state(const Solver& s, const std::vector<double>& in, double* E, double* H) {
-  const int N = s.N, NH = s.NH, R3 = 3 * N;
+  const int N = s.N, NH = s.NH, RB = state_rows(s);
   for (int64_t k = 0; k < s.K; ++k) {
     const int64_t u = s.perm[k];
     for (int c = 0; c < 3; ++c) {
       if (E)
-        for (int l = 0; l < N; ++l) E[(u * 3 + c) * N + l] = in[blk_index(k, c * N + l, 2 * R3)];
+        for (int l = 0; l < N; ++l) E[(u * 3 + c) * N + l] = in[blk_index(k, state_row(s, 0, c, l), RB)];
       if (H)
-        for (int l = 0; l < NH; ++l) H[(u * 3 + c) * NH + l] = in[blk_index(k, R3 + c * N + l, 2 * R3)];
+        for (int l = 0; l < NH; ++l) H[(u * 3 + c) * NH + l] = in[blk_index(k, state_row(s, 1, c, l), RB)];
     }
   }
 }
@@ -644,8 +643,8 @@ void unpack_state(const Solver& s, const std::vector<double>& in, double* E, dou
 void pack_aux(const Solver& s, const double* P, const double* Q, std::vector<double>& out) {
   // internal auxiliary = A^-T P / eps (Cartesian, scaled): the PML terms then
   // need no material factor inside the kernel
-  const int N = s.N, R3 = 3 * N;
-  out.assign(size_t(6) * N * s.Kppad, 0.0);
+  const int N = s.N, RB = state_rows(s);
+  out.assign(size_t(RB) * s.Kppad, 0.0);
   for (int which = 0; which < 2; ++which) {
     const double* in = which == 0 ? P : Q;
     if (!in) continue;
@@ -658,14 +657,14 @@ void pack_aux(const Solver& s, const double* P, const double* Q, std::vector<dou
         for (int j = 0; j < 3; ++j) {
           double v = 0;
           for (int i = 0; i < 3; ++i) v += Ai[3 * i + j] * in[(u * 3 + i) * Nw + l];
-          out[blk_index(pk, which * R3 + j * N + l, 2 * R3)] = v / m;
+          out[blk_index(pk, state_row(s, which, j, l), RB)] = v / m;
         }
     }
   }
 }
 
 void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, double* Q) {
-  const int N = s.N, R3 = 3 * N;
+  const int N = s.N, RB = state_rows(s);
   for (int which = 0; which < 2; ++which) {
     double* out = which == 0 ? P : Q;
     if (!out) continue;
@@ -678,7 +677,7 @@ void unpack_aux(const Solver& s, const std::vector<double>& in, double* P, doubl
       for (int l = 0; l < Nw; ++l)
         for (int j = 0; j < 3; ++j) {
           double v = 0;
-          for (int i = 0; i < 3; ++i) v += A[3 * i + j] * in[blk_index(pk, which * R3 + i * N + l, 2 * R3)];
+          for (int i = 0; i < 3; ++i) v += A[3 * i + j] * in[blk_index(pk, state_row(s, which, i, l), RB)];
           out[(u * 3 + j) * Nw + l] = v * m;
         }
     }

@@ -48,6 +48,12 @@ struct Dipole {
 // A wave reads one row of 64 elements as one contiguous 256/512-byte segment;
 // the field and the row of an access are small constant offsets.
 constexpr int BLK = 64;
+// Rows of one element in a state or auxiliary block: e (and p) with N modes
+// per component, then h (and q) with NH modes (fewer than N with mixed
+// orders): row c N + l of e, 3N + c NH + l of h.
+struct Solver;
+int state_rows(const Solver& s);
+int state_row(const Solver& s, int field, int c, int l);
 inline size_t blk_index(int64_t e, int row, int rows_per_block) {
   return (size_t(e / BLK) * rows_per_block + row) * BLK + size_t(e % BLK);
 }
@@ -119,6 +125,9 @@ struct Solver {
   size_t real_size() const { return opt.precision == MDG_FP32 ? 4 : 8; }
   bool sip() const { return opt.sip_alpha > 0; }
 };
+
+inline int state_rows(const Solver& s) { return 3 * (s.N + s.NH); }
+inline int state_row(const Solver& s, int field, int c, int l) { return field == 0 ? c * s.N + l : 3 * s.N + c * s.NH + l; }
 
 // ---- setup.cpp
 void setup_mesh(Solver& s, int64_t nv, const double* xyz, int64_t nt, const int64_t* tet);

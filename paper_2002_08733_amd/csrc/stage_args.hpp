@@ -59,15 +59,15 @@ struct DevArgs {
 
 template <typename R, int P>
 void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, bool persist,
-              hipStream_t st);
+              bool mix, hipStream_t st);
 template <typename R, int P>
-void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, hipStream_t st);
+void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, int nh, hipStream_t st);
 template <typename R, int P>
-void launch_publish_rp(const void* U, uint32_t nblk, const int32_t* pub, void* H, uint32_t hb, int K, int hreg,
-                       hipStream_t st);
+void launch_publish_rp(const void* U, uint32_t nblk, int nh, const int32_t* pub, void* H, uint32_t hb, int K,
+                       int hreg, hipStream_t st);
 template <typename R, int P>
 void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* geo, const int32_t* nbrg, int64_t K,
-                        double scale, hipStream_t st);
+                        double scale, int nh, hipStream_t st);
 
 // every (precision, order) pair the library is built for
 #define MDG_FOR_EACH_RP(X) X(float, 1) X(float, 2) X(float, 3) X(float, 4) X(double, 1) X(double, 2) X(double, 3) X(double, 4)

@@ -656,12 +656,15 @@ constexpr bool persistent_kernel() { return sizeof(R) == 4 && P <= 3; }
 // traces (one copy per element face; both sides compute the same update).
 // MF: the volume term by BF16x3 MFMA products (FP32, RK4 and operator calls,
 // 64-element tiles) instead of the sparse VALU contraction.
-template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false, bool MF = false>
+// MIX: mixed orders (e at order P, h at P-1): the state's h rows (and those
+// of its auxiliary q) hold only the dim P_{P-1} modes of h.
+template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false, bool MF = false, bool MIX = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_eu<R, P>()))) void stage_kernel(
     DevArgs a) {
   static_assert(!(LF && UPW), "leap-frog halves need the central flux");
   static_assert(!(SIP && UPW), "the SIP unknown comes with the central flux");
   static_assert(!MF || (sizeof(R) == 4 && LF == 0 && P <= 3), "MFMA volume: FP32, RK4, orders 1-3");
+  static_assert(!MIX || P >= 2, "mixed orders: e at order 2 or more");
   constexpr bool C = LF == 2;
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF, R3 = 3 * Ops<P>::N, NQ = nq<P>();
   // several tiles per workgroup (FP32, orders 1-3): in a loop the compiler
@@ -670,7 +673,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   constexpr bool PERSIST = persistent_kernel<R, P>();
   constexpr int SS = slot_stride<NF, C>();
   constexpr uint32_t RS = sizeof(R);
-  constexpr uint32_t SBLK = 2u * R3 * 64u * RS;  // bytes of one 64-element block of a state array
+  // modes of h per component in the state; rows of one element block (e
+  // rows c N + l, then h rows 3N + c NHc + l) and bytes of one 64-element block
+  constexpr int NHc = MIX ? Ops<(P > 1 ? P - 1 : 1)>::N : N;
+  constexpr uint32_t RB = 3u * (N + NHc);
+  constexpr uint32_t SBLK = RB * 64u * RS;
+  // an offset past any window: a load there reads 0 (rows of h that the
+  // compact layout does not hold)
+  constexpr uint32_t OOB = 0x40000000u;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
   // Tiles -> workgroups, XCD-major (dispatch places block b on XCD b % 8): the
@@ -735,22 +745,45 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const Rsrc rU = win_rsrc(A.Uin, A.nblk, b0, SBLK);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     lds_byte* dst = (lds_byte*)smem_raw + (uint32_t)SB * RS;
+    // state row of staging row sr ([staged field][3N]); with mixed orders
+    // the staging keeps N modes per component of h, the state only NHc:
+    // the others are zero-filled
+    auto src_row = [&](uint32_t sr, bool& zero) -> uint32_t {
+      const uint32_t f = C ? (uint32_t)fst : sr / R3, r = C ? sr : sr - f * R3;
+      if constexpr (MIX) {
+        const uint32_t cc = r / N, l = r - cc * N;
+        zero = f == 1 && l >= (uint32_t)NHc;
+        return f ? R3 + cc * NHc + l : r;
+      } else {
+        zero = false;
+        return f * R3 + r;
+      }
+    };
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     if (e0 % (uint32_t)tile == 0) {
       // the tile lies in one 64-element block: 16 bytes per lane
-      const uint32_t base = blk_rel(e0, b0, 2 * R3, RS) + (uint32_t)fst * rowb<R>(R3);
+      const uint32_t base = blk_rel(e0, b0, RB, RS);
       for (uint32_t c = wv; c * 1024u < nbytes; c += nwv) {
         const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
-        const uint32_t src = base + (vo >> rsh) * rowb<R>(1) + (vo & ((1u << rsh) - 1u));
-        if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 1024u, 16, src, 0, 0, 0);
+        bool zero;
+        const uint32_t src = base + src_row(vo >> rsh, zero) * rowb<R>(1) + (vo & ((1u << rsh) - 1u));
+        if (vo < nbytes) {
+          if (zero) *reinterpret_cast<u32x4*>(smem_raw + (uint32_t)SB * RS + vo) = u32x4{0u, 0u, 0u, 0u};
+          else __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 1024u, 16, src, 0, 0, 0);
+        }
       }
     } else {
       // a tile of the damped partition that straddles two blocks: 4 bytes
       // per lane, each addressed through its own element
       for (uint32_t c = wv; c * 256u < nbytes; c += nwv) {
         const uint32_t vo = c * 256u + (uint32_t)(tid & 63) * 4u;
-        const uint32_t row = vo >> rsh, w = vo & ((1u << rsh) - 1u);
-        const uint32_t src = blk_rel(e0 + w / RS, b0, 2 * R3, RS) + (uint32_t)(fst * R3 + row) * rowb<R>(1) + w % RS;
-        if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, 0);
+        const uint32_t w = vo & ((1u << rsh) - 1u);
+        bool zero;
+        const uint32_t src = blk_rel(e0 + w / RS, b0, RB, RS) + src_row(vo >> rsh, zero) * rowb<R>(1) + w % RS;
+        if (vo < nbytes) {
+          if (zero) *reinterpret_cast<uint32_t*>(smem_raw + (uint32_t)SB * RS + vo) = 0u;
+          else __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, 0);
+        }
       }
     }
   };
@@ -772,6 +805,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       if (vo < nbytes) __builtin_amdgcn_raw_ptr_buffer_load_lds(rH, dst + c * 1024u, 16, src, (uint32_t)hoff * RS, 0, 0);
     }
   };
+  // Rows of a lane's output field (role r: e or h) and of its auxiliary:
+  // component c, mode l at voffset base + out_v(r, c, l), soffset out_s(c, l).
+  // Equal orders: the soffset carries the whole row (uniform). Mixed orders:
+  // the h rows have their own stride, which depends on the lane's role, so
+  // the row goes into the voffset, and the rows l >= NHc of h are absent
+  // (loads there read 0, stores are dropped).
+  auto out_v = [&](int r, int c, int l) -> uint32_t {
+    if constexpr (MIX)
+      return r ? (l < NHc ? (uint32_t)(R3 + c * NHc + l) * rowb<R>(1) : OOB) : (uint32_t)(c * N + l) * rowb<R>(1);
+    else
+      return (uint32_t)r * rowb<R>(R3);
+  };
+  auto out_s = [&](int c, int l) -> uint32_t { return MIX ? 0u : (uint32_t)(c * N + l) * rowb<R>(1); };
+  auto out_ok = [&](int r, int l) -> bool { return !MIX || r == 0 || l < NHc; };
   // 2. RK operands of the part's output rows (absent operands read as 0),
   // requested with the tile's copies so that their latency overlaps the
   // trace, volume and flux work. FP32 loads the accumulator after barrier 1,
@@ -781,16 +828,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const Lane L = lane_of(A, tid);
     const uint32_t b0 = (uint32_t)(A.elem_begin + tix * tile) >> 6;
     const uint32_t e = (uint32_t)(A.elem_begin + tix * tile + L.li);
-    const uint32_t vo = blk_rel(e, b0, 2 * R3, RS) + L.role * rowb<R>(R3);
+    const uint32_t vo = blk_rel(e, b0, RB, RS);
     const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.nblk, b0, SBLK, A.bcoef, A.cdt, A.dt, LF == 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int l = L.part * NQ + q;
-        const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
-        ypre[c][q] = bld<R, CP_NT>(ef.y_rd, vo, so);
-        if constexpr (sizeof(R) == 8) apre[c][q] = bld<R, CP_NT>(ef.a_rd, vo, so);
+        const int l = min(L.part * NQ + q, N - 1);
+        const uint32_t v = vo + out_v(L.role, c, l), so = out_s(c, l);
+        ypre[c][q] = bld<R, CP_NT>(ef.y_rd, v, so);
+        if constexpr (sizeof(R) == 8) apre[c][q] = bld<R, CP_NT>(ef.a_rd, v, so);
       }
   };
   // everything a tile needs from memory before its first barrier; the
@@ -827,8 +874,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const uint32_t b0 = (uint32_t)start >> 6;  // first block of the tile (windows of the element arrays)
   const Rsrc rU = win_rsrc(a.Uin, a.nblk, b0, SBLK);
   const Rsrc rG = win_rsrc(a.geo, a.nblk, b0, NGEO * 64u * RS);
-  const uint32_t ebase = blk_rel(el, b0, 2 * R3, RS);   // element's state block
-  const uint32_t vout = ebase + role * rowb<R>(R3);       // output field
+  const uint32_t vout = blk_rel(el, b0, RB, RS);  // element's state block
   const uint32_t vgeo = blk_rel(el, b0, NGEO, RS);
   const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.nblk, b0, SBLK, a.bcoef, a.cdt, a.dt, LF == 1);
   const int hn = uniform_ld(a.halo_tile, 2 * t + 1);  // halo slots of this tile
@@ -918,8 +964,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int l = part * NQ + q;
-        const uint32_t so = (uint32_t)(c * N + (l < N ? l : N - 1)) * 64u * RS;
-        apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout, so);
+        const int lc = l < N ? l : N - 1;
+        apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout + out_v(role, c, lc), out_s(c, lc));
       }
   }
 
@@ -1017,12 +1063,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   }
 
   // mixed orders: h lives in the lower-order space, whose modes are the first
-  // nh of this basis; its other modes get no derivative (they stay zero), and
-  // the PML terms below then leave them at zero too
-  if (a.nh < N && role == 1) {
+  // NHc of this basis; its other modes get no derivative, so that they stay
+  // zero in the output (the state does not hold them, but the traces that
+  // the tile publishes are taken from the whole output), and the PML terms
+  // below leave them at zero too
+  if (MIX && role == 1) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
-      if (part * NQ + q >= a.nh) acc[0][q] = acc[1][q] = acc[2][q] = R(0);
+      if (part * NQ + q >= NHc) acc[0][q] = acc[1][q] = acc[2][q] = R(0);
   }
 
   const R bc = R(a.bcoef);
@@ -1039,7 +1087,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const Rsrc raU = win_rsrc(a.aUin, a.pnblk, pb0, SBLK);
     const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.pnblk, pb0, SBLK, a.bcoef, a.cdt, a.dt, false);
     const R ca = R(ea.c_out);
-    const uint32_t va = blk_rel(pk, pb0, 2 * R3, RS) + role * rowb<R>(R3);
+    const uint32_t va = blk_rel(pk, pb0, RB, RS);
     R AT[9], AiT[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -1064,9 +1112,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       R u[3], qa[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const uint32_t so = (uint32_t)(c * N + l) * 64u * RS;
-        u[c] = bld<R>(rU, vout, so);  // own output field at the stage input
-        qa[c] = bld<R>(raU, va, so);
+        u[c] = bld<R>(rU, vout + out_v(role, c, l), out_s(c, l));  // own output field at the stage input
+        qa[c] = bld<R>(raU, va + out_v(role, c, l), out_s(c, l));
       }
       const R cx = AiT[0] * u[0] + AiT[1] * u[1] + AiT[2] * u[2];
       const R cy = AiT[3] * u[0] + AiT[4] * u[1] + AiT[5] * u[2];
@@ -1090,7 +1137,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
           const R idet = R(1) / fma(h * h, xs[c], p1 * p2);
           xn[c] = (p2 * b1 - h * b2) * idet;
           const R yn = fma(p1, b2, h * xs[c] * b1) * idet;
-          if (wr) bst<R, CP_NT>(yn, raW, va, (uint32_t)(c * N + l) * 64u * RS);
+          if (wr && out_ok(role, l)) bst<R, CP_NT>(yn, raW, va + out_v(role, c, l), out_s(c, l));
         }
         // the new covariant field, stored as is by the epilogue
         acc[0][q] = AT[0] * xn[0] + AT[1] * xn[1] + AT[2] * xn[2];
@@ -1104,7 +1151,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       acc[2][q] -= AT[6] * y0 + AT[7] * y1 + AT[8] * y2;
       const R k[3] = {fma(qx, cx, -wx * qa[0]), fma(qy, cy, -wy * qa[1]), fma(qz, cz, -wzz * qa[2])};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) rk_store<R>(ea, k[c], va, (uint32_t)(c * N + l) * 64u * RS, bc, ca, live);
+      for (int c = 0; c < 3; ++c)
+        rk_store<R>(ea, k[c], va + out_v(role, c, l), out_s(c, l), bc, ca, live && out_ok(role, l));
     }
   }
 
@@ -1119,11 +1167,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       for (int q = 0; q < NQ; ++q) {
         const int l = part * NQ + q;
         if (l >= N) continue;
-        const uint32_t so = (uint32_t)(c * N + l) * 64u * RS;
+        const uint32_t v = vout + out_v(role, c, l), so = out_s(c, l);
+        const bool ok = wr && out_ok(role, l);
         if (direct) {
-          if (wr) bst<R, CP_NT>(acc[c][q], ef.out_wr, vout, so);
+          if (ok) bst<R, CP_NT>(acc[c][q], ef.out_wr, v, so);
         } else {
-          acc[c][q] = rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], vout, so, bc, cf, wr);
+          acc[c][q] = rk_store_pre<R>(ef, acc[c][q], ypre[c][q], apre[c][q], v, so, bc, cf, ok);
         }
       }
   }
@@ -1171,7 +1220,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 // W = 1/2 sum_T sum_l eps u_l^T M u_l + mu f_l^T M f_l, M = (G0^-1)^-1 = |det A| A^-1 A^-T
 template <typename R, int N>
 __global__ __launch_bounds__(256) void energy_kernel(const R* __restrict__ Y, const R* __restrict__ geo, int64_t K,
-                                                     double* __restrict__ part, double* __restrict__ eelem) {
+                                                     double* __restrict__ part, double* __restrict__ eelem, int nh) {
   __shared__ double red[4];
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double w = 0.0;
@@ -1184,13 +1233,15 @@ __global__ __launch_bounds__(256) void energy_kernel(const R* __restrict__ Y, co
     const double m00 = (d * f - e * e) * id, m01 = (c * e - b * f) * id, m02 = (b * e - c * d) * id;
     const double m11 = (a * f - c * c) * id, m12 = (b * c - a * e) * id, m22 = (a * d - b * b) * id;
     const double eps = 1.0 / (double)gk[G_IEPS * 64], mu = 1.0 / (double)gk[G_IMU * 64];
-    const R* yk = Y + (k >> 6) * 6 * N * 64 + (k & 63);
+    // e rows c N + l, then h rows 3N + c nh + l (nh modes of h)
+    const R* yk = Y + (k >> 6) * (int64_t)(3 * (N + nh)) * 64 + (k & 63);
     double sf[2] = {0.0, 0.0};
     for (int fld = 0; fld < 2; ++fld)
-      for (int l = 0; l < N; ++l) {
-        const double x = yk[(fld * 3 * N + 0 * N + l) * 64];
-        const double y = yk[(fld * 3 * N + 1 * N + l) * 64];
-        const double z = yk[(fld * 3 * N + 2 * N + l) * 64];
+      for (int l = 0; l < (fld ? nh : N); ++l) {
+        const int st = fld ? nh : N, b = fld * 3 * N;
+        const double x = yk[(b + 0 * st + l) * 64];
+        const double y = yk[(b + 1 * st + l) * 64];
+        const double z = yk[(b + 2 * st + l) * 64];
         sf[fld] += m00 * x * x + m11 * y * y + m22 * z * z + 2.0 * (m01 * x * y + m02 * x * z + m12 * y * z);
       }
     w = 0.5 * (eps * sf[0] + mu * sf[1]);
@@ -1220,7 +1271,7 @@ __device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], 
 }
 
 template <typename R, int P>
-__global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nblk, const int32_t* pub,
+__global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nblk, int nh, const int32_t* pub,
                                                       void* H, uint32_t hbuf_bytes, int K,
                                                       int hreg) {
   constexpr int N = Ops<P>::N, R3 = 3 * N;
@@ -1230,9 +1281,11 @@ __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nb
   if (el >= K) return;
   // the 32 elements of a wave lie in one 64-element block: windows at it
   const uint32_t b0 = (uint32_t)((blockIdx.x * 256 + (threadIdx.x & ~63u)) >> 1) >> 6;
-  const Rsrc rU = win_rsrc(U, nblk, b0, 2u * R3 * 64u * RS), rP = win_rsrc(pub, nblk, b0, 4u * 64u * 4u);
+  const uint32_t rb = 3u * (uint32_t)(N + nh);  // rows of an element block: e, then h with nh modes
+  const Rsrc rU = win_rsrc(U, nblk, b0, rb * 64u * RS), rP = win_rsrc(pub, nblk, b0, 4u * 64u * 4u);
   const Rsrc rH = make_rsrc(H, hbuf_bytes);
-  const uint32_t vo = blk_rel((uint32_t)el, b0, 2 * R3, RS) + (uint32_t)fld * rowb<R>(R3);
+  const uint32_t vo = blk_rel((uint32_t)el, b0, rb, RS) + (uint32_t)fld * rowb<R>(R3);
+  const int st = fld ? nh : N;  // row stride of the field's components
   int code[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) code[f] = bldi(rP, blk_rel((uint32_t)el, b0, 4, 4), (uint32_t)f * 256u);
@@ -1241,7 +1294,7 @@ __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nb
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int l = 0; l < N; ++l) w[c][l] = bld<R>(rU, vo, rowb<R>(c * N + l));
+    for (int l = 0; l < N; ++l) w[c][l] = l < st ? bld<R>(rU, vo, rowb<R>(c * st + l)) : R(0);
   if (code[0] >= 0) publish_face_global<P, 0, R>(w, fld, rH, code[0], hreg);
   if (code[1] >= 0) publish_face_global<P, 1, R>(w, fld, rH, code[1], hreg);
   if (code[2] >= 0) publish_face_global<P, 2, R>(w, fld, rH, code[2], hreg);
@@ -1264,10 +1317,11 @@ __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nb
 // traces of field fld (0: E, 1: H) of element e on face F (runtime)
 template <typename R, int P>
 __device__ void traces_rt(const R* __restrict__ u, int64_t e, int fld, int F, double (&t0)[Ops<P>::NF],
-                          double (&t1)[Ops<P>::NF]) {
+                          double (&t1)[Ops<P>::NF], int nh) {
   constexpr int N = Ops<P>::N;
-  const R* ue = u + (e >> 6) * 6 * N * 64 + (e & 63) + fld * 3 * N * 64;
-  auto v = [&](int c, int l) { return (double)ue[(c * N + l) * 64]; };
+  const int st = fld ? nh : N;  // e rows c N + l, then h rows 3N + c nh + l
+  const R* ue = u + (e >> 6) * (int64_t)(3 * (N + nh)) * 64 + (e & 63) + fld * 3 * N * 64;
+  auto v = [&](int c, int l) { return l < st ? (double)ue[(c * st + l) * 64] : 0.0; };
   switch (F) {
     case 0: face_trace<P, 0, double>(v, t0, t1); break;
     case 1: face_trace<P, 1, double>(v, t0, t1); break;
@@ -1281,7 +1335,7 @@ __device__ void traces_rt(const R* __restrict__ u, int64_t e, int fld, int F, do
 // derivatives of the own weight and of the penalty factor, for field role r
 template <typename R, int P>
 __device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, const R* __restrict__ geo,
-                           int64_t e, int F, int64_t en, int fn, bool has, int r, double dom, double dpen) {
+                           int64_t e, int F, int64_t en, int fn, bool has, int r, double dom, double dpen, int nh) {
   constexpr int NF = Ops<P>::NF;
   const double g = r ? -1.0 : 1.0;
   const double fin = has ? 1.0 : g, fout = has ? 1.0 : -g;  // PEC mirror of the input / output field
@@ -1294,22 +1348,22 @@ __device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, con
   const double idet = 1.0 / sqrt(g11 * g22 - g12 * g12);
   const double W11 = g22 * idet, W12 = -g12 * idet, W22 = g11 * idet;
   double ta0[NF], ta1[NF], v0[NF], v1[NF];
-  traces_rt<R, P>(a, e, r, F, ta0, ta1);  // the adjoint of the output field
+  traces_rt<R, P>(a, e, r, F, ta0, ta1, nh);  // the adjoint of the output field
   double s_avg = 0.0, s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
   // averaged input field: d(A1, A2)/dom = c (xm1 - xp1, -(xm0 - xp0))
-  traces_rt<R, P>(x, e, 1 - r, F, v0, v1);
+  traces_rt<R, P>(x, e, 1 - r, F, v0, v1, nh);
   for (int m = 0; m < NF; ++m) s_avg += ta0[m] * v1[m] - ta1[m] * v0[m];
-  traces_rt<R, P>(x, en, 1 - r, fn, v0, v1);
+  traces_rt<R, P>(x, en, 1 - r, fn, v0, v1, nh);
   for (int m = 0; m < NF; ++m) s_avg -= fin * (ta0[m] * v1[m] - ta1[m] * v0[m]);
   // penalty on the jump of the output field: d(A1, A2)/dpen = W (j0, j1)
-  traces_rt<R, P>(x, en, r, fn, v0, v1);
+  traces_rt<R, P>(x, en, r, fn, v0, v1, nh);
   for (int m = 0; m < NF; ++m) {
     s00 += fout * ta0[m] * v0[m];
     s01 += fout * ta0[m] * v1[m];
     s10 += fout * ta1[m] * v0[m];
     s11 += fout * ta1[m] * v1[m];
   }
-  traces_rt<R, P>(x, e, r, F, v0, v1);
+  traces_rt<R, P>(x, e, r, F, v0, v1, nh);
   for (int m = 0; m < NF; ++m) {
     s00 -= ta0[m] * v0[m];
     s01 -= ta0[m] * v1[m];
@@ -1322,7 +1376,7 @@ __device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, con
 template <typename R, int P>
 __global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout, const R* __restrict__ a,
                                                       const R* __restrict__ x, const R* __restrict__ geo,
-                                                      const int32_t* __restrict__ nbrg, int64_t K, double scale) {
+                                                      const int32_t* __restrict__ nbrg, int64_t K, double scale, int nh) {
   const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (k >= K) return;
   const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
@@ -1345,12 +1399,12 @@ __global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout,
         dom = 0.0;
         dpen = r ? 0.5 : -0.5 / (Z * Z);
       }
-      sum += upw_side<R, P>(a, x, geo, k, F, kn, fn, has, r, dom, dpen);
+      sum += upw_side<R, P>(a, x, geo, k, F, kn, fn, has, r, dom, dpen, nh);
       // the neighbour's equations, where T is the other side (Z_T = Z+)
       if (has) {
         const double dom2 = r ? Zn / S2 : -Zn / S2;
         const double dpen2 = r ? Zn * Zn / S2 : -1.0 / S2;
-        sum += upw_side<R, P>(a, x, geo, kn, fn, k, F, true, r, dom2, dpen2);
+        sum += upw_side<R, P>(a, x, geo, kn, fn, k, F, true, r, dom2, dpen2, nh);
       }
     }
   }
@@ -1380,9 +1434,9 @@ static int resident_workgroups(const void* kern, int block, size_t lds, int* cac
 // persist: a grid of the resident workgroups only (rounded down to whole
 // XCDs), each looping over its share of the tiles; otherwise one workgroup
 // per tile
-template <typename R, int P, bool UPW, bool PML, int LF, bool SIP = false, bool MF = false>
+template <typename R, int P, bool MIX, bool UPW, bool PML, int LF, bool SIP = false, bool MF = false>
 static void launch_one(const DevArgs& a, int tile, size_t lds, bool persist, hipStream_t st) {
-  const void* kern = reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP, MF>);
+  const void* kern = reinterpret_cast<const void*>(&stage_kernel<R, P, UPW, PML, LF, SIP, MF, MIX>);
   const int block = (LF == 2 ? 4 : 8) * tile;
   if (lds > 64 * 1024)
     hip_check(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
@@ -1397,25 +1451,25 @@ static void launch_one(const DevArgs& a, int tile, size_t lds, bool persist, hip
     // publishes, so the output is staged in the trace area
     b.out_base = 0;
   }
-  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP, MF>), dim3(grid), dim3(block), lds, st, b);
+  hipLaunchKernelGGL((stage_kernel<R, P, UPW, PML, LF, SIP, MF, MIX>), dim3(grid), dim3(block), lds, st, b);
   hip_check(hipGetLastError(), "stage_kernel launch");
 }
 
 // RK4 stage or operator call with the MFMA volume term (FP32, orders 1-3, 64-element tiles)
-template <typename R, int P>
+template <typename R, int P, bool MIX>
 static void launch_mfma(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool ps,
                         hipStream_t st) {
   if constexpr (sizeof(R) == 4 && P <= 3) {
     if (tile != 64) throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term needs 64-element tiles");
     if (upw) {
-      if (pml) launch_one<R, P, true, true, 0, false, true>(a, tile, lds, ps, st);
-      else launch_one<R, P, true, false, 0, false, true>(a, tile, lds, ps, st);
+      if (pml) launch_one<R, P, MIX, true, true, 0, false, true>(a, tile, lds, ps, st);
+      else launch_one<R, P, MIX, true, false, 0, false, true>(a, tile, lds, ps, st);
     } else if (sip) {
-      if (pml) launch_one<R, P, false, true, 0, true, true>(a, tile, lds, ps, st);
-      else launch_one<R, P, false, false, 0, true, true>(a, tile, lds, ps, st);
+      if (pml) launch_one<R, P, MIX, false, true, 0, true, true>(a, tile, lds, ps, st);
+      else launch_one<R, P, MIX, false, false, 0, true, true>(a, tile, lds, ps, st);
     } else {
-      if (pml) launch_one<R, P, false, true, 0, false, true>(a, tile, lds, ps, st);
-      else launch_one<R, P, false, false, 0, false, true>(a, tile, lds, ps, st);
+      if (pml) launch_one<R, P, MIX, false, true, 0, false, true>(a, tile, lds, ps, st);
+      else launch_one<R, P, MIX, false, false, 0, false, true>(a, tile, lds, ps, st);
     }
   } else {
     throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term is built for FP32 and orders 1-3");
@@ -1423,61 +1477,73 @@ static void launch_mfma(const DevArgs& a, bool upw, bool sip, bool pml, int tile
 }
 
 // central-flux launches with or without the SIP unknown
-template <typename R, int P, bool PML, int LF>
+template <typename R, int P, bool MIX, bool PML, int LF>
 static void launch_c(const DevArgs& a, bool sip, int tile, size_t lds, bool ps, hipStream_t st) {
-  if (sip) launch_one<R, P, false, PML, LF, true>(a, tile, lds, ps, st);
-  else launch_one<R, P, false, PML, LF, false>(a, tile, lds, ps, st);
+  if (sip) launch_one<R, P, MIX, false, PML, LF, true>(a, tile, lds, ps, st);
+  else launch_one<R, P, MIX, false, PML, LF, false>(a, tile, lds, ps, st);
 }
 
-template <typename R, int P>
-void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, bool ps,
-              hipStream_t st) {
+template <typename R, int P, bool MIX>
+static void launch_pm(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, bool ps,
+                      hipStream_t st) {
   if (upw && sip) throw Error(MDG_E_UNSUPPORTED, "the SIP unknown needs the central flux");
   if (mfma) {
     if (a.stage >= 4) throw Error(MDG_E_UNSUPPORTED, "the MFMA volume term runs with RK4");
-    launch_mfma<R, P>(a, upw, sip, pml, tile, lds, ps, st);
+    launch_mfma<R, P, MIX>(a, upw, sip, pml, tile, lds, ps, st);
     return;
   }
   if (a.stage >= 4) {  // leap-frog half (central flux, checked at creation)
     if (upw) throw Error(MDG_E_UNSUPPORTED, "leap-frog needs the central flux");
     if (tile % 64 == 0) {  // four lanes per element
-      if (pml) launch_c<R, P, true, 2>(a, sip, tile, lds, ps, st);
-      else launch_c<R, P, false, 2>(a, sip, tile, lds, ps, st);
+      if (pml) launch_c<R, P, MIX, true, 2>(a, sip, tile, lds, ps, st);
+      else launch_c<R, P, MIX, false, 2>(a, sip, tile, lds, ps, st);
     } else {
-      if (pml) launch_c<R, P, true, 1>(a, sip, tile, lds, ps, st);
-      else launch_c<R, P, false, 1>(a, sip, tile, lds, ps, st);
+      if (pml) launch_c<R, P, MIX, true, 1>(a, sip, tile, lds, ps, st);
+      else launch_c<R, P, MIX, false, 1>(a, sip, tile, lds, ps, st);
     }
   } else if (upw) {
-    if (pml) launch_one<R, P, true, true, 0>(a, tile, lds, ps, st);
-    else launch_one<R, P, true, false, 0>(a, tile, lds, ps, st);
+    if (pml) launch_one<R, P, MIX, true, true, 0>(a, tile, lds, ps, st);
+    else launch_one<R, P, MIX, true, false, 0>(a, tile, lds, ps, st);
   } else {
-    if (pml) launch_c<R, P, true, 0>(a, sip, tile, lds, ps, st);
-    else launch_c<R, P, false, 0>(a, sip, tile, lds, ps, st);
+    if (pml) launch_c<R, P, MIX, true, 0>(a, sip, tile, lds, ps, st);
+    else launch_c<R, P, MIX, false, 0>(a, sip, tile, lds, ps, st);
+  }
+}
+
+// mix: the state holds h (and q) with the modes of order P-1 only
+template <typename R, int P>
+void launch_p(const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma, bool ps, bool mix,
+              hipStream_t st) {
+  if (!mix) {
+    launch_pm<R, P, false>(a, upw, sip, pml, tile, lds, mfma, ps, st);
+  } else {
+    if constexpr (P >= 2) launch_pm<R, P, true>(a, upw, sip, pml, tile, lds, mfma, ps, st);
+    else throw Error(MDG_E_UNSUPPORTED, "mixed orders need e at order 2 or more");
   }
 }
 
 template <typename R, int P>
-void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, hipStream_t st) {
+void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, int nh, hipStream_t st) {
   const int64_t nblk = (K + 255) / 256;
   hipLaunchKernelGGL((energy_kernel<R, Ops<P>::N>), dim3(nblk), dim3(256), 0, st, static_cast<const R*>(Y),
-                     static_cast<const R*>(geo), K, part, eelem);
+                     static_cast<const R*>(geo), K, part, eelem, nh);
   hip_check(hipGetLastError(), "energy_kernel launch");
 }
 
 template <typename R, int P>
-void launch_publish_rp(const void* U, uint32_t nblk, const int32_t* pub, void* H, uint32_t hb, int K, int hreg,
-                       hipStream_t st) {
+void launch_publish_rp(const void* U, uint32_t nblk, int nh, const int32_t* pub, void* H, uint32_t hb, int K,
+                       int hreg, hipStream_t st) {
   const dim3 grid((unsigned)((2 * (int64_t)K + 255) / 256));
-  hipLaunchKernelGGL((publish_kernel<R, P>), grid, dim3(256), 0, st, U, nblk, pub, H, hb, K, hreg);
+  hipLaunchKernelGGL((publish_kernel<R, P>), grid, dim3(256), 0, st, U, nblk, nh, pub, H, hb, K, hreg);
   hip_check(hipGetLastError(), "publish_kernel launch");
 }
 
 template <typename R, int P>
 void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* geo, const int32_t* nbrg, int64_t K,
-                        double scale, hipStream_t st) {
+                        double scale, int nh, hipStream_t st) {
   const dim3 grid((unsigned)((K + 63) / 64));
   hipLaunchKernelGGL((grad_upw_kernel<R, P>), grid, dim3(64), 0, st, g, static_cast<const R*>(a),
-                     static_cast<const R*>(x), static_cast<const R*>(geo), nbrg, K, scale);
+                     static_cast<const R*>(x), static_cast<const R*>(geo), nbrg, K, scale, nh);
   hip_check(hipGetLastError(), "grad_upw_kernel launch");
 }
 

@@ -41,12 +41,12 @@ __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ p
 
 template <typename R>
 static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int tile, size_t lds, bool mfma,
-                     bool ps, hipStream_t st) {
+                     bool ps, bool mix, hipStream_t st) {
   switch (P) {
-    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
-    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
-    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
-    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, mfma, ps, st); break;
+    case 1: launch_p<R, 1>(a, upw, sip, pml, tile, lds, mfma, ps, mix, st); break;
+    case 2: launch_p<R, 2>(a, upw, sip, pml, tile, lds, mfma, ps, mix, st); break;
+    case 3: launch_p<R, 3>(a, upw, sip, pml, tile, lds, mfma, ps, mix, st); break;
+    case 4: launch_p<R, 4>(a, upw, sip, pml, tile, lds, mfma, ps, mix, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
 }
@@ -123,8 +123,9 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
     a.ntiles = part == 0 ? (int32_t)s.ntiles0 : (int32_t)(s.ntiles - s.ntiles0);
     if (a.ntiles == 0) continue;
     const bool ps = s.opt.launch == MDG_LAUNCH_PERSISTENT;
-    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, ps, st);
-    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, ps, st);
+    const bool mix = s.NH < s.N;
+    if (fp32) launch_r<float>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, ps, mix, st);
+    else launch_r<double>(s.P, a, upw, s.sip(), part == 1, s.tile, lds, s.opt.mfma != 0, ps, mix, st);
   }
 }
 
@@ -135,10 +136,10 @@ static void launch_energy_r(const Solver& s, const void* Y, hipStream_t st) {
   double* ee = reinterpret_cast<double*>(base + s.L.eelem);
   const void* geo = base + s.L.geo;
   switch (s.P) {
-    case 1: launch_energy_rp<R, 1>(Y, geo, s.K, part, ee, st); break;
-    case 2: launch_energy_rp<R, 2>(Y, geo, s.K, part, ee, st); break;
-    case 3: launch_energy_rp<R, 3>(Y, geo, s.K, part, ee, st); break;
-    case 4: launch_energy_rp<R, 4>(Y, geo, s.K, part, ee, st); break;
+    case 1: launch_energy_rp<R, 1>(Y, geo, s.K, part, ee, s.NH, st); break;
+    case 2: launch_energy_rp<R, 2>(Y, geo, s.K, part, ee, s.NH, st); break;
+    case 3: launch_energy_rp<R, 3>(Y, geo, s.K, part, ee, s.NH, st); break;
+    case 4: launch_energy_rp<R, 4>(Y, geo, s.K, part, ee, s.NH, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
   const int64_t nblk = (s.K + 255) / 256;
@@ -185,10 +186,10 @@ static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_
   const int32_t* pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
   const int K = (int)s.K, hreg = (int)s.hreg;
   switch (s.P) {
-    case 1: launch_publish_rp<R, 1>(U, nblk, pub, H, hb, K, hreg, st); break;
-    case 2: launch_publish_rp<R, 2>(U, nblk, pub, H, hb, K, hreg, st); break;
-    case 3: launch_publish_rp<R, 3>(U, nblk, pub, H, hb, K, hreg, st); break;
-    case 4: launch_publish_rp<R, 4>(U, nblk, pub, H, hb, K, hreg, st); break;
+    case 1: launch_publish_rp<R, 1>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
+    case 2: launch_publish_rp<R, 2>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
+    case 3: launch_publish_rp<R, 3>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
+    case 4: launch_publish_rp<R, 4>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
 }
@@ -205,7 +206,7 @@ void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, d
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int32_t* nb = reinterpret_cast<const int32_t*>(base + s.L.nbrg);
   const void* geo = base + s.L.geo;
-#define MDG_UPW(R, P) launch_grad_upw_rp<R, P>(g, a, x, geo, nb, s.K, scale, st)
+#define MDG_UPW(R, P) launch_grad_upw_rp<R, P>(g, a, x, geo, nb, s.K, scale, s.NH, st)
   const bool fp32 = s.opt.precision == MDG_FP32;
   switch (s.P) {
     case 1: if (fp32) MDG_UPW(float, 1); else MDG_UPW(double, 1); break;
