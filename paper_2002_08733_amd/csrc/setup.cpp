@@ -267,14 +267,38 @@ int tile_size_for(int P, bool fp32) {
   return 32;
 }
 
-static uint64_t spread21(uint64_t v) {
-  v &= 0x1fffff;
-  v = (v | v << 32) & 0x1f00000000ffffULL;
-  v = (v | v << 16) & 0x1f0000ff0000ffULL;
-  v = (v | v << 8) & 0x100f00f00f00f00fULL;
-  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
-  v = (v | v << 2) & 0x1249249249249249ULL;
-  return v;
+// Tile order: recursive coordinate bisection of the element centroids over
+// perm[b, e). A range is cut at the median of its longest centroid extent,
+// with the cut moved to the tile boundary (o + a multiple of `leaf`, o the
+// start of the tiled partition) nearest to the middle, until it holds no such multiple; that last range is
+// sorted along its longest extent, so that halving the tile later still
+// gives compact halves. Consecutive runs of `leaf` elements are then compact
+// boxes, with fewer faces on their boundary (fewer halo traces) than runs of
+// a space-filling curve, which follow octree cells only at powers of two.
+static void bisect(std::vector<int64_t>& perm, int64_t b, int64_t e, int64_t o, int64_t leaf,
+                   const std::vector<double>& cen) {
+  while (e - b > 1) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = b; i < e; ++i)
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = std::min(lo[c], cen[3 * perm[i] + c]);
+        hi[c] = std::max(hi[c], cen[3 * perm[i] + c]);
+      }
+    int ax = 0;
+    for (int c = 1; c < 3; ++c)
+      if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+    auto less = [&](int64_t x, int64_t y) { return cen[3 * x + ax] < cen[3 * y + ax]; };
+    // tile boundaries inside (b, e)
+    const int64_t first = o + (b - o) / leaf * leaf + leaf, last = o + (e - 1 - o) / leaf * leaf;
+    if (first > last) {
+      std::sort(perm.begin() + b, perm.begin() + e, less);
+      return;
+    }
+    const int64_t m = std::min(last, std::max(first, o + ((b + e) / 2 - o + leaf / 2) / leaf * leaf));
+    std::nth_element(perm.begin() + b, perm.begin() + m, perm.begin() + e, less);
+    bisect(perm, b, m, o, leaf, cen);
+    b = m;
+  }
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -286,43 +310,6 @@ void finalize(Solver& s) {
   if (!s.omega.empty())
     for (int64_t k = 0; k < nt; ++k)
       ispml[k] = (s.omega[3 * k] > 0 || s.omega[3 * k + 1] > 0 || s.omega[3 * k + 2] > 0);
-  // Morton order of centroids inside the bounding box, PML elements last
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int64_t v = 0; v < s.nv; ++v)
-    for (int c = 0; c < 3; ++c) {
-      lo[c] = std::min(lo[c], s.xyz[3 * v + c]);
-      hi[c] = std::max(hi[c], s.xyz[3 * v + c]);
-    }
-  std::vector<uint64_t> key(nt);
-  for (int64_t k = 0; k < nt; ++k) {
-    uint64_t code = 0;
-    for (int c = 0; c < 3; ++c) {
-      double m = 0;
-      for (int v = 0; v < 4; ++v) m += s.xyz[3 * s.tet[4 * k + v] + c];
-      m *= 0.25;
-      const double span = std::max(hi[c] - lo[c], 1e-300);
-      uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, (m - lo[c]) / span * 2097151.0));
-      code |= spread21(q) << c;
-    }
-    key[k] = code;
-  }
-  s.perm.resize(nt);
-  std::iota(s.perm.begin(), s.perm.end(), 0);
-  // non-PML elements, then PML elements; inside each, instance by instance,
-  // each along its Morton curve
-  std::stable_sort(s.perm.begin(), s.perm.end(), [&](int64_t a, int64_t b) {
-    if (ispml[a] != ispml[b]) return ispml[a] < ispml[b];
-    if (s.inst_of[a] != s.inst_of[b]) return s.inst_of[a] < s.inst_of[b];
-    return key[a] < key[b];
-  });
-  s.iperm.resize(nt);
-  for (int64_t k = 0; k < nt; ++k) s.iperm[s.perm[k]] = k;
-  s.K = nt;
-  s.K0 = 0;
-  for (int64_t k = 0; k < nt; ++k) s.K0 += !ispml[k];
-  s.Kp = nt - s.K0;
-  s.Kppad = (std::max<int64_t>(s.Kp, 1) + 63) / 64 * 64;
-
   const bool fp32 = s.opt.precision == MDG_FP32;
   const size_t rs = s.real_size();
   int tile0 = tile_size_for(s.P, fp32);
@@ -332,6 +319,37 @@ void finalize(Solver& s) {
   if (lf) tile0 = 64;
   const bool forced = s.opt.tile != 0;  // a caller's choice (e.g. an autotuner)
   if (forced) tile0 = s.opt.tile;
+  // non-PML elements, then PML elements; inside each, instance by instance,
+  // each in the bisection order of its centroids (leaves of the first tile
+  // size tried)
+  std::vector<double> cen(3 * nt);
+  for (int64_t k = 0; k < nt; ++k)
+    for (int c = 0; c < 3; ++c) {
+      double m = 0;
+      for (int v = 0; v < 4; ++v) m += s.xyz[3 * s.tet[4 * k + v] + c];
+      cen[3 * k + c] = 0.25 * m;
+    }
+  s.perm.resize(nt);
+  std::iota(s.perm.begin(), s.perm.end(), 0);
+  std::stable_sort(s.perm.begin(), s.perm.end(), [&](int64_t a, int64_t b) {
+    if (ispml[a] != ispml[b]) return ispml[a] < ispml[b];
+    return s.inst_of[a] < s.inst_of[b];
+  });
+  s.K = nt;
+  s.K0 = 0;
+  for (int64_t k = 0; k < nt; ++k) s.K0 += !ispml[k];
+  // the damped partition is tiled from K0 on
+  for (int64_t g0 = 0; g0 < nt;) {
+    int64_t g1 = g0 + 1;
+    while (g1 < nt && ispml[s.perm[g1]] == ispml[s.perm[g0]] && s.inst_of[s.perm[g1]] == s.inst_of[s.perm[g0]]) ++g1;
+    bisect(s.perm, g0, g1, ispml[s.perm[g0]] ? s.K0 : 0, tile0, cen);
+    g0 = g1;
+  }
+  s.iperm.resize(nt);
+  for (int64_t k = 0; k < nt; ++k) s.iperm[s.perm[k]] = k;
+  s.Kp = nt - s.K0;
+  s.Kppad = (std::max<int64_t>(s.Kp, 1) + 63) / 64 * 64;
+
   for (int tile = tile0;; tile /= 2) {
     s.tile = tile;
     // padded by a full tile: lanes past the end of a partial tile load freely

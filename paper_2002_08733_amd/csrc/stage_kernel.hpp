@@ -5,29 +5,37 @@
 // input of every element and performs that stage's RK4 update in the epilogue.
 //
 // Work decomposition
-//   * Elements are ordered along a Morton curve (PML elements last) and cut
-//     into tiles of TILE consecutive elements; one workgroup per tile, two
-//     lanes per element. Lane role 0 produces the E update and reads H as its
-//     volume input; role 1 produces the H update and reads E. Both roles run
-//     the same instruction stream on different data:
+//   * Elements are ordered by recursive coordinate bisection of their
+//     centroids (PML elements last) and cut into tiles of TILE consecutive
+//     elements (64, or 32 where the LDS of the trace exchange would be too
+//     large: FP64 from order 2, FP32 order 4); one workgroup per tile. Eight lanes
+//     per element: two roles x four parts. Role 0 produces the E update and
+//     reads H as its volume input, role 1 the H update from E:
 //        r_E = +s W(h) - Lift(h~) + Pen_Z([e]),   r_H = -s W(e) + Lift(e~) + Pen_Y([h])
 //     where W(v)[c] = sum_{a,d} eps_dac D_a v_d is the weak reference curl
 //     (D_a[l][m] = (d_a phi_l, phi_m), [KS eq. matrix_free_curl]; the H equation
 //     is used in its integrated-by-parts form, algebraically identical to the
 //     strong form of [KS eq. cwc] for polynomial fields), s = sign(det A).
+//     Part q traces and fluxes one face of the element and owns a quarter of
+//     the output modes (volume rows, lift rows, mass inverse, PML, epilogue).
+//     Leap-frog half steps give all lanes to the active field (four per
+//     element).
 //   * Reference matrices are compile-time constants (generated header): every
 //     multiply by a structural zero disappears and every nonzero becomes an FMA
-//     with an inline constant. No MFMA: the operators are sparse (p = 3: 202 of
-//     1200 curl entries, 337 of 800 trace entries), and at the resulting
-//     ~2 flop/B the stage is bound by HBM, not by arithmetic.
-//   * Face coupling: every lane computes the face traces of its input field on
-//     its 4 faces, tau_k(v)[m] = sum_l T_f[m][l] (v . t^_k)[l], and stores them
-//     in LDS; faces whose neighbour lies in another tile get the neighbour's
-//     trace recomputed from global memory (halo list sorted by neighbour face so
-//     a wave mostly takes one branch). After one barrier every lane reads own
-//     and neighbour traces, forms the flux in face coefficients and lifts it
-//     with T_f^T. Both elements of a face parametrise it from the face's
-//     vertices in ascending global id, so traces combine without permutation;
+//     with an inline constant (p = 3: 202 of 1200 curl entries, 337 of 800
+//     trace entries are nonzero). At ~2 flop/B the stage is bound by HBM; a
+//     BF16x3 split-product MFMA form of the volume term is built as an option.
+//   * Data movement per tile: the input fields are copied into LDS by
+//     asynchronous buffer-to-LDS loads, together with the tile's halo block
+//     and the RK operands, before the first barrier. Every lane traces its
+//     input field on its face, tau_k(v)[m] = sum_l T_f[m][l] (v . t^_k)[l],
+//     into an LDS slot. A face whose neighbour lies in another tile reads
+//     the neighbour's traces from the halo block, which the neighbour's tile
+//     wrote at the end of the previous launch: after its epilogue a tile
+//     stages its output in LDS, traces it on those faces and stores the
+//     traces into the reading tile's block of a global halo buffer. Both
+//     elements of a face parametrise it from the face's vertices in
+//     ascending global id, so traces combine without permutation;
 //     the tangential cross product of [KS eqs. uwc/cwc] reduces to
 //     int_F (a x n).b dS = sigma int (a.t2)(b.t1) - (a.t1)(b.t2) ds with
 //     a.t_k = a^.t^_k for covariant fields and sigma = s sigma^_f.
@@ -37,8 +45,8 @@
 //   * PML [KS Sec. IV, eqs. p_variable, q_variable] in Cartesian, eps-scaled
 //     auxiliaries P~ = A^-T P / eps: d_t u = (1/eps) G0^-1 r - A^T(eta.c + P~),
 //     d_t P~ = -w.P~ + xi.c, c = A^-T u.
-//   * Blocks are mapped to tiles XCD-major: consecutive tiles (spatial
-//     neighbours) run on the same XCD, so halo re-reads hit its L2.
+//   * Tiles are mapped to workgroups XCD-major: consecutive tiles (spatial
+//     neighbours) run on the same XCD and share its L2.
 //
 // This header holds the device code; stage_kernel.hip instantiates it for
 // one (precision, order) pair per object (MDG_R, MDG_P), and stage_launch.hip
@@ -65,8 +73,8 @@ __device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 // cache policy: CP_NT marks streaming data (read or written once per launch)
-// as non-temporal, so it does not push the stage input, which neighbouring
-// tiles gather for their halo faces, out of L2
+// as non-temporal, so that it does not push reused data (geometry, tables)
+// out of L2
 enum { CP_DEF = 0, CP_NT = 2 };
 template <typename R, int CP = CP_DEF>
 __device__ __forceinline__ R bld(Rsrc r, uint32_t vo, uint32_t so) {
@@ -206,16 +214,17 @@ struct Cst<double, P> {
 };
 
 // traces of a vector coefficient field on face F: t0/t1 = T_F (v . t^1/2)
-// v(c, l): coefficient l of component c (a register array or an LDS row)
-template <int P, int F, typename R, typename V>
+// v(c, l): coefficient l of component c (a register array or an LDS row);
+// MI: the field's modes (the first MI of the basis, the others are zero)
+template <int P, int F, typename R, int MI = Ops<P>::N, typename V>
 __device__ __forceinline__ void face_trace(const V& v, R (&t0)[Ops<P>::NF], R (&t1)[Ops<P>::NF]) {
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
+  constexpr int NF = Ops<P>::NF;
 #pragma unroll
   for (int m = 0; m < NF; ++m) {
     R s0 = 0, s1 = 0;
     bool first = true;
 #pragma unroll
-    for (int l = 0; l < N; ++l) {
+    for (int l = 0; l < MI; ++l) {
       if (Ops<P>::T[F][m][l] != 0.0) {
         const R c = Cst<R, P>::tr(F, m, l);
         const R a = tan0<F, R>(v(0, l), v(1, l), v(2, l));
@@ -236,16 +245,28 @@ __device__ __forceinline__ void face_trace(const V& v, R (&t0)[Ops<P>::NF], R (&
 // inverse, PML and epilogue.
 template <int P>
 constexpr int nq() { return (Ops<P>::N + 3) / 4; }
+// Face of part q. The trace work of a face is set by the sparsity of T_F
+// (face 0, the slanted one, is the densest, then faces 3, 2, 1) and the
+// volume and lift work of a mode group grows with its modes' degree, so
+// part q takes mode group q and the faces in the opposite order of cost:
+// this evens out the VALU work of the waves that meet at each barrier.
+constexpr int face_of(int q) { return q == 0 ? 0 : 4 - q; }
+// a compile-time count passed through a generic lambda
+template <int V>
+struct IC {
+  static constexpr int value = V;
+};
 
-// acc[j][i] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m]),  l = Q*NQ + i
-template <int P, int F, int Q, typename R>
+// acc[j][i] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m]),  l = Q*NQ + i,
+// for the output modes l < MO
+template <int P, int F, int Q, typename R, int MO = Ops<P>::N>
 __device__ __forceinline__ void face_lift_q(const R (&A1)[Ops<P>::NF], const R (&A2)[Ops<P>::NF],
                                             R (&acc)[3][nq<P>()]) {
-  constexpr int N = Ops<P>::N, NF = Ops<P>::NF, NQ = nq<P>();
+  constexpr int NF = Ops<P>::NF, NQ = nq<P>();
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int l = Q * NQ + i;
-    if (l >= N) continue;
+    if (l >= MO) continue;
     R L1 = 0, L2 = 0;
     bool first = true;
 #pragma unroll
@@ -263,16 +284,17 @@ __device__ __forceinline__ void face_lift_q(const R (&A1)[Ops<P>::NF], const R (
 
 // acc = gs * W(v) on the modes of part Q:
 //   W[x] = D_z v_y - D_y v_z, W[y] = D_x v_z - D_z v_x, W[z] = D_y v_x - D_x v_y
-template <int P, int Q, typename R, typename V>
+// for the input modes m < MI and the output modes l < MO (the others get 0)
+template <int P, int Q, typename R, int MI = Ops<P>::N, int MO = Ops<P>::N, typename V>
 __device__ __forceinline__ void volume_q(const V& v, R gs, R (&acc)[3][nq<P>()]) {
-  constexpr int N = Ops<P>::N, NQ = nq<P>();
+  constexpr int NQ = nq<P>();
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const int l = Q * NQ + i;
     R ax = 0, ay = 0, az = 0;
-    if (l < N) {
+    if (l < MO) {
 #pragma unroll
-      for (int m = 0; m < N; ++m) {
+      for (int m = 0; m < MI; ++m) {
         if (Ops<P>::D[0][l][m] != 0.0) {
           const R cx = Cst<R, P>::d(0, l, m);
           ay = fma(cx, v(2, m), ay);
@@ -361,17 +383,18 @@ constexpr bool face_needs(int c) {
 
 // trace of a field on face F from the LDS output staging [role][3N][tile],
 // stored to its halo-buffer slot: [input role of the field][k][m]
-template <int P, int F, typename R>
+// (MO: the field's modes)
+template <int P, int F, typename R, int MO = Ops<P>::N>
 __device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int tile, int li, Rsrc rH, int code,
                                              int hreg) {
   constexpr int N = Ops<P>::N, NF = Ops<P>::NF;
-  R w[3][N];
+  R w[3][MO];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int l = 0; l < N; ++l) w[c][l] = face_needs<F>(c) ? stg[((sf * 3 + c) * N + l) * tile + li] : R(0);
+    for (int l = 0; l < MO; ++l) w[c][l] = face_needs<F>(c) ? stg[((sf * 3 + c) * N + l) * tile + li] : R(0);
   R t0[NF], t1[NF];
-  face_trace<P, F, R>([&](int c, int l) { return w[c][l]; }, t0, t1);
+  face_trace<P, F, R, MO>([&](int c, int l) { return w[c][l]; }, t0, t1);
   // a field's traces feed the neighbour lanes of the other role (the region
   // of that role); the slot is 16-byte aligned, so it goes out in 16-byte stores
   const uint32_t base = (uint32_t)(code + (1 - role) * hreg) * (uint32_t)sizeof(R);
@@ -503,9 +526,10 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
 
 // lift of all four faces onto the modes of part Q; the flux coefficients of
 // face F of this element were published in its slot F*tile + li
-template <int P, int Q, typename R, bool C = false>
+template <int P, int Q, typename R, bool C = false, int MO = Ops<P>::N>
 __device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int li, R (&acc)[3][nq<P>()]) {
   constexpr int NF = Ops<P>::NF;
+  if constexpr (MO <= Q * nq<P>()) return;  // no output mode in this part
 #define MDG_LIFT_FACE(F)                                                   \
   {                                                                        \
     asm volatile("" ::: "memory");                                         \
@@ -515,7 +539,7 @@ __device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int
       A1[m] = s_[loff<NF>(0, m)];                                          \
       A2[m] = s_[loff<NF>(1, m)];                                          \
     }                                                                      \
-    face_lift_q<P, F, Q, R>(A1, A2, acc);                                  \
+    face_lift_q<P, F, Q, R, MO>(A1, A2, acc);                              \
   }
   MDG_LIFT_FACE(0)
   MDG_LIFT_FACE(1)
@@ -716,7 +740,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   typedef __attribute__((address_space(4))) const DevArgs KArgs;
   typedef __attribute__((address_space(3))) unsigned char lds_byte;
   // lane -> (part, role, element of the tile); the lanes of one part are a
-  // multiple of 64, so the part is uniform in a wave
+  // multiple of 64, so the part is uniform in a wave. Part q owns the modes
+  // q NQ + i of the output and the traces and fluxes of face face_of(q).
   struct Lane {
     int part, role, li;
   };
@@ -861,6 +886,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   KArgs& a = *ap;
   const Lane lane = lane_of(a, tid);
   const int part = lane.part, role = lane.role, li = lane.li;
+  const int face = part ? 4 - part : 0;  // face_of(part)
   const int t = a.tile_begin + tl;
   const int tnext = tl + nx;
   const bool more = PERSIST && tnext < tend;
@@ -902,7 +928,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       }
   }
 
-  // 4. trace of the input field on face `part` and the volume term of the
+  // 4. trace of the input field on the part's face and the volume term of the
   // part's modes, both reading the input field from the staging (not held in
   // registers, which keeps the register budget at five waves per SIMD)
   const R* vin_lds = stg + (C ? 0 : 1 - role) * R3 * tile + li;
@@ -914,21 +940,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   R acc[3][NQ];
   {
     R t0[NF], t1[NF];
-    if constexpr (MF) {
-      volume_mfma<P>(stg + (1 - role) * R3 * tile, part, g * sgn, acc);
-      asm volatile("" ::: "memory");
-      MDG_SWITCH_Q((face_trace<P, Q, R>(vl, t0, t1)));
-    } else {
-      MDG_SWITCH_Q((face_trace<P, Q, R>(vl, t0, t1)));
-      asm volatile("" ::: "memory");  // the volume term reads the staging again
-      MDG_SWITCH_Q((volume_q<P, Q, R>(vl, g * sgn, acc)));
-    }
+    // MI, MO: modes of the input and of the output field
+    auto trace_volume = [&](auto mi, auto mo) {
+      constexpr int MI = decltype(mi)::value, MO = decltype(mo)::value;
+      if constexpr (MF) {
+        volume_mfma<P>(stg + (1 - role) * R3 * tile, part, g * sgn, acc);
+        asm volatile("" ::: "memory");
+        MDG_SWITCH_Q((face_trace<P, face_of(Q), R, MI>(vl, t0, t1)));
+      } else {
+        MDG_SWITCH_Q((face_trace<P, face_of(Q), R, MI>(vl, t0, t1)));
+        asm volatile("" ::: "memory");  // the volume term reads the staging again
+        MDG_SWITCH_Q((volume_q<P, Q, R, MI, MO>(vl, g * sgn, acc)));
+      }
+    };
+    // mixed orders: the E lanes read h (NHc modes), the H lanes write it
+    if (MIX && role == 0) trace_volume(IC<NHc>{}, IC<N>{});
+    else trace_volume(IC<N>{}, IC<NHc>{});
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int i = 0; i < NQ; ++i) asm volatile("" : "+v"(acc[c][i]));
     __syncthreads();  // B0': every lane has read the staging
-    R* d = lds + lbase<NF, C>(part * tile + li, role);
+    R* d = lds + lbase<NF, C>(face * tile + li, role);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
       d[loff<NF>(0, m)] = t0[m];
@@ -937,7 +970,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   }
   __builtin_amdgcn_sched_barrier(0);
 
-  // 6. geometry and connectivity of face `part`, loaded while waiting at the
+  // 6. geometry and connectivity of the part's face, loaded while waiting at the
   // barrier (the input field is dead here)
   const R gxx = bld<R>(rG, vgeo, rowb<R>(G_XX)), gxy = bld<R>(rG, vgeo, rowb<R>(G_XY));
   const R gxz = bld<R>(rG, vgeo, rowb<R>(G_XZ)), gyy = bld<R>(rG, vgeo, rowb<R>(G_YY));
@@ -945,15 +978,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   R Z = 1, wz = 0.5;  // central: plain average
   if constexpr (UPW) {
     Z = bld<R>(rG, vgeo, rowb<R>(G_Z));
-    wz = bld<R>(rG, vgeo, rowb<R>(G_WZ0 + part));
+    wz = bld<R>(rG, vgeo, rowb<R>(G_WZ0 + face));
   }
-  R sipc = 0;  // alpha_F / mu_F of face `part`
-  if constexpr (SIP) sipc = bld<R>(rG, vgeo, rowb<R>(G_SIP0 + part));
+  R sipc = 0;  // alpha_F / mu_F of the face
+  if constexpr (SIP) sipc = bld<R>(rG, vgeo, rowb<R>(G_SIP0 + face));
   const R ieps = bld<R>(rG, vgeo, rowb<R>(G_IEPS)), imu = bld<R>(rG, vgeo, rowb<R>(G_IMU));
   const Rsrc rN = win_rsrc(a.nbr, a.nblk, b0, 4u * 64u * 4u);
-  const int code = bldi(rN, blk_rel(el, b0, 4, 4), (uint32_t)part * 256u);
+  const int code = bldi(rN, blk_rel(el, b0, 4, 4), (uint32_t)face * 256u);
   const Rsrc rPub = win_rsrc(a.pub, a.nblk, b0, 4u * 64u * 4u);
-  const int pcode = bldi(rPub, blk_rel(el, b0, 4, 4), (uint32_t)part * 256u);
+  const int pcode = bldi(rPub, blk_rel(el, b0, 4, 4), (uint32_t)face * 256u);
 
   __syncthreads();  // B1: traces of the tile and its halo are in LDS
   if constexpr (sizeof(R) == 4) {
@@ -969,17 +1002,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       }
   }
 
-  // 7. flux coefficients of face `part`
+  // 7. flux coefficients of the part's face
   {
     R A1[NF], A2[NF];
-    face_flux_coef<P, UPW, R, C>(part, lds, role, tile, li, hn, hb, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz,
+    face_flux_coef<P, UPW, R, C>(face, lds, role, tile, li, hn, hb, code, g, sgn, wz, Z, gxx, gxy, gxz, gyy, gyz,
                                  gzz, A1, A2);
     if constexpr (SIP) {
-      // face `part` of this element: sig = sign((t^1 x t^2) . n_out), rows
-      // (part, k, m) of the element's surface block
-      const R sig = ((part == 0 || part == 2) ? R(1) : R(-1)) * sgn;
+      // the face of this element: sig = sign((t^1 x t^2) . n_out), rows
+      // (face, k, m) of the element's surface block
+      const R sig = ((face == 0 || face == 2) ? R(1) : R(-1)) * sgn;
       const uint32_t vs = blk_rel(el, b0, 8 * NF, RS);
-      const int srow = part * 2 * NF;
+      const int srow = face * 2 * NF;
       if (role == 0) {
         // E: -(h_s x n, v)_F has the form of the averaged h term, so the
         // edge-tangent components of h_s add to the averaged traces
@@ -996,11 +1029,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         // D_k the face coefficients of (e- - e+) . t^k (e+ = 0 on PEC faces);
         // the physical metric g is |det A| g^, whose Jacobian cancels
         R g11, g12, g22;
-        face_metric_rt<R>(part, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
+        face_metric_rt<R>(face, gxx, gxy, gxz, gyy, gyz, gzz, g11, g12, g22);
         const R fs = sipc / sqrt(g11 * g22 - g12 * g12);
         const bool has = code >= 0;
-        const R* own = lds + lbase<NF, C>(part * tile + li, 1);
-        const R* nbr = lds + slot_base<NF, R, C>(has ? code : part * tile + li, 1, tile, hn, hb);
+        const R* own = lds + lbase<NF, C>(face * tile + li, 1);
+        const R* nbr = lds + slot_base<NF, R, C>(has ? code : face * tile + li, 1, tile, hn, hb);
         const R hn = has ? R(1) : R(0);
         const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip ? a.nblk : 0u, b0, 8u * NF * 64u * RS, a.bcoef,
                                 a.cdt, a.dt, false);
@@ -1019,8 +1052,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       }
     }
     __syncthreads();  // B2: every flux read of this tile is done
-    // publish the flux coefficients of face `part` in its own slot
-    R* d = lds + lbase<NF, C>(part * tile + li, role);
+    // publish the flux coefficients of the face in its own slot
+    R* d = lds + lbase<NF, C>(face * tile + li, role);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
       d[loff<NF>(0, m)] = A1[m];
@@ -1030,7 +1063,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   __syncthreads();  // B3
 
   // 8. lift of the four faces onto this part's modes
-  MDG_SWITCH_Q((lift_all_q<P, Q, R, C>(lds, role, tile, li, acc)));
+  if (MIX && role == 1) {
+    MDG_SWITCH_Q((lift_all_q<P, Q, R, C, NHc>(lds, role, tile, li, acc)));
+  } else {
+    MDG_SWITCH_Q((lift_all_q<P, Q, R, C>(lds, role, tile, li, acc)));
+  }
 
   // 9. point currents (E lanes): r_E -= g(t) phi_l(r0) (A^-1 d)_j, with the
   // amplitudes g(t) of the stage's time evaluated just before the launch
@@ -1179,7 +1216,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 
   // 13. traces of the output on faces that a neighbouring tile reads in the
   // next stage: stage the tile's output fields in LDS, then part Q traces
-  // face Q of its element into the neighbour tile's halo block. The next
+  // face face_of(Q) of its element into the neighbour tile's halo block. The next
   // tile's copies and operands are requested after the last barrier before
   // the final LDS reads of this tile.
   // the output is staged at OB: beside the trace slots when LDS has room
@@ -1201,7 +1238,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   if (more) prefetch(a, tid, tnext, early);
   if (a.publish && wr && pcode >= 0) {
     const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
-    MDG_SWITCH_Q((publish_face<P, Q, R>(lds + OB, sf, role, tile, li, rHo, pcode, a.hreg)));
+    if (MIX && role == 1) {
+      MDG_SWITCH_Q((publish_face<P, face_of(Q), R, NHc>(lds + OB, sf, role, tile, li, rHo, pcode, a.hreg)));
+    } else {
+      MDG_SWITCH_Q((publish_face<P, face_of(Q), R>(lds + OB, sf, role, tile, li, rHo, pcode, a.hreg)));
+    }
   }
   if (!more) break;
   tl = tnext;
