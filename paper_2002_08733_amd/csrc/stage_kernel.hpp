@@ -257,16 +257,16 @@ struct IC {
   static constexpr int value = V;
 };
 
-// acc[j][i] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m]),  l = Q*NQ + i,
-// for the output modes l < MO
-template <int P, int F, int Q, typename R, int MO = Ops<P>::N>
+// acc[j][i] += sum_m T_F[m][l] (t^1[j] A1[m] + t^2[j] A2[m]),  l = Q*QS + i
+// (QS modes per part), for the output modes l < MO
+template <int P, int F, int Q, typename R, int MO = Ops<P>::N, int QS = nq<P>()>
 __device__ __forceinline__ void face_lift_q(const R (&A1)[Ops<P>::NF], const R (&A2)[Ops<P>::NF],
                                             R (&acc)[3][nq<P>()]) {
   constexpr int NF = Ops<P>::NF, NQ = nq<P>();
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const int l = Q * NQ + i;
-    if (l >= MO) continue;
+    const int l = Q * QS + i;
+    if (i >= QS || l >= MO) continue;
     R L1 = 0, L2 = 0;
     bool first = true;
 #pragma unroll
@@ -282,17 +282,17 @@ __device__ __forceinline__ void face_lift_q(const R (&A1)[Ops<P>::NF], const R (
   }
 }
 
-// acc = gs * W(v) on the modes of part Q:
+// acc = gs * W(v) on the modes l = Q*QS + i of part Q (QS modes per part):
 //   W[x] = D_z v_y - D_y v_z, W[y] = D_x v_z - D_z v_x, W[z] = D_y v_x - D_x v_y
 // for the input modes m < MI and the output modes l < MO (the others get 0)
-template <int P, int Q, typename R, int MI = Ops<P>::N, int MO = Ops<P>::N, typename V>
+template <int P, int Q, typename R, int MI = Ops<P>::N, int MO = Ops<P>::N, int QS = nq<P>(), typename V>
 __device__ __forceinline__ void volume_q(const V& v, R gs, R (&acc)[3][nq<P>()]) {
   constexpr int NQ = nq<P>();
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const int l = Q * NQ + i;
+    const int l = Q * QS + i;
     R ax = 0, ay = 0, az = 0;
-    if (l < MO) {
+    if (i < QS && l < MO) {
 #pragma unroll
       for (int m = 0; m < MI; ++m) {
         if (Ops<P>::D[0][l][m] != 0.0) {
@@ -524,12 +524,13 @@ __device__ __forceinline__ void face_flux_coef(int F, const R* lds, int role, in
   }
 }
 
-// lift of all four faces onto the modes of part Q; the flux coefficients of
-// face F of this element were published in its slot F*tile + li
-template <int P, int Q, typename R, bool C = false, int MO = Ops<P>::N>
+// lift of all four faces onto the modes of part Q (QS per part, l < MO);
+// the flux coefficients of face F of this element were published in its
+// slot F*tile + li
+template <int P, int Q, typename R, bool C = false, int MO = Ops<P>::N, int QS = nq<P>()>
 __device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int li, R (&acc)[3][nq<P>()]) {
   constexpr int NF = Ops<P>::NF;
-  if constexpr (MO <= Q * nq<P>()) return;  // no output mode in this part
+  if constexpr (MO <= Q * QS) return;  // no output mode in this part
 #define MDG_LIFT_FACE(F)                                                   \
   {                                                                        \
     asm volatile("" ::: "memory");                                         \
@@ -539,7 +540,7 @@ __device__ __forceinline__ void lift_all_q(const R* lds, int role, int tile, int
       A1[m] = s_[loff<NF>(0, m)];                                          \
       A2[m] = s_[loff<NF>(1, m)];                                          \
     }                                                                      \
-    face_lift_q<P, F, Q, R, MO>(A1, A2, acc);                              \
+    face_lift_q<P, F, Q, R, MO, QS>(A1, A2, acc);                          \
   }
   MDG_LIFT_FACE(0)
   MDG_LIFT_FACE(1)
@@ -700,6 +701,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // modes of h per component in the state; rows of one element block (e
   // rows c N + l, then h rows 3N + c NHc + l) and bytes of one 64-element block
   constexpr int NHc = MIX ? Ops<(P > 1 ? P - 1 : 1)>::N : N;
+  // modes per part of the output h with mixed orders: its NHc modes spread
+  // over the four parts, so that no wave does two parts' work while another
+  // idles (the MFMA volume term keeps the parts of the full order)
+  constexpr int QSH = MIX && !MF ? (NHc + 3) / 4 : NQ;
   constexpr uint32_t RB = 3u * (N + NHc);
   constexpr uint32_t SBLK = RB * 64u * RS;
   // an offset past any window: a load there reads 0 (rows of h that the
@@ -771,8 +776,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     lds_byte* dst = (lds_byte*)smem_raw + (uint32_t)SB * RS;
     // state row of staging row sr ([staged field][3N]); with mixed orders
-    // the staging keeps N modes per component of h, the state only NHc:
-    // the others are zero-filled
+    // the staging keeps N modes per component of h, the state only NHc: the
+    // others are not copied (`zero`). Traces and the volume term read only
+    // the modes a field has; the MFMA volume term reads whole blocks, so for
+    // it those rows are cleared first, before any copy is in flight (an LDS
+    // store after an asynchronous copy into LDS waits for that copy).
     auto src_row = [&](uint32_t sr, bool& zero) -> uint32_t {
       const uint32_t f = C ? (uint32_t)fst : sr / R3, r = C ? sr : sr - f * R3;
       if constexpr (MIX) {
@@ -784,7 +792,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         return f * R3 + r;
       }
     };
-    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    if constexpr (MIX && MF) {
+      for (uint32_t vo = (uint32_t)tid * 4u; vo < nbytes; vo += nwv * 256u) {
+        bool zero;
+        src_row(vo >> rsh, zero);
+        if (zero) *reinterpret_cast<uint32_t*>(smem_raw + (uint32_t)SB * RS + vo) = 0u;
+      }
+    }
     if (e0 % (uint32_t)tile == 0) {
       // the tile lies in one 64-element block: 16 bytes per lane
       const uint32_t base = blk_rel(e0, b0, RB, RS);
@@ -792,10 +806,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
         bool zero;
         const uint32_t src = base + src_row(vo >> rsh, zero) * rowb<R>(1) + (vo & ((1u << rsh) - 1u));
-        if (vo < nbytes) {
-          if (zero) *reinterpret_cast<u32x4*>(smem_raw + (uint32_t)SB * RS + vo) = u32x4{0u, 0u, 0u, 0u};
-          else __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 1024u, 16, src, 0, 0, 0);
-        }
+        if (vo < nbytes && !zero) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 1024u, 16, src, 0, 0, 0);
       }
     } else {
       // a tile of the damped partition that straddles two blocks: 4 bytes
@@ -805,10 +816,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const uint32_t w = vo & ((1u << rsh) - 1u);
         bool zero;
         const uint32_t src = blk_rel(e0 + w / RS, b0, RB, RS) + src_row(vo >> rsh, zero) * rowb<R>(1) + w % RS;
-        if (vo < nbytes) {
-          if (zero) *reinterpret_cast<uint32_t*>(smem_raw + (uint32_t)SB * RS + vo) = 0u;
-          else __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, 0);
-        }
+        if (vo < nbytes && !zero) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, 0);
       }
     }
   };
@@ -844,6 +852,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   };
   auto out_s = [&](int c, int l) -> uint32_t { return MIX ? 0u : (uint32_t)(c * N + l) * rowb<R>(1); };
   auto out_ok = [&](int r, int l) -> bool { return !MIX || r == 0 || l < NHc; };
+  // output mode of slot q of part pt for role r, or N where there is none
+  auto mode_of = [&](int r, int pt, int q) -> int {
+    const int qs = MIX && r == 1 ? QSH : NQ, l = pt * qs + q;
+    return q < qs && l < (MIX && r == 1 ? NHc : N) ? l : N;
+  };
   // 2. RK operands of the part's output rows (absent operands read as 0),
   // requested with the tile's copies so that their latency overlaps the
   // trace, volume and flux work. FP32 loads the accumulator after barrier 1,
@@ -859,7 +872,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int l = min(L.part * NQ + q, N - 1);
+        const int l = min(mode_of(L.role, L.part, q), N - 1);
         const uint32_t v = vo + out_v(L.role, c, l), so = out_s(c, l);
         ypre[c][q] = bld<R, CP_NT>(ef.y_rd, v, so);
         if constexpr (sizeof(R) == 8) apre[c][q] = bld<R, CP_NT>(ef.a_rd, v, so);
@@ -923,8 +936,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
-        ypre[c][q] = stg[(role * R3 + c * N + (l < N ? l : N - 1)) * tile + li];
+        // (the staging does not hold the modes of h beyond its order)
+        const int l = mode_of(role, part, q);
+        ypre[c][q] = l < N ? stg[(role * R3 + c * N + l) * tile + li] : R(0);
       }
   }
 
@@ -941,8 +955,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   {
     R t0[NF], t1[NF];
     // MI, MO: modes of the input and of the output field
-    auto trace_volume = [&](auto mi, auto mo) {
-      constexpr int MI = decltype(mi)::value, MO = decltype(mo)::value;
+    auto trace_volume = [&](auto mi, auto mo, auto qs) {
+      constexpr int MI = decltype(mi)::value, MO = decltype(mo)::value, QS = decltype(qs)::value;
       if constexpr (MF) {
         volume_mfma<P>(stg + (1 - role) * R3 * tile, part, g * sgn, acc);
         asm volatile("" ::: "memory");
@@ -950,12 +964,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       } else {
         MDG_SWITCH_Q((face_trace<P, face_of(Q), R, MI>(vl, t0, t1)));
         asm volatile("" ::: "memory");  // the volume term reads the staging again
-        MDG_SWITCH_Q((volume_q<P, Q, R, MI, MO>(vl, g * sgn, acc)));
+        MDG_SWITCH_Q((volume_q<P, Q, R, MI, MO, QS>(vl, g * sgn, acc)));
       }
     };
     // mixed orders: the E lanes read h (NHc modes), the H lanes write it
-    if (MIX && role == 0) trace_volume(IC<NHc>{}, IC<N>{});
-    else trace_volume(IC<N>{}, IC<NHc>{});
+    if (MIX && role == 0) trace_volume(IC<NHc>{}, IC<N>{}, IC<NQ>{});
+    else trace_volume(IC<N>{}, IC<NHc>{}, IC<QSH>{});
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -996,8 +1010,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
-        const int lc = l < N ? l : N - 1;
+        const int lc = min(mode_of(role, part, q), N - 1);
         apre[c][q] = bld<R, CP_NT>(ef.a_rd, vout + out_v(role, c, lc), out_s(c, lc));
       }
   }
@@ -1064,7 +1077,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
 
   // 8. lift of the four faces onto this part's modes
   if (MIX && role == 1) {
-    MDG_SWITCH_Q((lift_all_q<P, Q, R, C, NHc>(lds, role, tile, li, acc)));
+    MDG_SWITCH_Q((lift_all_q<P, Q, R, C, NHc, QSH>(lds, role, tile, li, acc)));
   } else {
     MDG_SWITCH_Q((lift_all_q<P, Q, R, C>(lds, role, tile, li, acc)));
   }
@@ -1107,12 +1120,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   if (MIX && role == 1) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
-      if (part * NQ + q >= NHc) acc[0][q] = acc[1][q] = acc[2][q] = R(0);
+      if (mode_of(1, part, q) >= N) acc[0][q] = acc[1][q] = acc[2][q] = R(0);
   }
 
   const R bc = R(a.bcoef);
   const int stage = a.stage;
-  // rows of this part: row(c, q) = c*N + part*NQ + q, skipped past N
+  // rows of this part: row(c, q) = c*N + mode_of(role, part, q), skipped at N
   // 11. PML auxiliaries
   if constexpr (PML) {
     // damped elements are numbered from pml_base in the auxiliary arrays,
@@ -1144,7 +1157,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const Rsrc raW = win_rsrc(a.aYw, a.pnblk, pb0, SBLK, LF != 0);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int l = part * NQ + q;
+      const int l = mode_of(role, part, q);
       if (l >= N) continue;
       R u[3], qa[3];
 #pragma unroll
@@ -1202,7 +1215,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
+        const int l = mode_of(role, part, q);
         if (l >= N) continue;
         const uint32_t v = vout + out_v(role, c, l), so = out_s(c, l);
         const bool ok = wr && out_ok(role, l);
@@ -1230,7 +1243,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int l = part * NQ + q;
+        const int l = mode_of(role, part, q);
         if (l < N) sto[((sf * 3 + c) * N + l) * tile + li] = acc[c][q];
       }
     __syncthreads();  // B5
