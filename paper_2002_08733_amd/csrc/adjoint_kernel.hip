@@ -84,56 +84,70 @@ __global__ __launch_bounds__(256) void probe_add_kernel(R* __restrict__ nu, cons
   for (int r = threadIdx.x; r < 3 * N; r += 256) nu[base + r * 64] = (R)((double)nu[base + r * 64] + f * (double)u[base + r * 64]);
 }
 
-// g_T -= (a, A^T (eta c + q))_{M0, E, T} on PML elements, c = A^-T x_E and
-// q the scaled Cartesian auxiliary of the stage input: the damping part of
-// the stage derivative, which does not scale with 1/eps (with it, g_T gets
-// -(a, K_curl)_M0 where K_curl = K + A^T (eta c + q) is the part that does)
+// One forward stage of the reverse sweep, for every element T:
+//   g_T -= scale (a, K)_{M0, E, T}
+// and on the PML elements (k >= K0) the damping part of the stage derivative,
+// which does not scale with 1/eps, added back (with it g_T gets
+// -(a, K_curl)_M0 where K_curl = K + A^T (eta c + q) is the part that does):
+//   g_T -= scale (a, A^T (eta c + q))_{M0, E, T},  c = A^-T x_E,
+// q the scaled Cartesian auxiliary, (x, xa) + cs (dx, dxa) the forward stage
+// input (dx, dxa null: cs = 0). Four lanes per element, lane j taking the
+// modes l = j, j + 4, ...; the partial sums meet by shuffles in a fixed order.
 template <typename R, int N>
-__global__ __launch_bounds__(256) void grad_pml_kernel(double* __restrict__ g, const R* __restrict__ a,
-                                                       const R* __restrict__ x, const R* __restrict__ xa,
-                                                       const R* __restrict__ geo, const R* __restrict__ pml,
-                                                       int64_t K0, int64_t Kp, double scale, int64_t rb) {
-  const int64_t pk = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (pk >= Kp) return;
-  const int64_t k = K0 + pk;
-  double m[6];
-  mass0(geo, k, m);
-  const R* pr = pml + (pk >> 6) * NPML * 64 + (pk & 63);
-  double AT[9], AiT[9];
-  for (int i = 0; i < 9; ++i) {
-    AT[i] = pr[(PM_AT + i) * 64];
-    AiT[i] = pr[(PM_AIT + i) * 64];
+__global__ __launch_bounds__(256) void grad_stage_kernel(double* __restrict__ g, const R* __restrict__ a,
+                                                         const R* __restrict__ K, const R* __restrict__ x,
+                                                         const R* __restrict__ dx, const R* __restrict__ xa,
+                                                         const R* __restrict__ dxa, double cs,
+                                                         const R* __restrict__ geo, const R* __restrict__ pml,
+                                                         int64_t nk, int64_t K0, double scale, int64_t rb) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t k = t >> 2;
+  const int j = (int)(t & 3);
+  double s = 0.0;  // lanes past the last element add nothing but join the shuffles
+  if (k < nk) {
+    double m[6];
+    mass0(geo, k, m);
+    const int64_t ok = (k >> 6) * rb * 64 + (k & 63);
+    const R* ak = a + ok;
+    const R* kk = K + ok;
+    auto mdot = [&](const double (&v)[3], const double (&z)[3]) {
+      return v[0] * (m[0] * z[0] + m[1] * z[1] + m[2] * z[2]) + v[1] * (m[1] * z[0] + m[3] * z[1] + m[4] * z[2]) +
+             v[2] * (m[2] * z[0] + m[4] * z[1] + m[5] * z[2]);
+    };
+    for (int l = j; l < N; l += 4) {
+      double v[3], z[3];
+      for (int c = 0; c < 3; ++c) {
+        v[c] = ak[(c * N + l) * 64];
+        z[c] = kk[(c * N + l) * 64];
+      }
+      s += mdot(v, z);
+    }
+    if (k >= K0) {
+      const int64_t pk = k - K0, oq = (pk >> 6) * rb * 64 + (pk & 63);
+      const R* pr = pml + (pk >> 6) * NPML * 64 + (pk & 63);
+      double AT[9], AiT[9];
+      for (int i = 0; i < 9; ++i) {
+        AT[i] = pr[(PM_AT + i) * 64];
+        AiT[i] = pr[(PM_AIT + i) * 64];
+      }
+      const double wx = pr[(PM_OM + 0) * 64], wy = pr[(PM_OM + 1) * 64], wz = pr[(PM_OM + 2) * 64];
+      const double eta[3] = {wy + wz - wx, wz + wx - wy, wx + wy - wz};
+      auto xv = [&](int r) { return (double)x[ok + r * 64] + (dx ? cs * (double)dx[ok + r * 64] : 0.0); };
+      auto qv = [&](int r) { return (double)xa[oq + r * 64] + (dxa ? cs * (double)dxa[oq + r * 64] : 0.0); };
+      for (int l = j; l < N; l += 4) {
+        double u[3], y[3], z[3], v[3];
+        for (int c = 0; c < 3; ++c) u[c] = xv(c * N + l);
+        for (int i = 0; i < 3; ++i)
+          y[i] = eta[i] * (AiT[3 * i] * u[0] + AiT[3 * i + 1] * u[1] + AiT[3 * i + 2] * u[2]) + qv(i * N + l);
+        for (int c = 0; c < 3; ++c) z[c] = AT[3 * c] * y[0] + AT[3 * c + 1] * y[1] + AT[3 * c + 2] * y[2];
+        for (int c = 0; c < 3; ++c) v[c] = ak[(c * N + l) * 64];
+        s += mdot(v, z);
+      }
+    }
   }
-  const double wx = pr[(PM_OM + 0) * 64], wy = pr[(PM_OM + 1) * 64], wz = pr[(PM_OM + 2) * 64];
-  const double eta[3] = {wy + wz - wx, wz + wx - wy, wx + wy - wz};
-  const R* xk = x + (k >> 6) * rb * 64 + (k & 63);
-  const R* qk = xa + (pk >> 6) * rb * 64 + (pk & 63);
-  const R* ak = a + (k >> 6) * rb * 64 + (k & 63);
-  double s = 0.0;
-  for (int l = 0; l < N; ++l) {
-    double u[3], y[3], z[3], v[3];
-    for (int c = 0; c < 3; ++c) u[c] = xk[(c * N + l) * 64];
-    for (int i = 0; i < 3; ++i)
-      y[i] = eta[i] * (AiT[3 * i] * u[0] + AiT[3 * i + 1] * u[1] + AiT[3 * i + 2] * u[2]) +
-             (double)qk[(i * N + l) * 64];
-    for (int c = 0; c < 3; ++c) z[c] = AT[3 * c] * y[0] + AT[3 * c + 1] * y[1] + AT[3 * c + 2] * y[2];
-    for (int c = 0; c < 3; ++c) v[c] = ak[(c * N + l) * 64];
-    s += v[0] * (m[0] * z[0] + m[1] * z[1] + m[2] * z[2]) + v[1] * (m[1] * z[0] + m[3] * z[1] + m[4] * z[2]) +
-         v[2] * (m[2] * z[0] + m[4] * z[1] + m[5] * z[2]);
-  }
-  g[k] -= scale * s;
-}
-
-// g_T -= (a, K)_{M0, E, T} for every element
-template <typename R, int N>
-__global__ __launch_bounds__(256) void grad_acc_kernel(double* __restrict__ g, const R* __restrict__ a,
-                                                       const R* __restrict__ K, const R* __restrict__ geo, int64_t nk,
-                                                       double scale, int64_t rb) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= nk) return;
-  double m[6];
-  mass0(geo, k, m);
-  g[k] -= scale * e_dot<R, N>(a, K, m, k, rb);
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  if (j == 0 && k < nk) g[k] -= scale * s;
 }
 
 // ---------------------------------------------------------------- launch
@@ -181,36 +195,24 @@ void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* p
   check(hipGetLastError(), "probe_add_kernel launch");
 }
 
-void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, double scale, void* stream) {
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const void* geo = static_cast<char*>(s.ws) + s.L.geo;
-  const dim3 grid((unsigned)((s.K + 255) / 256));
-  const int64_t rb = state_rows(s);
-  if (s.opt.precision == MDG_FP32) {
-    MDG_BY_ORDER(float, grad_acc_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)K,
-                 (const float*)geo, s.K, scale, rb)
-  } else {
-    MDG_BY_ORDER(double, grad_acc_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)K,
-                 (const double*)geo, s.K, scale, rb)
-  }
-  check(hipGetLastError(), "grad_acc_kernel launch");
-}
-void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, double scale,
-                     void* stream) {
-  if (s.Kp == 0) return;
+void launch_grad_stage(const Solver& s, double* g, const void* a, const void* K, const void* x, const void* dx,
+                       const void* xa, const void* dxa, double c, double scale, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const void* geo = static_cast<char*>(s.ws) + s.L.geo;
   const void* pml = static_cast<char*>(s.ws) + s.L.pml;
-  const dim3 grid((unsigned)((s.Kp + 255) / 256));
+  const dim3 grid((unsigned)((4 * s.K + 255) / 256));
   const int64_t rb = state_rows(s);
+  const int64_t K0 = s.Kp > 0 ? s.K0 : s.K;  // no damped elements: no damping part
   if (s.opt.precision == MDG_FP32) {
-    MDG_BY_ORDER(float, grad_pml_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)x,
-                 (const float*)xa, (const float*)geo, (const float*)pml, s.K0, s.Kp, scale, rb)
+    MDG_BY_ORDER(float, grad_stage_kernel, grid, dim3(256), 0, st, g, (const float*)a, (const float*)K,
+                 (const float*)x, (const float*)dx, (const float*)xa, (const float*)dxa, c, (const float*)geo,
+                 (const float*)pml, s.K, K0, scale, rb)
   } else {
-    MDG_BY_ORDER(double, grad_pml_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)x,
-                 (const double*)xa, (const double*)geo, (const double*)pml, s.K0, s.Kp, scale, rb)
+    MDG_BY_ORDER(double, grad_stage_kernel, grid, dim3(256), 0, st, g, (const double*)a, (const double*)K,
+                 (const double*)x, (const double*)dx, (const double*)xa, (const double*)dxa, c,
+                 (const double*)geo, (const double*)pml, s.K, K0, scale, rb)
   }
-  check(hipGetLastError(), "grad_pml_kernel launch");
+  check(hipGetLastError(), "grad_stage_kernel launch");
 }
 #undef MDG_BY_ORDER
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -208,6 +209,10 @@ struct RKBufs {
   void *Y, *Ua, *Ub, *ACC;
   void *aY, *aUa, *aUb, *aACC;
   void *sY, *sUa, *sUb, *sACC;
+  // optional: the new state goes to Yout instead of Y; stage i stores its
+  // derivative in K[i]
+  void *Yout = nullptr, *aYout = nullptr, *sYout = nullptr;
+  void *K[4] = {}, *aK[4] = {}, *sK[4] = {};
 };
 
 RKBufs solver_bufs(const Solver& s) {
@@ -221,7 +226,8 @@ static const double RK_C[4] = {0.0, 0.5, 0.5, 1.0};
 
 // one classic RK4 step of the arrays b, one stage launch each (two with PML
 // elements): stage inputs Y -> Ua -> Ub -> Ua, the final update in place
-// into Y. The halo traces of Y must be in H0 (they are again after the step).
+// into Y (or into b.Yout). The halo traces of Y must be in H0 (those of the
+// new state are there after the step).
 // adj: the adjoint operator in the mass inner product (no sources); tick:
 // clock advanced by the last launch, or null. before(i, in): called before
 // stage i is enqueued, with the arrays of its input (Y, Ua or Ub).
@@ -256,6 +262,12 @@ void enqueue_rk4_step(Solver& s, const RKBufs& b, const double* clock, bool sour
     sp.sUin = sU[in];
     sp.sUout = i == 1 ? b.sUb : b.sUa;
     sp.sACC = b.sACC;
+    sp.Yout = b.Yout;
+    sp.aYout = b.aYout;
+    sp.sYout = b.sYout;
+    sp.Kout = b.K[i];
+    sp.aKout = b.aK[i];
+    sp.sKout = b.sK[i];
     // halo traces of the stage input in, of the stage output out
     sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
     sp.hout = dev(s, (i & 1) ? L.H0 : L.H1);
@@ -802,14 +814,16 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     };
     const int64_t k = std::min<int64_t>(every, nsteps);
     const int64_t nseg = (nsteps + k - 1) / k;
-    std::vector<SV> ck(nseg), seg(k);
+    // checkpoints u^{j k}; per step n of the segment being reversed its state
+    // x_n (seg, one more for the segment's end) and its stage derivatives
+    // K_1..K_4, stored by the recomputation (device memory: 5 k + 6 + nseg
+    // state vectors); the adjoint stepping arrays (nu is its base state)
+    std::vector<SV> ck(nseg), seg(k + 1);
+    std::vector<std::array<SV, 4>> Ks(k);
     for (auto& q : ck) q = alloc();
     for (auto& q : seg) q = alloc();
-    // forward stage values of one step: X_1 = x (the step's state), X_2..X_4
-    // and K_1..K_4; the adjoint stepping arrays (nu is its base state)
-    SV Xv[4], Kv[4];
-    for (int i = 1; i < 4; ++i) Xv[i] = alloc();
-    for (auto& q : Kv) q = alloc();
+    for (auto& st4 : Ks)
+      for (auto& q : st4) q = alloc();
     const SV nu = alloc(), aUa = alloc(), aUb = alloc(), aAcc = alloc(), uend = alloc();
     SV state;
     state.u = dev(s, s.L.Y);
@@ -855,73 +869,54 @@ mdg_status mdg_adjoint_probe_energy(mdg_solver* h, int64_t nsteps, int32_t every
     if (sip) hip_check(hipMemsetAsync(nu.s, 0, SS, st), "nu");
     launch_probe_add(s, nu.u, uend.u, pd, nprobe, dt, stream);
     const DevLayout& L = s.L;
-    // forward stage values of the step from x at clock ck: stage i < 3 is one
-    // launch with the first stage's epilogue and b = 1 (ACC <- K_i, the
-    // output <- X_{i+1} = x + c_{i+1} dt K_i, its halo traces published), K_4
-    // one operator launch
-    auto stage_values = [&](SV x, const double* ckl) {
-      launch_publish(s, x.u, dev(s, L.H0), stream);
-      for (int i = 0; i < 4; ++i) {
-        const SV in = i == 0 ? x : Xv[i];
-        StageParams sp{};
-        sp.stage = i < 3 ? 0 : -1;
-        sp.bcoef = 1.0;
-        sp.cdt = i < 3 ? RK_C[i + 1] * dt : 0.0;
-        sp.dt = dt;
-        sp.cstage = RK_C[i];
-        sp.clock = ckl;
-        sp.sources = true;
-        sp.Y = x.u;
-        sp.Uin = in.u;
-        sp.Uout = i < 3 ? Xv[i + 1].u : Kv[3].u;
-        sp.ACC = Kv[i].u;
-        sp.aY = x.q;
-        sp.aUin = in.q;
-        sp.aUout = i < 3 ? Xv[i + 1].q : Kv[3].q;
-        sp.aACC = Kv[i].q;
-        sp.sY = x.s;
-        sp.sUin = in.s;
-        sp.sUout = i < 3 ? Xv[i + 1].s : Kv[3].s;
-        sp.sACC = Kv[i].s;
-        sp.hin = dev(s, (i & 1) ? L.H1 : L.H0);
-        sp.hout = i < 3 ? dev(s, (i & 1) ? L.H0 : L.H1) : nullptr;
-        sp.publish = i < 3;
-        launch_stage(s, sp, stream);
-      }
-    };
     const RKBufs ab{nu.u, aUa.u, aUb.u, aAcc.u, nu.q, aUa.q, aUb.q, aAcc.q, nu.s, aUa.s, aUb.s, aAcc.s};
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
       const int64_t n0 = sgi * k, n1 = std::min(nsteps, n0 + k);
-      // recompute u^{n0 .. n1-1} from the checkpoint with the stepping path
+      // recompute the segment from its checkpoint by the stepping launches,
+      // each step from seg[j] into seg[j + 1], its stage derivatives into Ks[j]
       copy(seg[0], ck[sgi]);
-      copy(state, ck[sgi]);
-      hip_check(hipStreamSynchronize(st), "sync");
-      set_clock(s, s.L.clock, s.t0, double(nbase + n0));
-      s.halo_valid = false;
-      publish_if_needed(s, stream);
-      for (int64_t j = 1; j < n1 - n0; ++j) {
-        enqueue_steps(s, 1, stream);
-        copy(seg[j], state);
+      launch_publish(s, seg[0].u, dev(s, L.H0), stream);
+      for (int64_t j = 0; j < n1 - n0; ++j) {
+        RKBufs rb = solver_bufs(s);
+        rb.Y = seg[j].u;
+        rb.aY = seg[j].q;
+        rb.sY = seg[j].s;
+        rb.Yout = seg[j + 1].u;
+        rb.aYout = seg[j + 1].q;
+        rb.sYout = seg[j + 1].s;
+        for (int i = 0; i < 4; ++i) {
+          rb.K[i] = Ks[j][i].u;
+          rb.aK[i] = Ks[j][i].q;
+          rb.sK[i] = Ks[j][i].s;
+        }
+        enqueue_rk4_step(s, rb, clk + 2 * (n0 + j), true, false, nullptr, stream,
+                         [](int, const void*, const void*, const void*) {});
       }
+      // the halo traces of nu (the recomputation used the halo buffers); each
+      // adjoint step leaves those of its result in H0, and after the probe
+      // term only the probe elements' traces change
+      launch_publish(s, nu.u, dev(s, L.H0), stream);
       for (int64_t n = n1 - 1; n >= n0; --n) {
         const SV x = seg[n - n0];
-        stage_values(x, clk + 2 * n);
+        const std::array<SV, 4>& K = Ks[n - n0];
         // the adjoint step; before its stage i (input a_{4-i} / (b_{4-i} dt))
         // the gradient takes g -= (a, K_curl)_M0 over the E rows with the
-        // forward stage 4-i (only the curl part of K scales with 1/eps; PML
-        // elements add the damping part back) and, with the upwind flux,
-        // g += (a, dA/deps X) for the face impedances
-        launch_publish(s, nu.u, dev(s, L.H0), stream);
+        // forward stage f = 4-i (only the curl part of K scales with 1/eps;
+        // PML elements add the damping part back) and, with the upwind flux,
+        // g += (a, dA/deps X) for the face impedances, X_f = x + c_f dt K_{f-1}
+        // the forward stage input
         enqueue_rk4_step(s, ab, clk + 2 * n, false, true, nullptr, stream,
                          [&](int i, const void* in, const void*, const void*) {
                            const int f = 3 - i;  // forward stage
-                           const double sc = RK_B[f] * dt;
-                           launch_grad_acc(s, g, in, Kv[f].u, sc, stream);
-                           const SV Xf = f == 0 ? x : Xv[f];
-                           if (pml) launch_grad_pml(s, g, in, Xf.u, Xf.q, sc, stream);
-                           if (upw) launch_grad_upw(s, g, in, Xf.u, sc, stream);
+                           const double sc = RK_B[f] * dt, cf = RK_C[f] * dt;
+                           const SV kp = f ? K[f - 1] : SV{};
+                           launch_grad_stage(s, g, in, K[f].u, x.u, kp.u, x.q, kp.q, cf, sc, stream);
+                           if (upw) launch_grad_upw(s, g, in, x.u, kp.u, cf, sc, stream);
                          });
-        if (n >= 1) launch_probe_add(s, nu.u, x.u, pd, nprobe, dt, stream);
+        if (n >= 1) {
+          launch_probe_add(s, nu.u, x.u, pd, nprobe, dt, stream);
+          launch_publish(s, nu.u, dev(s, L.H0), stream, pd, nprobe);
+        }
       }
     }
     // the solver state is the forward end state

@@ -549,7 +549,7 @@ void finalize(Solver& s) {
   L.srcid = off; off = align256(off + size_t(s.Kpad) * 4);
   L.srcnext = off; off = align256(off + ndip * 4);
   L.srcwave = off; off = align256(off + ndip * 3 * 8);
-  L.srcamp = off; off = align256(off + ndip * 8);
+  L.srcamp = off; off = align256(off + 4 * ndip * 8);  // [RK4 stage][dipole]
   L.clock = off; off = align256(off + 2 * 8);
   L.rhs_clock = off; off = align256(off + 2 * 8);
   L.eelem = off; off = align256(off + size_t(s.K) * 8);

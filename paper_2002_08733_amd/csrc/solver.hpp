@@ -186,7 +186,8 @@ struct StageParams {
   const double* clock;
   bool sources = true;    // add the dipole currents
   double* tick = nullptr;  // device clock to advance by one step in this launch
-  // state buffers (E and H together, blocked layout)
+  // state buffers (E and H together, blocked layout); the final stage writes
+  // the new state to Yout, or in place into Y when Yout is null
   void* Y;
   const void* Uin;
   void* Uout;
@@ -200,6 +201,13 @@ struct StageParams {
   const void* sUin = nullptr;
   void* sUout = nullptr;
   void* sACC = nullptr;
+  void* Yout = nullptr;
+  void* aYout = nullptr;
+  void* sYout = nullptr;
+  // non-null: the stage derivative k is stored there as well
+  void* Kout = nullptr;
+  void* aKout = nullptr;
+  void* sKout = nullptr;
   // halo traces (see Solver::pub_code): read for the input, written for the output
   const void* hin;
   void* hout;
@@ -208,7 +216,9 @@ struct StageParams {
 };
 void launch_stage(const Solver& s, const StageParams& sp, void* stream);
 // halo traces of state U (blocked layout) into the halo buffer H
-void launch_publish(const Solver& s, const void* U, void* H, void* stream);
+// (list: only the nlist listed elements, a device array of element indices)
+void launch_publish(const Solver& s, const void* U, void* H, void* stream, const int64_t* list = nullptr,
+                    int nlist = 0);
 void launch_energy(const Solver& s, const void* Y, void* stream);
 // energy monitor: after launch_energy, compare the energy with the last one
 // recorded in mon (init: only record it); sets mon[1] to 1 on growth beyond
@@ -220,13 +230,15 @@ void launch_probe_energy(const Solver& s, const void* u, const int64_t* probes, 
                          void* stream);  // J += dt sum_probes (e, e)_M0
 void launch_probe_add(const Solver& s, void* nu, const void* u, const int64_t* probes, int np, double dt,
                       void* stream);  // nu_E += 2 dt / eps u_E on probes
-// g -= scale (a, K)_M0,E
-void launch_grad_acc(const Solver& s, double* g, const void* a, const void* K, double scale, void* stream);
-// PML elements: g -= scale (a, A^T (eta A^-T x_E + xa_E))_M0,E for stage input (x, xa)
-void launch_grad_pml(const Solver& s, double* g, const void* a, const void* x, const void* xa, double scale,
-                     void* stream);
-// upwind flux: g += scale (a, dA/deps x), the impedance dependence of the face
-// terms (stage_kernel.hip, where the face operators live)
-void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, double scale, void* stream);
+// one forward stage: g -= scale (a, K)_M0,E, and on PML elements
+// g -= scale (a, A^T (eta A^-T x_E + xa_E))_M0,E for the stage input
+// (x, xa) + c (dx, dxa) (dx, dxa null: the stage input is (x, xa))
+void launch_grad_stage(const Solver& s, double* g, const void* a, const void* K, const void* x, const void* dx,
+                       const void* xa, const void* dxa, double c, double scale, void* stream);
+// upwind flux: g += scale (a, dA/deps x) for the stage input x + c dx (dx may
+// be null), the impedance dependence of the face terms (stage_kernel.hip,
+// where the face operators live)
+void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, const void* dx, double c,
+                     double scale, void* stream);
 
 }  // namespace mdg

@@ -14,17 +14,19 @@ namespace mdg {
 struct DevArgs {
   const void* Y;      // RK base state u^n (E,H), blocked layout
   const void* Uin;    // stage input
-  void* Uout;         // next stage input / operator output
+  void* Uout;         // next stage input / operator output / new state (final stage)
+  void* Kout;         // non-null: the stage derivative k is stored here too
   void* ACC;          // RK accumulator
-  void* Yw;           // = Y (final in-place update)
   const void* aY;     // same for the PML auxiliaries
   const void* aUin;
   void* aUout;
+  void* aKout;
   void* aACC;
   void* aYw;
   const void* sY;     // SIP surface unknown [K/64][face][k][NF][64]: RK base (leap-frog: updated in place)
   const void* sUin;   // stage input
-  void* sUout;        // next stage input / operator output
+  void* sUout;        // next stage input / operator output / new state (final stage)
+  void* sKout;        // non-null: the stage derivative stored here too
   void* sACC;         // RK accumulator
   const void* geo;
   const int32_t* nbr;
@@ -36,7 +38,7 @@ struct DevArgs {
   const void* src;            // dipole load vectors [ndip][3][N]
   const int32_t* srcid;       // blocked [Kpad/64][64]: first dipole acting on the element, or -1
   const int32_t* srcnext;     // [ndip]: next dipole on the same element, or -1
-  const double* srcamp;       // [ndip]: g(t) of every dipole at the stage's time
+  const double* srcamp;       // [ndip]: g(t) of every dipole at the launch's time
   double* tick;               // non-null: advance this device clock (n += 1) once
   // array sizes: the element arrays (whole 64-element blocks) are addressed
   // through per-tile windows and given in blocks (any size): nblk for the
@@ -64,10 +66,10 @@ template <typename R, int P>
 void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, double* eelem, int nh, hipStream_t st);
 template <typename R, int P>
 void launch_publish_rp(const void* U, uint32_t nblk, int nh, const int32_t* pub, void* H, uint32_t hb, int K,
-                       int hreg, hipStream_t st);
+                       int hreg, const int64_t* list, int nlist, hipStream_t st);
 template <typename R, int P>
-void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* geo, const int32_t* nbrg, int64_t K,
-                        double scale, int nh, hipStream_t st);
+void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* dx, double cs, const void* geo,
+                        const int32_t* nbrg, int64_t K, double scale, int nh, hipStream_t st);
 
 // every (precision, order) pair the library is built for
 #define MDG_FOR_EACH_RP(X) X(float, 1) X(float, 2) X(float, 3) X(float, 4) X(double, 1) X(double, 2) X(double, 3) X(double, 4)

@@ -412,17 +412,19 @@ __device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int
 // traffic, a store through one is dropped.
 //   stage 0:    ACC = b k,         Uout = y + c dt k        (a = 0)
 //   stage 1,2:  ACC = a + b k,     Uout = y + c dt k
-//   stage 3:    Y   = y + dt (a + b k)                      (ACC store dropped)
+//   stage 3:    Uout = y + dt (a + b k)                     (ACC store dropped;
+//               Uout is Y itself for the in-place step)
 //   operator:   Uout = k                                    (y = a = 0, c dt = 1)
+// With a K array (k_on) the stage derivative k itself is stored there too.
 //   leap-frog half (stage 4: E, 5: H): Y = y + dt k for the active field, with
 //               y taken from the staged input (the stage input is Y itself) or,
 //               with four lanes per element, loaded like the RK4 operands
 struct Epi {
-  Rsrc y_rd, a_rd, a_wr, out_wr;
-  bool final_stage;
+  Rsrc y_rd, a_rd, a_wr, out_wr, k_wr;
+  bool final_stage, k_on;
   double c_out;  // c_{i+1} dt, dt (final, leap-frog) or 1 (operator)
 };
-__device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* ACC, const void* Uout,
+__device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* ACC, const void* Uout, const void* K,
                                         uint32_t nblk, uint32_t b0, uint32_t block_bytes, double bcoef,
                                         double cdt, double dt, bool y_staged) {
   Epi e;
@@ -431,7 +433,9 @@ __device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* AC
   e.y_rd = win_rsrc(Y, nblk, b0, block_bytes, !(op || (lf && y_staged)));
   e.a_rd = win_rsrc(ACC, nblk, b0, block_bytes, stage >= 1 && stage <= 3);
   e.a_wr = win_rsrc(ACC, nblk, b0, block_bytes, stage >= 0 && stage <= 2);
-  e.out_wr = win_rsrc((e.final_stage || lf) ? Y : Uout, nblk, b0, block_bytes);
+  e.out_wr = win_rsrc(lf ? Y : Uout, nblk, b0, block_bytes);
+  e.k_on = K != nullptr;
+  e.k_wr = win_rsrc(K, nblk, b0, block_bytes, e.k_on);
   e.c_out = op ? 1.0 : ((e.final_stage || lf) ? dt : cdt);
   (void)bcoef;
   return e;
@@ -444,6 +448,7 @@ __device__ __forceinline__ void rk_store(const Epi& e, R k, uint32_t vo, uint32_
   if (live) {
     bst<R, CP_NT>(acc, e.a_wr, vo, so);
     bst<R, CP_NT>(fma(c_out, e.final_stage ? acc : k, y), e.out_wr, vo, so);
+    if (e.k_on) bst<R, CP_NT>(k, e.k_wr, vo, so);
   }
 }
 // same with y and a loaded earlier; returns the value written to the output
@@ -456,6 +461,7 @@ __device__ __forceinline__ R rk_store_pre(const Epi& e, R k, R y, R a, uint32_t 
   if (live) {
     bst<R, CP_NT>(acc, e.a_wr, vo, so);
     bst<R, CP_NT>(out, e.out_wr, vo, so);
+    if (e.k_on) bst<R, CP_NT>(k, e.k_wr, vo, so);
   }
   return out;
 }
@@ -867,7 +873,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const uint32_t b0 = (uint32_t)(A.elem_begin + tix * tile) >> 6;
     const uint32_t e = (uint32_t)(A.elem_begin + tix * tile + L.li);
     const uint32_t vo = blk_rel(e, b0, RB, RS);
-    const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.nblk, b0, SBLK, A.bcoef, A.cdt, A.dt, LF == 1);
+    const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.Kout, A.nblk, b0, SBLK, A.bcoef, A.cdt, A.dt, LF == 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -915,7 +921,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const Rsrc rG = win_rsrc(a.geo, a.nblk, b0, NGEO * 64u * RS);
   const uint32_t vout = blk_rel(el, b0, RB, RS);  // element's state block
   const uint32_t vgeo = blk_rel(el, b0, NGEO, RS);
-  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.nblk, b0, SBLK, a.bcoef, a.cdt, a.dt, LF == 1);
+  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.Kout, a.nblk, b0, SBLK, a.bcoef, a.cdt, a.dt, LF == 1);
   const int hn = uniform_ld(a.halo_tile, 2 * t + 1);  // halo slots of this tile
   const int hb = HB;
   __syncthreads();  // B0: the tile's input field(s) and halo block are in LDS
@@ -1048,7 +1054,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const R* own = lds + lbase<NF, C>(face * tile + li, 1);
         const R* nbr = lds + slot_base<NF, R, C>(has ? code : face * tile + li, 1, tile, hn, hb);
         const R hn = has ? R(1) : R(0);
-        const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sip ? a.nblk : 0u, b0, 8u * NF * 64u * RS, a.bcoef,
+        const Epi es = make_epi(a.stage, a.sY, a.sACC, a.sUout, a.sKout, a.sip ? a.nblk : 0u, b0, 8u * NF * 64u * RS, a.bcoef,
                                 a.cdt, a.dt, false);
         const R cs = R(es.c_out), bs = R(a.bcoef);
 #pragma unroll
@@ -1135,7 +1141,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const Rsrc rP = win_rsrc(a.pml, a.pnblk, pb0, NPML * 64u * RS);
     const uint32_t vp = blk_rel(pk, pb0, NPML, RS);
     const Rsrc raU = win_rsrc(a.aUin, a.pnblk, pb0, SBLK);
-    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.pnblk, pb0, SBLK, a.bcoef, a.cdt, a.dt, false);
+    const Epi ea = make_epi(stage, a.aY, a.aACC, a.aUout, a.aKout, a.pnblk, pb0, SBLK, a.bcoef, a.cdt, a.dt, false);
     const R ca = R(ea.c_out);
     const uint32_t va = blk_rel(pk, pb0, RB, RS);
     R AT[9], AiT[9];
@@ -1325,16 +1331,27 @@ __device__ __forceinline__ void publish_face_global(const R (&w)[3][Ops<P>::N], 
 }
 
 template <typename R, int P>
+// (list non-null: only the listed elements, one per workgroup of 64 lanes)
 __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nblk, int nh, const int32_t* pub,
-                                                      void* H, uint32_t hbuf_bytes, int K,
-                                                      int hreg) {
+                                                      void* H, uint32_t hbuf_bytes, int K, int hreg,
+                                                      const int64_t* list) {
   constexpr int N = Ops<P>::N, R3 = 3 * N;
   constexpr uint32_t RS = sizeof(R);
-  const int gid = blockIdx.x * 256 + threadIdx.x;
-  const int el = gid >> 1, fld = gid & 1;
-  if (el >= K) return;
-  // the 32 elements of a wave lie in one 64-element block: windows at it
-  const uint32_t b0 = (uint32_t)((blockIdx.x * 256 + (threadIdx.x & ~63u)) >> 1) >> 6;
+  int el, fld;
+  uint32_t b0;  // windows at the block of the wave's elements
+  if (list) {
+    if (threadIdx.x >= 2) return;  // lanes 0, 1: the element's two fields
+    el = (int)list[blockIdx.x];
+    fld = (int)threadIdx.x;
+    b0 = (uint32_t)el >> 6;
+  } else {
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    el = gid >> 1;
+    fld = gid & 1;
+    if (el >= K) return;
+    // the 32 elements of a wave lie in one 64-element block
+    b0 = (uint32_t)((blockIdx.x * 256 + (threadIdx.x & ~63u)) >> 1) >> 6;
+  }
   const uint32_t rb = 3u * (uint32_t)(N + nh);  // rows of an element block: e, then h with nh modes
   const Rsrc rU = win_rsrc(U, nblk, b0, rb * 64u * RS), rP = win_rsrc(pub, nblk, b0, 4u * 64u * 4u);
   const Rsrc rH = make_rsrc(H, hbuf_bytes);
@@ -1368,14 +1385,19 @@ __global__ __launch_bounds__(256) void publish_kernel(const void* U, uint32_t nb
 // = sum_m tau_1(a)[m] A1[m] + tau_2(a)[m] A2[m] (the lift is the transposed
 // trace). Runs in FP64 on either state precision.
 
-// traces of field fld (0: E, 1: H) of element e on face F (runtime)
+// traces of field fld (0: E, 1: H) of element e of the state u + cs du (du
+// may be null) on face F (runtime)
 template <typename R, int P>
-__device__ void traces_rt(const R* __restrict__ u, int64_t e, int fld, int F, double (&t0)[Ops<P>::NF],
-                          double (&t1)[Ops<P>::NF], int nh) {
+__device__ void traces_rt(const R* __restrict__ u, const R* __restrict__ du, double cs, int64_t e, int fld, int F,
+                          double (&t0)[Ops<P>::NF], double (&t1)[Ops<P>::NF], int nh) {
   constexpr int N = Ops<P>::N;
   const int st = fld ? nh : N;  // e rows c N + l, then h rows 3N + c nh + l
-  const R* ue = u + (e >> 6) * (int64_t)(3 * (N + nh)) * 64 + (e & 63) + fld * 3 * N * 64;
-  auto v = [&](int c, int l) { return l < st ? (double)ue[(c * st + l) * 64] : 0.0; };
+  const int64_t o = (e >> 6) * (int64_t)(3 * (N + nh)) * 64 + (e & 63) + fld * 3 * N * 64;
+  auto v = [&](int c, int l) {
+    if (l >= st) return 0.0;
+    const int64_t r = o + (c * st + l) * 64;
+    return (double)u[r] + (du ? cs * (double)du[r] : 0.0);
+  };
   switch (F) {
     case 0: face_trace<P, 0, double>(v, t0, t1); break;
     case 1: face_trace<P, 1, double>(v, t0, t1); break;
@@ -1388,8 +1410,9 @@ __device__ void traces_rt(const R* __restrict__ u, int64_t e, int fld, int F, do
 // whose other side is (en, fn) (PEC: en = e, fn = F), given dom / dpen, the
 // derivatives of the own weight and of the penalty factor, for field role r
 template <typename R, int P>
-__device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, const R* __restrict__ geo,
-                           int64_t e, int F, int64_t en, int fn, bool has, int r, double dom, double dpen, int nh) {
+__device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, const R* __restrict__ dx, double cs,
+                           const R* __restrict__ geo, int64_t e, int F, int64_t en, int fn, bool has, int r,
+                           double dom, double dpen, int nh) {
   constexpr int NF = Ops<P>::NF;
   const double g = r ? -1.0 : 1.0;
   const double fin = has ? 1.0 : g, fout = has ? 1.0 : -g;  // PEC mirror of the input / output field
@@ -1402,22 +1425,22 @@ __device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, con
   const double idet = 1.0 / sqrt(g11 * g22 - g12 * g12);
   const double W11 = g22 * idet, W12 = -g12 * idet, W22 = g11 * idet;
   double ta0[NF], ta1[NF], v0[NF], v1[NF];
-  traces_rt<R, P>(a, e, r, F, ta0, ta1, nh);  // the adjoint of the output field
+  traces_rt<R, P>(a, nullptr, 0.0, e, r, F, ta0, ta1, nh);  // the adjoint of the output field
   double s_avg = 0.0, s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
   // averaged input field: d(A1, A2)/dom = c (xm1 - xp1, -(xm0 - xp0))
-  traces_rt<R, P>(x, e, 1 - r, F, v0, v1, nh);
+  traces_rt<R, P>(x, dx, cs, e, 1 - r, F, v0, v1, nh);
   for (int m = 0; m < NF; ++m) s_avg += ta0[m] * v1[m] - ta1[m] * v0[m];
-  traces_rt<R, P>(x, en, 1 - r, fn, v0, v1, nh);
+  traces_rt<R, P>(x, dx, cs, en, 1 - r, fn, v0, v1, nh);
   for (int m = 0; m < NF; ++m) s_avg -= fin * (ta0[m] * v1[m] - ta1[m] * v0[m]);
   // penalty on the jump of the output field: d(A1, A2)/dpen = W (j0, j1)
-  traces_rt<R, P>(x, en, r, fn, v0, v1, nh);
+  traces_rt<R, P>(x, dx, cs, en, r, fn, v0, v1, nh);
   for (int m = 0; m < NF; ++m) {
     s00 += fout * ta0[m] * v0[m];
     s01 += fout * ta0[m] * v1[m];
     s10 += fout * ta1[m] * v0[m];
     s11 += fout * ta1[m] * v1[m];
   }
-  traces_rt<R, P>(x, e, r, F, v0, v1, nh);
+  traces_rt<R, P>(x, dx, cs, e, r, F, v0, v1, nh);
   for (int m = 0; m < NF; ++m) {
     s00 -= ta0[m] * v0[m];
     s01 -= ta0[m] * v1[m];
@@ -1429,8 +1452,9 @@ __device__ double upw_side(const R* __restrict__ a, const R* __restrict__ x, con
 
 template <typename R, int P>
 __global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout, const R* __restrict__ a,
-                                                      const R* __restrict__ x, const R* __restrict__ geo,
-                                                      const int32_t* __restrict__ nbrg, int64_t K, double scale, int nh) {
+                                                      const R* __restrict__ x, const R* __restrict__ dx, double cs,
+                                                      const R* __restrict__ geo, const int32_t* __restrict__ nbrg,
+                                                      int64_t K, double scale, int nh) {
   const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (k >= K) return;
   const R* gk = geo + (k >> 6) * NGEO * 64 + (k & 63);
@@ -1453,12 +1477,12 @@ __global__ __launch_bounds__(64) void grad_upw_kernel(double* __restrict__ gout,
         dom = 0.0;
         dpen = r ? 0.5 : -0.5 / (Z * Z);
       }
-      sum += upw_side<R, P>(a, x, geo, k, F, kn, fn, has, r, dom, dpen, nh);
+      sum += upw_side<R, P>(a, x, dx, cs, geo, k, F, kn, fn, has, r, dom, dpen, nh);
       // the neighbour's equations, where T is the other side (Z_T = Z+)
       if (has) {
         const double dom2 = r ? Zn / S2 : -Zn / S2;
         const double dpen2 = r ? Zn * Zn / S2 : -1.0 / S2;
-        sum += upw_side<R, P>(a, x, geo, kn, fn, k, F, true, r, dom2, dpen2, nh);
+        sum += upw_side<R, P>(a, x, dx, cs, geo, kn, fn, k, F, true, r, dom2, dpen2, nh);
       }
     }
   }
@@ -1586,18 +1610,24 @@ void launch_energy_rp(const void* Y, const void* geo, int64_t K, double* part, d
 
 template <typename R, int P>
 void launch_publish_rp(const void* U, uint32_t nblk, int nh, const int32_t* pub, void* H, uint32_t hb, int K,
-                       int hreg, hipStream_t st) {
-  const dim3 grid((unsigned)((2 * (int64_t)K + 255) / 256));
-  hipLaunchKernelGGL((publish_kernel<R, P>), grid, dim3(256), 0, st, U, nblk, nh, pub, H, hb, K, hreg);
+                       int hreg, const int64_t* list, int nlist, hipStream_t st) {
+  if (list) {
+    if (nlist > 0)
+      hipLaunchKernelGGL((publish_kernel<R, P>), dim3(nlist), dim3(64), 0, st, U, nblk, nh, pub, H, hb, K, hreg, list);
+  } else {
+    const dim3 grid((unsigned)((2 * (int64_t)K + 255) / 256));
+    hipLaunchKernelGGL((publish_kernel<R, P>), grid, dim3(256), 0, st, U, nblk, nh, pub, H, hb, K, hreg, list);
+  }
   hip_check(hipGetLastError(), "publish_kernel launch");
 }
 
 template <typename R, int P>
-void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* geo, const int32_t* nbrg, int64_t K,
-                        double scale, int nh, hipStream_t st) {
+void launch_grad_upw_rp(double* g, const void* a, const void* x, const void* dx, double cs, const void* geo,
+                        const int32_t* nbrg, int64_t K, double scale, int nh, hipStream_t st) {
   const dim3 grid((unsigned)((K + 63) / 64));
   hipLaunchKernelGGL((grad_upw_kernel<R, P>), grid, dim3(64), 0, st, g, static_cast<const R*>(a),
-                     static_cast<const R*>(x), static_cast<const R*>(geo), nbrg, K, scale, nh);
+                     static_cast<const R*>(x), static_cast<const R*>(dx), cs, static_cast<const R*>(geo), nbrg, K,
+                     scale, nh);
   hip_check(hipGetLastError(), "grad_upw_kernel launch");
 }
 

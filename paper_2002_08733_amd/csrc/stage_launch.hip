@@ -14,18 +14,22 @@ static void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(MDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// dipole amplitudes at the stage's time t = t0 + (n + cstage) dt of the
-// device clock: the Gaussian-modulated sinusoid
+// dipole amplitudes at the times t = t0 + (n + c_j) dt of the device clock,
+// j < ns, into amp[j][d]: the Gaussian-modulated sinusoid
 // g(t) = sin(2 pi f0 (t - tc)) exp(-(t - tc)^2 / (2 s^2)), s = 1/(2 pi bw), in FP64
-__global__ __launch_bounds__(256) void src_amp_kernel(const double* __restrict__ clock, double cstage, double dt,
+struct StageTimes {
+  double c[4];
+};
+__global__ __launch_bounds__(256) void src_amp_kernel(const double* __restrict__ clock, StageTimes cs, int ns, double dt,
                                                       const double* __restrict__ wave, int nd,
                                                       double* __restrict__ amp) {
-  const int d = blockIdx.x * 256 + threadIdx.x;
-  if (d >= nd) return;
-  const double t = clock[0] + (clock[1] + cstage) * dt;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= ns * nd) return;
+  const int j = i / nd, d = i - j * nd;
+  const double t = clock[0] + (clock[1] + cs.c[j]) * dt;
   const double pi = 3.14159265358979323846;
   const double tau = t - wave[3 * d + 2], sg = 1.0 / (2.0 * pi * wave[3 * d + 1]);
-  amp[d] = sin(2.0 * pi * wave[3 * d] * tau) * exp(-tau * tau / (2.0 * sg * sg));
+  amp[i] = sin(2.0 * pi * wave[3 * d] * tau) * exp(-tau * tau / (2.0 * sg * sg));
 }
 
 __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ part, int64_t n,
@@ -54,19 +58,23 @@ static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int 
 void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   char* base = static_cast<char*>(s.ws);
   DevArgs a{};
+  // the final RK4 stage writes the new state through Uout: into Yout, or in place
+  const bool fin = sp.stage == 3;
   a.Y = sp.Y;
-  a.Yw = sp.Y;
   a.Uin = sp.Uin;
-  a.Uout = sp.Uout;
+  a.Uout = fin ? (sp.Yout ? sp.Yout : sp.Y) : sp.Uout;
+  a.Kout = sp.Kout;
   a.ACC = sp.ACC;
   a.aY = sp.aY;
   a.aYw = sp.aY;
   a.aUin = sp.aUin;
-  a.aUout = sp.aUout;
+  a.aUout = fin ? (sp.aYout ? sp.aYout : sp.aY) : sp.aUout;
+  a.aKout = sp.aKout;
   a.aACC = sp.aACC;
   a.sY = sp.sY;
   a.sUin = sp.sUin;
-  a.sUout = sp.sUout;
+  a.sUout = fin ? (sp.sYout ? sp.sYout : sp.sY) : sp.sUout;
+  a.sKout = sp.sKout;
   a.sACC = sp.sACC;
   a.geo = base + s.L.geo;
   a.nbr = reinterpret_cast<const int32_t*>(base + s.L.nbr);
@@ -107,11 +115,20 @@ void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   a.tile = s.tile;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (a.has_src) {
+    // the amplitudes of all four stages of an RK4 step are evaluated before
+    // its first stage (the clock advances in its last), those of any other
+    // launch before it
     const int nd = (int)s.dips.size();
-    hipLaunchKernelGGL(src_amp_kernel, dim3((nd + 255) / 256), dim3(256), 0, st, sp.clock, sp.cstage, sp.dt,
-                       reinterpret_cast<const double*>(base + s.L.srcwave), nd,
-                       reinterpret_cast<double*>(base + s.L.srcamp));
-    hip_check(hipGetLastError(), "src_amp_kernel launch");
+    const bool rk = sp.stage >= 0 && sp.stage <= 3;
+    double* amp = reinterpret_cast<double*>(base + s.L.srcamp);
+    if (!rk || sp.stage == 0) {
+      const int ns = rk ? 4 : 1;
+      const StageTimes cs = rk ? StageTimes{{0.0, 0.5, 0.5, 1.0}} : StageTimes{{sp.cstage, 0.0, 0.0, 0.0}};
+      hipLaunchKernelGGL(src_amp_kernel, dim3((ns * nd + 255) / 256), dim3(256), 0, st, sp.clock, cs, ns, sp.dt,
+                         reinterpret_cast<const double*>(base + s.L.srcwave), nd, amp);
+      hip_check(hipGetLastError(), "src_amp_kernel launch");
+    }
+    a.srcamp = amp + (rk ? sp.stage : 0) * nd;
   }
   // non-PML tiles, then PML tiles; the last launch carries the clock tick
   const int last = s.ntiles > s.ntiles0 ? 1 : 0;
@@ -178,7 +195,8 @@ void launch_monitor(const Solver& s, bool init, bool growth, double tol, void* s
 }
 
 template <typename R>
-static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_t st) {
+static void launch_publish_r(const Solver& s, const void* U, void* H, const int64_t* list, int nlist,
+                             hipStream_t st) {
   char* base = static_cast<char*>(s.ws);
   const size_t rs = s.real_size();
   const uint32_t nblk = (uint32_t)(s.Kpad / 64);
@@ -186,27 +204,28 @@ static void launch_publish_r(const Solver& s, const void* U, void* H, hipStream_
   const int32_t* pub = reinterpret_cast<const int32_t*>(base + s.L.pub);
   const int K = (int)s.K, hreg = (int)s.hreg;
   switch (s.P) {
-    case 1: launch_publish_rp<R, 1>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
-    case 2: launch_publish_rp<R, 2>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
-    case 3: launch_publish_rp<R, 3>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
-    case 4: launch_publish_rp<R, 4>(U, nblk, s.NH, pub, H, hb, K, hreg, st); break;
+    case 1: launch_publish_rp<R, 1>(U, nblk, s.NH, pub, H, hb, K, hreg, list, nlist, st); break;
+    case 2: launch_publish_rp<R, 2>(U, nblk, s.NH, pub, H, hb, K, hreg, list, nlist, st); break;
+    case 3: launch_publish_rp<R, 3>(U, nblk, s.NH, pub, H, hb, K, hreg, list, nlist, st); break;
+    case 4: launch_publish_rp<R, 4>(U, nblk, s.NH, pub, H, hb, K, hreg, list, nlist, st); break;
     default: throw Error(MDG_E_UNSUPPORTED, "order not compiled");
   }
 }
 
-void launch_publish(const Solver& s, const void* U, void* H, void* stream) {
+void launch_publish(const Solver& s, const void* U, void* H, void* stream, const int64_t* list, int nlist) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (s.nhalo == 0) return;
-  if (s.opt.precision == MDG_FP32) launch_publish_r<float>(s, U, H, st);
-  else launch_publish_r<double>(s, U, H, st);
+  if (s.opt.precision == MDG_FP32) launch_publish_r<float>(s, U, H, list, nlist, st);
+  else launch_publish_r<double>(s, U, H, list, nlist, st);
 }
 
-void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, double scale, void* stream) {
+void launch_grad_upw(const Solver& s, double* g, const void* a, const void* x, const void* dx, double c,
+                     double scale, void* stream) {
   char* base = static_cast<char*>(s.ws);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int32_t* nb = reinterpret_cast<const int32_t*>(base + s.L.nbrg);
   const void* geo = base + s.L.geo;
-#define MDG_UPW(R, P) launch_grad_upw_rp<R, P>(g, a, x, geo, nb, s.K, scale, s.NH, st)
+#define MDG_UPW(R, P) launch_grad_upw_rp<R, P>(g, a, x, dx, c, geo, nb, s.K, scale, s.NH, st)
   const bool fp32 = s.opt.precision == MDG_FP32;
   switch (s.P) {
     case 1: if (fp32) MDG_UPW(float, 1); else MDG_UPW(double, 1); break;
