@@ -316,8 +316,8 @@ mdg_status mdg_probe_energy_noalloc(mdg_solver* s, int64_t nsteps, int32_t nprob
  * advanced state) accumulating
  *   J = sum_{n=1..nsteps} dt sum_{T in probes} ||e^n||^2_{L2(T)},
  * then sweeps the adjoint of every step backwards, recomputing the forward
- * states of each interval of `every` steps from checkpoints kept on the
- * device, and returns J and grad_eps[nt] = dJ/deps_T (caller's element order;
+ * states and stage derivatives of each interval of `every` steps from
+ * checkpoints kept on the device, and returns J and grad_eps[nt] = dJ/deps_T (caller's element order;
  * FP64 reductions, the state precision of the solver). probes[nprobe] are
  * element indices. Requires MDG_RK4 (MDG_E_UNSUPPORTED). The averaged part
  * of the face terms and the volume curl are skew, the upwind penalties
@@ -327,8 +327,9 @@ mdg_status mdg_probe_energy_noalloc(mdg_solver* s, int64_t nsteps, int32_t nprob
  * equations are written for P/eps and Q/mu, whose values at the start are
  * held fixed: zero for a PML at rest) and, with the upwind flux, through the
  * face impedances sqrt(mu/eps) of every face of an element.
- * Allocates (nsteps/every + every + 10) state vectors (fields and PML
- * auxiliaries) of device memory for the call. Synchronous. */
+ * Allocates (ceil(nsteps/every) + 5 min(every, nsteps) + 6) state vectors
+ * (fields, PML auxiliaries, SIP unknown) of device memory for the call
+ * (MDG_E_OOM if they do not fit: a smaller `every` needs less). Synchronous. */
 mdg_status mdg_adjoint_probe_energy(mdg_solver* s, int64_t nsteps, int32_t every, int32_t nprobe,
                                      const int64_t* probes, double* J, double* grad_eps, void* stream);
 

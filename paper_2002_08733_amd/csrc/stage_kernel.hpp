@@ -778,6 +778,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const uint32_t e0 = (uint32_t)(A.elem_begin + tix * tile), b0 = e0 >> 6;
     const uint32_t rsh = __builtin_ctz((uint32_t)tile * RS);  // log2 of the row bytes
     const uint32_t nbytes = (uint32_t)ST * RS;
+    // cache policy of the copies: the input is read once per launch; marking
+    // it non-temporal pays in FP64 (32-element tiles), not in FP32 (measured)
+    constexpr int DMA_CP = sizeof(R) == 8 ? CP_NT : CP_DEF;
     const Rsrc rU = win_rsrc(A.Uin, A.nblk, b0, SBLK);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     lds_byte* dst = (lds_byte*)smem_raw + (uint32_t)SB * RS;
@@ -812,7 +815,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const uint32_t vo = c * 1024u + (uint32_t)(tid & 63) * 16u;
         bool zero;
         const uint32_t src = base + src_row(vo >> rsh, zero) * rowb<R>(1) + (vo & ((1u << rsh) - 1u));
-        if (vo < nbytes && !zero) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 1024u, 16, src, 0, 0, 0);
+        if (vo < nbytes && !zero) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 1024u, 16, src, 0, 0, DMA_CP);
       }
     } else {
       // a tile of the damped partition that straddles two blocks: 4 bytes
@@ -822,7 +825,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
         const uint32_t w = vo & ((1u << rsh) - 1u);
         bool zero;
         const uint32_t src = blk_rel(e0 + w / RS, b0, RB, RS) + src_row(vo >> rsh, zero) * rowb<R>(1) + w % RS;
-        if (vo < nbytes && !zero) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, 0);
+        if (vo < nbytes && !zero) __builtin_amdgcn_raw_ptr_buffer_load_lds(rU, dst + c * 256u, 4, src, 0, 0, DMA_CP);
       }
     }
   };
