@@ -779,8 +779,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const uint32_t rsh = __builtin_ctz((uint32_t)tile * RS);  // log2 of the row bytes
     const uint32_t nbytes = (uint32_t)ST * RS;
     // cache policy of the copies: the input is read once per launch; marking
-    // it non-temporal pays in FP64 (32-element tiles), not in FP32 (measured)
-    constexpr int DMA_CP = sizeof(R) == 8 ? CP_NT : CP_DEF;
+    // it non-temporal pays in FP64 (measured: RK4 stages 5%, leap-frog halves
+    // with the SIP unknown 9%), except in the four-lane leap-frog halves
+    // without it (4% slower), and not in FP32 (3% slower)
+    constexpr int DMA_CP = sizeof(R) == 8 && (!C || SIP) ? CP_NT : CP_DEF;
     const Rsrc rU = win_rsrc(A.Uin, A.nblk, b0, SBLK);
     const uint32_t wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     lds_byte* dst = (lds_byte*)smem_raw + (uint32_t)SB * RS;
