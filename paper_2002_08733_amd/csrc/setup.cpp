@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <utility>
 
 #include "refbasis.hpp"
 #include "refops_gen.h"
@@ -301,6 +302,38 @@ static void bisect(std::vector<int64_t>& perm, int64_t b, int64_t e, int64_t o, 
   }
 }
 
+static uint64_t spread21(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+// Halo slots of the tiles of perm[b, e) (runs of `leaf` from o): the largest
+// count of faces of one tile whose neighbour lies in another tile, and the
+// total. tile_of is scratch (all -1 on entry and on return).
+static std::pair<int64_t, int64_t> halo_counts(const Solver& s, const std::vector<int64_t>& perm, int64_t b, int64_t e,
+                                               int64_t o, int64_t leaf, std::vector<int64_t>& tile_of) {
+  for (int64_t i = b; i < e; ++i) tile_of[perm[i]] = (i - o) / leaf;
+  std::vector<int64_t> cnt((e - 1 - o) / leaf - (b - o) / leaf + 1, 0);
+  int64_t total = 0;
+  for (int64_t i = b; i < e; ++i) {
+    const int64_t ku = perm[i], t = tile_of[ku];
+    for (int f = 0; f < 4; ++f) {
+      const int64_t sd = s.side[4 * ku + f];
+      if (sd >= 0 && tile_of[sd / 4] != t) {
+        ++cnt[t - (b - o) / leaf];
+        ++total;
+      }
+    }
+  }
+  for (int64_t i = b; i < e; ++i) tile_of[perm[i]] = -1;
+  return {*std::max_element(cnt.begin(), cnt.end()), total};
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 void finalize(Solver& s) {
@@ -321,7 +354,11 @@ void finalize(Solver& s) {
   if (forced) tile0 = s.opt.tile;
   // non-PML elements, then PML elements; inside each, instance by instance,
   // each in the bisection order of its centroids (leaves of the first tile
-  // size tried)
+  // size tried) or along its Morton curve, whichever gives the smaller
+  // largest halo block (it sizes every workgroup's LDS), then the fewer halo
+  // slots: bisection cuts compact boxes out of a convex region, but leaves
+  // of a hollow one (a PML shell) can hold elements from both sides of the
+  // hole
   std::vector<double> cen(3 * nt);
   for (int64_t k = 0; k < nt; ++k)
     for (int c = 0; c < 3; ++c) {
@@ -338,11 +375,31 @@ void finalize(Solver& s) {
   s.K = nt;
   s.K0 = 0;
   for (int64_t k = 0; k < nt; ++k) s.K0 += !ispml[k];
-  // the damped partition is tiled from K0 on
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t k = 0; k < nt; ++k)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = std::min(lo[c], cen[3 * k + c]);
+      hi[c] = std::max(hi[c], cen[3 * k + c]);
+    }
+  std::vector<uint64_t> mkey(nt);
+  for (int64_t k = 0; k < nt; ++k) {
+    uint64_t code = 0;
+    for (int c = 0; c < 3; ++c) {
+      const double span = std::max(hi[c] - lo[c], 1e-300);
+      code |= spread21((uint64_t)std::min(2097151.0, std::max(0.0, (cen[3 * k + c] - lo[c]) / span * 2097151.0))) << c;
+    }
+    mkey[k] = code;
+  }
+  std::vector<int64_t> tile_of(nt, -1), morton(nt);
   for (int64_t g0 = 0; g0 < nt;) {
     int64_t g1 = g0 + 1;
     while (g1 < nt && ispml[s.perm[g1]] == ispml[s.perm[g0]] && s.inst_of[s.perm[g1]] == s.inst_of[s.perm[g0]]) ++g1;
-    bisect(s.perm, g0, g1, ispml[s.perm[g0]] ? s.K0 : 0, tile0, cen);
+    const int64_t o = ispml[s.perm[g0]] ? s.K0 : 0;  // the damped partition is tiled from K0 on
+    std::copy(s.perm.begin() + g0, s.perm.begin() + g1, morton.begin() + g0);
+    std::stable_sort(morton.begin() + g0, morton.begin() + g1, [&](int64_t x, int64_t y) { return mkey[x] < mkey[y]; });
+    bisect(s.perm, g0, g1, o, tile0, cen);
+    if (halo_counts(s, morton, g0, g1, o, tile0, tile_of) < halo_counts(s, s.perm, g0, g1, o, tile0, tile_of))
+      std::copy(morton.begin() + g0, morton.begin() + g1, s.perm.begin() + g0);
     g0 = g1;
   }
   s.iperm.resize(nt);
