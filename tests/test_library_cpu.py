@@ -383,3 +383,42 @@ def test_mfma_option_is_checked(lib):
     with pytest.raises(lib.MdgError) as e:
         lib.Solver(4, "fp32", mfma=True)
     assert e.value.status == lib.MDG_E_UNSUPPORTED
+
+
+def _cross_tile_faces(verts, tets, tile_of):
+    """Interior faces whose two elements lie in different tiles (counted once
+    per side, like the library's halo slots)."""
+    f = np.sort(np.stack([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]], axis=1),
+                axis=2).reshape(-1, 3)
+    key = (f[:, 0].astype(np.int64) * len(verts) + f[:, 1]) * len(verts) + f[:, 2]
+    o = np.argsort(key, kind="stable")
+    same = np.nonzero(key[o][1:] == key[o][:-1])[0]
+    a, b = o[same] // 4, o[same + 1] // 4
+    return 2 * int(np.count_nonzero(tile_of[a] != tile_of[b]))
+
+
+def test_tile_order_cuts_compact_tiles(lib):
+    """Tiles are runs of the element order (setup.cpp::finalize): on the
+    jittered cube the bisection order must give fewer cross-tile faces than
+    cutting the same mesh along a plain lexicographic order of centroids
+    would, and on the open-domain mesh, whose PML shell is hollow, the order
+    must keep 64-element FP32 tiles (a bisection leaf that spans the hole has
+    only halo faces, and the largest halo block sizes every workgroup's LDS)."""
+    w = W.jittered(16, 3, seed=2, flux="upwind")
+    s = lib.Solver(3, "fp32", "upwind", dt=1e-4)
+    s.set_mesh(w.verts, w.tets)
+    q = s.query()
+    s.close()
+    assert q["tile_size"] == 64
+    cen = w.verts[w.tets].mean(axis=1)
+    lex = np.lexsort((cen[:, 0], cen[:, 1], cen[:, 2]))
+    tile_of = np.empty(len(w.tets), np.int64)
+    tile_of[lex] = np.arange(len(w.tets)) // 64
+    assert q["n_halo"] < 0.8 * _cross_tile_faces(w.verts, w.tets, tile_of)
+    wp = W.open_pml(48, 3)  # the open-domain configuration (663,552 tets; 3 s on the host)
+    s = lib.Solver(3, "fp32", "upwind", dt=1e-4)
+    s.set_mesh(wp.verts, wp.tets)
+    s.set_pml(wp.omega)
+    qp = s.query()
+    s.close()
+    assert qp["tile_size"] == 64 and qp["n_pml"] > 0
