@@ -419,6 +419,7 @@ __device__ __forceinline__ void publish_face(const R* stg, int sf, int role, int
 //   leap-frog half (stage 4: E, 5: H): Y = y + dt k for the active field, with
 //               y taken from the staged input (the stage input is Y itself) or,
 //               with four lanes per element, loaded like the RK4 operands
+// y_staged: y comes from the staged input in leap-frog halves and stage 0
 struct Epi {
   Rsrc y_rd, a_rd, a_wr, out_wr, k_wr;
   bool final_stage, k_on;
@@ -430,7 +431,7 @@ __device__ __forceinline__ Epi make_epi(int stage, const void* Y, const void* AC
   Epi e;
   const bool op = stage < 0, lf = stage >= 4;
   e.final_stage = stage == 3;
-  e.y_rd = win_rsrc(Y, nblk, b0, block_bytes, !(op || (lf && y_staged)));
+  e.y_rd = win_rsrc(Y, nblk, b0, block_bytes, !(op || (y_staged && (lf || stage == 0))));
   e.a_rd = win_rsrc(ACC, nblk, b0, block_bytes, stage >= 1 && stage <= 3);
   e.a_wr = win_rsrc(ACC, nblk, b0, block_bytes, stage >= 0 && stage <= 2);
   e.out_wr = win_rsrc(lf ? Y : Uout, nblk, b0, block_bytes);
@@ -711,6 +712,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   // over the four parts, so that no wave does two parts' work while another
   // idles (the MFMA volume term keeps the parts of the full order)
   constexpr int QSH = MIX && !MF ? (NHc + 3) / 4 : NQ;
+  // FP64 RK4: the first stage takes y from the staged input (its input is Y)
+  constexpr bool YS0 = sizeof(R) == 8 && LF == 0;
   constexpr uint32_t RB = 3u * (N + NHc);
   constexpr uint32_t SBLK = RB * 64u * RS;
   // an offset past any window: a load there reads 0 (rows of h that the
@@ -878,7 +881,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
     const uint32_t b0 = (uint32_t)(A.elem_begin + tix * tile) >> 6;
     const uint32_t e = (uint32_t)(A.elem_begin + tix * tile + L.li);
     const uint32_t vo = blk_rel(e, b0, RB, RS);
-    const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.Kout, A.nblk, b0, SBLK, A.bcoef, A.cdt, A.dt, LF == 1);
+    const Epi ef = make_epi(A.stage, A.Y, A.ACC, A.Uout, A.Kout, A.nblk, b0, SBLK, A.bcoef, A.cdt, A.dt, LF == 1 || YS0);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -926,23 +929,26 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   const Rsrc rG = win_rsrc(a.geo, a.nblk, b0, NGEO * 64u * RS);
   const uint32_t vout = blk_rel(el, b0, RB, RS);  // element's state block
   const uint32_t vgeo = blk_rel(el, b0, NGEO, RS);
-  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.Kout, a.nblk, b0, SBLK, a.bcoef, a.cdt, a.dt, LF == 1);
+  const Epi ef = make_epi(a.stage, a.Y, a.ACC, a.Uout, a.Kout, a.nblk, b0, SBLK, a.bcoef, a.cdt, a.dt, LF == 1 || YS0);
   const int hn = uniform_ld(a.halo_tile, 2 * t + 1);  // halo slots of this tile
   const int hb = HB;
   __syncthreads();  // B0: the tile's input field(s) and halo block are in LDS
   const R* stg = lds + SB;
 
-  // leap-frog half: the stage input is the state itself, so the own rows of
-  // the output field come from the staging (no second read of Y), and only
-  // the lanes of the active field store and publish. The other role's lanes
-  // run along and their results are dropped (skipping their work gains
+  // leap-frog half, and the first RK4 stage in FP64: the stage input is the
+  // state itself, so the own rows of the output field come from the staging
+  // (no second read of Y: in FP64 the non-temporal copy leaves no copy of it
+  // in L2; in FP32 the second read hits L2 and the LDS reads cost more). In
+  // the leap-frog half only the lanes of the active field store and publish.
+  // The other role's lanes run along and their results are dropped (skipping
+  // their work gains
   // nothing: the launch is bound by the workgroup's chain of loads and
   // barriers, and with 32-element tiles the two roles share waves). With the
   // central flux the active field's derivative reads no trace of its own
   // field, which is what lets the halves share one halo buffer.
   const int lf = LF ? a.stage - 4 : -1;
   const bool wr = live && (!LF || lf == role);
-  if (LF == 1) {
+  if (LF == 1 || (YS0 && a.stage == 0)) {
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll

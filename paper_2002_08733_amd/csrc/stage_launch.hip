@@ -58,6 +58,9 @@ static void launch_r(int P, const DevArgs& a, bool upw, bool sip, bool pml, int 
 void launch_stage(const Solver& s, const StageParams& sp, void* stream) {
   char* base = static_cast<char*>(s.ws);
   DevArgs a{};
+  // the first RK4 stage reads its base state as its input (the FP64 kernel
+  // takes y from the staged input there)
+  if (sp.stage == 0 && sp.Uin != sp.Y) throw Error(MDG_E_STATE, "RK4 stage 0 takes the base state as its input");
   // the final RK4 stage writes the new state through Uout: into Yout, or in place
   const bool fin = sp.stage == 3;
   a.Y = sp.Y;
