@@ -210,10 +210,10 @@ def batched_main(args):
     """64 independent instances on uneven meshes (n_i^3 cubes x 6, n_i ~ U{8..24},
     jitter 0.1h, own eps ~ U[1,4], a z-dipole each), p=3, upwind, advanced by
     one launch per RK stage over all instances, the steps replayed from a HIP
-    graph; tile chosen by the autotuner on this workload."""
+    graph; tile and launch grid chosen by the autotuner on this workload."""
     import torch
     from paper_2002_08733_amd import Solver
-    from paper_2002_08733_amd.autotune import autotune_tile
+    from paper_2002_08733_amd.autotune import autotune, launch_candidates
     t0 = time.time()
     w = W.batched(args.instances, 3, seed=4)
     dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
@@ -224,8 +224,8 @@ def batched_main(args):
     wave = np.array([[d[2][0], d[2][1], 5.0 / (2.0 * np.pi * d[2][1])] for d in w.dipoles])
     inst = [d[3] for d in w.dipoles]
 
-    def make(prec, tile):
-        s = Solver(3, prec, "upwind", dt=dt, tile=tile)
+    def make(prec, tile, launch="auto"):
+        s = Solver(3, prec, "upwind", dt=dt, tile=tile, launch=launch)
         s.set_mesh(w.verts, w.tets)
         s.set_instances(w.info["first"])
         s.set_material(w.eps, w.mu)
@@ -238,9 +238,10 @@ def batched_main(args):
     sp = stream.cuda_stream
     for prec in (["fp32"] if args.skip_fp64 else ["fp32", "fp64"]):
         t1 = time.time()
-        tile, tune = autotune_tile(lambda t: make(prec, t), candidates=(32, 64), steps=5, warmup=2)
-        log(f"[bench] {prec}: autotune {tune} -> tile {tile} ({time.time() - t1:.1f} s)")
-        s = make(prec, tile)
+        shape, tune = autotune(lambda **kw: make(prec, **kw), launch_candidates(prec, 3), steps=5, warmup=2)
+        tile = shape["tile"]
+        log(f"[bench] {prec}: autotune {tune} -> tile {tile}, launch {shape['launch']} ({time.time() - t1:.1f} s)")
+        s = make(prec, tile, shape["launch"])
         info = s.query()
         with torch.cuda.stream(stream):
             s.step_graph(args.warmup, args.graph_steps, sp)
@@ -270,7 +271,7 @@ def batched_main(args):
                           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                                        "algorithmic_bytes_per_launch": info["bytes_per_stage"]},
-                          "tile": tile, "autotune_us_per_step": tune,
+                          "tile": tile, "launch": shape["launch"], "autotune_us_per_step": tune,
                           "energy_min": float(Wi.min()), "energy_max": float(Wi.max())}
         log(f"[bench] {prec}: {gdof:.1f} GDOF/s, {1e6 * sec / stages:.1f} us/stage (graph), "
             f"eager {1e6 * res['eager'] / stages:.1f} us/stage, {100 * achieved / HBM_PEAK_GBS:.1f}% of HBM")

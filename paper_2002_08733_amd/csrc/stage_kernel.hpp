@@ -1265,7 +1265,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
       }
     __syncthreads();  // B5
   }
-  if (more) prefetch(a, tid, tnext, early);
+  // the next tile's copies and operand loads; the first barrier of a tile
+  // waits for all but the operand loads, so the copies must be issued before
+  // those on every path into it
+  if (more) {
+    if (early) prefetch(a, tid, tnext, true);
+    else halo_copy(a, tid, a.tile_begin + tnext);
+  }
   if (a.publish && wr && pcode >= 0) {
     const Rsrc rHo = make_rsrc(a.hout, a.hbuf_bytes);
     if (MIX && role == 1) {
@@ -1277,10 +1283,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(waves_per_e
   if (!more) break;
   tl = tnext;
   // without room for the next tile's input beside the output staging it is
-  // copied now, once every lane has read the staging (B6)
+  // copied now, once every lane has read the staging (B6), and the operand
+  // loads follow it
   if (!early) {
     __syncthreads();  // B6
     input_copy(a, tid, tl);
+    __builtin_amdgcn_sched_barrier(0);
+    load_operands(a, tid, tl);
   }
   }  // tile loop
 }

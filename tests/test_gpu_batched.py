@@ -6,8 +6,12 @@ launches, HIP-graph replay of the step sequence, and the tile autotuner.
 * One instance of a batch against the FP64 oracle (dipole-driven from zero).
 * Graph replay against eager stepping, replayed several times with eager
   work and synchronisations in between; every replay is checked.
-* The autotuner returns one of its candidates, with a timing for each.
+* The autotuner returns one of its candidates, with a timing for each, also
+  over launch grids.
 * Instances with the SIP unknown reproduce their individual runs.
+* The persistent grid (only the resident workgroups, each looping over its
+  tiles) gives the same bits as one workgroup per tile: RK4 with PML elements
+  and a dipole, leap-frog halves, and replayed from a HIP graph.
 """
 import numpy as np
 import pytest
@@ -204,3 +208,73 @@ def test_autotune_tile_returns_a_candidate():
     say(f"[autotune] K={w.nt}: {times} -> tile {best}")
     assert best in (32, 64) and set(times) == {32, 64}
     assert all(v > 0 for v in times.values())
+
+
+def test_autotune_searches_launch_grids():
+    from paper_2002_08733_amd import Solver
+    from paper_2002_08733_amd.autotune import autotune, launch_candidates
+    w = W.jittered(10, 3, seed=5, flux="upwind")
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, 0.3)
+
+    def make(tile, launch):
+        s = Solver(3, "fp32", "upwind", dt=dt, tile=tile, launch=launch)
+        s.set_mesh(w.verts, w.tets)
+        s.set_material(w.eps, w.mu)
+        s.bind_torch_workspace()
+        return s
+
+    cands = launch_candidates("fp32", 3)
+    assert len(cands) == 4 and len(launch_candidates("fp64", 3)) == 2
+    best, times = autotune(make, cands, steps=5, warmup=2)
+    say(f"[autotune] K={w.nt}: {times} -> {best}")
+    assert best in cands and set(times) == {"32/per_tile", "64/per_tile", "32/persistent", "64/persistent"}
+    assert all(v > 0 for v in times.values())
+
+
+def _run_launch(w, launch, integrator, steps, graph=False):
+    import torch
+    from paper_2002_08733_amd import Solver
+    cfl = 0.2 if integrator == "leapfrog" else 0.3
+    dt = W.cfl_dt(w.verts, w.tets, w.eps, w.mu, w.p, cfl)
+    s = Solver(w.p, "fp32", w.flux, dt=dt, integrator=integrator, launch=launch)
+    s.set_mesh(w.verts, w.tets)
+    s.set_material(w.eps, w.mu)
+    if w.omega is not None:
+        s.set_pml(w.omega)
+    if w.dipoles:
+        d = w.dipoles[0]
+        s.set_dipoles(d[0][None], d[1][None], np.array([_wave(d)]))
+    s.bind_torch_workspace()
+    x = s.projection_points(4)
+    s.project(4, W.gaussian_curl_e(x, 0.3), None)
+    if graph:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s.step_graph(steps, 5, stream.cuda_stream)
+    else:
+        s.step(steps)
+    torch.cuda.synchronize()
+    E, H, _ = s.get_state()
+    q = s.query()
+    s.close()
+    return E, H, q
+
+
+@pytest.mark.parametrize("case", ["rk4_pml_dipole", "leapfrog", "rk4_graph"])
+def test_persistent_launch_matches_one_workgroup_per_tile(case):
+    """More tiles than resident workgroups (256 CUs x 2 for RK4, x 4 for the
+    four-lane leap-frog halves), so that the workgroups of the persistent grid
+    loop over several tiles."""
+    if case == "rk4_pml_dipole":
+        w = W.open_pml(28, 3)
+    elif case == "leapfrog":
+        w = W.jittered(24, 3, seed=3, flux="central")
+    else:
+        w = W.jittered(24, 3, seed=4, flux="upwind")
+    integ = "leapfrog" if case == "leapfrog" else "rk4"
+    say(f"[persistent] {case}: K={len(w.tets)}")
+    E0, H0, q = _run_launch(w, "per_tile", integ, 10, graph=case == "rk4_graph")
+    E1, H1, _ = _run_launch(w, "persistent", integ, 10, graph=case == "rk4_graph")
+    assert q["n_tiles"] > 1024
+    assert np.abs(E0).max() > 0
+    assert np.array_equal(E0, E1) and np.array_equal(H0, H1)
