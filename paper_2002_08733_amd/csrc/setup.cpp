@@ -16,6 +16,7 @@
 // face-basis coefficients can be combined without any permutation.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -334,6 +335,110 @@ static std::pair<int64_t, int64_t> halo_counts(const Solver& s, const std::vecto
   return {*std::max_element(cnt.begin(), cnt.end()), total};
 }
 
+// Refines the tiles of perm[b, e) (runs of `leaf` from o) by swapping
+// elements between face-adjacent tiles. Every element offers a move to each
+// tile it touches, with the gain (its faces into that tile minus its faces
+// into its own); the offers between two tiles are paired best first in both
+// directions, and a pair is swapped when the gains recomputed at that moment
+// (less 2 if the two are neighbours) add up to a positive number, so every
+// swap removes cross-tile faces and tile sizes stay fixed. Sweeps repeat
+// while they gain; the result is kept only if its largest halo block is not
+// larger than the starting one. Each tile's elements are then sorted along
+// its longest centroid extent (halving a tile still gives compact halves).
+static void refine_tiles(const Solver& s, std::vector<int64_t>& perm, int64_t b, int64_t e, int64_t o, int64_t leaf,
+                         const std::vector<double>& cen, std::vector<int64_t>& tile_of) {
+  if (e - b <= leaf) return;
+  const std::vector<int64_t> start(perm.begin() + b, perm.begin() + e);
+  const int64_t max0 = halo_counts(s, perm, b, e, o, leaf, tile_of).first;
+  struct Move {
+    int64_t a, t, gain, i;  // from tile a to tile t, the element at position i
+  };
+  // faces of element x into tile t (t = its own tile: the faces kept inside)
+  auto faces_into = [&](int64_t x, int64_t t) {
+    int64_t c = 0;
+    for (int f = 0; f < 4; ++f) {
+      const int64_t sd = s.side[4 * x + f];
+      c += sd >= 0 && tile_of[sd / 4] == t;
+    }
+    return c;
+  };
+  auto order = [](const Move& p, const Move& q) {
+    if (p.a != q.a) return p.a < q.a;
+    if (p.t != q.t) return p.t < q.t;
+    return p.gain > q.gain;
+  };
+  std::vector<Move> moves;
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    for (int64_t i = b; i < e; ++i) tile_of[perm[i]] = (i - o) / leaf;
+    moves.clear();
+    for (int64_t i = b; i < e; ++i) {
+      const int64_t x = perm[i], a = tile_of[x], own = faces_into(x, a);
+      for (int f = 0; f < 4; ++f) {
+        const int64_t sd = s.side[4 * x + f];
+        if (sd < 0) continue;
+        const int64_t t = tile_of[sd / 4];
+        if (t < 0 || t == a) continue;  // another group, or inside
+        bool seen = false;
+        for (int g = 0; g < f; ++g) seen = seen || (s.side[4 * x + g] >= 0 && tile_of[s.side[4 * x + g] / 4] == t);
+        if (!seen) moves.push_back({a, t, faces_into(x, t) - own, i});
+      }
+    }
+    std::sort(moves.begin(), moves.end(), order);
+    int64_t swaps = 0;
+    for (size_t k = 0; k < moves.size();) {
+      const int64_t a = moves[k].a, t = moves[k].t;
+      size_t k1 = k;
+      while (k1 < moves.size() && moves[k1].a == a && moves[k1].t == t) ++k1;
+      if (a < t) {
+        auto q = std::lower_bound(moves.begin(), moves.end(), Move{t, a, INT64_MAX, 0}, order);
+        for (size_t p = k; p < k1 && q != moves.end() && q->a == t && q->t == a;) {
+          const int64_t xa = perm[moves[p].i], xb = perm[q->i];
+          if (tile_of[xa] != a) { ++p; continue; }  // moved already
+          if (tile_of[xb] != t) { ++q; continue; }
+          bool adj = false;
+          for (int f = 0; f < 4; ++f) adj = adj || (s.side[4 * xa + f] >= 0 && s.side[4 * xa + f] / 4 == xb);
+          const int64_t g = faces_into(xa, t) - faces_into(xa, a) + faces_into(xb, a) - faces_into(xb, t) -
+                            (adj ? 2 : 0);
+          if (g <= 0) {
+            if (moves[p].gain + q->gain <= 0) break;  // the remaining offers gain less
+            if (moves[p].gain >= q->gain) ++q; else ++p;
+            continue;
+          }
+          std::swap(perm[moves[p].i], perm[q->i]);
+          tile_of[xa] = t;
+          tile_of[xb] = a;
+          ++swaps;
+          ++p;
+          ++q;
+        }
+      }
+      k = k1;
+    }
+    for (int64_t i = b; i < e; ++i) tile_of[perm[i]] = -1;
+    if (swaps == 0) break;
+  }
+  if (halo_counts(s, perm, b, e, o, leaf, tile_of).first > max0) {
+    std::copy(start.begin(), start.end(), perm.begin() + b);
+    return;
+  }
+  // compact halves inside every tile
+  for (int64_t t0 = b; t0 < e;) {
+    const int64_t t1 = std::min(e, o + ((t0 - o) / leaf + 1) * leaf);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = t0; i < t1; ++i)
+      for (int c = 0; c < 3; ++c) {
+        lo[c] = std::min(lo[c], cen[3 * perm[i] + c]);
+        hi[c] = std::max(hi[c], cen[3 * perm[i] + c]);
+      }
+    int ax = 0;
+    for (int c = 1; c < 3; ++c)
+      if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+    std::sort(perm.begin() + t0, perm.begin() + t1,
+              [&](int64_t x, int64_t y) { return cen[3 * x + ax] < cen[3 * y + ax]; });
+    t0 = t1;
+  }
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 void finalize(Solver& s) {
@@ -358,7 +463,7 @@ void finalize(Solver& s) {
   // largest halo block (it sizes every workgroup's LDS), then the fewer halo
   // slots: bisection cuts compact boxes out of a convex region, but leaves
   // of a hollow one (a PML shell) can hold elements from both sides of the
-  // hole
+  // hole; then refined by swaps between adjacent tiles
   std::vector<double> cen(3 * nt);
   for (int64_t k = 0; k < nt; ++k)
     for (int c = 0; c < 3; ++c) {
@@ -400,6 +505,7 @@ void finalize(Solver& s) {
     bisect(s.perm, g0, g1, o, tile0, cen);
     if (halo_counts(s, morton, g0, g1, o, tile0, tile_of) < halo_counts(s, s.perm, g0, g1, o, tile0, tile_of))
       std::copy(morton.begin() + g0, morton.begin() + g1, s.perm.begin() + g0);
+    refine_tiles(s, s.perm, g0, g1, o, tile0, cen, tile_of);
     g0 = g1;
   }
   s.iperm.resize(nt);
